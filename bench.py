@@ -1,0 +1,231 @@
+"""Throughput of the micromagnetic RK4 step on one MI355X.
+
+Workload (default): the 512 x 512 x 16 film (4.19M cubic cells of 3 nm,
+Ms 8e5 A/m, A 1.3e-11 J/m, Ku 0, alpha 0.1, H_ext 0, seeded random m), FP32,
+zero-padded FFT 1024 x 1024 x 32, RK4 dt 5e-14 s.  A step is one full RK4 step:
+four effective-field evaluations (five FFT passes each) and four fused
+LLG/RK4 stage passes.  value = cells * steps / seconds (cell-updates/s).
+
+Printed: one JSON line with the throughput, the roofline of the dominant
+kernel (its average launch time measured with HIP events inside the timed
+region), an FP64 leg, the sampled field error against the FP64 oracle, and the
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_IDS = ["x_fwd", "y_fwd", "kspace", "y_inv", "x_inv", "llg"]
+
+
+def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
+    """Bytes each kernel must move per launch (reads + writes of its inputs and
+    outputs once, nothing for the zero padding it never stores)."""
+    N = nx * ny * nz
+    hx, Py = plan["hx"], plan["py"]
+    cz = 2 * esz                           # one complex value
+    real3 = 3 * N * esz                    # m or H, three components
+    half_x = 3 * nz * ny * hx * cz         # after the x pass
+    if plan["passes"] == 5:
+        full_y = 3 * nz * Py * hx * cz     # after the y pass
+        kern = plan["spectrum_elems"] * esz
+        b = {"x_fwd": real3 + half_x, "y_fwd": half_x + full_y, "kspace": 2 * full_y + kern,
+             "y_inv": full_y + half_x, "x_inv": half_x + real3}
+    else:
+        kern = plan["spectrum_elems"] * esz
+        b = {"x_fwd": real3 + half_x, "y_fwd": 0, "kspace": 2 * half_x + kern, "y_inv": 0,
+             "x_inv": half_x + real3}
+    # LLG stage: reads m_s, H_d (+ m_n, acc for stages 2-4), writes acc/out:
+    # 4, 6, 6, 5 vector arrays -> 21/4 vector arrays on average per launch.
+    b["llg"] = int(21 * 3 * N * esz / 4)
+    return b
+
+
+def run_gpu(args, cfg, precision: str, steps: int, warmup: int, profile: bool):
+    import torch
+
+    import paper_1501_07293_amd as mm
+    from synthetic import random_unit_m
+
+    sim = mm.Sim(cfg.nx, cfg.ny, cfg.nz, cfg.cell, Ms=cfg.Ms, A=cfg.A, Ku=cfg.Ku, alpha=cfg.alpha,
+                 gamma=cfg.gamma, precision=precision, graph=args.graph, device="cuda:0")
+    sim.set_hext(cfg.hext)
+    m0 = random_unit_m(cfg.shape, seed=0)
+    sim.set_m(m0)
+    plan = sim.plan()
+    sim.step(warmup, cfg.dt)
+    torch.cuda.synchronize()
+    per_kernel = {}
+    if profile:
+        # short untimed pass: average duration of every kernel class
+        for k in KERNEL_IDS:
+            if plan["passes"] == 3 and k in ("y_fwd", "y_inv"):
+                continue
+            sim.profile_begin(k)
+            sim.step(2, cfg.dt)
+            ms, n = sim.profile_end()
+            per_kernel[k] = (ms / max(n, 1), n)
+        dom = max(per_kernel, key=lambda k: per_kernel[k][0] * per_kernel[k][1])
+        sim.profile_begin(dom)
+    else:
+        dom = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, cfg.dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms = dom_n = None
+    if dom is not None:
+        tot, dom_n = sim.profile_end()
+        dom_ms = tot / max(dom_n, 1)
+    energy = sim.energy()
+    return sim, plan, t1 - t0, per_kernel, dom, dom_ms, dom_n, energy
+
+
+def field_error_sampled(sim, cfg, pb, nsamp: int, seed: int = 1):
+    import oracle
+    rng = np.random.default_rng(seed)
+    N = cfg.N
+    corners = [0, cfg.nx - 1, (cfg.ny - 1) * cfg.nx, N - 1]
+    obs = np.unique(np.concatenate([corners, rng.integers(0, N, size=nsamp)])).astype(np.int64)
+    m = sim.get_m().double().cpu().numpy()
+    hd = sim.field("demag").double().cpu().numpy().reshape(3, -1)[:, obs]
+    t0 = time.perf_counter()
+    ref = oracle.demag(pb, m, obs)
+    dt = time.perf_counter() - t0
+    err = float(np.abs(hd - ref).max() / np.abs(ref).max())
+    return err, len(obs), dt, m
+
+
+def cpu_baseline(cfg, pb, m, target_s: float):
+    """The FP64 oracle on the host cores: direct-sum demag on a sample of
+    observation cells plus the O(N) local terms over the whole grid, scaled to
+    one RK4 step (four field evaluations for every cell)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(7)
+    N = cfg.N
+    nobs = 16
+    t_obs = 0.0
+    while True:
+        obs = rng.integers(0, N, size=nobs).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.demag(pb, m, obs)
+        t_obs = time.perf_counter() - t0
+        if t_obs > 0.25 * target_s or nobs >= N:
+            break
+        nobs = int(min(N, nobs * max(2.0, 0.3 * target_s / max(t_obs, 1e-3))))
+    t0 = time.perf_counter()
+    h = oracle.exchange(pb, m)
+    oracle.llg_rhs(pb, m, h)
+    t_local = time.perf_counter() - t0
+    per_step = 4 * (t_obs / nobs * N + t_local)
+    return {"value": N / per_step, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"direct-sum demag at {nobs} sampled observation cells ({t_obs:.1f} s) + "
+                      f"local terms on all {N} cells ({t_local:.2f} s), scaled to 4 field "
+                      f"evaluations per cell per RK4 step (extrapolated; O(N^2) oracle vs "
+                      f"O(N log N) GPU path)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", default="large", choices=["large", "mid", "small"])
+    ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--samples", type=int, default=64)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              f"a multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthetic
+
+    cfg = {"large": synthetic.LARGE, "mid": synthetic.MID, "small": synthetic.SMALL}[args.workload]
+    esz = 4 if args.precision == "f32" else 8
+    sim, plan, secs, per_kernel, dom, dom_ms, dom_n, energy = run_gpu(
+        args, cfg, args.precision, args.steps, args.warmup, not args.no_profile)
+    value = cfg.N * args.steps / secs
+    out = {
+        "metric": "cell-updates/s per LLG step (FP32 vs FP64 at stated err), % HBM roofline",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"{cfg.name} cells={cfg.N} cell={cfg.cell:g} m, RK4 dt={cfg.dt:g} s, "
+                               f"padded FFT {plan['px']}x{plan['py']}x{plan['pz']}",
+                   "precision": args.precision, "graph": bool(args.graph),
+                   "fft_passes_per_field": plan["passes"], "threads_per_fft_wg": plan["threads"]},
+    }
+    if dom is not None:
+        ab = algorithmic_bytes(plan, cfg.nx, cfg.ny, cfg.nz, esz)
+        achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": mm_kernel_symbol(dom, args.precision, plan),
+                           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": dom_ms,
+                           "launches_timed": dom_n}
+        step_bytes = 4 * sum(ab.values())
+        out["kernels"] = {k: {"avg_ms": v[0], "gbs": ab[k] / (v[0] * 1e-3) / 1e9 if v[0] else None}
+                          for k, v in per_kernel.items()}
+        out["step_model_bytes_per_cell"] = step_bytes / cfg.N
+        out["effective_gbs"] = step_bytes / (secs / args.steps) / 1e9
+    out["energy_J"] = energy.tolist()
+
+    need_oracle = not args.no_cpu_baseline
+    if need_oracle:
+        import oracle
+        pb = oracle.Problem(cfg.nx, cfg.ny, cfg.nz, cfg.cell, Ms=cfg.Ms, A=cfg.A, Ku=cfg.Ku,
+                            alpha=cfg.alpha, gamma=cfg.gamma, hext=tuple(cfg.hext))
+        t0 = time.perf_counter()
+        pb.table()
+        t_table = time.perf_counter() - t0
+        err, nobs, _, m = field_error_sampled(sim, cfg, pb, args.samples)
+        out["err"] = {"demag_field_rel_max_sampled": err, "sampled_cells": nobs,
+                      "tolerance": 1e-5 if args.precision == "f32" else 1e-11}
+        cb = cpu_baseline(cfg, pb, m, args.cpu_seconds)
+        cb["setup_s"] = t_table
+        out["cpu_baseline"] = cb
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    if not args.no_fp64_leg and args.precision == "f32":
+        fsteps = max(1, args.steps // 10)
+        sim64, _, secs64, _, _, _, _, _ = run_gpu(args, cfg, "f64", fsteps, 2, False)
+        out["fp64"] = {"value": cfg.N * fsteps / secs64, "steps": fsteps,
+                       "ms_per_step": 1e3 * secs64 / fsteps}
+        sim64.close()
+    print(json.dumps(out), flush=True)
+
+
+def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
+    base = {"x_fwd": "k_row_r2c", "y_fwd": "k_col_fft", "kspace": "k_kspace", "y_inv": "k_col_fft",
+            "x_inv": "k_row_c2r", "llg": "k_llg_stage"}[k]
+    t = "float" if precision == "f32" else "double"
+    if k == "llg":
+        return f"mm::{base}<{t}>"
+    return f"mm::{base}<{t}, {plan['threads']}>"
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * mmag.h -- C ABI of the MI355X (gfx950) finite-difference micromagnetic step.
+ *
+ * The library evaluates the effective field of Zhu, arXiv:1501.07293, Sec. 2
+ * (Eq. 3: exchange + uniaxial anisotropy + demagnetisation + applied field)
+ * on an nx x ny x nz grid of cubic cells and advances the magnetisation with
+ * the Landau-Lifshitz form of the LLG equation (Eq. 2) and classical RK4,
+ * renormalising every cell once per step.
+ *   - exchange: six-neighbour Laplacian, Neumann boundary (Sec. 2.1, Eqs. 5-7)
+ *   - anisotropy: easy axis x, field on the x component (Sec. 2.2, Eq. 8)
+ *   - demag: convolution of M with the tensor of Eqs. 10-11 (Sec. 2.3,
+ *     Eqs. 12-13), evaluated by a zero-padded 3-D FFT (Eq. 14, Fig. 1)
+ *
+ * Conventions (every entry point):
+ *   - Returns mm_status; 0 is success.  Nothing throws across the ABI.  On
+ *     error, mm_last_error() returns a thread-local message.
+ *   - Units are SI: lengths m, fields A/m, Ms A/m, A J/m, Ku J/m^3, gamma
+ *     m/(A s) multiplying H in A/m, time s, energy J.
+ *   - Arrays of vectors are planar [3][nz][ny][nx], x fastest, in the working
+ *     precision of the handle (float for MM_F32, double for MM_F64).  Scalar
+ *     maps are [nz][ny][nx].
+ *   - `on_device` = 1: the pointer is device memory on the handle's device;
+ *     0: host memory.  The caller owns every buffer it passes; the library
+ *     keeps no pointer to caller arrays after a call returns.
+ *   - Work is enqueued on the handle's stream (a hipStream_t passed as void*;
+ *     NULL = the null stream).  mm_step returns without waiting; calls that
+ *     return host values (get_energy, get_mean_m, get_* to host) synchronise.
+ *   - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef MMAG_H
+#define MMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,      /* invalid argument (dims, material, dt, NaN / zero m, small workspace) */
+    MM_ENOMEM = -2,      /* device allocation failed */
+    MM_EHIP = -3,        /* HIP runtime error; mm_last_error() has the HIP text */
+    MM_ESTATE = -4,      /* call order (e.g. step before set_m) */
+    MM_ENOTSUP = -5,     /* valid but unsupported size / option */
+    MM_ENONFINITE = -6   /* a reduction met NaN or Inf in m */
+} mm_status;
+
+typedef enum { MM_F32 = 0, MM_F64 = 1 } mm_precision;
+
+typedef enum {
+    MM_H_EXCH = 0,   /* Eqs. 5-7 */
+    MM_H_ANIS = 1,   /* Eq. 8 */
+    MM_H_DEMAG = 2,  /* Eqs. 12-14 */
+    MM_H_EXT = 3,    /* applied field */
+    MM_H_EFF = 4     /* Eq. 3, the sum */
+} mm_term;
+
+/* Option flags. */
+#define MM_NO_DEMAG 0x1u   /* drop the demag term (exchange, anisotropy, applied only) */
+#define MM_USE_GRAPH 0x2u  /* mm_step replays a captured hipGraph of whole RK4 steps */
+
+typedef struct {
+    int32_t nx, ny, nz; /* cells along x, y, z; each >= 1 */
+    double cell;        /* cubic cell edge delta, m, > 0 */
+} mm_grid;
+
+typedef struct {
+    double Ms;    /* saturation magnetisation, A/m, > 0 */
+    double A;     /* exchange constant, J/m, >= 0 */
+    double Ku;    /* uniaxial anisotropy along x, J/m^3 (uniform; see mm_set_ku_map) */
+    double alpha; /* damping, >= 0 */
+    double gamma; /* gyromagnetic ratio, m/(A s), > 0 (e.g. 2.211e5) */
+} mm_material;
+
+typedef struct {
+    int32_t prec;        /* mm_precision */
+    int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
+                            smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
+                            size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH */
+    int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
+} mm_options;
+
+typedef struct {
+    int32_t px, py, pz;  /* padded sizes */
+    int32_t hx;          /* px/2 + 1 stored half-spectrum bins along x */
+    int32_t ncomp;       /* 6 kernel spectra, or 4 (xx, xy, yy, zz) when nz == 1 */
+    int32_t threads;     /* FFT work-group size in use */
+    int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*(py/2+1)*hx */
+    int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1, else 5) */
+    double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
+} mm_plan_info;
+
+typedef struct mm_sim mm_sim;
+
+/* Bytes of device workspace mm_create needs for this grid and options. */
+mm_status mm_workspace_query(const mm_grid* grid, const mm_options* opt, size_t* bytes);
+
+/* Creates a handle.  d_workspace: caller-owned device memory of ws_bytes
+ * (>= mm_workspace_query), 256-byte aligned; NULL lets the library allocate
+ * (freed by mm_destroy).  Builds the demag tensor (Eqs. 10-11, FP64, origin
+ * included) and its FP64 3-D FFT (the kernel spectrum, stored as a real
+ * octant in the working precision) on `stream`.  *out is NULL on failure. */
+mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_options* opt,
+                    void* d_workspace, size_t ws_bytes, void* stream, mm_sim** out);
+
+/* Destroys a handle (NULL is accepted).  Waits for its stream. */
+mm_status mm_destroy(mm_sim* sim);
+
+mm_status mm_set_stream(mm_sim* sim, void* stream);
+
+/* Sets m from [3][nz][ny][nx] values; each cell is normalised to unit length.
+ * A zero-length or non-finite cell gives MM_EINVAL (and leaves no valid m). */
+mm_status mm_set_m(mm_sim* sim, const void* m, int on_device);
+mm_status mm_get_m(mm_sim* sim, void* out, int on_device);
+
+/* Applied field, A/m, constant until changed. */
+mm_status mm_set_hext(mm_sim* sim, const double h[3]);
+mm_status mm_set_alpha(mm_sim* sim, double alpha);
+
+/* Per-cell Ku map [nz][ny][nx] in J/m^3 (working precision); NULL restores the
+ * uniform material Ku. */
+mm_status mm_set_ku_map(mm_sim* sim, const void* ku, int on_device);
+
+/* Advances nsteps classical RK4 steps of dt seconds (dt > 0, finite).  Each step
+ * evaluates the effective field four times and renormalises m once.
+ * Asynchronous on the handle's stream.  MM_ESTATE before mm_set_m. */
+mm_status mm_step(mm_sim* sim, int64_t nsteps, double dt);
+
+/* One term of the effective field at the current m, A/m, [3][nz][ny][nx]. */
+mm_status mm_get_field(mm_sim* sim, int32_t term, void* out, int on_device);
+
+/* Energies of Eq. 1 at the current m, J: {exchange, anisotropy, demag, Zeeman,
+ * total}; FP64 reductions.  MM_ENONFINITE if m holds NaN or Inf. */
+mm_status mm_get_energy(mm_sim* sim, double out[5]);
+
+/* Mean of m over the cells (FP64). */
+mm_status mm_get_mean_m(mm_sim* sim, double out[3]);
+
+mm_status mm_get_plan(mm_sim* sim, mm_plan_info* out);
+
+/* Kernel-spectrum octant [ncomp][pz/2+1][py/2+1][hx], working precision,
+ * already scaled by 1/(px py pz) (the normalisation of the inverse FFT). */
+mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
+
+/* Demag tensor of Eqs. 10-11 over every offset |I|<nx, |J|<ny, |K|<nz, FP64,
+ * dimensionless: d_out[6][2nz-1][2ny-1][2nx-1] (device memory, caller-owned),
+ * component order xx, xy, xz, yy, yz, zz, offset index (K+nz-1, J+ny-1, I+nx-1). */
+mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream);
+
+/* Per-kernel timing with HIP events on the handle's stream.  kernel: 0 x-forward,
+ * 1 y-forward, 2 k-space, 3 y-inverse, 4 x-inverse, 5 LLG stage.  While a
+ * profile is open mm_step launches kernels directly (no graph replay) and
+ * brackets every launch of that kernel with an event pair.  mm_profile_end
+ * synchronises and returns the summed duration (ms) and the launch count. */
+mm_status mm_profile_begin(mm_sim* sim, int32_t kernel);
+mm_status mm_profile_end(mm_sim* sim, double* total_ms, int64_t* launches);
+const char* mm_kernel_name(int32_t kernel);
+
+const char* mm_status_string(mm_status s);
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMAG_H */

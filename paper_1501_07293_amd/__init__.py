@@ -1,0 +1,268 @@
+"""MI355X-native finite-difference micromagnetic LLG step (arXiv:1501.07293).
+
+Thin ctypes binding of ``libmmag.so`` (the C ABI declared in include/mmag.h).
+PyTorch supplies device memory (the workspace and array arguments) and the
+stream; every step of the computation runs in the library's HIP kernels.
+There is no CPU fallback: without the built library every call raises.
+
+Arrays are torch tensors of shape (3, nz, ny, nx) in the handle's precision
+(float32 for "f32", float64 for "f64") on the GPU; host numpy arrays are
+accepted by ``set_m`` and converted.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmmag.so")
+
+MM_F32, MM_F64 = 0, 1
+MM_NO_DEMAG, MM_USE_GRAPH = 0x1, 0x2
+TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
+KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
+
+EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
+           "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_get_field",
+           "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
+           "mm_demag_tensor", "mm_profile_begin", "mm_profile_end", "mm_kernel_name",
+           "mm_status_string", "mm_last_error"]
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {status_name(status)} ({status}): {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("cell", ctypes.c_double)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("Ku", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
+                ("pz", ctypes.c_int32), ("flags", ctypes.c_uint32), ("threads", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("px", ctypes.c_int32), ("py", ctypes.c_int32), ("pz", ctypes.c_int32),
+                ("hx", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("spectrum_elems", ctypes.c_int64), ("passes", ctypes.c_int32),
+                ("kernel_imag_ratio", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmmag.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1501_07293_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mm_workspace_query": [ctypes.POINTER(Grid), ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)],
+        "mm_create": [ctypes.POINTER(Grid), ctypes.POINTER(Material), ctypes.POINTER(Options), vp,
+                      ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+        "mm_destroy": [vp],
+        "mm_set_stream": [vp, vp],
+        "mm_set_m": [vp, vp, ctypes.c_int],
+        "mm_get_m": [vp, vp, ctypes.c_int],
+        "mm_set_hext": [vp, ctypes.POINTER(dbl)],
+        "mm_set_alpha": [vp, dbl],
+        "mm_set_ku_map": [vp, vp, ctypes.c_int],
+        "mm_step": [vp, i64, dbl],
+        "mm_get_field": [vp, i32, vp, ctypes.c_int],
+        "mm_get_energy": [vp, ctypes.POINTER(dbl)],
+        "mm_get_mean_m": [vp, ctypes.POINTER(dbl)],
+        "mm_get_plan": [vp, ctypes.POINTER(PlanInfo)],
+        "mm_get_kernel_spectrum": [vp, vp, ctypes.c_int],
+        "mm_demag_tensor": [i32, i32, i32, vp, vp],
+        "mm_profile_begin": [vp, i32],
+        "mm_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.mm_kernel_name.argtypes = [i32]
+    lib.mm_kernel_name.restype = ctypes.c_char_p
+    lib.mm_status_string.argtypes = [ctypes.c_int]
+    lib.mm_status_string.restype = ctypes.c_char_p
+    lib.mm_last_error.argtypes = []
+    lib.mm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_name(s: int) -> str:
+    return load_library().mm_status_string(s).decode()
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise MMError(st, where, load_library().mm_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1501_07293_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream_ptr(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Sim:
+    """One grid + material on one GPU (handle around mm_create / mm_step)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, cell: float, Ms: float = 8.0e5,
+                 A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
+                 precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
+                 graph: bool = False, threads: int = 0, device: str = "cuda:0"):
+        torch = _torch()
+        lib = load_library()
+        self._torch = torch
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nz, self.cell, self.Ms = nx, ny, nz, cell, Ms
+        self.N = nx * ny * nz
+        self.shape = (3, nz, ny, nx)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        self._grid = Grid(nx, ny, nz, cell)
+        self._mat = Material(Ms, A, Ku, alpha, gamma)
+        flags = (0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+        self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
+                            threads)
+        nbytes = ctypes.c_size_t()
+        _check(lib.mm_workspace_query(ctypes.byref(self._grid), ctypes.byref(self._opt),
+                                      ctypes.byref(nbytes)), "mm_workspace_query")
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            _check(lib.mm_create(ctypes.byref(self._grid), ctypes.byref(self._mat),
+                                 ctypes.byref(self._opt), self.workspace.data_ptr(), nbytes.value,
+                                 _stream_ptr(torch, self.device), ctypes.byref(h)), "mm_create")
+        self._h = h
+        self._lib = lib
+
+    # ---------------------------------------------------------------- state
+    def _sync_stream(self):
+        _check(self._lib.mm_set_stream(self._h, _stream_ptr(self._torch, self.device)), "mm_set_stream")
+
+    def set_m(self, m):
+        torch = self._torch
+        if isinstance(m, np.ndarray):
+            m = torch.from_numpy(np.ascontiguousarray(m))
+        t = m.to(device=self.device, dtype=self.dtype).contiguous().reshape(self.shape)
+        self._sync_stream()
+        _check(self._lib.mm_set_m(self._h, t.data_ptr(), 1), "mm_set_m")
+
+    def get_m(self):
+        out = self._torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_get_m(self._h, out.data_ptr(), 1), "mm_get_m")
+        return out
+
+    def set_hext(self, h: Sequence[float]):
+        arr = (ctypes.c_double * 3)(*[float(v) for v in h])
+        _check(self._lib.mm_set_hext(self._h, arr), "mm_set_hext")
+
+    def set_alpha(self, alpha: float):
+        _check(self._lib.mm_set_alpha(self._h, float(alpha)), "mm_set_alpha")
+
+    def set_ku_map(self, ku):
+        if ku is None:
+            _check(self._lib.mm_set_ku_map(self._h, None, 0), "mm_set_ku_map")
+            return
+        torch = self._torch
+        if isinstance(ku, np.ndarray):
+            ku = torch.from_numpy(np.ascontiguousarray(ku))
+        t = ku.to(device=self.device, dtype=self.dtype).contiguous().reshape(self.nz, self.ny, self.nx)
+        self._sync_stream()
+        _check(self._lib.mm_set_ku_map(self._h, t.data_ptr(), 1), "mm_set_ku_map")
+
+    def step(self, nsteps: int, dt: float):
+        self._sync_stream()
+        _check(self._lib.mm_step(self._h, int(nsteps), float(dt)), "mm_step")
+
+    # --------------------------------------------------------------- readout
+    def field(self, term: str = "eff"):
+        out = self._torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_get_field(self._h, TERMS[term], out.data_ptr(), 1), "mm_get_field")
+        return out
+
+    def energy(self) -> np.ndarray:
+        out = (ctypes.c_double * 5)()
+        self._sync_stream()
+        _check(self._lib.mm_get_energy(self._h, out), "mm_get_energy")
+        return np.array(out[:])
+
+    def mean_m(self) -> np.ndarray:
+        out = (ctypes.c_double * 3)()
+        self._sync_stream()
+        _check(self._lib.mm_get_mean_m(self._h, out), "mm_get_mean_m")
+        return np.array(out[:])
+
+    def plan(self) -> dict:
+        p = PlanInfo()
+        _check(self._lib.mm_get_plan(self._h, ctypes.byref(p)), "mm_get_plan")
+        return {k: getattr(p, k) for k, _ in PlanInfo._fields_}
+
+    def kernel_spectrum(self):
+        p = self.plan()
+        out = self._torch.empty(int(p["spectrum_elems"]), dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_get_kernel_spectrum(self._h, out.data_ptr(), 1), "mm_get_kernel_spectrum")
+        return out.reshape(p["ncomp"], p["pz"] // 2 + 1, p["py"] // 2 + 1, p["hx"])
+
+    # ------------------------------------------------------------- profiling
+    def profile_begin(self, kernel: str):
+        self._sync_stream()
+        _check(self._lib.mm_profile_begin(self._h, KERNELS[kernel]), "mm_profile_begin")
+
+    def profile_end(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self._lib.mm_profile_end(self._h, ctypes.byref(ms), ctypes.byref(n)), "mm_profile_end")
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def demag_tensor(nx: int, ny: int, nz: int, device: str = "cuda:0"):
+    """Demag tensor of Eqs. 10-11 on the GPU in FP64: (6, 2nz-1, 2ny-1, 2nx-1)."""
+    torch = _torch()
+    lib = load_library()
+    out = torch.empty((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1), dtype=torch.float64, device=device)
+    _check(lib.mm_demag_tensor(nx, ny, nz, out.data_ptr(), _stream_ptr(torch, torch.device(device))),
+           "mm_demag_tensor")
+    return out
+
+
+def kernel_name(k: int) -> str:
+    return load_library().mm_kernel_name(k).decode()

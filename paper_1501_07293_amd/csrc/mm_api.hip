@@ -1,0 +1,937 @@
+// mm_api.hip -- host side of the library: argument checks, plan (padded sizes,
+// radix schedules, tile shapes), workspace carve-up, the one-time kernel
+// spectrum build, the RK4 driver with optional hipGraph replay, field and
+// energy read-out, and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mmag.h"
+#include "mm_kernels.hpp"
+
+using namespace mm;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kMu0 = 4.0e-7 * kPi;
+
+thread_local std::string g_err;
+
+mm_status fail(mm_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(MM_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                        __LINE__);                                                            \
+    } while (0)
+
+bool smooth7(int n)
+{
+    if (n < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+int auto_pad(int n)
+{
+    if (smooth7(2 * n)) return 2 * n;
+    int p = 2 * n - 1;
+    while (!smooth7(p)) ++p;
+    return p;
+}
+
+bool make_fft_plan(int P, FftPlan* pl)
+{
+    memset(pl, 0, sizeof *pl);
+    pl->P = P;
+    int rest = P, span = 1, s = 0;
+    const int order[] = {16, 8, 4, 2, 3, 5, 7};
+    while (rest > 1) {
+        int r = 0;
+        for (int c : order)
+            if (rest % c == 0) {
+                r = c;
+                break;
+            }
+        if (r == 0 || s >= kMaxStages) return false;
+        pl->radix[s] = r;
+        pl->span[s] = span;
+        pl->tstride[s] = P / (span * r);
+        span *= r;
+        rest /= r;
+        ++s;
+    }
+    pl->nst = s;
+    return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    int nx, ny, nz;
+    int64_t N;
+    int Px, Py, Pz, hx;
+    int64_t sx;        // row stride (complex elements) of the working spectrum
+    int64_t sxd;       // row stride of the FP64 setup spectrum
+    bool three_d;
+    int ncomp;
+    int nt;
+    int prec;
+    size_t esz;        // sizeof(T)
+    FftPlan fx, fy, fz;
+    int x_lines, y_tw, k_tw;
+    int64_t S_planes, S_rows;  // spectrum [3][S_planes][S_rows][sx]
+    int64_t oct_elems;         // per component
+    // workspace offsets
+    size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_kern, o_twx, o_twy, o_twz;
+    size_t o_twxd, o_twyd, o_twzd, o_red, o_redout, o_flags, o_setR, o_setS, total;
+};
+
+mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
+{
+    if (!g) return fail(MM_EINVAL, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(MM_EINVAL, "grid dims must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+    if (!(g->cell > 0.0) || !std::isfinite(g->cell))
+        return fail(MM_EINVAL, "cell size must be finite and > 0");
+    mm_options def{};
+    if (!o) o = &def;
+    if (o->prec != MM_F32 && o->prec != MM_F64) return fail(MM_EINVAL, "prec must be MM_F32 or MM_F64");
+    *p = Plan{};
+    p->nx = g->nx;
+    p->ny = g->ny;
+    p->nz = g->nz;
+    p->N = (int64_t)g->nx * g->ny * g->nz;
+    if (p->N > (int64_t)1 << 30) return fail(MM_ENOTSUP, "grid too large (%lld cells)", (long long)p->N);
+    p->prec = o->prec;
+    p->esz = o->prec == MM_F32 ? 4 : 8;
+    p->three_d = g->nz > 1;
+    auto pick = [](int n, int req, bool allow1, int* out) -> mm_status {
+        if (req == 0) {
+            *out = (allow1 && n == 1) ? 1 : auto_pad(n);
+            return MM_OK;
+        }
+        if (req == 1 && allow1 && n == 1) {
+            *out = 1;
+            return MM_OK;
+        }
+        if (req < 2 * n - 1 || !smooth7(req))
+            return fail(MM_EINVAL, "padded size %d must be 7-smooth and >= 2n-1 = %d", req, 2 * n - 1);
+        *out = req;
+        return MM_OK;
+    };
+    mm_status st;
+    if ((st = pick(g->nx, o->px, false, &p->Px)) != MM_OK) return st;
+    if ((st = pick(g->ny, o->py, false, &p->Py)) != MM_OK) return st;
+    if ((st = pick(g->nz, o->pz, true, &p->Pz)) != MM_OK) return st;
+    if (p->Pz == 1 && g->nz != 1) return fail(MM_EINVAL, "pz = 1 needs nz = 1");
+    // a padded z axis with nz == 1 still works through the 3-D schedule
+    p->three_d = p->Pz > 1;
+    p->hx = p->Px / 2 + 1;
+    const int sx_align = p->esz == 4 ? 8 : 4;
+    p->sx = (p->hx + sx_align - 1) / sx_align * sx_align;
+    p->sxd = (p->hx + 3) / 4 * 4;
+    p->ncomp = p->three_d ? 6 : 4;
+    // FFT work-group size: each thread keeps kElemsPerThread elements; the
+    // k-space pass holds 3 components of its last axis.
+    const int last = p->three_d ? p->Pz : p->Py;
+    int nt = o->threads;
+    if (nt != 0 && nt != 256 && nt != 512) return fail(MM_EINVAL, "threads must be 0, 256 or 512");
+    auto fits = [&](int t) {
+        const int cap = kElemsPerThread * t;
+        return p->Px <= cap && p->Py <= cap && p->Pz <= cap && 3 * last <= cap;
+    };
+    if (nt == 0) nt = fits(256) ? 256 : 512;
+    if (!fits(nt)) return fail(MM_ENOTSUP, "padded sizes %d x %d x %d exceed the FFT work-group capacity",
+                               p->Px, p->Py, p->Pz);
+    p->nt = nt;
+    if (!make_fft_plan(p->Px, &p->fx) || !make_fft_plan(p->Py, &p->fy) || !make_fft_plan(p->Pz, &p->fz))
+        return fail(MM_EINVAL, "padded sizes must be 7-smooth");
+    const int cap = kElemsPerThread * nt, ldscap = cap + 64;
+    p->x_lines = std::min(cap / p->Px, ldscap / (p->Px + 1));
+    p->y_tw = std::max(1, std::min(64, cap / p->Py));
+    p->k_tw = std::max(1, std::min(64, cap / (3 * last)));
+    if (p->three_d) {
+        p->S_planes = p->nz;
+        p->S_rows = p->Py;
+    } else {
+        p->S_planes = 1;
+        p->S_rows = p->ny;
+    }
+    p->oct_elems = (int64_t)(p->Pz / 2 + 1) * (p->Py / 2 + 1) * p->hx;
+    // workspace
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const size_t vec = 3 * (size_t)p->N * p->esz;
+    p->o_mn = take(vec);
+    p->o_ma = take(vec);
+    p->o_mb = take(vec);
+    p->o_acc = take(vec);
+    p->o_hd = take(vec);
+    p->o_ku = take((size_t)p->N * p->esz);
+    p->o_S = take(3 * (size_t)p->S_planes * p->S_rows * p->sx * 2 * p->esz);
+    p->o_kern = take((size_t)p->ncomp * p->oct_elems * p->esz);
+    p->o_twx = take((size_t)p->Px * 2 * p->esz);
+    p->o_twy = take((size_t)p->Py * 2 * p->esz);
+    p->o_twz = take((size_t)p->Pz * 2 * p->esz);
+    p->o_twxd = take((size_t)p->Px * 16);
+    p->o_twyd = take((size_t)p->Py * 16);
+    p->o_twzd = take((size_t)p->Pz * 16);
+    p->o_red = take(1024 * 8 * sizeof(double));
+    p->o_redout = take(8 * sizeof(double));
+    p->o_flags = take(64);
+    p->o_setR = take((size_t)p->Px * p->Py * p->Pz * sizeof(double));
+    p->o_setS = take((size_t)p->Pz * p->Py * p->sxd * 16);
+    p->total = off;
+    return MM_OK;
+}
+
+bool check_material(const mm_material* m)
+{
+    return m && m->Ms > 0 && std::isfinite(m->Ms) && m->A >= 0 && std::isfinite(m->A) &&
+           std::isfinite(m->Ku) && m->alpha >= 0 && std::isfinite(m->alpha) && m->gamma > 0 &&
+           std::isfinite(m->gamma);
+}
+
+}  // namespace
+
+struct mm_sim {
+    Plan p;
+    mm_material mat;
+    double cell;
+    uint32_t flags;
+    char* ws;
+    bool own_ws;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    double hext[3];
+    double alpha;
+    bool has_m;
+    bool has_ku_map;
+    double imag_ratio;
+    // graph
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_valid;
+    double graph_dt;
+    int graph_chunk;
+    // profiling
+    int prof_kernel;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used;
+
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+enum { KX_FWD = 0, KY_FWD = 1, KSPACE = 2, KY_INV = 3, KX_INV = 4, KLLG = 5, KCOUNT = 6 };
+
+mm_status prof_pre(mm_sim* s, int kid, hipStream_t st)
+{
+    if (s->prof_kernel != kid) return MM_OK;
+    if (s->ev_used + 2 > s->ev.size()) {
+        for (int q = 0; q < 256; ++q) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            s->ev.push_back(e);
+        }
+    }
+    HIP_TRY(hipEventRecord(s->ev[s->ev_used], st));
+    return MM_OK;
+}
+
+mm_status prof_post(mm_sim* s, int kid, hipStream_t st)
+{
+    if (s->prof_kernel != kid) return MM_OK;
+    HIP_TRY(hipEventRecord(s->ev[s->ev_used + 1], st));
+    s->ev_used += 2;
+    return MM_OK;
+}
+
+#define LAUNCH(kid, call)                                                     \
+    do {                                                                      \
+        mm_status ps_ = prof_pre(s, kid, st);                                 \
+        if (ps_ != MM_OK) return ps_;                                         \
+        HIP_TRY(call);                                                        \
+        ps_ = prof_post(s, kid, st);                                          \
+        if (ps_ != MM_OK) return ps_;                                         \
+    } while (0)
+
+// Demag field (reduced, h = H/Ms) of m_src into hd: Eq. 14 with zero padding.
+template <typename T>
+mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
+{
+    const Plan& p = s->p;
+    void* S = s->at<char>(p.o_S);
+    const int64_t plane = p.S_rows * p.sx;
+    RowR2CArgs xr{};
+    xr.in = msrc;
+    xr.in_row_stride = p.nx;
+    xr.nrows = (int)(3 * p.nz * p.ny);
+    xr.nvalid = p.nx;
+    xr.out = S;
+    xr.rows_per_plane = p.ny;
+    xr.out_plane_stride = plane;
+    xr.sx = p.sx;
+    xr.hx = p.hx;
+    xr.lines_per_wg = p.x_lines;
+    xr.pl = p.fx;
+    xr.tw = s->at<char>(p.o_twx);
+    LAUNCH(KX_FWD, launch_row_r2c<T>(xr, p.nt, st));
+
+    ColArgs cy{};
+    if (p.three_d) {
+        cy.buf = S;
+        cy.nplanes = 3 * p.nz;
+        cy.plane_stride = plane;
+        cy.ncols = p.hx;
+        cy.cols_per_row = p.hx;
+        cy.row2_stride = 0;
+        cy.es = p.sx;
+        cy.nin = p.ny;
+        cy.nout = p.Py;
+        cy.inverse = 0;
+        cy.tw_cols = p.y_tw;
+        cy.pl = p.fy;
+        cy.tw = s->at<char>(p.o_twy);
+        LAUNCH(KY_FWD, launch_col_fft<T>(cy, p.nt, st));
+    }
+
+    KspArgs k{};
+    k.buf = S;
+    k.kern = s->at<char>(p.o_kern);
+    k.ncomp = p.ncomp;
+    k.hx = p.hx;
+    k.Py = p.Py;
+    k.Pz = p.Pz;
+    k.k_cs = p.oct_elems;
+    k.k_zs = (int64_t)(p.Py / 2 + 1) * p.hx;
+    k.k_ys = p.hx;
+    k.tw_cols = p.k_tw;
+    if (p.three_d) {
+        k.comp_stride = p.S_planes * plane;
+        k.ncols = p.Py * p.hx;
+        k.cols_per_row = p.hx;
+        k.row2_stride = p.sx;
+        k.es = plane;
+        k.nvalid = p.nz;
+        k.pl = p.fz;
+        k.tw = s->at<char>(p.o_twz);
+        k.axis_is_z = 1;
+    } else {
+        k.comp_stride = plane;
+        k.ncols = p.hx;
+        k.cols_per_row = p.hx;
+        k.row2_stride = 0;
+        k.es = p.sx;
+        k.nvalid = p.ny;
+        k.pl = p.fy;
+        k.tw = s->at<char>(p.o_twy);
+        k.axis_is_z = 0;
+    }
+    LAUNCH(KSPACE, launch_kspace<T>(k, p.nt, st));
+
+    if (p.three_d) {
+        cy.nin = p.Py;
+        cy.nout = p.ny;
+        cy.inverse = 1;
+        LAUNCH(KY_INV, launch_col_fft<T>(cy, p.nt, st));
+    }
+
+    RowC2RArgs xi{};
+    xi.in = S;
+    xi.rows_per_plane = p.ny;
+    xi.in_plane_stride = plane;
+    xi.sx = p.sx;
+    xi.hx = p.hx;
+    xi.nrows = (int)(3 * p.nz * p.ny);
+    xi.out = hd;
+    xi.out_row_stride = p.nx;
+    xi.nvalid = p.nx;
+    xi.lines_per_wg = p.x_lines;
+    xi.pl = p.fx;
+    xi.tw = s->at<char>(p.o_twx);
+    LAUNCH(KX_INV, launch_row_c2r<T>(xi, p.nt, st));
+    return MM_OK;
+}
+
+template <typename T>
+LlgArgs<T> llg_args(const mm_sim* s, double dt)
+{
+    const Plan& p = s->p;
+    const double Ms = s->mat.Ms;
+    LlgArgs<T> a{};
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.N = p.N;
+    a.cex = (T)(2.0 * s->mat.A / (kMu0 * Ms * Ms * s->cell * s->cell));
+    a.can = (T)(2.0 * s->mat.Ku / (kMu0 * Ms * Ms));
+    a.hx = (T)(s->hext[0] / Ms);
+    a.hy = (T)(s->hext[1] / Ms);
+    a.hz = (T)(s->hext[2] / Ms);
+    a.alpha = (T)s->alpha;
+    a.gdt = (T)(s->mat.gamma * Ms * dt / (1.0 + s->alpha * s->alpha));
+    a.ku = s->has_ku_map ? s->at<T>(p.o_ku) : nullptr;
+    a.hd = (s->flags & MM_NO_DEMAG) ? nullptr : s->at<T>(p.o_hd);
+    return a;
+}
+
+}  // namespace
+
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// One RK4 step of dt on stream st.  Stage inputs cycle m_n -> m_a -> m_b -> m_a;
+// stage 4 writes the renormalised result back into m_n.
+template <typename T>
+mm_status rk4_step(mm_sim* s, double dt, hipStream_t st)
+{
+    const Plan& p = s->p;
+    T* mn = s->at<T>(p.o_mn);
+    T* ma = s->at<T>(p.o_ma);
+    T* mb = s->at<T>(p.o_mb);
+    T* acc = s->at<T>(p.o_acc);
+    T* hd = s->at<T>(p.o_hd);
+    T* src[4] = {mn, ma, mb, ma};
+    T* dst[4] = {ma, mb, ma, mn};
+    LlgArgs<T> a = llg_args<T>(s, dt);
+    a.mn = mn;
+    a.acc = acc;
+    for (int stg = 0; stg < 4; ++stg) {
+        if (!(s->flags & MM_NO_DEMAG)) {
+            mm_status r = demag<T>(s, src[stg], hd, st);
+            if (r != MM_OK) return r;
+        }
+        a.ms = src[stg];
+        a.out = dst[stg];
+        a.stage = stg + 1;
+        LAUNCH(KLLG, launch_llg_stage<T>(a, st));
+    }
+    return MM_OK;
+}
+
+template <typename T>
+mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
+{
+    const Plan& p = s->p;
+    HIP_TRY(launch_twiddles<T>(s->at<char>(p.o_twx), p.Px, st));
+    HIP_TRY(launch_twiddles<T>(s->at<char>(p.o_twy), p.Py, st));
+    HIP_TRY(launch_twiddles<T>(s->at<char>(p.o_twz), p.Pz, st));
+    HIP_TRY(launch_twiddles<double>(s->at<char>(p.o_twxd), p.Px, st));
+    HIP_TRY(launch_twiddles<double>(s->at<char>(p.o_twyd), p.Py, st));
+    HIP_TRY(launch_twiddles<double>(s->at<char>(p.o_twzd), p.Pz, st));
+    unsigned long long* stats = s->at<unsigned long long>(p.o_flags);
+    HIP_TRY(hipMemsetAsync(stats, 0, 64, st));
+    if (s->flags & MM_NO_DEMAG) return MM_OK;
+    double* R = s->at<double>(p.o_setR);
+    void* Sd = s->at<char>(p.o_setS);
+    const int comps6[6] = {0, 1, 2, 3, 4, 5};
+    const int comps4[4] = {0, 1, 3, 5};  // xx, xy, yy, zz: xz and yz vanish on one plane
+    const int* comps = p.ncomp == 6 ? comps6 : comps4;
+    const double scale = 1.0 / ((double)p.Px * p.Py * p.Pz);
+    const int nt = p.nt;
+    const int cap = kElemsPerThread * nt, ldscap = cap + 64;
+    for (int q = 0; q < p.ncomp; ++q) {
+        HIP_TRY(launch_tensor_wrapped(R, comps[q], p.nx, p.ny, p.nz, p.Px, p.Py, p.Pz, st));
+        RowR2CArgs xr{};
+        xr.in = R;
+        xr.in_row_stride = p.Px;
+        xr.nrows = p.Py * p.Pz;
+        xr.nvalid = p.Px;
+        xr.out = Sd;
+        xr.rows_per_plane = p.Py * p.Pz;
+        xr.out_plane_stride = 0;
+        xr.sx = p.sxd;
+        xr.hx = p.hx;
+        xr.lines_per_wg = std::min(cap / p.Px, ldscap / (p.Px + 1));
+        xr.pl = p.fx;
+        xr.tw = s->at<char>(p.o_twxd);
+        if (xr.lines_per_wg < 1) return fail(MM_ENOTSUP, "px too large for the FP64 setup FFT");
+        HIP_TRY(launch_row_r2c<double>(xr, nt, st));
+        ColArgs c{};
+        c.buf = Sd;
+        c.nplanes = p.Pz;
+        c.plane_stride = (int64_t)p.Py * p.sxd;
+        c.ncols = p.hx;
+        c.cols_per_row = p.hx;
+        c.row2_stride = 0;
+        c.es = p.sxd;
+        c.nin = p.Py;
+        c.nout = p.Py;
+        c.inverse = 0;
+        c.tw_cols = std::max(1, std::min(64, cap / p.Py));
+        c.pl = p.fy;
+        c.tw = s->at<char>(p.o_twyd);
+        if (p.Py > cap) return fail(MM_ENOTSUP, "py too large for the FP64 setup FFT");
+        HIP_TRY(launch_col_fft<double>(c, nt, st));
+        if (p.Pz > 1) {
+            ColArgs z{};
+            z.buf = Sd;
+            z.nplanes = 1;
+            z.plane_stride = 0;
+            z.ncols = p.Py * p.hx;
+            z.cols_per_row = p.hx;
+            z.row2_stride = p.sxd;
+            z.es = (int64_t)p.Py * p.sxd;
+            z.nin = p.Pz;
+            z.nout = p.Pz;
+            z.inverse = 0;
+            z.tw_cols = std::max(1, std::min(64, cap / p.Pz));
+            z.pl = p.fz;
+            z.tw = s->at<char>(p.o_twzd);
+            HIP_TRY(launch_col_fft<double>(z, nt, st));
+        }
+        HIP_TRY(launch_octant<T>(s->at<char>(p.o_kern) + (size_t)q * p.oct_elems * p.esz, Sd, p.hx,
+                                 p.Py, p.Pz, p.sxd, scale, stats, st));
+    }
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double im, re;
+    memcpy(&im, &h[0], 8);
+    memcpy(&re, &h[1], 8);
+    s->imag_ratio = re > 0 ? im / re : 0.0;
+    return MM_OK;
+}
+
+void drop_graph(mm_sim* s)
+{
+    if (s->gexec) hipGraphExecDestroy(s->gexec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_valid = false;
+}
+
+template <typename T>
+mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
+{
+    hipStream_t st = s->stream;
+    const bool use_graph = (s->flags & MM_USE_GRAPH) && s->prof_kernel < 0;
+    if (!use_graph) {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            mm_status r = rk4_step<T>(s, dt, st);
+            if (r != MM_OK) return r;
+        }
+        return MM_OK;
+    }
+    const int chunk = 8;
+    if (!s->graph_valid || s->graph_dt != dt) {
+        drop_graph(s);
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = MM_OK;
+        for (int q = 0; q < chunk && r == MM_OK; ++q) r = rk4_step<T>(s, dt, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (r != MM_OK) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        s->graph = g;
+        HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+        s->graph_valid = true;
+        s->graph_dt = dt;
+        s->graph_chunk = chunk;
+    }
+    int64_t n = 0;
+    for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, st));
+    for (; n < nsteps; ++n) {
+        mm_status r = rk4_step<T>(s, dt, st);
+        if (r != MM_OK) return r;
+    }
+    return MM_OK;
+}
+
+template <typename T>
+mm_status field_impl(mm_sim* s, int term, void* out, int on_device)
+{
+    const Plan& p = s->p;
+    hipStream_t st = s->stream;
+    LlgArgs<T> a = llg_args<T>(s, 0.0);
+    T* mn = s->at<T>(p.o_mn);
+    a.ms = mn;
+    a.mn = mn;
+    if (!(s->flags & MM_NO_DEMAG) && (term == MM_H_DEMAG || term == MM_H_EFF)) {
+        mm_status r = demag<T>(s, mn, s->at<T>(p.o_hd), st);
+        if (r != MM_OK) return r;
+    }
+    T* dst = on_device ? (T*)out : s->at<T>(p.o_mb);
+    HIP_TRY(launch_field_term<T>(a, term, (T)s->mat.Ms, dst, st));
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(out, dst, 3 * p.N * sizeof(T), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return MM_OK;
+}
+
+template <typename T>
+mm_status reduce_impl(mm_sim* s, double out8[8])
+{
+    const Plan& p = s->p;
+    hipStream_t st = s->stream;
+    LlgArgs<T> a = llg_args<T>(s, 0.0);
+    T* mn = s->at<T>(p.o_mn);
+    a.ms = mn;
+    a.mn = mn;
+    if (!(s->flags & MM_NO_DEMAG)) {
+        mm_status r = demag<T>(s, mn, s->at<T>(p.o_hd), st);
+        if (r != MM_OK) return r;
+    }
+    double* dout = s->at<double>(p.o_redout);
+    HIP_TRY(launch_reduce<T>(a, s->at<double>(p.o_red), reduce_blocks(p.N), dout, st));
+    HIP_TRY(hipMemcpyAsync(out8, dout, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+template <typename T>
+mm_status set_m_impl(mm_sim* s, const void* m, int on_device)
+{
+    const Plan& p = s->p;
+    hipStream_t st = s->stream;
+    T* mn = s->at<T>(p.o_mn);
+    HIP_TRY(hipMemcpyAsync(mn, m, 3 * p.N * sizeof(T),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    unsigned int* bad = reinterpret_cast<unsigned int*>(s->at<char>(p.o_flags) + 32);
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), st));
+    HIP_TRY(launch_normalize<T>(mn, p.N, bad, st));
+    unsigned int nbad = 0;
+    HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nbad) {
+        s->has_m = false;
+        return fail(MM_EINVAL, "m has %u zero-length or non-finite cells", nbad);
+    }
+    s->has_m = true;
+    return MM_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+mm_status mm_workspace_query(const mm_grid* grid, const mm_options* opt, size_t* bytes)
+{
+    if (!bytes) return fail(MM_EINVAL, "bytes is NULL");
+    Plan p;
+    mm_status st = build_plan(grid, opt, &p);
+    if (st != MM_OK) return st;
+    *bytes = p.total;
+    return MM_OK;
+}
+
+mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_options* opt,
+                    void* d_workspace, size_t ws_bytes, void* stream, mm_sim** out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Plan p;
+    mm_status st = build_plan(grid, opt, &p);
+    if (st != MM_OK) return st;
+    if (!check_material(mat))
+        return fail(MM_EINVAL, "material needs Ms > 0, A >= 0, alpha >= 0, gamma > 0, all finite");
+    if (d_workspace && ws_bytes < p.total)
+        return fail(MM_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, p.total);
+    if (d_workspace && (reinterpret_cast<uintptr_t>(d_workspace) & 255))
+        return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    mm_sim* s = new mm_sim();
+    s->p = p;
+    s->mat = *mat;
+    s->cell = grid->cell;
+    s->flags = opt ? opt->flags : 0;
+    s->stream = as_stream(stream);
+    s->alpha = mat->alpha;
+    s->hext[0] = s->hext[1] = s->hext[2] = 0.0;
+    s->prof_kernel = -1;
+    if (d_workspace) {
+        s->ws = static_cast<char*>(d_workspace);
+    } else {
+        void* w = nullptr;
+        hipError_t e = hipMalloc(&w, p.total);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(MM_ENOMEM, "hipMalloc(%zu): %s", p.total, hipGetErrorString(e));
+        }
+        s->ws = static_cast<char*>(w);
+        s->own_ws = true;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (s->own_ws) hipFree(s->ws);
+        delete s;
+        return fail(MM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    st = p.prec == MM_F32 ? build_kernel_spectrum<float>(s, s->stream)
+                          : build_kernel_spectrum<double>(s, s->stream);
+    if (st != MM_OK) {
+        std::string keep = g_err;
+        mm_destroy(s);
+        g_err = keep;
+        return st;
+    }
+    *out = s;
+    return MM_OK;
+}
+
+mm_status mm_destroy(mm_sim* s)
+{
+    if (!s) return MM_OK;
+    hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    for (hipEvent_t e : s->ev) hipEventDestroy(e);
+    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+    if (s->own_ws) hipFree(s->ws);
+    delete s;
+    return MM_OK;
+}
+
+mm_status mm_set_stream(mm_sim* s, void* stream)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    s->stream = as_stream(stream);
+    return MM_OK;
+}
+
+mm_status mm_set_m(mm_sim* s, const void* m, int on_device)
+{
+    if (!s || !m) return fail(MM_EINVAL, "sim or m is NULL");
+    return s->p.prec == MM_F32 ? set_m_impl<float>(s, m, on_device) : set_m_impl<double>(s, m, on_device);
+}
+
+mm_status mm_get_m(mm_sim* s, void* out, int on_device)
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
+    const size_t bytes = 3 * (size_t)s->p.N * s->p.esz;
+    HIP_TRY(hipMemcpyAsync(out, s->at<char>(s->p.o_mn), bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));
+    return MM_OK;
+}
+
+mm_status mm_set_hext(mm_sim* s, const double h[3])
+{
+    if (!s || !h) return fail(MM_EINVAL, "sim or h is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(h[a])) return fail(MM_EINVAL, "applied field must be finite");
+    for (int a = 0; a < 3; ++a) s->hext[a] = h[a];
+    s->graph_valid = false;
+    return MM_OK;
+}
+
+mm_status mm_set_alpha(mm_sim* s, double alpha)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (!(alpha >= 0) || !std::isfinite(alpha)) return fail(MM_EINVAL, "alpha must be finite and >= 0");
+    s->alpha = alpha;
+    s->graph_valid = false;
+    return MM_OK;
+}
+
+mm_status mm_set_ku_map(mm_sim* s, const void* ku, int on_device)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    s->graph_valid = false;
+    if (!ku) {
+        s->has_ku_map = false;
+        return MM_OK;
+    }
+    const Plan& p = s->p;
+    const size_t n = (size_t)p.N;
+    const double f = 2.0 / (kMu0 * s->mat.Ms * s->mat.Ms);  // Ku -> reduced 2 Ku / (mu0 Ms^2)
+    if (p.prec == MM_F32) {
+        std::vector<float> h(n);
+        if (on_device) {
+            HIP_TRY(hipMemcpy(h.data(), ku, n * 4, hipMemcpyDeviceToHost));
+        } else {
+            memcpy(h.data(), ku, n * 4);
+        }
+        for (auto& v : h) {
+            if (!std::isfinite(v)) return fail(MM_EINVAL, "Ku map must be finite");
+            v = (float)(v * f);
+        }
+        HIP_TRY(hipMemcpyAsync(s->at<char>(p.o_ku), h.data(), n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    } else {
+        std::vector<double> h(n);
+        if (on_device) {
+            HIP_TRY(hipMemcpy(h.data(), ku, n * 8, hipMemcpyDeviceToHost));
+        } else {
+            memcpy(h.data(), ku, n * 8);
+        }
+        for (auto& v : h) {
+            if (!std::isfinite(v)) return fail(MM_EINVAL, "Ku map must be finite");
+            v = v * f;
+        }
+        HIP_TRY(hipMemcpyAsync(s->at<char>(p.o_ku), h.data(), n * 8, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    s->has_ku_map = true;
+    return MM_OK;
+}
+
+mm_status mm_step(mm_sim* s, int64_t nsteps, double dt)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!s->has_m) return fail(MM_ESTATE, "mm_step before mm_set_m");
+    return s->p.prec == MM_F32 ? step_impl<float>(s, nsteps, dt) : step_impl<double>(s, nsteps, dt);
+}
+
+mm_status mm_get_field(mm_sim* s, int32_t term, void* out, int on_device)
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (term < 0 || term > 4) return fail(MM_EINVAL, "term must be 0..4");
+    if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
+    return s->p.prec == MM_F32 ? field_impl<float>(s, term, out, on_device)
+                               : field_impl<double>(s, term, out, on_device);
+}
+
+mm_status mm_get_energy(mm_sim* s, double out[5])
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
+    double r[8];
+    mm_status st = s->p.prec == MM_F32 ? reduce_impl<float>(s, r) : reduce_impl<double>(s, r);
+    if (st != MM_OK) return st;
+    if (r[7] != 0.0) return fail(MM_ENONFINITE, "m holds %.0f non-finite cells", r[7]);
+    const double Ms = s->mat.Ms, V = s->cell * s->cell * s->cell;
+    out[0] = s->mat.A * s->cell * r[0];                // A delta sum over pairs |m_a - m_b|^2
+    out[1] = 0.5 * kMu0 * Ms * Ms * V * r[1];          // sum Ku (my^2 + mz^2) V
+    out[2] = -0.5 * kMu0 * Ms * Ms * V * r[2];         // -mu0/2 sum M.H_d V
+    out[3] = -kMu0 * Ms * Ms * V * r[3];               // -mu0 sum M.H_ext V
+    out[4] = out[0] + out[1] + out[2] + out[3];
+    return MM_OK;
+}
+
+mm_status mm_get_mean_m(mm_sim* s, double out[3])
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
+    double r[8];
+    const uint32_t keep = s->flags;
+    s->flags |= MM_NO_DEMAG;  // the mean needs no field
+    mm_status st = s->p.prec == MM_F32 ? reduce_impl<float>(s, r) : reduce_impl<double>(s, r);
+    s->flags = keep;
+    if (st != MM_OK) return st;
+    if (r[7] != 0.0) return fail(MM_ENONFINITE, "m holds %.0f non-finite cells", r[7]);
+    for (int a = 0; a < 3; ++a) out[a] = r[4 + a] / (double)s->p.N;
+    return MM_OK;
+}
+
+mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    out->px = s->p.Px;
+    out->py = s->p.Py;
+    out->pz = s->p.Pz;
+    out->hx = s->p.hx;
+    out->ncomp = s->p.ncomp;
+    out->threads = s->p.nt;
+    out->spectrum_elems = (int64_t)s->p.ncomp * s->p.oct_elems;
+    out->passes = s->p.three_d ? 5 : 3;
+    out->kernel_imag_ratio = s->imag_ratio;
+    return MM_OK;
+}
+
+mm_status mm_get_kernel_spectrum(mm_sim* s, void* out, int on_device)
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (s->flags & MM_NO_DEMAG) return fail(MM_ESTATE, "handle was created without demag");
+    const size_t bytes = (size_t)s->p.ncomp * s->p.oct_elems * s->p.esz;
+    HIP_TRY(hipMemcpyAsync(out, s->at<char>(s->p.o_kern), bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return MM_OK;
+}
+
+mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !d_out) return fail(MM_EINVAL, "dims must be >= 1 and d_out non-NULL");
+    if ((int64_t)(2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1) > ((int64_t)1 << 34))
+        return fail(MM_ENOTSUP, "tensor table too large");
+    HIP_TRY(launch_tensor_table(d_out, nx, ny, nz, as_stream(stream)));
+    return MM_OK;
+}
+
+mm_status mm_profile_begin(mm_sim* s, int32_t kernel)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (kernel < 0 || kernel >= KCOUNT) return fail(MM_EINVAL, "kernel id must be 0..5");
+    s->prof_kernel = kernel;
+    s->ev_used = 0;
+    return MM_OK;
+}
+
+mm_status mm_profile_end(mm_sim* s, double* total_ms, int64_t* launches)
+{
+    if (!s || !total_ms || !launches) return fail(MM_EINVAL, "NULL argument");
+    if (s->prof_kernel < 0) return fail(MM_ESTATE, "no profile open");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (size_t q = 0; q + 1 < s->ev_used; q += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(s->ev_used / 2);
+    s->prof_kernel = -1;
+    s->ev_used = 0;
+    return MM_OK;
+}
+
+const char* mm_kernel_name(int32_t kernel)
+{
+    static const char* names[KCOUNT] = {"k_row_r2c", "k_col_fft(fwd)", "k_kspace", "k_col_fft(inv)",
+                                        "k_row_c2r", "k_llg_stage"};
+    return (kernel >= 0 && kernel < KCOUNT) ? names[kernel] : "unknown";
+}
+
+const char* mm_status_string(mm_status s)
+{
+    switch (s) {
+    case MM_OK: return "MM_OK";
+    case MM_EINVAL: return "MM_EINVAL";
+    case MM_ENOMEM: return "MM_ENOMEM";
+    case MM_EHIP: return "MM_EHIP";
+    case MM_ESTATE: return "MM_ESTATE";
+    case MM_ENOTSUP: return "MM_ENOTSUP";
+    case MM_ENONFINITE: return "MM_ENONFINITE";
+    }
+    return "unknown";
+}
+
+const char* mm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// mm_kernels.hpp -- argument blocks and host launchers of every kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mm_common.hpp"
+
+namespace mm {
+
+// Forward transform along x of pairs of real rows (the two rows of a pair are
+// the real and imaginary parts of one complex FFT), zero padded from nvalid
+// to P; writes the half spectrum (hx = P/2+1 entries) of every row.
+struct RowR2CArgs {
+    const void* in;          // real rows
+    int64_t in_row_stride;   // elements
+    int nrows;               // real rows
+    int nvalid;              // leading nonzero entries per row (<= P)
+    void* out;               // complex rows
+    int rows_per_plane;      // output row r goes to (r / rpp) * plane_stride + (r % rpp) * sx
+    int64_t out_plane_stride;
+    int64_t sx;
+    int hx;
+    int lines_per_wg;        // complex lines (row pairs) per work-group
+    FftPlan pl;
+    const void* tw;
+};
+
+// Inverse transform along x (Hermitian half spectrum -> real rows), keeping
+// the first nvalid outputs of every row.
+struct RowC2RArgs {
+    const void* in;          // complex rows (layout as RowR2CArgs::out)
+    int rows_per_plane;
+    int64_t in_plane_stride;
+    int64_t sx;
+    int hx;
+    int nrows;
+    void* out;               // real rows
+    int64_t out_row_stride;
+    int nvalid;
+    int lines_per_wg;
+    FftPlan pl;
+    const void* tw;
+};
+
+// Complex FFT along a strided axis of a column set.  Column c of plane q sits
+// at q * plane_stride + (c / cols_per_row) * row2_stride + c % cols_per_row,
+// consecutive elements es apart.  Inputs beyond nin are zero; the first nout
+// outputs are stored; inverse = conjugate in and out (unnormalised).
+struct ColArgs {
+    void* buf;
+    int nplanes;
+    int64_t plane_stride;
+    int ncols;
+    int cols_per_row;
+    int64_t row2_stride;
+    int64_t es;
+    int nin, nout;
+    int inverse;
+    int tw_cols;             // columns per work-group
+    FftPlan pl;
+    const void* tw;
+};
+
+// k-space pass on the last non-trivial axis: forward FFT of the three
+// components of a column set, the symmetric tensor product of Eq. 14 with the
+// real kernel spectrum, inverse FFT, keep the first nvalid outputs.
+struct KspArgs {
+    void* buf;
+    int64_t comp_stride;
+    int ncols;
+    int cols_per_row;
+    int64_t row2_stride;
+    int64_t es;
+    int nvalid;
+    int tw_cols;
+    FftPlan pl;
+    const void* tw;
+    const void* kern;        // real octant
+    int ncomp;               // 6 (3-D) or 4 (xx, xy, yy, zz when the grid is one cell thick)
+    int axis_is_z;           // 1: columns are (ky, kx), transform over kz; 0: columns kx, over ky
+    int hx, Py, Pz;
+    int64_t k_cs, k_zs, k_ys;  // octant strides for component, kz, ky
+};
+
+template <typename T>
+hipError_t launch_row_r2c(const RowR2CArgs& a, int nt, hipStream_t s);
+template <typename T>
+hipError_t launch_row_c2r(const RowC2RArgs& a, int nt, hipStream_t s);
+template <typename T>
+hipError_t launch_col_fft(const ColArgs& a, int nt, hipStream_t s);
+template <typename T>
+hipError_t launch_kspace(const KspArgs& a, int nt, hipStream_t s);
+
+// ---------------------------------------------------------------- setup
+// Demag tensor component `comp` (0..5 = xx,xy,xz,yy,yz,zz) of Eqs. 10-11 in
+// the wrapped layout of a [Pz][Py][Px] FP64 array.
+hipError_t launch_tensor_wrapped(double* out, int comp, int nx, int ny, int nz, int Px, int Py,
+                                 int Pz, hipStream_t s);
+// All six components on the offset table [6][2nz-1][2ny-1][2nx-1] (FP64).
+hipError_t launch_tensor_table(double* out, int nx, int ny, int nz, hipStream_t s);
+// tw[t] = exp(-2 pi i t / P), computed in FP64, stored in T.
+template <typename T>
+hipError_t launch_twiddles(void* tw, int P, hipStream_t s);
+// Real part of the octant of a [Pz][Py][sx] FP64 spectrum, times scale, to T.
+// Records max |imag| (as FP64 bits) in *imag_max_bits.
+template <typename T>
+hipError_t launch_octant(void* out, const void* spec, int hx, int Py, int Pz, int64_t sx,
+                         double scale, unsigned long long* imag_max_bits, hipStream_t s);
+
+// ---------------------------------------------------------------- LLG
+template <typename T>
+struct LlgArgs {
+    const T* ms;     // stage input
+    const T* mn;     // state at the start of the step
+    T* acc;          // RK4 accumulator
+    T* out;          // stage output (m_n itself at stage 4)
+    const T* hd;     // reduced demag field or nullptr
+    const T* ku;     // reduced anisotropy map 2 Ku/(mu0 Ms^2) or nullptr
+    int nx, ny, nz;
+    int64_t N;
+    T cex;           // 2 A / (mu0 Ms^2 delta^2)
+    T can;           // 2 Ku / (mu0 Ms^2) when ku == nullptr
+    T hx, hy, hz;    // reduced applied field H_ext / Ms
+    T alpha;
+    T gdt;           // gamma Ms dt / (1 + alpha^2)
+    int stage;       // 1..4
+};
+template <typename T>
+hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s);
+
+// Per-term field in A/m: term 0 exch, 1 anis, 2 demag, 3 ext, 4 effective.
+template <typename T>
+hipError_t launch_field_term(const LlgArgs<T>& a, int term, T Ms, T* out, hipStream_t s);
+
+// FP64 reductions over m (and hd): out[0] = sum |dm|^2 over neighbour pairs,
+// out[1] = sum ku_red (my^2 + mz^2), out[2] = sum m.hd, out[3] = sum m.hext,
+// out[4..6] = sum m, out[7] = count of non-finite entries.  partial holds
+// nblocks*8 doubles.
+template <typename T>
+hipError_t launch_reduce(const LlgArgs<T>& a, double* partial, int nblocks, double* out,
+                         hipStream_t s);
+int reduce_blocks(int64_t N);
+
+// m <- m / |m| per cell; counts zero-norm or non-finite cells into *bad.
+template <typename T>
+hipError_t launch_normalize(T* m, int64_t N, unsigned int* bad, hipStream_t s);
+
+}  // namespace mm

@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes its workspace and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1501_07293_amd as mm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mmag.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mm.LIB_PATH):
+        from paper_1501_07293_amd import build
+        build.build()
+    return mm.load_library()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(mm.EXPORTS)
+
+
+def q(lib, nx, ny, nz, cell=5e-9, prec=0, pad=(0, 0, 0), threads=0):
+    g = mm.Grid(nx, ny, nz, cell)
+    o = mm.Options(prec, pad[0], pad[1], pad[2], 0, threads)
+    b = ctypes.c_size_t()
+    st = lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b))
+    return st, b.value
+
+
+def test_workspace_query_sizes(lib):
+    st, b32 = q(lib, 512, 512, 16)
+    assert st == 0
+    st, b64 = q(lib, 512, 512, 16, prec=1)
+    assert st == 0 and b64 > b32
+    # the working set of the 4.19M-cell film (FP32) stays far below one GPU's HBM
+    assert b32 < 4 << 30
+    st, b = q(lib, 1, 1, 1)
+    assert st == 0 and b > 0
+
+
+@pytest.mark.parametrize("args", [(0, 4, 4), (4, -1, 4), (4, 4, 0)])
+def test_workspace_query_rejects_bad_dims(lib, args):
+    st, _ = q(lib, *args)
+    assert st == -1
+    assert b"dims" in lib.mm_last_error()
+
+
+def test_workspace_query_rejects_bad_options(lib):
+    assert q(lib, 8, 8, 1, cell=0.0)[0] == -1
+    assert q(lib, 8, 8, 1, cell=float("nan"))[0] == -1
+    assert q(lib, 8, 8, 1, prec=7)[0] == -1
+    assert q(lib, 8, 8, 2, pad=(11, 0, 0))[0] == -1      # 11 is not 7-smooth
+    assert q(lib, 8, 8, 2, pad=(14, 0, 0))[0] == -1      # below 2n-1 = 15
+    assert q(lib, 8, 8, 2, pad=(15, 0, 0))[0] == 0       # 15 = 3*5 is allowed
+    assert q(lib, 8, 8, 2, pad=(0, 0, 1))[0] == -1       # pz = 1 needs nz = 1
+    assert q(lib, 8, 8, 2, threads=100)[0] == -1
+
+
+def test_create_rejects_bad_material_without_gpu_work(lib):
+    g = mm.Grid(8, 8, 1, 5e-9)
+    o = mm.Options(0, 0, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    for mat in (mm.Material(-1, 1e-11, 0, 0.5, 2.2e5), mm.Material(8e5, -1, 0, 0.5, 2.2e5),
+                mm.Material(8e5, 1e-11, 0, -0.1, 2.2e5), mm.Material(8e5, 1e-11, 0, 0.5, 0.0),
+                mm.Material(8e5, 1e-11, float("inf"), 0.5, 2.2e5)):
+        st = lib.mm_create(ctypes.byref(g), ctypes.byref(mat), ctypes.byref(o), None, 0, None,
+                           ctypes.byref(h))
+        assert st == -1
+        assert not h.value
+    # undersized caller workspace
+    mat = mm.Material(8e5, 1.3e-11, 0, 0.5, 2.2e5)
+    st = lib.mm_create(ctypes.byref(g), ctypes.byref(mat), ctypes.byref(o), 256, 16, None,
+                       ctypes.byref(h))
+    assert st == -1 and b"workspace" in lib.mm_last_error()
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.mm_destroy(None) == 0
+    assert lib.mm_step(None, 1, 1e-13) == -1
+    assert lib.mm_set_m(None, None, 0) == -1
+    assert lib.mm_get_energy(None, None) == -1
+    assert lib.mm_demag_tensor(0, 1, 1, None, None) == -1
+    assert lib.mm_status_string(-6) == b"MM_ENONFINITE"
+    assert lib.mm_kernel_name(2) == b"k_kspace"
+
+
+def test_product_has_no_cpu_fallback():
+    # The package never imports the oracle.
+    import inspect
+    src = inspect.getsource(mm)
+    assert "oracle" not in src
+    pkg = os.path.dirname(mm.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                assert "import oracle" not in open(os.path.join(root, f)).read()

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path fields <= 1e-11 relative max, FP32 path fields <= 1e-5
+relative max (relative to the largest entry of the oracle field), the demag
+tensor <= 1e-14 absolute, trajectories after 1000 steps <= 1e-9 (FP64) and
+<= 1e-4 (FP32) in m.  FP32 comparisons give the oracle the GPU's own
+(FP32-normalised) m so that only the arithmetic differs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import SMALL, mT_to_Apm, random_unit_m, smooth_unit_m
+from tests.gpu_util import problem, rel_max, to_np
+
+pytestmark = pytest.mark.gpu
+
+mmag = pytest.importorskip("paper_1501_07293_amd")
+
+FIELD_TOL = {"f64": 1e-11, "f32": 1e-5}
+
+
+def make_sim(pb, precision, **kw):
+    return mmag.Sim(pb.nx, pb.ny, pb.nz, pb.cell, Ms=pb.Ms, A=pb.A, Ku=pb.Ku, alpha=pb.alpha,
+                    gamma=pb.gamma, precision=precision, demag=pb.demag, **kw)
+
+
+# ------------------------------------------------------------ tensor (Eqs. 10-11)
+@pytest.mark.parametrize("dims", [(1, 1, 1), (4, 3, 2), (9, 5, 3), (32, 8, 1), (17, 30, 4)])
+def test_demag_tensor_matches_oracle(dims):
+    t = to_np(mmag.demag_tensor(*dims))
+    ref = oracle.tensor_table(*dims)
+    assert t.shape == ref.shape
+    assert np.abs(t - ref).max() <= 1e-14
+
+
+def wrapped_spectrum(pb, P):
+    """Real octant of the DFT of the oracle's tensor in the wrapped padded layout
+    (numpy FFT as the library primitive), scaled by 1/(Px Py Pz)."""
+    Px, Py, Pz = P
+    tab = pb.table()
+    out = []
+    comps = [0, 1, 2, 3, 4, 5] if Pz > 1 else [0, 1, 3, 5]
+    nx, ny, nz = pb.nx, pb.ny, pb.nz
+    I = np.arange(-(nx - 1), nx) % Px
+    J = np.arange(-(ny - 1), ny) % Py
+    K = np.arange(-(nz - 1), nz) % Pz
+    for c in comps:
+        w = np.zeros((Pz, Py, Px))
+        w[np.ix_(K, J, I)] = tab[c]
+        f = np.fft.fftn(w) / (Px * Py * Pz)
+        out.append(f[: Pz // 2 + 1, : Py // 2 + 1, : Px // 2 + 1])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("dims", [(32, 8, 1), (13, 7, 3), (12, 10, 6), (33, 17, 1)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_kernel_spectrum_matches_fft_of_oracle_tensor(dims, precision):
+    pb = problem(*dims, cell=5e-9)
+    sim = make_sim(pb, precision)
+    p = sim.plan()
+    spec = to_np(sim.kernel_spectrum())
+    ref = wrapped_spectrum(pb, (p["px"], p["py"], p["pz"]))
+    # the wrapped tensor is even/odd per axis, so its spectrum is real
+    assert np.abs(ref.imag).max() <= 1e-13 * np.abs(ref.real).max()
+    assert p["kernel_imag_ratio"] <= 1e-12
+    tol = 1e-12 if precision == "f64" else 1e-6
+    assert rel_max(spec, ref.real) <= tol
+
+
+# ---------------------------------------------------- effective-field terms
+SHAPES = [(32, 8, 1), (33, 17, 1), (12, 10, 6), (13, 7, 3), (1, 1, 1), (5, 1, 4), (64, 48, 2),
+          (100, 36, 3), (1, 40, 2), (70, 3, 5)]
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_field_terms_match_oracle(dims, precision):
+    hext = mT_to_Apm([12.0, -5.0, 3.0])
+    pb = problem(*dims, cell=4e-9, Ku=2.0e4, hext=hext)
+    m0 = random_unit_m(pb.shape, seed=sum(dims))
+    sim = make_sim(pb, precision)
+    sim.set_hext(hext)
+    sim.set_m(m0)
+    m_gpu = to_np(sim.get_m())
+    ref = oracle.heff_terms(pb, m_gpu)
+    for term in ("exch", "anis", "demag", "ext", "eff"):
+        got = to_np(sim.field(term))
+        if np.abs(ref[term]).max() == 0:
+            assert np.abs(got).max() == 0, term
+            continue
+        err = rel_max(got, ref[term])
+        assert err <= FIELD_TOL[precision], (term, err)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_uniform_m_exchange_vanishes_and_cube_demag(precision):
+    pb = problem(6, 6, 6, 3e-9)
+    m = np.zeros(pb.shape)
+    m[0] = 1.0
+    sim = make_sim(pb, precision)
+    sim.set_m(m)
+    assert np.abs(to_np(sim.field("exch"))).max() == 0.0
+    hd = to_np(sim.field("demag"))
+    # cubic symmetry: the averaged demag factor of a cube is 1/3
+    assert abs(hd[0].mean() / pb.Ms + 1.0 / 3.0) < (1e-12 if precision == "f64" else 1e-6)
+
+
+# --------------------------------------------------------------- trajectories
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_small_config_trajectory(precision):
+    c = SMALL
+    pb = problem(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma)
+    m0 = random_unit_m(pb.shape, seed=0)
+    sim = make_sim(pb, precision)
+    sim.set_m(m0)
+    m_start = to_np(sim.get_m())
+    m_ref = oracle.rk4(pb, m_start, c.dt, 1000)
+    sim.step(1000, c.dt)
+    err1000 = np.abs(to_np(sim.get_m()) - m_ref).max()
+    m_ref2 = oracle.rk4(pb, m_ref, c.dt, 1000)
+    sim.step(1000, c.dt)
+    m2 = to_np(sim.get_m())
+    err2000 = np.abs(m2 - m_ref2).max()
+    tol = 1e-9 if precision == "f64" else 1e-4
+    assert err1000 <= tol, err1000
+    assert err2000 <= 10 * tol, err2000
+    assert np.abs(np.sqrt((m2 ** 2).sum(axis=0)) - 1).max() < (1e-14 if precision == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_energy_and_mean_match_oracle(precision):
+    hext = mT_to_Apm([-20.0, 3.0, 0.0])
+    pb = problem(24, 12, 3, 4e-9, Ku=500.0, hext=hext)
+    m0 = smooth_unit_m(pb.shape, seed=3)
+    sim = make_sim(pb, precision)
+    sim.set_hext(hext)
+    sim.set_m(m0)
+    m_gpu = to_np(sim.get_m())
+    e = sim.energy()
+    e_ref = oracle.energy(pb, m_gpu)
+    scale = np.abs(e_ref).max()
+    tol = 1e-10 if precision == "f64" else 1e-5
+    assert np.abs(e - e_ref).max() / scale <= tol, (e, e_ref)
+    mm = sim.mean_m()
+    assert np.abs(mm - oracle.mean_m(pb, m_gpu)).max() <= (1e-14 if precision == "f64" else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_energy_decreases_under_damping(precision):
+    pb = problem(16, 16, 2, 5e-9, Ku=500.0, alpha=0.5, hext=mT_to_Apm([10.0, 0.0, 0.0]))
+    sim = make_sim(pb, precision)
+    sim.set_hext(pb.hext)
+    sim.set_m(random_unit_m(pb.shape, seed=11))
+    e_prev = sim.energy()[4]
+    for _ in range(30):
+        sim.step(5, 1e-13)
+        e = sim.energy()[4]
+        assert e <= e_prev + (1e-12 if precision == "f64" else 1e-6) * abs(e_prev)
+        e_prev = e
+
+
+def test_graph_replay_matches_eager():
+    pb = problem(40, 20, 3, 4e-9, Ku=500.0, alpha=0.3)
+    m0 = random_unit_m(pb.shape, seed=5)
+    outs = []
+    for graph in (False, True):
+        sim = make_sim(pb, "f32", graph=graph)
+        sim.set_m(m0)
+        sim.step(19, 1e-13)     # 2 graph replays of 8 steps + 3 direct steps
+        outs.append(to_np(sim.get_m()))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_deterministic_bitwise():
+    pb = problem(48, 24, 4, 4e-9, Ku=500.0)
+    m0 = random_unit_m(pb.shape, seed=6)
+    outs = []
+    for _ in range(2):
+        sim = make_sim(pb, "f32")
+        sim.set_m(m0)
+        sim.step(10, 1e-13)
+        outs.append((to_np(sim.get_m()), sim.energy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_fp32_vs_fp64_gpu_agree_mid_film():
+    # 256x64x4 film, step field (-20, 3, 0) mT, alpha 0.02, dt 5e-14: FP32 tracks FP64.
+    from synthetic import MID
+    c = MID
+    m0 = smooth_unit_m(c.shape, seed=0)
+    res = []
+    for prec in ("f64", "f32"):
+        sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
+                       gamma=c.gamma, precision=prec)
+        sim.set_hext(c.hext)
+        sim.set_m(m0)
+        sim.step(1000, c.dt)
+        res.append(to_np(sim.get_m()))
+    assert np.abs(res[0] - res[1]).max() <= 1e-4
