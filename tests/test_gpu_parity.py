@@ -186,16 +186,23 @@ def test_deterministic_bitwise():
 
 
 def test_fp32_vs_fp64_gpu_agree_mid_film():
-    # 256x64x4 film, step field (-20, 3, 0) mT, alpha 0.02, dt 5e-14: FP32 tracks FP64.
+    # 256x64x4 film: relax a seeded random state (alpha 0.5, no field), then apply the
+    # step field (-20, 3, 0) mT with alpha 0.02, dt 5e-14 s; FP32 tracks FP64 over 1000 steps.
     from synthetic import MID
     c = MID
-    m0 = smooth_unit_m(c.shape, seed=0)
+    relax = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=0.5, gamma=c.gamma,
+                     precision="f64")
+    relax.set_m(random_unit_m(c.shape, seed=0))
+    relax.step(4000, c.dt)
+    m_relaxed = to_np(relax.get_m())
     res = []
     for prec in ("f64", "f32"):
         sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
                        gamma=c.gamma, precision=prec)
         sim.set_hext(c.hext)
-        sim.set_m(m0)
+        sim.set_m(m_relaxed)
         sim.step(1000, c.dt)
         res.append(to_np(sim.get_m()))
-    assert np.abs(res[0] - res[1]).max() <= 1e-4
+    err = np.abs(res[0] - res[1]).max()
+    print("mid film FP32 vs FP64 after 1000 steps:", err)
+    assert err <= 1e-4
