@@ -60,6 +60,8 @@ typedef enum {
 /* Option flags. */
 #define MM_NO_DEMAG 0x1u   /* drop the demag term (exchange, anisotropy, applied only) */
 #define MM_USE_GRAPH 0x2u  /* mm_step replays a captured hipGraph of whole RK4 steps */
+#define MM_GENERIC_FFT 0x4u /* use the runtime-radix FFT passes even where a size-specialised
+                               pass exists (both give the same result up to rounding) */
 
 typedef struct {
     int32_t nx, ny, nz; /* cells along x, y, z; each >= 1 */
@@ -79,7 +81,7 @@ typedef struct {
     int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
-    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH */
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
 } mm_options;
 
@@ -88,7 +90,7 @@ typedef struct {
     int32_t hx;          /* px/2 + 1 stored half-spectrum bins along x */
     int32_t ncomp;       /* 6 kernel spectra, or 4 (xx, xy, yy, zz) when nz == 1 */
     int32_t threads;     /* FFT work-group size in use */
-    int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*(py/2+1)*hx */
+    int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*hx*(py/2+1) */
     int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1, else 5) */
     double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
 } mm_plan_info;
@@ -141,8 +143,9 @@ mm_status mm_get_mean_m(mm_sim* sim, double out[3]);
 
 mm_status mm_get_plan(mm_sim* sim, mm_plan_info* out);
 
-/* Kernel-spectrum octant [ncomp][pz/2+1][py/2+1][hx], working precision,
- * already scaled by 1/(px py pz) (the normalisation of the inverse FFT). */
+/* Kernel-spectrum octant [ncomp][pz/2+1][hx][py/2+1] (ky fastest), working
+ * precision, already scaled by 1/(px py pz) (the normalisation of the inverse
+ * FFT).  Component order xx, xy, xz, yy, yz, zz, or xx, xy, yy, zz when ncomp == 4. */
 mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
 
 /* Demag tensor of Eqs. 10-11 over every offset |I|<nx, |J|<ny, |K|<nz, FP64,

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
-MM_NO_DEMAG, MM_USE_GRAPH = 0x1, 0x2
+MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT = 0x1, 0x2, 0x4
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
@@ -133,7 +133,8 @@ class Sim:
     def __init__(self, nx: int, ny: int, nz: int, cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
-                 graph: bool = False, threads: int = 0, device: str = "cuda:0"):
+                 graph: bool = False, threads: int = 0, generic_fft: bool = False,
+                 device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch = torch
@@ -145,7 +146,8 @@ class Sim:
         self.dtype = torch.float32 if precision == "f32" else torch.float64
         self._grid = Grid(nx, ny, nz, cell)
         self._mat = Material(Ms, A, Ku, alpha, gamma)
-        flags = (0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+        flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+                 | (MM_GENERIC_FFT if generic_fft else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads)
         nbytes = ctypes.c_size_t()
@@ -229,7 +231,7 @@ class Sim:
         out = self._torch.empty(int(p["spectrum_elems"]), dtype=self.dtype, device=self.device)
         self._sync_stream()
         _check(self._lib.mm_get_kernel_spectrum(self._h, out.data_ptr(), 1), "mm_get_kernel_spectrum")
-        return out.reshape(p["ncomp"], p["pz"] // 2 + 1, p["py"] // 2 + 1, p["hx"])
+        return out.reshape(p["ncomp"], p["pz"] // 2 + 1, p["hx"], p["py"] // 2 + 1)
 
     # ------------------------------------------------------------- profiling
     def profile_begin(self, kernel: str):

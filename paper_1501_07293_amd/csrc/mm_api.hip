@@ -98,7 +98,7 @@ struct Plan {
     size_t esz;        // sizeof(T)
     FftPlan fx, fy, fz;
     int x_lines, y_tw, k_tw;
-    int64_t S_planes, S_rows;  // spectrum [3][S_planes][S_rows][sx]
+    int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
     int64_t oct_elems;         // per component
     // workspace offsets
     size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_kern, o_twx, o_twy, o_twz;
@@ -169,13 +169,9 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->x_lines = std::min(cap / p->Px, ldscap / (p->Px + 1));
     p->y_tw = std::max(1, std::min(64, cap / p->Py));
     p->k_tw = std::max(1, std::min(64, cap / (3 * last)));
-    if (p->three_d) {
-        p->S_planes = p->nz;
-        p->S_rows = p->Py;
-    } else {
-        p->S_planes = 1;
-        p->S_rows = p->ny;
-    }
+    // spectrum [3][nz][hx][S_rows]: the y pass expands ny rows to Py in place on 3-D grids
+    p->S_planes = p->nz;
+    p->S_rows = p->three_d ? p->Py : p->ny;
     p->oct_elems = (int64_t)(p->Pz / 2 + 1) * (p->Py / 2 + 1) * p->hx;
     // workspace
     size_t off = 0;
@@ -191,7 +187,7 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->o_acc = take(vec);
     p->o_hd = take(vec);
     p->o_ku = take((size_t)p->N * p->esz);
-    p->o_S = take(3 * (size_t)p->S_planes * p->S_rows * p->sx * 2 * p->esz);
+    p->o_S = take(3 * (size_t)p->S_planes * p->hx * p->S_rows * 2 * p->esz);
     p->o_kern = take((size_t)p->ncomp * p->oct_elems * p->esz);
     p->o_twx = take((size_t)p->Px * 2 * p->esz);
     p->o_twy = take((size_t)p->Py * 2 * p->esz);
@@ -281,101 +277,158 @@ mm_status prof_post(mm_sim* s, int kid, hipStream_t st)
         if (ps_ != MM_OK) return ps_;                                         \
     } while (0)
 
-// Demag field (reduced, h = H/Ms) of m_src into hd: Eq. 14 with zero padding.
-template <typename T>
-mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
+// ---- the five passes of one demag evaluation.  Spectrum S = [3][nz][hx][Sy]
+// (Sy = Py on 3-D grids, ny otherwise).  Each pass uses the size-specialised
+// kernel when one exists (and MM_GENERIC_FFT is not set), else the generic one.
+struct PassCtx {
+    const Plan& p;
+    void* S;
+    int64_t Sy, plane;
+    int nplanes;
+    bool fast;
+    const void *twx, *twy, *twz, *kern;
+};
+
+PassCtx pass_ctx(const mm_sim* s)
 {
     const Plan& p = s->p;
-    void* S = s->at<char>(p.o_S);
-    const int64_t plane = p.S_rows * p.sx;
-    RowR2CArgs xr{};
-    xr.in = msrc;
-    xr.in_row_stride = p.nx;
-    xr.nrows = (int)(3 * p.nz * p.ny);
-    xr.nvalid = p.nx;
-    xr.out = S;
-    xr.rows_per_plane = p.ny;
-    xr.out_plane_stride = plane;
-    xr.sx = p.sx;
-    xr.hx = p.hx;
-    xr.lines_per_wg = p.x_lines;
-    xr.pl = p.fx;
-    xr.tw = s->at<char>(p.o_twx);
-    LAUNCH(KX_FWD, launch_row_r2c<T>(xr, p.nt, st));
+    return PassCtx{p,
+                   s->at<char>(p.o_S),
+                   p.S_rows,
+                   (int64_t)p.hx * p.S_rows,
+                   3 * p.nz,
+                   !(s->flags & MM_GENERIC_FFT),
+                   s->at<char>(p.o_twx),
+                   s->at<char>(p.o_twy),
+                   s->at<char>(p.o_twz),
+                   s->at<char>(p.o_kern)};
+}
 
+template <typename T>
+hipError_t pass_x_forward(const PassCtx& c, const T* m, hipStream_t st)
+{
+    const Plan& p = c.p;
+    XLineArgs xa{m, c.S, c.nplanes, p.ny, p.nx, c.Sy, c.twx};
+    if (c.fast && launch_xline<T>(xa, p.Px, 0, st)) return hipGetLastError();
+    RowR2CArgs r{};
+    r.in = m;
+    r.in_row_stride = p.nx;
+    r.nrows = c.nplanes * p.ny;
+    r.nvalid = p.nx;
+    r.out = c.S;
+    r.rows_per_plane = p.ny;
+    r.out_plane_stride = c.plane;
+    r.rstride = 1;
+    r.kstride = c.Sy;
+    r.hx = p.hx;
+    r.lines_per_wg = p.x_lines;
+    r.pl = p.fx;
+    r.tw = c.twx;
+    return launch_row_r2c<T>(r, p.nt, st);
+}
+
+template <typename T>
+hipError_t pass_y(const PassCtx& c, int inverse, hipStream_t st)
+{
+    const Plan& p = c.p;
+    const int nin = inverse ? p.Py : p.ny, nout = inverse ? p.ny : p.Py;
+    YLineArgs ya{c.S, c.nplanes * p.hx, c.Sy, nin, nout, c.twy};
+    if (c.fast && launch_yline<T>(ya, p.Py, inverse, st)) return hipGetLastError();
     ColArgs cy{};
-    if (p.three_d) {
-        cy.buf = S;
-        cy.nplanes = 3 * p.nz;
-        cy.plane_stride = plane;
-        cy.ncols = p.hx;
-        cy.cols_per_row = p.hx;
-        cy.row2_stride = 0;
-        cy.es = p.sx;
-        cy.nin = p.ny;
-        cy.nout = p.Py;
-        cy.inverse = 0;
-        cy.tw_cols = p.y_tw;
-        cy.pl = p.fy;
-        cy.tw = s->at<char>(p.o_twy);
-        LAUNCH(KY_FWD, launch_col_fft<T>(cy, p.nt, st));
-    }
+    cy.buf = c.S;
+    cy.nplanes = c.nplanes;
+    cy.plane_stride = c.plane;
+    cy.ncols = p.hx;
+    cy.cols_per_row = 1;
+    cy.row2_stride = c.Sy;
+    cy.es = 1;
+    cy.nin = nin;
+    cy.nout = nout;
+    cy.inverse = inverse;
+    cy.tw_cols = p.y_tw;
+    cy.pl = p.fy;
+    cy.tw = c.twy;
+    return launch_col_fft<T>(cy, p.nt, st);
+}
 
+template <typename T>
+hipError_t pass_kspace(const PassCtx& c, hipStream_t st)
+{
+    const Plan& p = c.p;
+    const int64_t k_xs = p.Py / 2 + 1, k_zs = (int64_t)p.hx * (p.Py / 2 + 1);
     KspArgs k{};
-    k.buf = S;
-    k.kern = s->at<char>(p.o_kern);
+    k.buf = c.S;
+    k.kern = c.kern;
     k.ncomp = p.ncomp;
     k.hx = p.hx;
     k.Py = p.Py;
     k.Pz = p.Pz;
     k.k_cs = p.oct_elems;
-    k.k_zs = (int64_t)(p.Py / 2 + 1) * p.hx;
-    k.k_ys = p.hx;
+    k.k_zs = k_zs;
+    k.k_xs = k_xs;
     k.tw_cols = p.k_tw;
     if (p.three_d) {
-        k.comp_stride = p.S_planes * plane;
-        k.ncols = p.Py * p.hx;
-        k.cols_per_row = p.hx;
-        k.row2_stride = p.sx;
-        k.es = plane;
+        KzArgs kz{c.S, (int64_t)p.nz * c.plane, (int)c.plane, p.nz, p.Py, c.twz, c.kern, p.oct_elems,
+                  k_zs, k_xs};
+        if (c.fast && launch_kspace_z<T>(kz, p.Pz, st)) return hipGetLastError();
+        k.comp_stride = (int64_t)p.nz * c.plane;
+        k.ncols = (int)c.plane;
+        k.cols_per_row = (int)c.plane;
+        k.row2_stride = 0;
+        k.es = c.plane;
         k.nvalid = p.nz;
         k.pl = p.fz;
-        k.tw = s->at<char>(p.o_twz);
+        k.tw = c.twz;
         k.axis_is_z = 1;
     } else {
-        k.comp_stride = plane;
+        KyArgs ky{c.S, c.plane, c.Sy, p.hx, p.ny, c.twy, c.kern, p.oct_elems, k_xs};
+        if (c.fast && launch_kspace_y<T>(ky, p.Py, st)) return hipGetLastError();
+        k.comp_stride = c.plane;
         k.ncols = p.hx;
-        k.cols_per_row = p.hx;
-        k.row2_stride = 0;
-        k.es = p.sx;
+        k.cols_per_row = 1;
+        k.row2_stride = c.Sy;
+        k.es = 1;
         k.nvalid = p.ny;
         k.pl = p.fy;
-        k.tw = s->at<char>(p.o_twy);
+        k.tw = c.twy;
         k.axis_is_z = 0;
     }
-    LAUNCH(KSPACE, launch_kspace<T>(k, p.nt, st));
+    return launch_kspace<T>(k, p.nt, st);
+}
 
-    if (p.three_d) {
-        cy.nin = p.Py;
-        cy.nout = p.ny;
-        cy.inverse = 1;
-        LAUNCH(KY_INV, launch_col_fft<T>(cy, p.nt, st));
-    }
+template <typename T>
+hipError_t pass_x_inverse(const PassCtx& c, T* h, hipStream_t st)
+{
+    const Plan& p = c.p;
+    XLineArgs xa{c.S, h, c.nplanes, p.ny, p.nx, c.Sy, c.twx};
+    if (c.fast && launch_xline<T>(xa, p.Px, 1, st)) return hipGetLastError();
+    RowC2RArgs r{};
+    r.in = c.S;
+    r.rows_per_plane = p.ny;
+    r.in_plane_stride = c.plane;
+    r.rstride = 1;
+    r.kstride = c.Sy;
+    r.hx = p.hx;
+    r.nrows = c.nplanes * p.ny;
+    r.out = h;
+    r.out_row_stride = p.nx;
+    r.nvalid = p.nx;
+    r.lines_per_wg = p.x_lines;
+    r.pl = p.fx;
+    r.tw = c.twx;
+    return launch_row_c2r<T>(r, p.nt, st);
+}
 
-    RowC2RArgs xi{};
-    xi.in = S;
-    xi.rows_per_plane = p.ny;
-    xi.in_plane_stride = plane;
-    xi.sx = p.sx;
-    xi.hx = p.hx;
-    xi.nrows = (int)(3 * p.nz * p.ny);
-    xi.out = hd;
-    xi.out_row_stride = p.nx;
-    xi.nvalid = p.nx;
-    xi.lines_per_wg = p.x_lines;
-    xi.pl = p.fx;
-    xi.tw = s->at<char>(p.o_twx);
-    LAUNCH(KX_INV, launch_row_c2r<T>(xi, p.nt, st));
+// Demag field (reduced, h = H/Ms) of msrc into hd: Eq. 14 with zero padding.
+template <typename T>
+mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
+{
+    const PassCtx c = pass_ctx(s);
+    LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
+    if (c.p.three_d) LAUNCH(KY_FWD, pass_y<T>(c, 0, st));
+    LAUNCH(KSPACE, pass_kspace<T>(c, st));
+    if (c.p.three_d) LAUNCH(KY_INV, pass_y<T>(c, 1, st));
+    LAUNCH(KX_INV, pass_x_inverse<T>(c, hd, st));
     return MM_OK;
 }
 
@@ -468,7 +521,8 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
         xr.out = Sd;
         xr.rows_per_plane = p.Py * p.Pz;
         xr.out_plane_stride = 0;
-        xr.sx = p.sxd;
+        xr.rstride = p.sxd;
+        xr.kstride = 1;
         xr.hx = p.hx;
         xr.lines_per_wg = std::min(cap / p.Px, ldscap / (p.Px + 1));
         xr.pl = p.fx;

@@ -16,9 +16,10 @@ struct RowR2CArgs {
     int nrows;               // real rows
     int nvalid;              // leading nonzero entries per row (<= P)
     void* out;               // complex rows
-    int rows_per_plane;      // output row r goes to (r / rpp) * plane_stride + (r % rpp) * sx
-    int64_t out_plane_stride;
-    int64_t sx;
+    int rows_per_plane;      // bin k of row r goes to (r / rpp) * plane_stride + (r % rpp) * rstride
+    int64_t out_plane_stride;//   + k * kstride
+    int64_t rstride;
+    int64_t kstride;
     int hx;
     int lines_per_wg;        // complex lines (row pairs) per work-group
     FftPlan pl;
@@ -31,7 +32,8 @@ struct RowC2RArgs {
     const void* in;          // complex rows (layout as RowR2CArgs::out)
     int rows_per_plane;
     int64_t in_plane_stride;
-    int64_t sx;
+    int64_t rstride;
+    int64_t kstride;
     int hx;
     int nrows;
     void* out;               // real rows
@@ -75,12 +77,58 @@ struct KspArgs {
     int tw_cols;
     FftPlan pl;
     const void* tw;
-    const void* kern;        // real octant
+    const void* kern;        // real octant [ncomp][Pz/2+1][hx][Py/2+1]
     int ncomp;               // 6 (3-D) or 4 (xx, xy, yy, zz when the grid is one cell thick)
-    int axis_is_z;           // 1: columns are (ky, kx), transform over kz; 0: columns kx, over ky
+    int axis_is_z;           // 1: column c is (kx, ky) = (c / Py, c % Py), transform over kz;
+                             // 0: column c is kx, transform over ky
     int hx, Py, Pz;
-    int64_t k_cs, k_zs, k_ys;  // octant strides for component, kz, ky
+    int64_t k_cs, k_zs, k_xs;  // octant strides for component, kz, kx (ky is contiguous)
 };
+
+// Compile-time specialised passes for power-of-two sizes (mm_fast.hip).  Each
+// launcher returns false (and launches nothing) when no specialisation fits.
+struct YLineArgs {           // contiguous lines, transformed in place
+    void* buf;
+    int nlines;
+    int64_t line_stride;
+    int nin, nout;           // inputs beyond nin are zero; first nout outputs stored
+    const void* tw;
+};
+struct XLineArgs {           // x pass over [nplanes][ny][nx] real rows <-> [nplanes][hx][srows] bins
+    const void* in;
+    void* out;
+    int nplanes;
+    int ny, nx;
+    int64_t srows;
+    const void* tw;
+};
+struct KzArgs {              // z k-space pass, columns (kx, ky) = (c / Py, c % Py)
+    void* buf;
+    int64_t comp_stride;
+    int ncols;               // hx * Py; also the z stride
+    int nz;
+    int Py;
+    const void* tw;
+    const void* kern;        // octant [6][Pz/2+1][hx][Py/2+1]
+    int64_t k_cs, k_zs, k_xs;
+};
+struct KyArgs {              // y k-space pass of a one-cell-thick grid, lines (component, kx)
+    void* buf;
+    int64_t comp_stride;     // hx * ny
+    int64_t line_stride;     // ny
+    int hx, ny;
+    const void* tw;
+    const void* kern;        // octant [4][1][hx][Py/2+1]: xx, xy, yy, zz
+    int64_t k_cs, k_xs;
+};
+template <typename T>
+bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s);
+template <typename T>
+bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s);
+template <typename T>
+bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s);
+template <typename T>
+bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s);
 
 template <typename T>
 hipError_t launch_row_r2c(const RowR2CArgs& a, int nt, hipStream_t s);
@@ -101,8 +149,9 @@ hipError_t launch_tensor_table(double* out, int nx, int ny, int nz, hipStream_t 
 // tw[t] = exp(-2 pi i t / P), computed in FP64, stored in T.
 template <typename T>
 hipError_t launch_twiddles(void* tw, int P, hipStream_t s);
-// Real part of the octant of a [Pz][Py][sx] FP64 spectrum, times scale, to T.
-// Records max |imag| (as FP64 bits) in *imag_max_bits.
+// Real part of the octant of a [Pz][Py][sx] FP64 spectrum, times scale, to T,
+// stored as [Pz/2+1][hx][Py/2+1].  Records max |imag| and max |real| (as FP64
+// bits) in stats[0], stats[1].
 template <typename T>
 hipError_t launch_octant(void* out, const void* spec, int hx, int Py, int Pz, int64_t sx,
                          double scale, unsigned long long* imag_max_bits, hipStream_t s);

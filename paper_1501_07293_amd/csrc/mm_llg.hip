@@ -58,48 +58,90 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
     }
 }
 
+// One thread per (x, y) column of cells marching up in z: m of the planes
+// z-1, z, z+1 stays in registers, so every m value is read from HBM once; the
+// x and y neighbours come from the same or adjacent rows (L1/L2 hits).
 template <typename T>
 __global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
 {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= a.N) return;
-    const int i = (int)(c % a.nx);
-    const int j = (int)((c / a.nx) % a.ny);
-    const int k = (int)(c / ((int64_t)a.nx * a.ny));
-    Cell<T> o;
-    exchange_at(a, c, i, j, k, o);
-    T h[3];
-    heff_at(a, c, o, h);
-    const T* m = o.m;
-    const T tx = m[1] * h[2] - m[2] * h[1];
-    const T ty = m[2] * h[0] - m[0] * h[2];
-    const T tz = m[0] * h[1] - m[1] * h[0];
-    const T dx = m[1] * tz - m[2] * ty;
-    const T dy = m[2] * tx - m[0] * tz;
-    const T dz = m[0] * ty - m[1] * tx;
-    const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
-                    -a.gdt * (tz + a.alpha * dz)};
-    const int64_t N = a.N;
-    if (a.stage == 1) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t plane = (int64_t)a.nx * a.ny;
+    if (t >= plane) return;
+    const int i = (int)(t % a.nx);
+    const int j = (int)(t / a.nx);
+    const int64_t N = a.N, sy = a.nx;
+    const T* ms = a.ms;
+    T prev[3], cur[3], next[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        cur[d] = ms[d * N + t];
+        prev[d] = cur[d];
+        next[d] = cur[d];
+    }
+    int64_t c = t;
+    for (int k = 0; k < a.nz; ++k, c += plane) {
+        const bool up = k + 1 < a.nz, down = k > 0;
+        if (up) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) next[d] = ms[d * N + c + plane];
+        }
+        T h[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            a.acc[d * N + c] = F[d];
-            a.out[d * N + c] = m[d] + (T)0.5 * F[d];
+            const T* u = ms + d * N;
+            const T mc = cur[d];
+            T acc = (T)0;
+            if (i > 0) acc += u[c - 1] - mc;
+            if (i < a.nx - 1) acc += u[c + 1] - mc;
+            if (j > 0) acc += u[c - sy] - mc;
+            if (j < a.ny - 1) acc += u[c + sy] - mc;
+            if (down) acc += prev[d] - mc;
+            if (up) acc += next[d] - mc;
+            h[d] = a.cex * acc;
         }
-    } else if (a.stage == 2 || a.stage == 3) {
-        const T w = a.stage == 2 ? (T)0.5 : (T)1;
+        h[0] += (a.ku ? a.ku[c] : a.can) * cur[0] + a.hx;
+        h[1] += a.hy;
+        h[2] += a.hz;
+        if (a.hd) {
+            h[0] += a.hd[c];
+            h[1] += a.hd[N + c];
+            h[2] += a.hd[2 * N + c];
+        }
+        const T* m = cur;
+        const T tx = m[1] * h[2] - m[2] * h[1];
+        const T ty = m[2] * h[0] - m[0] * h[2];
+        const T tz = m[0] * h[1] - m[1] * h[0];
+        const T dx = m[1] * tz - m[2] * ty;
+        const T dy = m[2] * tx - m[0] * tz;
+        const T dz = m[0] * ty - m[1] * tx;
+        const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
+                        -a.gdt * (tz + a.alpha * dz)};
+        if (a.stage == 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                a.acc[d * N + c] = F[d];
+                a.out[d * N + c] = m[d] + (T)0.5 * F[d];
+            }
+        } else if (a.stage == 2 || a.stage == 3) {
+            const T w = a.stage == 2 ? (T)0.5 : (T)1;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                a.acc[d * N + c] += (T)2 * F[d];
+                a.out[d * N + c] = a.mn[d * N + c] + w * F[d];
+            }
+        } else {
+            T v[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[d] = a.mn[d * N + c] + (a.acc[d * N + c] + F[d]) / (T)6;
+            const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            a.acc[d * N + c] += (T)2 * F[d];
-            a.out[d * N + c] = a.mn[d * N + c] + w * F[d];
+            prev[d] = cur[d];
+            cur[d] = next[d];
         }
-    } else {
-        T v[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = a.mn[d * N + c] + (a.acc[d * N + c] + F[d]) / (T)6;
-        const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
     }
 }
 
@@ -235,7 +277,7 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_llg_stage<T>, dim3(blocks_for(a.N)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_llg_stage<T>, dim3(blocks_for((int64_t)a.nx * a.ny)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -16,10 +16,10 @@ namespace mm {
 
 constexpr int lds_elems(int nt) { return kElemsPerThread * nt + 64; }
 
-__device__ inline int64_t row_off(int r, int rpp, int64_t plane_stride, int64_t sx)
+__device__ inline int64_t row_off(int r, int rpp, int64_t plane_stride, int64_t rstride)
 {
     const int pl = r / rpp;
-    return (int64_t)pl * plane_stride + (int64_t)(r - pl * rpp) * sx;
+    return (int64_t)pl * plane_stride + (int64_t)(r - pl * rpp) * rstride;
 }
 
 __device__ inline int64_t col_off(int c, int cpr, int64_t row2)
@@ -58,8 +58,10 @@ __global__ __launch_bounds__(NT) void k_row_r2c(RowR2CArgs a)
         const cpx<T> A = scale(zk + conj(zm), (T)0.5);
         const cpx<T> Bv = scale(mul_mi(zk - conj(zm)), (T)0.5);
         const int r0 = 2 * pr;
-        out[row_off(r0, a.rows_per_plane, a.out_plane_stride, a.sx) + k] = A;
-        if (r0 + 1 < a.nrows) out[row_off(r0 + 1, a.rows_per_plane, a.out_plane_stride, a.sx) + k] = Bv;
+        const int64_t ko = (int64_t)k * a.kstride;
+        out[row_off(r0, a.rows_per_plane, a.out_plane_stride, a.rstride) + ko] = A;
+        if (r0 + 1 < a.nrows)
+            out[row_off(r0 + 1, a.rows_per_plane, a.out_plane_stride, a.rstride) + ko] = Bv;
     }
 }
 
@@ -79,19 +81,20 @@ __global__ __launch_bounds__(NT) void k_row_c2r(RowC2RArgs a)
         if (pr < npairs) {
             const int r0 = 2 * pr;
             const bool has1 = r0 + 1 < a.nrows;
-            const int64_t o0 = row_off(r0, a.rows_per_plane, a.in_plane_stride, a.sx);
-            const int64_t o1 = has1 ? row_off(r0 + 1, a.rows_per_plane, a.in_plane_stride, a.sx) : 0;
+            const int64_t o0 = row_off(r0, a.rows_per_plane, a.in_plane_stride, a.rstride);
+            const int64_t o1 = has1 ? row_off(r0 + 1, a.rows_per_plane, a.in_plane_stride, a.rstride) : 0;
+            const int64_t ks = a.kstride;
             cpx<T> A, Bv = {(T)0, (T)0};
             if (x < a.hx) {
-                A = in[o0 + x];
-                if (has1) Bv = in[o1 + x];
+                A = in[o0 + x * ks];
+                if (has1) Bv = in[o1 + x * ks];
                 if (x == 0 || (evenP && 2 * x == P)) {  // DC and Nyquist bins are real
                     A.im = (T)0;
                     Bv.im = (T)0;
                 }
             } else {
-                A = conj(in[o0 + (P - x)]);
-                if (has1) Bv = conj(in[o1 + (P - x)]);
+                A = conj(in[o0 + (P - x) * ks]);
+                if (has1) Bv = conj(in[o1 + (P - x) * ks]);
             }
             z = {A.re - Bv.im, A.im + Bv.re};  // A + i B
         }
@@ -166,8 +169,8 @@ __global__ __launch_bounds__(NT) void k_kspace(KspArgs a)
         if (col >= a.ncols) continue;
         int kx, ky, kz;
         if (a.axis_is_z) {
-            ky = col / a.hx;
-            kx = col - ky * a.hx;
+            kx = col / a.Py;
+            ky = col - kx * a.Py;
             kz = e;
         } else {
             kx = col;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_kspace(KspArgs a)
             kz = a.Pz - kz;
             sz = (T)-1;
         }
-        const int64_t ko = kz * a.k_zs + ky * a.k_ys + kx;
+        const int64_t ko = kz * a.k_zs + kx * a.k_xs + ky;
         T kxx, kxy, kxz, kyy, kyz, kzz;
         if (a.ncomp == 6) {
             kxx = K[ko];

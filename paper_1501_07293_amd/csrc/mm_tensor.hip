@@ -109,15 +109,25 @@ __global__ void k_octant(T* out, const cpx<double>* spec, int hx, int Py, int Pz
 {
     const int oy = Py / 2 + 1, oz = Pz / 2 + 1;
     const int64_t total = (int64_t)oz * oy * hx;
+    double im_max = 0.0, re_max = 0.0;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const int kx = (int)(q % hx);
-        const int ky = (int)((q / hx) % oy);
+        const int ky = (int)(q % oy);
+        const int kx = (int)((q / oy) % hx);
         const int kz = (int)(q / ((int64_t)hx * oy));
         const cpx<double> v = spec[((int64_t)kz * Py + ky) * sx + kx];
         out[q] = (T)(v.re * scale);
-        atomic_max_pos(&stats[0], fabs(v.im * scale));
-        atomic_max_pos(&stats[1], fabs(v.re * scale));
+        im_max = fmax(im_max, fabs(v.im * scale));
+        re_max = fmax(re_max, fabs(v.re * scale));
+    }
+    // one atomic per wave: reduce across the wave first
+    for (int off = 32; off > 0; off >>= 1) {
+        im_max = fmax(im_max, __shfl_xor(im_max, off));
+        re_max = fmax(re_max, __shfl_xor(re_max, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_pos(&stats[0], im_max);
+        atomic_max_pos(&stats[1], re_max);
     }
 }
 
