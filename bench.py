@@ -93,6 +93,23 @@ def run_gpu(args, cfg, precision: str, steps: int, warmup: int, profile: bool):
     return sim, plan, t1 - t0, per_kernel, dom, dom_ms, dom_n, energy
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
+    """GB/s of a plain device-to-device copy (read + write counted) on this GPU."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").uniform_()
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes * reps / dt / 1e9
+
+
 def field_error_sampled(sim, cfg, pb, nsamp: int, seed: int = 1):
     import oracle
     rng = np.random.default_rng(seed)
@@ -190,6 +207,7 @@ def main():
         out["step_model_bytes_per_cell"] = step_bytes / cfg.N
         out["effective_gbs"] = step_bytes / (secs / args.steps) / 1e9
     out["energy_J"] = energy.tolist()
+    out["copy_gbs_measured"] = copy_bandwidth()
 
     need_oracle = not args.no_cpu_baseline
     if need_oracle:

@@ -41,8 +41,10 @@ constexpr int span_of() { return S == 0 ? 1 : (S == 1 ? Sched<P>::R0 : Sched<P>:
 // LDS index with one pad slot every 16 entries (breaks the stride-R1 bank pattern
 // of the first-stage writes).
 __device__ constexpr int pad16(int e) { return e + (e >> 4); }
+// LDS line length: the in-line pad plus one slot so consecutive lines start on
+// different banks.
 template <int P>
-constexpr int padded_len() { return P + P / 16; }
+constexpr int padded_len() { return P + P / 16 + 1; }
 
 // Stage S >= 1 on one LDS line: each thread does R0/R butterflies.  Reads all,
 // barrier, writes all, barrier.

@@ -58,56 +58,69 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
     }
 }
 
-// One thread per (x, y) column of cells marching up in z: m of the planes
-// z-1, z, z+1 stays in registers, so every m value is read from HBM once; the
-// x and y neighbours come from the same or adjacent rows (L1/L2 hits).
+// One thread per (x, y) column and chunk of kLlgZ planes.  Every load of the
+// chunk (m of planes k0-1 .. k0+kLlgZ, in-plane neighbours, H_d, Ku, m_n, acc)
+// is issued before the first store, so a thread keeps many loads in flight;
+// the z neighbours come from registers, the x and y neighbours from rows that
+// neighbouring threads load anyway (L1/L2 hits).
+constexpr int kLlgZ = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
 {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    constexpr int KZ = kLlgZ;
     const int64_t plane = (int64_t)a.nx * a.ny;
-    if (t >= plane) return;
-    const int i = (int)(t % a.nx);
-    const int j = (int)(t / a.nx);
+    const int nzc = (a.nz + KZ - 1) / KZ;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= plane * nzc) return;
+    const int kc = (int)(t / plane);
+    const int64_t pc = t - (int64_t)kc * plane;
+    const int i = (int)(pc % a.nx), j = (int)(pc / a.nx);
+    const int k0 = kc * KZ;
     const int64_t N = a.N, sy = a.nx;
-    const T* ms = a.ms;
-    T prev[3], cur[3], next[3];
+    const T* __restrict__ ms = a.ms;
+    T col[KZ + 2][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        cur[d] = ms[d * N + t];
-        prev[d] = cur[d];
-        next[d] = cur[d];
+    for (int q = 0; q < KZ + 2; ++q) {
+        const int k = k0 - 1 + q;
+        const bool in = k >= 0 && k < a.nz;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) col[q][d] = in ? ms[d * N + pc + k * plane] : (T)0;
     }
-    int64_t c = t;
-    for (int k = 0; k < a.nz; ++k, c += plane) {
-        const bool up = k + 1 < a.nz, down = k > 0;
-        if (up) {
+    T lap[KZ][3], hd[KZ][3], mn[KZ][3], ac[KZ][3], kan[KZ];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) next[d] = ms[d * N + c + plane];
-        }
-        T h[3];
+    for (int q = 0; q < KZ; ++q) {
+        const int k = k0 + q;
+        const bool in = k < a.nz;
+        const int64_t c = pc + (int64_t)(in ? k : 0) * plane;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const T* u = ms + d * N;
-            const T mc = cur[d];
+            const T mc = col[q + 1][d];
             T acc = (T)0;
-            if (i > 0) acc += u[c - 1] - mc;
-            if (i < a.nx - 1) acc += u[c + 1] - mc;
-            if (j > 0) acc += u[c - sy] - mc;
-            if (j < a.ny - 1) acc += u[c + sy] - mc;
-            if (down) acc += prev[d] - mc;
-            if (up) acc += next[d] - mc;
-            h[d] = a.cex * acc;
+            if (in) {
+                if (i > 0) acc += u[c - 1] - mc;
+                if (i < a.nx - 1) acc += u[c + 1] - mc;
+                if (j > 0) acc += u[c - sy] - mc;
+                if (j < a.ny - 1) acc += u[c + sy] - mc;
+                if (k > 0) acc += col[q][d] - mc;
+                if (k < a.nz - 1) acc += col[q + 2][d] - mc;
+            }
+            lap[q][d] = acc;
+            hd[q][d] = (in && a.hd) ? a.hd[d * N + c] : (T)0;
+            mn[q][d] = (in && a.stage > 1) ? a.mn[d * N + c] : (T)0;
+            ac[q][d] = (in && a.stage > 1) ? a.acc[d * N + c] : (T)0;
         }
-        h[0] += (a.ku ? a.ku[c] : a.can) * cur[0] + a.hx;
-        h[1] += a.hy;
-        h[2] += a.hz;
-        if (a.hd) {
-            h[0] += a.hd[c];
-            h[1] += a.hd[N + c];
-            h[2] += a.hd[2 * N + c];
-        }
-        const T* m = cur;
+        kan[q] = (in && a.ku) ? a.ku[c] : a.can;
+    }
+#pragma unroll
+    for (int q = 0; q < KZ; ++q) {
+        const int k = k0 + q;
+        if (k >= a.nz) break;
+        const int64_t c = pc + (int64_t)k * plane;
+        const T* m = col[q + 1];
+        const T h[3] = {a.cex * lap[q][0] + kan[q] * m[0] + a.hx + hd[q][0],
+                        a.cex * lap[q][1] + a.hy + hd[q][1], a.cex * lap[q][2] + a.hz + hd[q][2]};
         const T tx = m[1] * h[2] - m[2] * h[1];
         const T ty = m[2] * h[0] - m[0] * h[2];
         const T tz = m[0] * h[1] - m[1] * h[0];
@@ -126,21 +139,16 @@ __global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
             const T w = a.stage == 2 ? (T)0.5 : (T)1;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                a.acc[d * N + c] += (T)2 * F[d];
-                a.out[d * N + c] = a.mn[d * N + c] + w * F[d];
+                a.acc[d * N + c] = ac[q][d] + (T)2 * F[d];
+                a.out[d * N + c] = mn[q][d] + w * F[d];
             }
         } else {
             T v[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) v[d] = a.mn[d * N + c] + (a.acc[d * N + c] + F[d]) / (T)6;
+            for (int d = 0; d < 3; ++d) v[d] = mn[q][d] + (ac[q][d] + F[d]) / (T)6;
             const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 #pragma unroll
             for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            prev[d] = cur[d];
-            cur[d] = next[d];
         }
     }
 }
@@ -277,7 +285,8 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_llg_stage<T>, dim3(blocks_for((int64_t)a.nx * a.ny)), dim3(256), 0, s, a);
+    const int64_t threads = (int64_t)a.nx * a.ny * ((a.nz + kLlgZ - 1) / kLlgZ);
+    hipLaunchKernelGGL(k_llg_stage<T>, dim3(blocks_for(threads)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
