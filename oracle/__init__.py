@@ -65,8 +65,10 @@ def _load():
         lib.or_rk4.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64]
         lib.or_energy.argtypes = [pp, dp, dp, dp]
         lib.or_mean_m.argtypes = [pp, dp, dp]
+        lib.or_rk4_adjoint.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
         for f in ("or_tensor_point", "or_tensor_table", "or_demag", "or_exchange",
-                  "or_anisotropy", "or_heff", "or_llg_rhs", "or_rk4", "or_energy", "or_mean_m"):
+                  "or_anisotropy", "or_heff", "or_llg_rhs", "or_rk4", "or_energy", "or_mean_m",
+                  "or_rk4_adjoint"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -223,3 +225,18 @@ def mean_m(pb: Problem, m) -> np.ndarray:
     out = np.zeros(3)
     _load().or_mean_m(ctypes.byref(p), _dptr(m), _dptr(out))
     return out
+
+
+def rk4_adjoint(pb: Problem, m0, dt: float, nsteps: int, lam_final):
+    """Discrete adjoint of rk4(): given dLoss/dm at the final state, returns
+    (dLoss/dKu per cell (nz, ny, nx), dLoss/dm0 (3, nz, ny, nx)).  FP64; keeps
+    every stage state in memory, so for small grids."""
+    m0 = _m(pb, m0)
+    lam = _m(pb, lam_final)
+    tab = pb.table() if pb.demag else np.zeros(1)
+    p = pb._params()
+    dku = np.zeros((pb.nz, pb.ny, pb.nx))
+    dm0 = np.zeros(pb.shape)
+    _load().or_rk4_adjoint(ctypes.byref(p), _dptr(m0), _dptr(tab), float(dt), int(nsteps),
+                           _dptr(lam), _dptr(dku), _dptr(dm0))
+    return dku, dm0

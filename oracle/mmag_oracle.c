@@ -304,3 +304,142 @@ void or_mean_m(const or_params *p, const double *m, double out[3])
         out[a] = s / (double)N;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of nsteps RK4 steps with renormalisation (test infrastructure
+ * for the gradient of a loss of the final state).  With the effective field
+ * H(m) = L m + H_ext (L symmetric: exchange Laplacian with the Neumann rule,
+ * diagonal anisotropy, symmetric demag tensor) and
+ *   f(m) = -g [ m x H + alpha m x (m x H) ],   g = gamma / (1 + alpha^2),
+ * the transpose Jacobian applied to a covector lam is
+ *   (df/dm)^T lam = -g [ H x lam + alpha ((m x H) x lam + H x (lam x m)) ] + L nu,
+ *   nu = -g [ lam x m + alpha (lam x m) x m ],
+ * and the anisotropy map enters through dH_x/dKu(c) = 2 m_x(c) / (mu0 Ms), so
+ * dLoss/dKu(c) collects nu_x(c) m_x(c) 2 / (mu0 Ms) over every stage.
+ * lam_final = dLoss/dm at the final state; outputs dku (N) and dm0 ([3][N]),
+ * either may be NULL.  Stores every stage of every step (small grids only). */
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* out = (df/dm)^T lam at (m, H); nu_out = nu (both [3][N]). */
+static void rhs_vjp(const or_params *p, const double *m, const double *H, const double *lam,
+                    const double *table, double *out, double *nu_out)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const double g = p->gamma / (1.0 + p->alpha * p->alpha);
+    for (int64_t c = 0; c < N; ++c) {
+        double mm[3] = {m[c], m[N + c], m[2 * N + c]};
+        double hh[3] = {H[c], H[N + c], H[2 * N + c]};
+        double ll[3] = {lam[c], lam[N + c], lam[2 * N + c]};
+        double mxh[3], t1[3], t2[3], lxm[3], t3[3], t4[3];
+        cross3(hh, ll, t1);        /* H x lam */
+        cross3(mm, hh, mxh);       /* m x H */
+        cross3(mxh, ll, t2);       /* (m x H) x lam */
+        cross3(ll, mm, lxm);       /* lam x m */
+        cross3(hh, lxm, t3);       /* H x (lam x m) */
+        cross3(lxm, mm, t4);       /* (lam x m) x m */
+        for (int a = 0; a < 3; ++a) {
+            out[a * N + c] = -g * (t1[a] + p->alpha * (t2[a] + t3[a]));
+            nu_out[a * N + c] = -g * (lxm[a] + p->alpha * t4[a]);
+        }
+    }
+    /* + L nu: the field operator without the applied field, applied to nu */
+    or_params q = *p;
+    q.hext[0] = q.hext[1] = q.hext[2] = 0.0;
+    double *Lnu = (double *)malloc(sizeof(double) * 3 * N);
+    or_heff(&q, nu_out, table, NULL, NULL, NULL, Lnu);
+    for (int64_t k = 0; k < 3 * N; ++k) out[k] += Lnu[k];
+    free(Lnu);
+}
+
+void or_rk4_adjoint(const or_params *p, const double *m0, const double *table, double dt,
+                    int64_t nsteps, const double *lam_final, double *dku, double *dm0)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz, L = 3 * N;
+    /* forward: every stage state and its field */
+    double *ms = (double *)malloc(sizeof(double) * L * 4 * nsteps);  /* m_n, m2, m3, m4 */
+    double *hs = (double *)malloc(sizeof(double) * L * 4 * nsteps);
+    double *mend = (double *)malloc(sizeof(double) * L * (nsteps + 1));
+    double *k = (double *)malloc(sizeof(double) * L * 4);
+    memcpy(mend, m0, sizeof(double) * L);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        double *S = ms + 4 * n * L, *Hh = hs + 4 * n * L;
+        const double *mn = mend + n * L;
+        memcpy(S, mn, sizeof(double) * L);
+        const double cf[3] = {0.5, 0.5, 1.0};
+        for (int s = 0; s < 4; ++s) {
+            or_heff(p, S + s * L, table, NULL, NULL, NULL, Hh + s * L);
+            or_llg_rhs(p, S + s * L, Hh + s * L, k + s * L);
+            if (s < 3)
+                for (int64_t q = 0; q < L; ++q) S[(s + 1) * L + q] = mn[q] + cf[s] * dt * k[s * L + q];
+        }
+        double *mnext = mend + (n + 1) * L;
+        for (int64_t q = 0; q < L; ++q)
+            mnext[q] = mn[q] + dt / 6.0 * (k[q] + 2 * k[L + q] + 2 * k[2 * L + q] + k[3 * L + q]);
+        for (int64_t c = 0; c < N; ++c) {
+            double nrm = sqrt(mnext[c] * mnext[c] + mnext[N + c] * mnext[N + c] +
+                              mnext[2 * N + c] * mnext[2 * N + c]);
+            for (int a = 0; a < 3; ++a) mnext[a * N + c] /= nrm;
+        }
+    }
+    /* reverse */
+    double *lam = (double *)malloc(sizeof(double) * L);
+    double *mu = (double *)malloc(sizeof(double) * L);
+    double *dF = (double *)malloc(sizeof(double) * L);
+    double *a = (double *)malloc(sizeof(double) * L);
+    double *nu = (double *)malloc(sizeof(double) * L);
+    double *acc = (double *)malloc(sizeof(double) * L);
+    double *mstar = (double *)malloc(sizeof(double) * L);
+    memcpy(lam, lam_final, sizeof(double) * L);
+    if (dku) memset(dku, 0, sizeof(double) * N);
+    const double kfac = 2.0 / (OR_MU0 * p->Ms);
+    for (int64_t n = nsteps - 1; n >= 0; --n) {
+        double *S = ms + 4 * n * L, *Hh = hs + 4 * n * L;
+        const double *mn = mend + n * L;
+        for (int s = 0; s < 4; ++s) or_llg_rhs(p, S + s * L, Hh + s * L, k + s * L);
+        for (int64_t q = 0; q < L; ++q)
+            mstar[q] = mn[q] + dt / 6.0 * (k[q] + 2 * k[L + q] + 2 * k[2 * L + q] + k[3 * L + q]);
+        /* renormalisation: mp = mstar / norm, so mu = (lam - (lam . mp) mp) / norm */
+        for (int64_t c = 0; c < N; ++c) {
+            double nrm = sqrt(mstar[c] * mstar[c] + mstar[N + c] * mstar[N + c] +
+                              mstar[2 * N + c] * mstar[2 * N + c]);
+            double mp[3] = {mstar[c] / nrm, mstar[N + c] / nrm, mstar[2 * N + c] / nrm};
+            double dot = lam[c] * mp[0] + lam[N + c] * mp[1] + lam[2 * N + c] * mp[2];
+            for (int d = 0; d < 3; ++d) mu[d * N + c] = (lam[d * N + c] - dot * mp[d]) / nrm;
+        }
+        /* m* = m_n + (F1 + 2F2 + 2F3 + F4)/6 with F_s = dt f(m_s);
+         * m2 = m_n + F1/2, m3 = m_n + F2/2, m4 = m_n + F3. */
+        memcpy(acc, mu, sizeof(double) * L);
+        for (int64_t q = 0; q < L; ++q) dF[q] = mu[q] / 6.0;
+        for (int s = 3; s >= 0; --s) {
+            rhs_vjp(p, S + s * L, Hh + s * L, dF, table, a, nu);
+            for (int64_t q = 0; q < L; ++q) a[q] *= dt;
+            if (dku)
+                for (int64_t c = 0; c < N; ++c) dku[c] += dt * nu[c] * S[s * L + c] * kfac;
+            for (int64_t q = 0; q < L; ++q) acc[q] += a[q];
+            if (s == 3)
+                for (int64_t q = 0; q < L; ++q) dF[q] = 2.0 * mu[q] / 6.0 + a[q];
+            else if (s == 2)
+                for (int64_t q = 0; q < L; ++q) dF[q] = 2.0 * mu[q] / 6.0 + 0.5 * a[q];
+            else if (s == 1)
+                for (int64_t q = 0; q < L; ++q) dF[q] = mu[q] / 6.0 + 0.5 * a[q];
+        }
+        memcpy(lam, acc, sizeof(double) * L);
+    }
+    if (dm0) memcpy(dm0, lam, sizeof(double) * L);
+    free(ms);
+    free(hs);
+    free(mend);
+    free(k);
+    free(lam);
+    free(mu);
+    free(dF);
+    free(a);
+    free(nu);
+    free(acc);
+    free(mstar);
+}

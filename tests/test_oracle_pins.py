@@ -375,3 +375,35 @@ def test_energy_rate_matches_dissipation():
     V = pb.cell ** 3
     expect = -MU0 * V * pb.Ms * pb.alpha * pb.gamma / (1 + pb.alpha ** 2) * (t * t).sum()
     assert abs(dEdt / expect - 1) < 1e-3
+
+
+# ------------------------------------------------------ adjoint of RK4 + renormalisation
+def _loss(pb, m0, dt, n, w):
+    return float((oracle.rk4(pb, m0, dt, n) * w).sum())
+
+
+def test_oracle_adjoint_matches_finite_differences():
+    # The discrete adjoint (dLoss/dKu, dLoss/dm0) of n RK4 steps against central
+    # differences of the forward run in FP64, for a linear loss sum(w * m_n).
+    g = np.random.default_rng(21)
+    nx, ny, nz = 5, 4, 2
+    ku = 500.0 + 50.0 * g.standard_normal((nz, ny, nx))
+    pb = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku,
+                        hext=tuple(mT_to_Apm([8.0, -3.0, 5.0])))
+    m0 = random_unit_m(pb.shape, 22)
+    w = g.standard_normal(pb.shape)
+    dt, n = 1e-13, 6
+    dku, dm0 = oracle.rk4_adjoint(pb, m0, dt, n, w)
+    for trial in range(3):
+        v = g.standard_normal(ku.shape)
+        eps = 2.0
+        pb_p = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku + eps * v, hext=pb.hext)
+        pb_m = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku - eps * v, hext=pb.hext)
+        fd = (_loss(pb_p, m0, dt, n, w) - _loss(pb_m, m0, dt, n, w)) / (2 * eps)
+        ad = float((dku * v).sum())
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (trial, fd, ad)
+        vm = g.standard_normal(pb.shape)
+        em = 1e-6
+        fdm = (_loss(pb, m0 + em * vm, dt, n, w) - _loss(pb, m0 - em * vm, dt, n, w)) / (2 * em)
+        adm = float((dm0 * vm).sum())
+        assert abs(fdm - adm) <= 1e-6 * abs(adm), (trial, fdm, adm)
