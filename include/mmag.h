@@ -153,6 +153,30 @@ mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
  * component order xx, xy, xz, yy, yz, zz, offset index (K+nz-1, J+ny-1, I+nx-1). */
 mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream);
 
+/* ---- differentiation (adjoint) ------------------------------------------
+ * Gradients of a loss of the final state of an RK4 rollout with respect to the
+ * per-cell anisotropy map (set by mm_set_ku_map) and the initial state, by the
+ * discrete adjoint of the RK4 step with renormalisation (hand-written
+ * vector-Jacobian products; the transposed demag convolution is the demag
+ * convolution itself, the tensor being symmetric and even).
+ *
+ * mm_rollout: nsteps RK4 steps of dt from the current m, like mm_step, and
+ *   stores the state at the start of every segment of ckpt_every steps into
+ *   d_ckpt (device, caller-owned, ceil(nsteps/ckpt_every) x [3][nz][ny][nx]).
+ * mm_adjoint_workspace_query: device bytes mm_backward needs for ckpt_every.
+ * mm_backward: given d_lam_final = dLoss/dm at the final state ([3][nz][ny][nx],
+ *   working precision, device), recomputes each segment from its checkpoint and
+ *   runs the reverse sweep; writes d_dku = dLoss/dKu per cell (FP64, device, N
+ *   values; loss units per J/m^3) and, if d_dm0 is not NULL, dLoss/dm0
+ *   ([3][nz][ny][nx], working precision, device).  nsteps, dt and ckpt_every
+ *   must be those of the rollout, with m, Ku map, alpha and H_ext unchanged.
+ *   The handle's m is preserved.  Uses the caller's adjoint workspace. */
+mm_status mm_rollout(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every, void* d_ckpt);
+mm_status mm_adjoint_workspace_query(mm_sim* sim, int64_t ckpt_every, size_t* bytes);
+mm_status mm_backward(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every,
+                      const void* d_ckpt, const void* d_lam_final, double* d_dku, void* d_dm0,
+                      void* d_adj_ws, size_t adj_ws_bytes);
+
 /* Per-kernel timing with HIP events on the handle's stream.  kernel: 0 x-forward,
  * 1 y-forward, 2 k-space, 3 y-inverse, 4 x-inverse, 5 LLG stage.  While a
  * profile is open mm_step launches kernels directly (no graph replay) and

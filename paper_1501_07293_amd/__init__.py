@@ -28,8 +28,9 @@ KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5
 EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
            "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_get_field",
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
-           "mm_demag_tensor", "mm_profile_begin", "mm_profile_end", "mm_kernel_name",
-           "mm_status_string", "mm_last_error"]
+           "mm_demag_tensor", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
+           "mm_profile_begin", "mm_profile_end", "mm_kernel_name", "mm_status_string",
+           "mm_last_error"]
 
 
 class MMError(RuntimeError):
@@ -90,6 +91,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_get_plan": [vp, ctypes.POINTER(PlanInfo)],
         "mm_get_kernel_spectrum": [vp, vp, ctypes.c_int],
         "mm_demag_tensor": [i32, i32, i32, vp, vp],
+        "mm_rollout": [vp, i64, dbl, i64, vp],
+        "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
         "mm_profile_begin": [vp, i32],
         "mm_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
@@ -233,6 +237,35 @@ class Sim:
         _check(self._lib.mm_get_kernel_spectrum(self._h, out.data_ptr(), 1), "mm_get_kernel_spectrum")
         return out.reshape(p["ncomp"], p["pz"] // 2 + 1, p["hx"], p["py"] // 2 + 1)
 
+    # ----------------------------------------------------------- adjoint
+    def rollout_ckpt(self, nsteps: int, dt: float, ckpt_every: int):
+        """nsteps RK4 steps from the current m; returns the segment checkpoints."""
+        nseg = (nsteps + ckpt_every - 1) // ckpt_every
+        ck = self._torch.empty((nseg,) + self.shape, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_rollout(self._h, int(nsteps), float(dt), int(ckpt_every), ck.data_ptr()),
+               "mm_rollout")
+        return ck
+
+    def backward(self, nsteps: int, dt: float, ckpt_every: int, ckpt, lam_final,
+                 want_dm0: bool = True):
+        """Reverse sweep: returns (dLoss/dKu per cell (float64, (nz, ny, nx)),
+        dLoss/dm0 or None) for dLoss/dm_final = lam_final."""
+        torch = self._torch
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.mm_adjoint_workspace_query(self._h, int(ckpt_every), ctypes.byref(nbytes)),
+               "mm_adjoint_workspace_query")
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        lam = lam_final.to(device=self.device, dtype=self.dtype).contiguous()
+        dku = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        dm0 = torch.empty(self.shape, dtype=self.dtype, device=self.device) if want_dm0 else None
+        self._sync_stream()
+        _check(self._lib.mm_backward(self._h, int(nsteps), float(dt), int(ckpt_every), ckpt.data_ptr(),
+                                     lam.data_ptr(), dku.data_ptr(),
+                                     dm0.data_ptr() if dm0 is not None else None, ws.data_ptr(),
+                                     nbytes.value), "mm_backward")
+        return dku, dm0
+
     # ------------------------------------------------------------- profiling
     def profile_begin(self, kernel: str):
         self._sync_stream()
@@ -268,3 +301,45 @@ def demag_tensor(nx: int, ny: int, nz: int, device: str = "cuda:0"):
 
 def kernel_name(k: int) -> str:
     return load_library().mm_kernel_name(k).decode()
+
+
+def _rollout_function():
+    import torch
+
+    class Rollout(torch.autograd.Function):
+        """m_final = RK4^nsteps(m0; Ku map) on the GPU, with the hand-written
+        adjoint (checkpoint every ckpt_every steps, segments recomputed in the
+        backward pass).  Gradients flow to the Ku map (J/m^3, per cell) and to m0
+        (taken as the normalised initial state)."""
+
+        @staticmethod
+        def forward(ctx, ku, m0, sim, nsteps, dt, ckpt_every):
+            sim.set_ku_map(ku.detach())
+            sim.set_m(m0.detach())
+            ck = sim.rollout_ckpt(nsteps, dt, ckpt_every)
+            ctx.sim, ctx.nsteps, ctx.dt, ctx.ckpt_every = sim, nsteps, dt, ckpt_every
+            ctx.save_for_backward(ck)
+            ctx.ku_dtype, ctx.m0_dtype = ku.dtype, m0.dtype
+            return sim.get_m()
+
+        @staticmethod
+        def backward(ctx, grad_m):
+            (ck,) = ctx.saved_tensors
+            dku, dm0 = ctx.sim.backward(ctx.nsteps, ctx.dt, ctx.ckpt_every, ck, grad_m,
+                                        want_dm0=ctx.needs_input_grad[1])
+            gku = dku.to(ctx.ku_dtype) if ctx.needs_input_grad[0] else None
+            gm0 = dm0.to(ctx.m0_dtype) if dm0 is not None else None
+            return gku, gm0, None, None, None, None
+
+    return Rollout
+
+
+_ROLLOUT = None
+
+
+def rollout(sim: Sim, ku, m0, nsteps: int, dt: float, ckpt_every: int = 50):
+    """Differentiable RK4 rollout (torch.autograd): returns m after nsteps."""
+    global _ROLLOUT
+    if _ROLLOUT is None:
+        _ROLLOUT = _rollout_function()
+    return _ROLLOUT.apply(ku, m0, sim, nsteps, dt, ckpt_every)

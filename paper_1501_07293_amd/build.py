@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmag.so")
-SOURCES = ["mm_api.hip", "mm_passes.hip", "mm_fast.hip", "mm_tensor.hip", "mm_llg.hip"]
+SOURCES = ["mm_api.hip", "mm_passes.hip", "mm_fast.hip", "mm_tensor.hip", "mm_llg.hip",
+           "mm_adjoint.hip"]
 ARCH = os.environ.get("MMAG_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

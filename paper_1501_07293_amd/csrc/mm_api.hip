@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mmag.h"
@@ -688,6 +690,137 @@ mm_status set_m_impl(mm_sim* s, const void* m, int on_device)
     return MM_OK;
 }
 
+// ---------------------------------------------------------------- adjoint
+size_t adj_bytes(const Plan& p, int64_t ck)
+{
+    const size_t vec = align256(3 * (size_t)p.N * p.esz);
+    return (size_t)ck * vec + 15 * vec;
+}
+
+template <typename T>
+mm_status rollout_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, T* ckpt)
+{
+    const Plan& p = s->p;
+    const size_t vec = 3 * (size_t)p.N;
+    T* mn = s->at<T>(p.o_mn);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if (n % ck == 0)
+            HIP_TRY(hipMemcpyAsync(ckpt + (n / ck) * vec, mn, vec * sizeof(T), hipMemcpyDeviceToDevice,
+                                   s->stream));
+        mm_status r = rk4_step<T>(s, dt, s->stream);
+        if (r != MM_OK) return r;
+    }
+    return MM_OK;
+}
+
+template <typename T>
+mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const T* ckpt,
+                        const T* lam_final, double* dku, T* dm0, char* ws)
+{
+    const Plan& p = s->p;
+    hipStream_t st = s->stream;
+    const size_t vec = 3 * (size_t)p.N, vbytes = align256(vec * sizeof(T));
+    T* seg = reinterpret_cast<T*>(ws);
+    char* q = ws + (size_t)ck * vbytes;
+    auto take = [&]() {
+        T* r = reinterpret_cast<T*>(q);
+        q += vbytes;
+        return r;
+    };
+    T *m2 = take(), *m3 = take(), *m4 = take(), *h1 = take(), *h2 = take(), *h3 = take(),
+      *h4 = take();
+    T *lam = take(), *accl = take(), *mu = take(), *dF = take(), *nu = take(), *loc = take(),
+      *scr = take(), *msave = take();
+    T* mn_sim = s->at<T>(p.o_mn);
+    T* hd = s->at<T>(p.o_hd);
+    const bool with_demag = !(s->flags & MM_NO_DEMAG);
+    HIP_TRY(hipMemcpyAsync(msave, mn_sim, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(lam, lam_final, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(dku, 0, (size_t)p.N * sizeof(double), st));
+
+    LlgArgs<T> la = llg_args<T>(s, dt);
+    AdjArgs<T> aa{};
+    aa.nx = p.nx;
+    aa.ny = p.ny;
+    aa.nz = p.nz;
+    aa.N = p.N;
+    aa.m2 = m2;
+    aa.m3 = m3;
+    aa.m4 = m4;
+    aa.h1 = h1;
+    aa.h2 = h2;
+    aa.h3 = h3;
+    aa.h4 = h4;
+    aa.lam = lam;
+    aa.mu = mu;
+    aa.dF = dF;
+    aa.accl = accl;
+    aa.nu = nu;
+    aa.loc = loc;
+    aa.hd = with_demag ? hd : nullptr;
+    aa.ku = la.ku;
+    aa.can = la.can;
+    aa.cex = la.cex;
+    aa.G = la.gdt;
+    aa.alpha = la.alpha;
+    aa.dku = dku;
+    aa.kfac = 2.0 / (kMu0 * s->mat.Ms * s->mat.Ms);
+    T* ms_of[4] = {nullptr, m2, m3, m4};
+    T* hs_of[4] = {h1, h2, h3, h4};
+
+    const int64_t nseg = (nsteps + ck - 1) / ck;
+    for (int64_t g = nseg - 1; g >= 0; --g) {
+        const int64_t len = std::min(ck, nsteps - g * ck);
+        // recompute the segment's step-start states from its checkpoint
+        HIP_TRY(hipMemcpyAsync(seg, ckpt + g * vec, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(mn_sim, seg, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+        for (int64_t n = 1; n < len; ++n) {
+            mm_status r = rk4_step<T>(s, dt, st);
+            if (r != MM_OK) return r;
+            HIP_TRY(hipMemcpyAsync(seg + n * vec, mn_sim, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+        }
+        for (int64_t n = len - 1; n >= 0; --n) {
+            T* mn = seg + n * vec;
+            ms_of[0] = mn;
+            // stage inputs m_s and fields h_s of this step
+            la.mn = mn;
+            la.acc = scr;
+            for (int stg = 0; stg < 4; ++stg) {
+                la.ms = ms_of[stg];
+                if (with_demag) {
+                    mm_status r = demag<T>(s, ms_of[stg], hd, st);
+                    if (r != MM_OK) return r;
+                }
+                HIP_TRY(launch_field_term<T>(la, 4, (T)1, hs_of[stg], st));
+                if (stg < 3) {
+                    la.out = ms_of[stg + 1];
+                    la.stage = stg + 1;
+                    HIP_TRY(launch_llg_stage<T>(la, st));
+                }
+            }
+            // reverse: renormalisation, then stages 4..1
+            aa.mn = mn;
+            HIP_TRY(launch_adj_renorm<T>(aa, st));
+            const T cmu[4] = {(T)0, (T)(1.0 / 6.0), (T)(2.0 / 6.0), (T)(2.0 / 6.0)};
+            const T ca[4] = {(T)0, (T)0.5, (T)0.5, (T)1};
+            for (int stg = 3; stg >= 0; --stg) {
+                HIP_TRY(launch_adj_nu<T>(aa, ms_of[stg], hs_of[stg], st));
+                if (with_demag) {
+                    mm_status r = demag<T>(s, nu, hd, st);
+                    if (r != MM_OK) return r;
+                }
+                HIP_TRY(launch_adj_apply<T>(aa, cmu[stg], ca[stg], st));
+            }
+            std::swap(lam, accl);
+            aa.lam = lam;
+            aa.accl = accl;
+        }
+    }
+    if (dm0) HIP_TRY(hipMemcpyAsync(dm0, lam, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(mn_sim, msave, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return MM_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -936,6 +1069,45 @@ mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, voi
         return fail(MM_ENOTSUP, "tensor table too large");
     HIP_TRY(launch_tensor_table(d_out, nx, ny, nz, as_stream(stream)));
     return MM_OK;
+}
+
+mm_status mm_rollout(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, void* d_ckpt)
+{
+    if (!s || !d_ckpt) return fail(MM_EINVAL, "sim or checkpoint buffer is NULL");
+    if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!s->has_m) return fail(MM_ESTATE, "mm_rollout before mm_set_m");
+    return s->p.prec == MM_F32 ? rollout_impl<float>(s, nsteps, dt, ckpt_every, (float*)d_ckpt)
+                               : rollout_impl<double>(s, nsteps, dt, ckpt_every, (double*)d_ckpt);
+}
+
+mm_status mm_adjoint_workspace_query(mm_sim* s, int64_t ckpt_every, size_t* bytes)
+{
+    if (!s || !bytes) return fail(MM_EINVAL, "sim or bytes is NULL");
+    if (ckpt_every < 1) return fail(MM_EINVAL, "ckpt_every must be >= 1");
+    *bytes = adj_bytes(s->p, ckpt_every);
+    return MM_OK;
+}
+
+mm_status mm_backward(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, const void* d_ckpt,
+                      const void* d_lam_final, double* d_dku, void* d_dm0, void* d_adj_ws,
+                      size_t adj_ws_bytes)
+{
+    if (!s || !d_ckpt || !d_lam_final || !d_dku || !d_adj_ws)
+        return fail(MM_EINVAL, "NULL argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!s->has_m) return fail(MM_ESTATE, "mm_backward before mm_set_m");
+    if (adj_ws_bytes < adj_bytes(s->p, ckpt_every))
+        return fail(MM_EINVAL, "adjoint workspace of %zu bytes is smaller than the %zu needed", adj_ws_bytes,
+                    adj_bytes(s->p, ckpt_every));
+    if (reinterpret_cast<uintptr_t>(d_adj_ws) & 255) return fail(MM_EINVAL, "adjoint workspace must be 256-byte aligned");
+    return s->p.prec == MM_F32
+               ? backward_impl<float>(s, nsteps, dt, ckpt_every, (const float*)d_ckpt,
+                                      (const float*)d_lam_final, d_dku, (float*)d_dm0, (char*)d_adj_ws)
+               : backward_impl<double>(s, nsteps, dt, ckpt_every, (const double*)d_ckpt,
+                                       (const double*)d_lam_final, d_dku, (double*)d_dm0,
+                                       (char*)d_adj_ws);
 }
 
 mm_status mm_profile_begin(mm_sim* s, int32_t kernel)

@@ -190,6 +190,28 @@ hipError_t launch_reduce(const LlgArgs<T>& a, double* partial, int nblocks, doub
                          hipStream_t s);
 int reduce_blocks(int64_t N);
 
+// ---------------------------------------------------------------- adjoint
+template <typename T>
+struct AdjArgs {
+    int nx, ny, nz;
+    int64_t N;
+    const T *mn, *m2, *m3, *m4;  // stage inputs of the step
+    const T *h1, *h2, *h3, *h4;  // their reduced effective fields
+    const T* lam;                // dLoss/dm at the end of the step
+    T *mu, *dF, *accl, *nu, *loc;
+    const T* hd;                 // reduced demag field of nu
+    const T* ku;                 // reduced anisotropy map or nullptr
+    T can, cex, G, alpha;        // G = gamma Ms dt / (1 + alpha^2)
+    double* dku;                 // dLoss/dKu accumulator (FP64) or nullptr
+    double kfac;                 // 2 / (mu0 Ms^2)
+};
+template <typename T>
+hipError_t launch_adj_renorm(const AdjArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_nu(const AdjArgs<T>& a, const T* ms, const T* hs, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_apply(const AdjArgs<T>& a, T cmu, T ca, hipStream_t s);
+
 // m <- m / |m| per cell; counts zero-norm or non-finite cells into *bad.
 template <typename T>
 hipError_t launch_normalize(T* m, int64_t N, unsigned int* bad, hipStream_t s);

@@ -1,0 +1,149 @@
+"""GPU adjoint (hand-written VJPs of the RK4 step with renormalisation) against
+the oracle's plain FP64 adjoint and against finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import DIFF, ku_map, mT_to_Apm, random_unit_m, vortex_target
+from tests.gpu_util import rel_max, to_np
+
+pytestmark = pytest.mark.gpu
+
+mmag = pytest.importorskip("paper_1501_07293_amd")
+
+
+def make(pb, precision):
+    return mmag.Sim(pb.nx, pb.ny, pb.nz, pb.cell, Ms=pb.Ms, A=pb.A, Ku=0.0, alpha=pb.alpha,
+                    gamma=pb.gamma, precision=precision)
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 1), (5, 4, 2), (9, 7, 3)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_matches_oracle_adjoint(dims, precision):
+    g = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    ku = 500.0 + 50.0 * g.standard_normal((nz, ny, nx))
+    hext = mT_to_Apm([6.0, -2.0, 4.0])
+    pb = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.1, ku_map=ku, hext=tuple(hext))
+    m0 = random_unit_m(pb.shape, 3)
+    w = g.standard_normal(pb.shape)
+    dt, nsteps, ck = 1e-13, 12, 5      # segments of 5, 5 and 2 steps
+    sim = make(pb, precision)
+    sim.set_hext(hext)
+    sim.set_ku_map(ku)
+    sim.set_m(m0)
+    m_used = to_np(sim.get_m())
+    ckpt = sim.rollout_ckpt(nsteps, dt, ck)
+    m_end = to_np(sim.get_m())
+    import torch
+    lam = torch.tensor(w, dtype=sim.dtype, device=sim.device)
+    dku, dm0 = sim.backward(nsteps, dt, ck, ckpt, lam)
+    # the handle's state is preserved by the reverse sweep
+    assert np.array_equal(to_np(sim.get_m()), m_end)
+    ref_ku, ref_m0 = oracle.rk4_adjoint(pb, m_used, dt, nsteps, w)
+    tol = 1e-9 if precision == "f64" else 1e-4
+    assert rel_max(to_np(dku), ref_ku) <= tol
+    assert rel_max(to_np(dm0), ref_m0) <= tol
+
+
+def diff_problem():
+    c = DIFF
+    ku = ku_map(c, seed=1)
+    m0 = random_unit_m(c.shape, seed=2)
+    target = vortex_target(c, seed=3)
+    return c, ku, m0, target
+
+
+def loss_fp64(c, ku, m0, target, nsteps):
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                   precision="f64")
+    sim.set_ku_map(ku)
+    sim.set_m(m0)
+    sim.step(nsteps, c.dt)
+    m = to_np(sim.get_m())
+    return float(((m - target) ** 2).sum(axis=0).mean())
+
+
+def adjoint_grad(c, ku, m0, target, nsteps, precision, ck=50):
+    import torch
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                   precision=precision)
+    ku_t = torch.tensor(ku, dtype=sim.dtype, device=sim.device, requires_grad=True)
+    m0_t = torch.tensor(m0, dtype=sim.dtype, device=sim.device, requires_grad=True)
+    tgt = torch.tensor(target, dtype=sim.dtype, device=sim.device)
+    m_final = mmag.rollout(sim, ku_t, m0_t, nsteps, c.dt, ck)
+    loss = ((m_final - tgt) ** 2).sum(dim=0).mean()
+    loss.backward()
+    return to_np(ku_t.grad)
+
+
+def fd_richardson(c, ku, m0, target, nsteps, v, eps=2.0):
+    """Central differences at eps and eps/2 of the FP64 GPU forward, Richardson-
+    extrapolated (error O(eps^4))."""
+    d1 = (loss_fp64(c, ku + eps * v, m0, target, nsteps)
+          - loss_fp64(c, ku - eps * v, m0, target, nsteps)) / (2 * eps)
+    e2 = eps / 2
+    d2 = (loss_fp64(c, ku + e2 * v, m0, target, nsteps)
+          - loss_fp64(c, ku - e2 * v, m0, target, nsteps)) / (2 * e2)
+    return (4 * d2 - d1) / 3
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_matches_finite_differences_on_the_128x128_case(precision):
+    # 128x128x1, delta 5 nm, alpha 0.1, Ku map 500 + N(0, 50^2), loss = mean |m_N - m_target|^2
+    # after 500 RK4 steps of 1e-13 s, checkpoint every 50 steps.  Directional derivatives
+    # along seeded directions of the Ku map against central differences of the FP64 GPU
+    # forward (Richardson-extrapolated).
+    # FP64: |ad - fd| <= 1e-6 |fd| per direction.  FP32: the error is bounded against
+    # max(|fd|, rms projection), the rms of <grad, v> over unit-variance directions v,
+    # i.e. |grad|_2 |v|_2 / sqrt(N); FP32 rounding over 500 steps leaves ~1e-4 relative
+    # error in the gradient vector, which a projection that happens to be small inflates.
+    c, ku, m0, target = diff_problem()
+    nsteps = c.steps
+    gku = adjoint_grad(c, ku, m0, target, nsteps, precision)
+    g = np.random.default_rng(4)
+    for trial in range(3):
+        v = g.standard_normal(ku.shape)
+        fd = fd_richardson(c, ku, m0, target, nsteps, v)
+        ad = float((gku * v).sum())
+        rel = abs(ad - fd) / abs(fd)
+        rms = np.sqrt((gku ** 2).sum()) * np.sqrt((v ** 2).sum() / v.size)
+        rel_rms = abs(ad - fd) / max(abs(fd), rms)
+        print(f"{precision} direction {trial}: adjoint {ad:.9e}  fd {fd:.9e}  rel {rel:.2e}  "
+              f"rel-to-rms {rel_rms:.2e}")
+        if precision == "f64":
+            assert rel <= 1e-6
+        else:
+            assert rel_rms <= 1e-4
+
+
+def test_fp32_adjoint_tracks_fp64_adjoint():
+    c, ku, m0, target = diff_problem()
+    g32 = adjoint_grad(c, ku, m0, target, c.steps, "f32")
+    g64 = adjoint_grad(c, ku, m0, target, c.steps, "f64")
+    l2 = np.sqrt(((g32 - g64) ** 2).sum() / (g64 ** 2).sum())
+    mx = rel_max(g32, g64)
+    print(f"FP32 vs FP64 adjoint gradient: relative L2 {l2:.2e}, relative max {mx:.2e}")
+    assert l2 <= 1e-4 and mx <= 1e-3
+
+
+def test_rollout_autograd_matches_direct_backward():
+    import torch
+    c, ku, m0, target = diff_problem()
+    nsteps, ck = 60, 25
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                   precision="f32")
+    ku_t = torch.tensor(ku, dtype=torch.float32, device=sim.device, requires_grad=True)
+    m0_t = torch.tensor(m0, dtype=torch.float32, device=sim.device, requires_grad=True)
+    out = mmag.rollout(sim, ku_t, m0_t, nsteps, c.dt, ck)
+    w = torch.tensor(np.random.default_rng(5).standard_normal(out.shape), dtype=torch.float32,
+                     device=sim.device)
+    (out * w).sum().backward()
+    sim2 = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                    precision="f32")
+    sim2.set_ku_map(ku)
+    sim2.set_m(m0)
+    ckpt = sim2.rollout_ckpt(nsteps, c.dt, ck)
+    dku, dm0 = sim2.backward(nsteps, c.dt, ck, ckpt, w)
+    assert np.array_equal(to_np(ku_t.grad), to_np(dku.float()))
+    assert np.array_equal(to_np(m0_t.grad), to_np(dm0))
