@@ -153,6 +153,28 @@ mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
  * component order xx, xy, xz, yy, yz, zz, offset index (K+nz-1, J+ny-1, I+nx-1). */
 mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream);
 
+/* ---- batched form --------------------------------------------------------
+ * n independent grids of uneven sizes (each its own padding and applied
+ * field; one material and precision) advanced together: every pass of a field
+ * evaluation and every LLG stage is one kernel launch over all grids, and with
+ * MM_USE_GRAPH mm_batch_step replays captured RK4 steps.  m arrays are the
+ * concatenation, grid by grid, of [3][nz][ny][nx] blocks.  Sizes must fit the
+ * 256-thread FFT work-group (padded lengths up to 4096, last axis up to 1365).
+ * hext: [n][3] applied fields in A/m (NULL = zero).  Ownership, streams and
+ * errors as for the single-grid handle. */
+typedef struct mm_batch mm_batch;
+mm_status mm_batch_workspace_query(int32_t n, const mm_grid* grids, const mm_options* opt,
+                                   size_t* bytes);
+mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* mat,
+                          const double* hext, const mm_options* opt, void* d_workspace,
+                          size_t ws_bytes, void* stream, mm_batch** out);
+mm_status mm_batch_destroy(mm_batch* b);
+mm_status mm_batch_set_stream(mm_batch* b, void* stream);
+mm_status mm_batch_set_m(mm_batch* b, const void* m, int on_device);
+mm_status mm_batch_get_m(mm_batch* b, void* out, int on_device);
+mm_status mm_batch_step(mm_batch* b, int64_t nsteps, double dt);
+mm_status mm_batch_cells(mm_batch* b, int64_t* total_cells);
+
 /* ---- differentiation (adjoint) ------------------------------------------
  * Gradients of a loss of the final state of an RK4 rollout with respect to the
  * per-cell anisotropy map (set by mm_set_ku_map) and the initial state, by the

@@ -28,7 +28,9 @@ KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5
 EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
            "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_get_field",
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
-           "mm_demag_tensor", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
+           "mm_demag_tensor", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
+           "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
+           "mm_batch_cells", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
            "mm_profile_begin", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
@@ -91,6 +93,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_get_plan": [vp, ctypes.POINTER(PlanInfo)],
         "mm_get_kernel_spectrum": [vp, vp, ctypes.c_int],
         "mm_demag_tensor": [i32, i32, i32, vp, vp],
+        "mm_batch_workspace_query": [i32, ctypes.POINTER(Grid), ctypes.POINTER(Options),
+                                     ctypes.POINTER(ctypes.c_size_t)],
+        "mm_batch_create": [i32, ctypes.POINTER(Grid), ctypes.POINTER(Material), ctypes.POINTER(dbl),
+                            ctypes.POINTER(Options), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+        "mm_batch_destroy": [vp],
+        "mm_batch_set_stream": [vp, vp],
+        "mm_batch_set_m": [vp, vp, ctypes.c_int],
+        "mm_batch_get_m": [vp, vp, ctypes.c_int],
+        "mm_batch_step": [vp, i64, dbl],
+        "mm_batch_cells": [vp, ctypes.POINTER(i64)],
         "mm_rollout": [vp, i64, dbl, i64, vp],
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
@@ -280,6 +292,92 @@ class Sim:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSim:
+    """Many independent grids (uneven sizes, one material) advanced together:
+    one kernel launch per pass over all grids (handle around mm_batch_*)."""
+
+    def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
+                 A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
+                 hext=None, precision: str = "f32", demag: bool = True, graph: bool = False,
+                 device: str = "cuda:0"):
+        torch = _torch()
+        lib = load_library()
+        self._torch, self._lib = torch, lib
+        self.device = torch.device(device)
+        self.n = len(grids)
+        self.shapes = [(3, int(g[2]), int(g[1]), int(g[0])) for g in grids]
+        self.sizes = [3 * g[0] * g[1] * g[2] for g in grids]
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        garr = (Grid * self.n)(*[Grid(int(g[0]), int(g[1]), int(g[2]), cell) for g in grids])
+        self._grids = garr
+        self._mat = Material(Ms, A, Ku, alpha, gamma)
+        flags = (0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+        self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0)
+        h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
+        self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
+        nbytes = ctypes.c_size_t()
+        _check(lib.mm_batch_workspace_query(self.n, garr, ctypes.byref(self._opt), ctypes.byref(nbytes)),
+               "mm_batch_workspace_query")
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            hdl = ctypes.c_void_p()
+            _check(lib.mm_batch_create(self.n, garr, ctypes.byref(self._mat), self._hext,
+                                       ctypes.byref(self._opt), self.workspace.data_ptr(), nbytes.value,
+                                       _stream_ptr(torch, self.device), ctypes.byref(hdl)),
+                   "mm_batch_create")
+        self._h = hdl
+        c = ctypes.c_int64()
+        _check(lib.mm_batch_cells(self._h, ctypes.byref(c)), "mm_batch_cells")
+        self.cells = c.value
+
+    def _sync_stream(self):
+        _check(self._lib.mm_batch_set_stream(self._h, _stream_ptr(self._torch, self.device)),
+               "mm_batch_set_stream")
+
+    def set_m(self, ms):
+        """ms: list of per-grid (3, nz, ny, nx) arrays (or one flat array)."""
+        torch = self._torch
+        if isinstance(ms, (list, tuple)):
+            flat = np.concatenate([np.asarray(m, dtype=np.float64).reshape(-1) for m in ms])
+            t = torch.from_numpy(flat)
+        else:
+            t = ms if isinstance(ms, torch.Tensor) else torch.from_numpy(np.asarray(ms))
+        t = t.to(device=self.device, dtype=self.dtype).contiguous().reshape(-1)
+        assert t.numel() == sum(self.sizes)
+        self._sync_stream()
+        _check(self._lib.mm_batch_set_m(self._h, t.data_ptr(), 1), "mm_batch_set_m")
+
+    def get_m_flat(self):
+        out = self._torch.empty(sum(self.sizes), dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_batch_get_m(self._h, out.data_ptr(), 1), "mm_batch_get_m")
+        return out
+
+    def get_m(self):
+        flat = self.get_m_flat()
+        out, off = [], 0
+        for shp, sz in zip(self.shapes, self.sizes):
+            out.append(flat[off:off + sz].reshape(shp))
+            off += sz
+        return out
+
+    def step(self, nsteps: int, dt: float):
+        self._sync_stream()
+        _check(self._lib.mm_batch_step(self._h, int(nsteps), float(dt)), "mm_batch_step")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

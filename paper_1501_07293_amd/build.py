@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmag.so")
 SOURCES = ["mm_api.hip", "mm_passes.hip", "mm_fast.hip", "mm_tensor.hip", "mm_llg.hip",
-           "mm_adjoint.hip"]
+           "mm_adjoint.hip", "mm_batch.hip"]
 ARCH = os.environ.get("MMAG_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

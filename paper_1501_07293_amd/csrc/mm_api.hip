@@ -821,6 +821,245 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
     return MM_OK;
 }
 
+// ---------------------------------------------------------------- batched
+struct BatchLayout {
+    std::vector<Plan> plans;
+    std::vector<BatchDesc> desc;
+    std::vector<int> prefix[5];   // x forward, y, k-space, x inverse, LLG
+    int64_t vec_elems = 0, S_elems = 0, kern_elems = 0, tw_elems = 0, cells = 0;
+    size_t scratch = 0;
+    size_t o_desc, o_prefix, o_mn, o_ma, o_mb, o_acc, o_hd, o_S, o_kern, o_tw, o_flags, o_scratch, total;
+    int prec;
+    size_t esz;
+};
+
+mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, BatchLayout* L)
+{
+    if (n < 1) return fail(MM_EINVAL, "batch needs at least one grid");
+    if (!grids) return fail(MM_EINVAL, "grids is NULL");
+    mm_options o = opt ? *opt : mm_options{};
+    o.threads = 256;
+    L->plans.resize(n);
+    L->desc.resize(n);
+    for (int q = 0; q < 5; ++q) L->prefix[q].assign(n + 1, 0);
+    for (int s = 0; s < n; ++s) {
+        Plan& p = L->plans[s];
+        mm_status st = build_plan(&grids[s], &o, &p);
+        if (st != MM_OK) {
+            std::string keep = g_err;
+            return fail(st, "grid %d: %s", s, keep.c_str());
+        }
+        const int cap = kElemsPerThread * 256, ldscap = cap + 64;
+        BatchDesc& d = L->desc[s];
+        memset(&d, 0, sizeof d);
+        d.nx = p.nx;
+        d.ny = p.ny;
+        d.nz = p.nz;
+        d.Px = p.Px;
+        d.Py = p.Py;
+        d.Pz = p.Pz;
+        d.hx = p.hx;
+        d.Sy = (int)p.S_rows;
+        d.three_d = p.three_d ? 1 : 0;
+        d.x_lines = p.x_lines;
+        d.y_lines = std::min(cap / p.Py, ldscap / (p.Py + 1));
+        d.k_tw = p.k_tw;
+        d.moff = L->vec_elems;
+        d.soff = L->S_elems;
+        d.koff = L->kern_elems;
+        d.oct = p.oct_elems;
+        d.twx = L->tw_elems;
+        d.twy = d.twx + p.Px;
+        d.twz = d.twy + p.Py;
+        d.fx = p.fx;
+        d.fy = p.fy;
+        d.fz = p.fz;
+        L->vec_elems += 3 * p.N;
+        L->S_elems += 3 * (int64_t)p.nz * p.hx * p.S_rows;
+        L->kern_elems += (int64_t)p.ncomp * p.oct_elems;
+        L->tw_elems += p.Px + p.Py + p.Pz;
+        L->cells += p.N;
+        L->scratch = std::max(L->scratch, p.total);
+        const int npairs = (3 * p.nz * p.ny + 1) / 2;
+        const int tiles[5] = {
+            (npairs + p.x_lines - 1) / p.x_lines,
+            p.three_d ? (3 * p.nz * p.hx + d.y_lines - 1) / d.y_lines : 0,
+            p.three_d ? (int)((p.hx * (int64_t)p.Py + p.k_tw - 1) / p.k_tw) : (p.hx + p.k_tw - 1) / p.k_tw,
+            (npairs + p.x_lines - 1) / p.x_lines,
+            (int)((p.nx * (int64_t)p.ny * ((p.nz + kLlgZ - 1) / kLlgZ) + 255) / 256)};
+        for (int q = 0; q < 5; ++q) L->prefix[q][s + 1] = L->prefix[q][s] + tiles[q];
+    }
+    L->prec = o.prec;
+    L->esz = o.prec == MM_F32 ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const size_t vec = (size_t)L->vec_elems * L->esz;
+    L->o_desc = take(n * sizeof(BatchDesc));
+    L->o_prefix = take(5 * (size_t)(n + 1) * sizeof(int));
+    L->o_mn = take(vec);
+    L->o_ma = take(vec);
+    L->o_mb = take(vec);
+    L->o_acc = take(vec);
+    L->o_hd = take(vec);
+    L->o_S = take((size_t)L->S_elems * 2 * L->esz);
+    L->o_kern = take((size_t)L->kern_elems * L->esz);
+    L->o_tw = take((size_t)L->tw_elems * 2 * L->esz);
+    L->o_flags = take(64);
+    L->o_scratch = take(L->scratch);
+    L->total = off;
+    return MM_OK;
+}
+
+}  // namespace
+
+struct mm_batch {
+    BatchLayout L;
+    int n;
+    mm_material mat;
+    uint32_t flags;
+    char* ws;
+    bool own_ws;
+    hipStream_t stream, cap_stream;
+    bool has_m;
+    double alpha;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_valid;
+    double graph_dt;
+    int graph_chunk;
+    template <typename U>
+    U* at(size_t off) const { return reinterpret_cast<U*>(ws + off); }
+};
+
+namespace {
+
+template <typename T>
+mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
+{
+    const BatchLayout& L = b->L;
+    T* mn = b->at<T>(L.o_mn);
+    T* ma = b->at<T>(L.o_ma);
+    T* mb = b->at<T>(L.o_mb);
+    T* acc = b->at<T>(L.o_acc);
+    T* hd = b->at<T>(L.o_hd);
+    T* src[4] = {mn, ma, mb, ma};
+    T* dst[4] = {ma, mb, ma, mn};
+    const int* pre = b->at<int>(L.o_prefix);
+    const int n = b->n;
+    const bool with_demag = !(b->flags & MM_NO_DEMAG);
+    BatchPass<T> p{};
+    p.d = b->at<BatchDesc>(L.o_desc);
+    p.n = n;
+    p.S = b->at<cpx<T>>(L.o_S);
+    p.kern = b->at<T>(L.o_kern);
+    p.tw = b->at<cpx<T>>(L.o_tw);
+    p.out = hd;
+    BatchLlg<T> g{};
+    g.mn = mn;
+    g.acc = acc;
+    g.hd = with_demag ? hd : nullptr;
+    const double Ms = b->mat.Ms;
+    g.can = (T)(2.0 * b->mat.Ku / (kMu0 * Ms * Ms));
+    g.alpha = (T)b->alpha;
+    g.gdt = (T)(b->mat.gamma * Ms * dt / (1.0 + b->alpha * b->alpha));
+    for (int stg = 0; stg < 4; ++stg) {
+        if (with_demag) {
+            p.in = src[stg];
+            p.prefix = pre + 0 * (n + 1);
+            HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, nullptr, st));
+            p.prefix = pre + 1 * (n + 1);
+            HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 0, nullptr, st));
+            p.prefix = pre + 2 * (n + 1);
+            HIP_TRY(launch_batch_pass<T>(2, p, L.prefix[2][n], 0, nullptr, st));
+            p.prefix = pre + 1 * (n + 1);
+            HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 1, nullptr, st));
+            p.prefix = pre + 3 * (n + 1);
+            HIP_TRY(launch_batch_pass<T>(3, p, L.prefix[3][n], 0, nullptr, st));
+        }
+        g.ms = src[stg];
+        g.out = dst[stg];
+        g.stage = stg + 1;
+        p.prefix = pre + 4 * (n + 1);
+        HIP_TRY(launch_batch_pass<T>(4, p, L.prefix[4][n], 0, &g, st));
+    }
+    return MM_OK;
+}
+
+void batch_drop_graph(mm_batch* b)
+{
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
+template <typename T>
+mm_status batch_step_impl(mm_batch* b, int64_t nsteps, double dt)
+{
+    hipStream_t st = b->stream;
+    if (!(b->flags & MM_USE_GRAPH)) {
+        for (int64_t q = 0; q < nsteps; ++q) {
+            mm_status r = batch_rk4_step<T>(b, dt, st);
+            if (r != MM_OK) return r;
+        }
+        return MM_OK;
+    }
+    const int chunk = 8;
+    if (!b->graph_valid || b->graph_dt != dt) {
+        batch_drop_graph(b);
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = MM_OK;
+        for (int q = 0; q < chunk && r == MM_OK; ++q) r = batch_rk4_step<T>(b, dt, b->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (r != MM_OK) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+        b->graph_valid = true;
+        b->graph_dt = dt;
+        b->graph_chunk = chunk;
+    }
+    int64_t q = 0;
+    for (; q + b->graph_chunk <= nsteps; q += b->graph_chunk) HIP_TRY(hipGraphLaunch(b->gexec, st));
+    for (; q < nsteps; ++q) {
+        mm_status r = batch_rk4_step<T>(b, dt, st);
+        if (r != MM_OK) return r;
+    }
+    return MM_OK;
+}
+
+template <typename T>
+mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
+{
+    const BatchLayout& L = b->L;
+    hipStream_t st = b->stream;
+    T* mn = b->at<T>(L.o_mn);
+    HIP_TRY(hipMemcpyAsync(mn, m, (size_t)L.vec_elems * sizeof(T),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    unsigned int* bad = reinterpret_cast<unsigned int*>(b->at<char>(L.o_flags));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned int), st));
+    for (int s = 0; s < b->n; ++s)
+        HIP_TRY(launch_normalize<T>(mn + L.desc[s].moff, L.plans[s].N, bad, st));
+    unsigned int nbad = 0;
+    HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nbad) {
+        b->has_m = false;
+        return fail(MM_EINVAL, "m has %u zero-length or non-finite cells", nbad);
+    }
+    b->has_m = true;
+    return MM_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1108,6 +1347,161 @@ mm_status mm_backward(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, 
                : backward_impl<double>(s, nsteps, dt, ckpt_every, (const double*)d_ckpt,
                                        (const double*)d_lam_final, d_dku, (double*)d_dm0,
                                        (char*)d_adj_ws);
+}
+
+mm_status mm_batch_workspace_query(int32_t n, const mm_grid* grids, const mm_options* opt,
+                                   size_t* bytes)
+{
+    if (!bytes) return fail(MM_EINVAL, "bytes is NULL");
+    BatchLayout L;
+    mm_status st = batch_layout(n, grids, opt, &L);
+    if (st != MM_OK) return st;
+    *bytes = L.total;
+    return MM_OK;
+}
+
+mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* mat,
+                          const double* hext, const mm_options* opt, void* d_workspace,
+                          size_t ws_bytes, void* stream, mm_batch** out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!check_material(mat))
+        return fail(MM_EINVAL, "material needs Ms > 0, A >= 0, alpha >= 0, gamma > 0, all finite");
+    BatchLayout L;
+    mm_status st = batch_layout(n, grids, opt, &L);
+    if (st != MM_OK) return st;
+    if (hext)
+        for (int q = 0; q < 3 * n; ++q)
+            if (!std::isfinite(hext[q])) return fail(MM_EINVAL, "applied fields must be finite");
+    if (d_workspace && ws_bytes < L.total)
+        return fail(MM_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+    if (d_workspace && (reinterpret_cast<uintptr_t>(d_workspace) & 255))
+        return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    mm_batch* b = new mm_batch();
+    b->n = n;
+    b->mat = *mat;
+    b->flags = opt ? opt->flags : 0;
+    b->stream = as_stream(stream);
+    b->alpha = mat->alpha;
+    const double Ms = mat->Ms;
+    for (int s = 0; s < n; ++s) {
+        BatchDesc& d = L.desc[s];
+        for (int a = 0; a < 3; ++a) d.hred[a] = hext ? hext[3 * s + a] / Ms : 0.0;
+        d.cex = 2.0 * mat->A / (kMu0 * Ms * Ms * grids[s].cell * grids[s].cell);
+    }
+    b->L = std::move(L);
+    const BatchLayout& BL = b->L;
+    auto bail = [&](mm_status e) {
+        std::string keep = g_err;
+        mm_batch_destroy(b);
+        g_err = keep;
+        return e;
+    };
+    if (d_workspace) {
+        b->ws = static_cast<char*>(d_workspace);
+    } else {
+        void* w = nullptr;
+        hipError_t e = hipMalloc(&w, BL.total);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(MM_ENOMEM, "hipMalloc(%zu): %s", BL.total, hipGetErrorString(e));
+        }
+        b->ws = static_cast<char*>(w);
+        b->own_ws = true;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(fail(MM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)));
+    hipStream_t hs = b->stream;
+    e = hipMemcpyAsync(b->at<char>(BL.o_desc), BL.desc.data(), n * sizeof(BatchDesc),
+                       hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return bail(fail(MM_EHIP, "descriptor upload: %s", hipGetErrorString(e)));
+    std::vector<int> pre(5 * (size_t)(n + 1));
+    for (int q = 0; q < 5; ++q)
+        for (int s = 0; s <= n; ++s) pre[q * (n + 1) + s] = BL.prefix[q][s];
+    e = hipMemcpyAsync(b->at<char>(BL.o_prefix), pre.data(), pre.size() * sizeof(int),
+                       hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return bail(fail(MM_EHIP, "prefix upload: %s", hipGetErrorString(e)));
+    // kernel spectra and twiddles: one single-grid setup per grid on the scratch region
+    mm_options o = opt ? *opt : mm_options{};
+    o.threads = 256;
+    o.flags &= ~(uint32_t)MM_USE_GRAPH;
+    for (int s = 0; s < n; ++s) {
+        const Plan& p = BL.plans[s];
+        const BatchDesc& d = BL.desc[s];
+        mm_sim* t = nullptr;
+        mm_status r = mm_create(&grids[s], mat, &o, b->at<char>(BL.o_scratch), BL.scratch, stream, &t);
+        if (r != MM_OK) return bail(r);
+        const size_t esz = BL.esz;
+        hipError_t ce = hipMemcpyAsync(b->at<char>(BL.o_kern) + d.koff * esz, t->at<char>(p.o_kern),
+                                       (size_t)p.ncomp * p.oct_elems * esz, hipMemcpyDeviceToDevice, hs);
+        const size_t cz = 2 * esz;
+        if (ce == hipSuccess)
+            ce = hipMemcpyAsync(b->at<char>(BL.o_tw) + d.twx * cz, t->at<char>(p.o_twx), p.Px * cz,
+                                hipMemcpyDeviceToDevice, hs);
+        if (ce == hipSuccess)
+            ce = hipMemcpyAsync(b->at<char>(BL.o_tw) + d.twy * cz, t->at<char>(p.o_twy), p.Py * cz,
+                                hipMemcpyDeviceToDevice, hs);
+        if (ce == hipSuccess)
+            ce = hipMemcpyAsync(b->at<char>(BL.o_tw) + d.twz * cz, t->at<char>(p.o_twz), p.Pz * cz,
+                                hipMemcpyDeviceToDevice, hs);
+        mm_destroy(t);  // waits for the stream, so the scratch is free for the next grid
+        if (ce != hipSuccess) return bail(fail(MM_EHIP, "spectrum copy: %s", hipGetErrorString(ce)));
+    }
+    *out = b;
+    return MM_OK;
+}
+
+mm_status mm_batch_destroy(mm_batch* b)
+{
+    if (!b) return MM_OK;
+    hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    if (b->own_ws) hipFree(b->ws);
+    delete b;
+    return MM_OK;
+}
+
+mm_status mm_batch_set_m(mm_batch* b, const void* m, int on_device)
+{
+    if (!b || !m) return fail(MM_EINVAL, "batch or m is NULL");
+    return b->L.prec == MM_F32 ? batch_set_m_impl<float>(b, m, on_device)
+                               : batch_set_m_impl<double>(b, m, on_device);
+}
+
+mm_status mm_batch_get_m(mm_batch* b, void* out, int on_device)
+{
+    if (!b || !out) return fail(MM_EINVAL, "batch or out is NULL");
+    if (!b->has_m) return fail(MM_ESTATE, "m has not been set");
+    HIP_TRY(hipMemcpyAsync(out, b->at<char>(b->L.o_mn), (size_t)b->L.vec_elems * b->L.esz,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));
+    return MM_OK;
+}
+
+mm_status mm_batch_step(mm_batch* b, int64_t nsteps, double dt)
+{
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!b->has_m) return fail(MM_ESTATE, "mm_batch_step before mm_batch_set_m");
+    return b->L.prec == MM_F32 ? batch_step_impl<float>(b, nsteps, dt) : batch_step_impl<double>(b, nsteps, dt);
+}
+
+mm_status mm_batch_set_stream(mm_batch* b, void* stream)
+{
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    b->stream = as_stream(stream);
+    return MM_OK;
+}
+
+mm_status mm_batch_cells(mm_batch* b, int64_t* total_cells)
+{
+    if (!b || !total_cells) return fail(MM_EINVAL, "NULL argument");
+    *total_cells = b->L.cells;
+    return MM_OK;
 }
 
 mm_status mm_profile_begin(mm_sim* s, int32_t kernel)

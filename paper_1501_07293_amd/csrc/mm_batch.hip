@@ -1,0 +1,184 @@
+// mm_batch.hip -- the batched form: many independent grids of uneven sizes
+// advanced together.  Every pass of a field evaluation (and the LLG stage) is
+// ONE kernel launch over all grids: the launch's tiles are the concatenation
+// of every grid's tiles, and a work-group finds its grid by binary search in
+// the per-pass tile prefix sums, then runs the same device body as the
+// single-grid runtime-radix kernels with that grid's descriptor.
+#include "mm_generic.hpp"
+#include "mm_llg_body.hpp"
+
+namespace mm {
+
+constexpr int kBatchNT = 256;
+
+__device__ inline int find_sample(const int* prefix, int n, int tile)
+{
+    int lo = 0, hi = n;  // prefix[lo] <= tile < prefix[hi]; empty grids are skipped
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchNT) void kb_xfwd(BatchPass<T> p)
+{
+    __shared__ cpx<T> lds[lds_elems(kBatchNT)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int s = find_sample(p.prefix, p.n, tile);
+    const BatchDesc& d = p.d[s];
+    RowR2CArgs a{};
+    a.in = p.in + d.moff;
+    a.in_row_stride = d.nx;
+    a.nrows = 3 * d.nz * d.ny;
+    a.nvalid = d.nx;
+    a.out = p.S + d.soff;
+    a.rows_per_plane = d.ny;
+    a.out_plane_stride = (int64_t)d.hx * d.Sy;
+    a.rstride = 1;
+    a.kstride = d.Sy;
+    a.hx = d.hx;
+    a.lines_per_wg = d.x_lines;
+    a.tw = p.tw + d.twx;
+    body_row_r2c<T, kBatchNT>(a, d.fx, tile - p.prefix[s], lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchNT) void kb_y(BatchPass<T> p, int inverse)
+{
+    __shared__ cpx<T> lds[lds_elems(kBatchNT)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int s = find_sample(p.prefix, p.n, tile);
+    const BatchDesc& d = p.d[s];
+    LineArgs a{};
+    a.buf = p.S + d.soff;
+    a.nlines = 3 * d.nz * d.hx;
+    a.line_stride = d.Sy;
+    a.nin = inverse ? d.Py : d.ny;
+    a.nout = inverse ? d.ny : d.Py;
+    a.inverse = inverse;
+    a.lines_per_wg = d.y_lines;
+    a.tw = p.tw + d.twy;
+    body_line_c2c<T, kBatchNT>(a, d.fy, tile - p.prefix[s], lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchNT) void kb_kspace(BatchPass<T> p)
+{
+    __shared__ cpx<T> lds[lds_elems(kBatchNT)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int s = find_sample(p.prefix, p.n, tile);
+    const BatchDesc& d = p.d[s];
+    const int64_t plane = (int64_t)d.hx * d.Sy;
+    KspArgs a{};
+    a.buf = p.S + d.soff;
+    a.kern = p.kern + d.koff;
+    a.hx = d.hx;
+    a.Py = d.Py;
+    a.Pz = d.Pz;
+    a.k_cs = d.oct;
+    a.k_zs = (int64_t)d.hx * (d.Py / 2 + 1);
+    a.k_xs = d.Py / 2 + 1;
+    a.tw_cols = d.k_tw;
+    if (d.three_d) {
+        a.ncomp = 6;
+        a.comp_stride = (int64_t)d.nz * plane;
+        a.ncols = (int)plane;
+        a.cols_per_row = (int)plane;
+        a.row2_stride = 0;
+        a.es = plane;
+        a.nvalid = d.nz;
+        a.axis_is_z = 1;
+        a.tw = p.tw + d.twz;
+        body_kspace<T, kBatchNT>(a, d.fz, tile - p.prefix[s], lds);
+    } else {
+        a.ncomp = 4;
+        a.comp_stride = plane;
+        a.ncols = d.hx;
+        a.cols_per_row = 1;
+        a.row2_stride = d.Sy;
+        a.es = 1;
+        a.nvalid = d.ny;
+        a.axis_is_z = 0;
+        a.tw = p.tw + d.twy;
+        body_kspace<T, kBatchNT>(a, d.fy, tile - p.prefix[s], lds);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchNT) void kb_xinv(BatchPass<T> p)
+{
+    __shared__ cpx<T> lds[lds_elems(kBatchNT)];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int s = find_sample(p.prefix, p.n, tile);
+    const BatchDesc& d = p.d[s];
+    RowC2RArgs a{};
+    a.in = p.S + d.soff;
+    a.rows_per_plane = d.ny;
+    a.in_plane_stride = (int64_t)d.hx * d.Sy;
+    a.rstride = 1;
+    a.kstride = d.Sy;
+    a.hx = d.hx;
+    a.nrows = 3 * d.nz * d.ny;
+    a.out = p.out + d.moff;
+    a.out_row_stride = d.nx;
+    a.nvalid = d.nx;
+    a.lines_per_wg = d.x_lines;
+    a.tw = p.tw + d.twx;
+    body_row_c2r<T, kBatchNT>(a, d.fx, tile - p.prefix[s], lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int s = find_sample(p.prefix, p.n, tile);
+    const BatchDesc& d = p.d[s];
+    LlgArgs<T> a{};
+    a.ms = g.ms + d.moff;
+    a.mn = g.mn + d.moff;
+    a.acc = g.acc + d.moff;
+    a.out = g.out + d.moff;
+    a.hd = g.hd ? g.hd + d.moff : nullptr;
+    a.ku = nullptr;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.N = (int64_t)d.nx * d.ny * d.nz;
+    a.cex = (T)d.cex;
+    a.can = g.can;
+    a.hx = (T)d.hred[0];
+    a.hy = (T)d.hred[1];
+    a.hz = (T)d.hred[2];
+    a.alpha = g.alpha;
+    a.gdt = g.gdt;
+    a.stage = g.stage;
+    body_llg_stage<T>(a, (int64_t)(tile - p.prefix[s]) * kBatchNT + threadIdx.x);
+}
+
+template <typename T>
+hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,
+                             const BatchLlg<T>* g, hipStream_t s)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    const dim3 grid(total_tiles), block(kBatchNT);
+    switch (which) {
+    case 0: hipLaunchKernelGGL(kb_xfwd<T>, grid, block, 0, s, p); break;
+    case 1: hipLaunchKernelGGL(kb_y<T>, grid, block, 0, s, p, inverse); break;
+    case 2: hipLaunchKernelGGL(kb_kspace<T>, grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(kb_xinv<T>, grid, block, 0, s, p); break;
+    default: hipLaunchKernelGGL(kb_llg<T>, grid, block, 0, s, p, *g); break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_pass<float>(int, const BatchPass<float>&, int, int,
+                                             const BatchLlg<float>*, hipStream_t);
+template hipError_t launch_batch_pass<double>(int, const BatchPass<double>&, int, int,
+                                              const BatchLlg<double>*, hipStream_t);
+
+}  // namespace mm

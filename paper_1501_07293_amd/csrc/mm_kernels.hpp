@@ -63,6 +63,18 @@ struct ColArgs {
     const void* tw;
 };
 
+// Complex FFT of contiguous lines (line l at buf + l * line_stride), in place.
+struct LineArgs {
+    void* buf;
+    int nlines;
+    int64_t line_stride;
+    int nin, nout;
+    int inverse;
+    int lines_per_wg;
+    FftPlan pl;
+    const void* tw;
+};
+
 // k-space pass on the last non-trivial axis: forward FFT of the three
 // components of a column set, the symmetric tensor product of Eq. 14 with the
 // real kernel spectrum, inverse FFT, keep the first nvalid outputs.
@@ -174,6 +186,8 @@ struct LlgArgs {
     T gdt;           // gamma Ms dt / (1 + alpha^2)
     int stage;       // 1..4
 };
+// the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes
+constexpr int kLlgZ = 4;
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s);
 
@@ -211,6 +225,46 @@ template <typename T>
 hipError_t launch_adj_nu(const AdjArgs<T>& a, const T* ms, const T* hs, hipStream_t s);
 template <typename T>
 hipError_t launch_adj_apply(const AdjArgs<T>& a, T cmu, T ca, hipStream_t s);
+
+// ---------------------------------------------------------------- batched
+// One grid of a batch (device-resident descriptor).  Offsets count elements
+// of the batch arrays: moff in the [3][N] vector arrays, soff in the complex
+// spectrum, koff in the real kernel octants, twx/twy/twz in the complex
+// twiddle tables.
+struct BatchDesc {
+    int nx, ny, nz, Px, Py, Pz, hx, Sy, three_d;
+    int x_lines, y_lines, k_tw;
+    int64_t moff, soff, koff, oct;
+    int64_t twx, twy, twz;
+    double hred[3];   // H_ext / Ms
+    double cex;       // 2 A / (mu0 Ms^2 delta^2) of this grid
+    FftPlan fx, fy, fz;
+};
+template <typename T>
+struct BatchPass {
+    const BatchDesc* d;
+    int n;
+    const int* prefix;   // n + 1 tile prefix sums of this pass
+    const T* in;         // x forward: the stage input m
+    T* out;              // x inverse: the demag field
+    cpx<T>* S;
+    const T* kern;
+    const cpx<T>* tw;
+};
+template <typename T>
+struct BatchLlg {
+    const T* ms;
+    const T* mn;
+    T* acc;
+    T* out;
+    const T* hd;
+    T can, alpha, gdt;
+    int stage;
+};
+// which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse, 4 LLG stage.
+template <typename T>
+hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,
+                             const BatchLlg<T>* g, hipStream_t s);
 
 // m <- m / |m| per cell; counts zero-norm or non-finite cells into *bad.
 template <typename T>

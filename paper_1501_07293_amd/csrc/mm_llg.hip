@@ -15,6 +15,7 @@
 //   stage 4: m_n <- normalise(m_n + (acc + F4) / 6)   (the per-step renormalisation)
 #include "mm_common.hpp"
 #include "mm_kernels.hpp"
+#include "mm_llg_body.hpp"
 
 namespace mm {
 
@@ -58,99 +59,10 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
     }
 }
 
-// One thread per (x, y) column and chunk of kLlgZ planes.  Every load of the
-// chunk (m of planes k0-1 .. k0+kLlgZ, in-plane neighbours, H_d, Ku, m_n, acc)
-// is issued before the first store, so a thread keeps many loads in flight;
-// the z neighbours come from registers, the x and y neighbours from rows that
-// neighbouring threads load anyway (L1/L2 hits).
-constexpr int kLlgZ = 4;
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
 {
-    constexpr int KZ = kLlgZ;
-    const int64_t plane = (int64_t)a.nx * a.ny;
-    const int nzc = (a.nz + KZ - 1) / KZ;
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= plane * nzc) return;
-    const int kc = (int)(t / plane);
-    const int64_t pc = t - (int64_t)kc * plane;
-    const int i = (int)(pc % a.nx), j = (int)(pc / a.nx);
-    const int k0 = kc * KZ;
-    const int64_t N = a.N, sy = a.nx;
-    const T* __restrict__ ms = a.ms;
-    T col[KZ + 2][3];
-#pragma unroll
-    for (int q = 0; q < KZ + 2; ++q) {
-        const int k = k0 - 1 + q;
-        const bool in = k >= 0 && k < a.nz;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) col[q][d] = in ? ms[d * N + pc + k * plane] : (T)0;
-    }
-    T lap[KZ][3], hd[KZ][3], mn[KZ][3], ac[KZ][3], kan[KZ];
-#pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        const int k = k0 + q;
-        const bool in = k < a.nz;
-        const int64_t c = pc + (int64_t)(in ? k : 0) * plane;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T* u = ms + d * N;
-            const T mc = col[q + 1][d];
-            T acc = (T)0;
-            if (in) {
-                if (i > 0) acc += u[c - 1] - mc;
-                if (i < a.nx - 1) acc += u[c + 1] - mc;
-                if (j > 0) acc += u[c - sy] - mc;
-                if (j < a.ny - 1) acc += u[c + sy] - mc;
-                if (k > 0) acc += col[q][d] - mc;
-                if (k < a.nz - 1) acc += col[q + 2][d] - mc;
-            }
-            lap[q][d] = acc;
-            hd[q][d] = (in && a.hd) ? a.hd[d * N + c] : (T)0;
-            mn[q][d] = (in && a.stage > 1) ? a.mn[d * N + c] : (T)0;
-            ac[q][d] = (in && a.stage > 1) ? a.acc[d * N + c] : (T)0;
-        }
-        kan[q] = (in && a.ku) ? a.ku[c] : a.can;
-    }
-#pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        const int k = k0 + q;
-        if (k >= a.nz) break;
-        const int64_t c = pc + (int64_t)k * plane;
-        const T* m = col[q + 1];
-        const T h[3] = {a.cex * lap[q][0] + kan[q] * m[0] + a.hx + hd[q][0],
-                        a.cex * lap[q][1] + a.hy + hd[q][1], a.cex * lap[q][2] + a.hz + hd[q][2]};
-        const T tx = m[1] * h[2] - m[2] * h[1];
-        const T ty = m[2] * h[0] - m[0] * h[2];
-        const T tz = m[0] * h[1] - m[1] * h[0];
-        const T dx = m[1] * tz - m[2] * ty;
-        const T dy = m[2] * tx - m[0] * tz;
-        const T dz = m[0] * ty - m[1] * tx;
-        const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
-                        -a.gdt * (tz + a.alpha * dz)};
-        if (a.stage == 1) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                a.acc[d * N + c] = F[d];
-                a.out[d * N + c] = m[d] + (T)0.5 * F[d];
-            }
-        } else if (a.stage == 2 || a.stage == 3) {
-            const T w = a.stage == 2 ? (T)0.5 : (T)1;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                a.acc[d * N + c] = ac[q][d] + (T)2 * F[d];
-                a.out[d * N + c] = mn[q][d] + w * F[d];
-            }
-        } else {
-            T v[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) v[d] = mn[q][d] + (ac[q][d] + F[d]) / (T)6;
-            const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
-        }
-    }
+    body_llg_stage<T>(a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
 
 template <typename T>

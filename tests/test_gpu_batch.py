@@ -1,0 +1,102 @@
+"""Batched form: many uneven grids advanced by one launch per pass, against the
+same grids run one at a time and against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import BATCH_TEMPLATE, batch_samples, mT_to_Apm, random_unit_m
+from tests.gpu_util import rel_max, to_np
+
+pytestmark = pytest.mark.gpu
+
+mmag = pytest.importorskip("paper_1501_07293_amd")
+
+C = BATCH_TEMPLATE
+MIXED = [(33, 47, 1), (32, 32, 2), (64, 40, 1), (37, 128, 2), (128, 128, 1), (5, 3, 2),
+         (1, 1, 1), (45, 32, 2), (97, 61, 1), (70, 3, 2)]
+
+
+def fields_for(n, seed=0):
+    g = np.random.default_rng(seed)
+    return mT_to_Apm(g.uniform(-40, 40, size=(n, 3)))
+
+
+def run_single(grid, hext, m0, precision, nsteps):
+    nx, ny, nz = grid
+    sim = mmag.Sim(nx, ny, nz, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                   precision=precision, generic_fft=True, threads=256)
+    sim.set_hext(hext)
+    sim.set_m(m0)
+    sim.step(nsteps, C.dt)
+    return to_np(sim.get_m())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_matches_single_grid_runs(precision):
+    hext = fields_for(len(MIXED))
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=100 + i) for i, g in enumerate(MIXED)]
+    b = mmag.BatchSim(MIXED, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision=precision)
+    b.set_m(m0)
+    b.step(20, C.dt)
+    got = [to_np(x) for x in b.get_m()]
+    worst = 0.0
+    for i, g in enumerate(MIXED):
+        ref = run_single(g, hext[i], m0[i], precision, 20)
+        worst = max(worst, float(np.abs(got[i] - ref).max()))
+    print(f"batch vs single-grid runs ({precision}): max |dm| = {worst:.3e}")
+    assert worst <= (1e-13 if precision == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_matches_oracle(precision):
+    grids = [(6, 5, 1), (7, 4, 2), (9, 3, 1), (4, 4, 3)]
+    hext = fields_for(len(grids), seed=3)
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=200 + i) for i, g in enumerate(grids)]
+    b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision=precision)
+    b.set_m(m0)
+    m_used = [to_np(x) for x in b.get_m()]
+    b.step(15, C.dt)
+    got = [to_np(x) for x in b.get_m()]
+    for i, g in enumerate(grids):
+        pb = oracle.Problem(g[0], g[1], g[2], C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha,
+                            gamma=C.gamma, hext=tuple(hext[i]))
+        ref = oracle.rk4(pb, m_used[i], C.dt, 15)
+        err = np.abs(got[i] - ref).max()
+        assert err <= (1e-11 if precision == "f64" else 1e-5), (g, err)
+
+
+def test_batch_graph_replay_matches_eager():
+    hext = fields_for(len(MIXED), seed=5)
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=300 + i) for i, g in enumerate(MIXED)]
+    outs = []
+    for graph in (False, True):
+        b = mmag.BatchSim(MIXED, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                          hext=hext, precision="f32", graph=graph)
+        b.set_m(m0)
+        b.step(19, C.dt)
+        outs.append(to_np(b.get_m_flat()))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_full_batched_workload_512_grids():
+    # 512 grids, nx, ny uniform in [32, 128], nz in {1, 2}, fields in a 50 mT ball.
+    samples = batch_samples(512, seed=0)
+    grids = [(s.nx, s.ny, s.nz) for s in samples]
+    hext = np.array([s.hext for s in samples])
+    m0 = [random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples]
+    b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision="f32", graph=True)
+    b.set_m(m0)
+    b.step(10, C.dt)
+    got = [to_np(x) for x in b.get_m()]
+    for x in got:
+        assert np.isfinite(x).all()
+        assert np.abs(np.sqrt((x * x).sum(axis=0)) - 1).max() < 1e-6
+    # the smallest, the largest and a few others against single-grid runs
+    sizes = [g[0] * g[1] * g[2] for g in grids]
+    pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 1, 100, 311, 511]))
+    for i in pick:
+        ref = run_single(grids[i], hext[i], m0[i], "f32", 10)
+        assert np.abs(got[i] - ref).max() <= 1e-6, (i, grids[i])
