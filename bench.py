@@ -110,6 +110,62 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes * reps / dt / 1e9
 
 
+def batched_leg(steps: int, warmup: int = 2) -> dict:
+    """512 uneven grids (nx, ny in [32, 128], nz in {1, 2}), FP32, one launch per pass
+    over all grids, graph replay; value = total cells * steps / s."""
+    import torch
+
+    import paper_1501_07293_amd as mm
+    import synthetic
+    c = synthetic.BATCH_TEMPLATE
+    samples = synthetic.batch_samples(512, seed=0)
+    grids = [(s.nx, s.ny, s.nz) for s in samples]
+    hext = np.array([s.hext for s in samples])
+    b = mm.BatchSim(grids, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
+                    hext=hext, precision="f32", graph=True)
+    b.set_m([synthetic.random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples])
+    b.step(warmup, c.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps, c.dt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"grids": len(grids), "cells": b.cells, "steps": steps, "ms_per_step": 1e3 * dt / steps,
+           "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32"}
+    b.close()
+    return out
+
+
+def adjoint_leg() -> dict:
+    """128x128x1 Ku-map rollout of 500 RK4 steps (checkpoint every 50) and its
+    hand-written adjoint, FP32: forward and backward wall time."""
+    import torch
+
+    import paper_1501_07293_amd as mm
+    import synthetic
+    c = synthetic.DIFF
+    sim = mm.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                 precision="f32")
+    ku = torch.tensor(synthetic.ku_map(c, seed=1), dtype=torch.float32, device="cuda:0",
+                      requires_grad=True)
+    m0 = torch.tensor(synthetic.random_unit_m(c.shape, seed=2), dtype=torch.float32, device="cuda:0")
+    tgt = torch.tensor(synthetic.vortex_target(c, seed=3), dtype=torch.float32, device="cuda:0")
+    mm.rollout(sim, ku, m0, 20, c.dt, 10)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mf = mm.rollout(sim, ku, m0, c.steps, c.dt, 50)
+    loss = ((mf - tgt) ** 2).sum(dim=0).mean()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.close()
+    return {"workload": "128x128x1 Ku-map rollout, 500 RK4 steps, checkpoint 50, FP32",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "forward_cell_updates_per_s": c.N * c.steps / (t1 - t0)}
+
+
 def field_error_sampled(sim, cfg, pb, nsamp: int, seed: int = 1):
     import oracle
     rng = np.random.default_rng(seed)
@@ -166,6 +222,8 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batched-leg", action="store_true")
+    ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--samples", type=int, default=64)
     args = ap.parse_args()
@@ -233,16 +291,37 @@ def main():
         out["fp64"] = {"value": cfg.N * fsteps / secs64, "steps": fsteps,
                        "ms_per_step": 1e3 * secs64 / fsteps}
         sim64.close()
+        del sim64
+        torch.cuda.empty_cache()
+    if not args.no_batched_leg:
+        out["batched"] = batched_leg(max(10, args.steps // 10))
+    if not args.no_adjoint_leg:
+        out["adjoint"] = adjoint_leg()
     print(json.dumps(out), flush=True)
 
 
 def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
-    base = {"x_fwd": "k_row_r2c", "y_fwd": "k_col_fft", "kspace": "k_kspace", "y_inv": "k_col_fft",
-            "x_inv": "k_row_c2r", "llg": "k_llg_stage"}[k]
+    """Symbol of the kernel the library launches for pass k under this plan (the
+    size-specialised one where it exists, as the library's dispatch decides)."""
     t = "float" if precision == "f32" else "double"
+    fast = not plan.get("generic_fft", 0)
+    px, py, pz = plan["px"], plan["py"], plan["pz"]
+    pow2 = lambda v: v & (v - 1) == 0
+    x_ok = fast and pow2(px) and 16 <= px <= (2048 if t == "float" else 1024)
+    y_ok = fast and pow2(py) and 16 <= py <= 2048
     if k == "llg":
-        return f"mm::{base}<{t}>"
-    return f"mm::{base}<{t}, {plan['threads']}>"
+        return f"mm::k_llg_stage<{t}>"
+    if k in ("x_fwd", "x_inv"):
+        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}>" if x_ok else \
+            f"mm::k_row_{'r2c' if k == 'x_fwd' else 'c2r'}<{t}, {plan['threads']}>"
+    if k in ("y_fwd", "y_inv"):
+        return f"mm::k_yline<{t}, {py}, {'true' if k == 'y_inv' else 'false'}>" if y_ok else \
+            f"mm::k_col_fft<{t}, {plan['threads']}>"
+    if plan["passes"] == 5:
+        z_ok = fast and pow2(pz) and 2 <= pz <= (64 if t == "float" else 32)
+        return f"mm::k_kspace_z<{t}, {pz}>" if z_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
+    ky_ok = fast and pow2(py) and 16 <= py <= 1024
+    return f"mm::k_kspace_y<{t}, {py}>" if ky_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
 
 
 if __name__ == "__main__":

@@ -62,6 +62,11 @@ typedef enum {
 #define MM_USE_GRAPH 0x2u  /* mm_step replays a captured hipGraph of whole RK4 steps */
 #define MM_GENERIC_FFT 0x4u /* use the runtime-radix FFT passes even where a size-specialised
                                pass exists (both give the same result up to rounding) */
+#define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
+                               2n-smooth vs power of two, specialised vs runtime-radix passes,
+                               256 vs 512 threads) and keeps the fastest; results are cached per
+                               process and, if MMAG_TUNE_CACHE names a file, across processes.
+                               Explicit px/py/pz/threads are ignored under this flag. */
 
 typedef struct {
     int32_t nx, ny, nz; /* cells along x, y, z; each >= 1 */
@@ -81,7 +86,7 @@ typedef struct {
     int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
-    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT */
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
 } mm_options;
 
@@ -93,6 +98,10 @@ typedef struct {
     int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*hx*(py/2+1) */
     int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1, else 5) */
     double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
+    int32_t generic_fft; /* 1 when the runtime-radix passes are forced */
+    int32_t tuned;       /* 1 when the schedule came from the autotuner */
+    int32_t candidates;  /* schedules the autotuner timed (0 if cached or not tuned) */
+    double tuned_demag_ms; /* the chosen schedule's time per demag evaluation, ms (0 if not tuned) */
 } mm_plan_info;
 
 typedef struct mm_sim mm_sim;

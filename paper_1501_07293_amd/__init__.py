@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
-MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT = 0x1, 0x2, 0x4
+MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE = 0x1, 0x2, 0x4, 0x8
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
@@ -60,7 +60,9 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("px", ctypes.c_int32), ("py", ctypes.c_int32), ("pz", ctypes.c_int32),
                 ("hx", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("spectrum_elems", ctypes.c_int64), ("passes", ctypes.c_int32),
-                ("kernel_imag_ratio", ctypes.c_double)]
+                ("kernel_imag_ratio", ctypes.c_double), ("generic_fft", ctypes.c_int32),
+                ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("tuned_demag_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -150,7 +152,7 @@ class Sim:
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
-                 device: str = "cuda:0"):
+                 autotune: bool = False, device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch = torch
@@ -163,7 +165,7 @@ class Sim:
         self._grid = Grid(nx, ny, nz, cell)
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-                 | (MM_GENERIC_FFT if generic_fft else 0))
+                 | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads)
         nbytes = ctypes.c_size_t()

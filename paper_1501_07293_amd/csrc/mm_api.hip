@@ -8,7 +8,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <utility>
 #include <vector>
@@ -229,6 +234,8 @@ struct mm_sim {
     bool has_m;
     bool has_ku_map;
     double imag_ratio;
+    int tuned, tune_candidates;
+    double tuned_ms;
     // graph
     hipGraph_t graph;
     hipGraphExec_t gexec;
@@ -1060,6 +1067,141 @@ mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
     return MM_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+struct TuneChoice {
+    int px, py, pz, generic, threads;
+    double ms;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune_cache;
+bool g_tune_file_loaded = false;
+
+std::string tune_key(const mm_grid* g, const mm_options* o)
+{
+    std::ostringstream k;
+    k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1);
+    return k.str();
+}
+
+void tune_file_load()
+{
+    if (g_tune_file_loaded) return;
+    g_tune_file_loaded = true;
+    const char* path = getenv("MMAG_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    TuneChoice c;
+    while (f >> key >> c.px >> c.py >> c.pz >> c.generic >> c.threads >> c.ms) g_tune_cache[key] = c;
+}
+
+void tune_file_append(const std::string& key, const TuneChoice& c)
+{
+    const char* path = getenv("MMAG_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << c.px << " " << c.py << " " << c.pz << " " << c.generic << " " << c.threads << " "
+      << c.ms << "\n";
+}
+
+int next_pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+template <typename T>
+mm_status time_demag(mm_sim* s, hipStream_t st, double* ms_out)
+{
+    const Plan& p = s->p;
+    T* mn = s->at<T>(p.o_mn);
+    T* hd = s->at<T>(p.o_hd);
+    HIP_TRY(hipMemsetAsync(mn, 0, 3 * (size_t)p.N * sizeof(T), st));
+    for (int w = 0; w < 2; ++w) {
+        mm_status r = demag<T>(s, mn, hd, st);
+        if (r != MM_OK) return r;
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int reps = 5;
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int q = 0; q < reps; ++q) {
+        mm_status r = demag<T>(s, mn, hd, st);
+        if (r != MM_OK) return r;
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms_out = ms / reps;
+    return MM_OK;
+}
+
+// Candidate schedules of a grid: padded sizes (7-smooth default vs the power of
+// two that the specialised passes handle), specialised vs runtime-radix
+// passes, and the runtime-radix work-group size.
+std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
+{
+    std::vector<int> pxs{auto_pad(g->nx)}, pys{auto_pad(g->ny)};
+    std::vector<int> pzs{g->nz == 1 ? 1 : auto_pad(g->nz)};
+    auto add_pow2 = [](std::vector<int>& v, int n) {
+        const int q = next_pow2_at_least(2 * n - 1);
+        if (q != v[0] && q <= 4096) v.push_back(q);
+    };
+    add_pow2(pxs, g->nx);
+    add_pow2(pys, g->ny);
+    if (g->nz > 1) add_pow2(pzs, g->nz);
+    std::vector<mm_options> out;
+    for (int px : pxs)
+        for (int py : pys)
+            for (int pz : pzs)
+                for (int generic = 0; generic < 2; ++generic)
+                    for (int threads : {256, 512}) {
+                        if (!generic && threads == 512) continue;  // the specialised passes fix their shape
+                        mm_options c = *o;
+                        c.px = px;
+                        c.py = py;
+                        c.pz = pz;
+                        c.threads = threads;
+                        c.flags = (o->flags & ~(MM_AUTOTUNE | MM_USE_GRAPH | MM_GENERIC_FFT)) |
+                                  (generic ? MM_GENERIC_FFT : 0u);
+                        Plan p;
+                        if (build_plan(g, &c, &p) == MM_OK) out.push_back(c);
+                    }
+    return out;
+}
+
+// Times every candidate; each gets its own temporary handle and workspace.
+mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o, hipStream_t st,
+                   TuneChoice* best, int* ncand)
+{
+    best->ms = 1e300;
+    *ncand = 0;
+    for (const mm_options& c : tune_candidates(g, o)) {
+        Plan p;
+        if (build_plan(g, &c, &p) != MM_OK) continue;
+        void* w = nullptr;
+        if (hipMalloc(&w, p.total) != hipSuccess) continue;
+        mm_sim* t = nullptr;
+        mm_status r = mm_create(g, mat, &c, w, p.total, st, &t);
+        double ms = 0;
+        if (r == MM_OK) r = p.prec == MM_F32 ? time_demag<float>(t, st, &ms) : time_demag<double>(t, st, &ms);
+        if (t) mm_destroy(t);
+        hipFree(w);
+        if (r != MM_OK) continue;
+        ++*ncand;
+        if (ms < best->ms)
+            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, ms};
+    }
+    if (*ncand == 0) return fail(MM_ENOTSUP, "no schedule of this grid could be built");
+    return MM_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1072,6 +1214,11 @@ mm_status mm_workspace_query(const mm_grid* grid, const mm_options* opt, size_t*
     mm_status st = build_plan(grid, opt, &p);
     if (st != MM_OK) return st;
     *bytes = p.total;
+    if (opt && (opt->flags & MM_AUTOTUNE))  // room for whichever schedule wins
+        for (const mm_options& c : tune_candidates(grid, opt)) {
+            Plan q;
+            if (build_plan(grid, &c, &q) == MM_OK) *bytes = std::max(*bytes, q.total);
+        }
     return MM_OK;
 }
 
@@ -1080,6 +1227,46 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
 {
     if (!out) return fail(MM_EINVAL, "out is NULL");
     *out = nullptr;
+    if (opt && (opt->flags & MM_AUTOTUNE)) {
+        Plan probe;
+        mm_status st0 = build_plan(grid, opt, &probe);  // argument checks first
+        if (st0 != MM_OK) return st0;
+        if (!check_material(mat))
+            return fail(MM_EINVAL, "material needs Ms > 0, A >= 0, alpha >= 0, gamma > 0, all finite");
+        const std::string key = tune_key(grid, opt);
+        TuneChoice ch{};
+        int ncand = 0;
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_file_load();
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                ch = it->second;
+                have = true;
+            }
+        }
+        if (!have) {
+            mm_status r = autotune(grid, mat, opt, as_stream(stream), &ch, &ncand);
+            if (r != MM_OK) return r;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = ch;
+            tune_file_append(key, ch);
+        }
+        mm_options c = *opt;
+        c.px = ch.px;
+        c.py = ch.py;
+        c.pz = ch.pz;
+        c.threads = ch.threads;
+        c.flags = (opt->flags & ~(MM_AUTOTUNE | MM_GENERIC_FFT)) | (ch.generic ? MM_GENERIC_FFT : 0u);
+        mm_status r = mm_create(grid, mat, &c, d_workspace, ws_bytes, stream, out);
+        if (r == MM_OK) {
+            (*out)->tuned = 1;
+            (*out)->tune_candidates = ncand;
+            (*out)->tuned_ms = ch.ms;
+        }
+        return r;
+    }
     Plan p;
     mm_status st = build_plan(grid, opt, &p);
     if (st != MM_OK) return st;
@@ -1287,6 +1474,10 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->spectrum_elems = (int64_t)s->p.ncomp * s->p.oct_elems;
     out->passes = s->p.three_d ? 5 : 3;
     out->kernel_imag_ratio = s->imag_ratio;
+    out->generic_fft = (s->flags & MM_GENERIC_FFT) ? 1 : 0;
+    out->tuned = s->tuned;
+    out->candidates = s->tune_candidates;
+    out->tuned_demag_ms = s->tuned_ms;
     return MM_OK;
 }
 

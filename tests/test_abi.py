@@ -34,9 +34,9 @@ def test_exports_every_declared_symbol(lib):
     assert set(names) == set(mm.EXPORTS)
 
 
-def q(lib, nx, ny, nz, cell=5e-9, prec=0, pad=(0, 0, 0), threads=0):
+def q(lib, nx, ny, nz, cell=5e-9, prec=0, pad=(0, 0, 0), threads=0, flags=0):
     g = mm.Grid(nx, ny, nz, cell)
-    o = mm.Options(prec, pad[0], pad[1], pad[2], 0, threads)
+    o = mm.Options(prec, pad[0], pad[1], pad[2], flags, threads)
     b = ctypes.c_size_t()
     st = lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b))
     return st, b.value
@@ -51,6 +51,26 @@ def test_workspace_query_sizes(lib):
     assert b32 < 4 << 30
     st, b = q(lib, 1, 1, 1)
     assert st == 0 and b > 0
+
+
+def test_autotune_workspace_covers_every_candidate(lib):
+    st, plain = q(lib, 65, 33, 3)
+    st2, tuned = q(lib, 65, 33, 3, flags=mm.MM_AUTOTUNE)
+    st3, pow2 = q(lib, 65, 33, 3, pad=(256, 128, 8))
+    assert st == st2 == st3 == 0
+    assert tuned >= max(plain, pow2)
+
+
+def test_batch_workspace_query(lib):
+    grids = (mm.Grid * 3)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(77, 33, 2, 5e-9), mm.Grid(1, 1, 1, 5e-9))
+    o = mm.Options(0, 0, 0, 0, 0, 0)
+    b = ctypes.c_size_t()
+    assert lib.mm_batch_workspace_query(3, grids, ctypes.byref(o), ctypes.byref(b)) == 0
+    assert b.value > 0
+    bad = (mm.Grid * 2)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(0, 33, 2, 5e-9))
+    assert lib.mm_batch_workspace_query(2, bad, ctypes.byref(o), ctypes.byref(b)) == -1
+    assert b"grid 1" in lib.mm_last_error()
+    assert lib.mm_batch_workspace_query(0, grids, ctypes.byref(o), ctypes.byref(b)) == -1
 
 
 @pytest.mark.parametrize("args", [(0, 4, 4), (4, -1, 4), (4, 4, 0)])
