@@ -166,6 +166,41 @@ def adjoint_leg() -> dict:
             "forward_cell_updates_per_s": c.N * c.steps / (t1 - t0)}
 
 
+PAPER_TABLE1_MS = {8: (3.99, 24.15, 22.58), 16: (26.56, 26.97, 23.97), 32: (248.8, 45.21, 26.89),
+                   64: (2903.0, 238.0, 76.24)}   # CPU, GPU FP64, GPU FP32 ms per Euler step
+
+
+def cube_sweep_leg(steps: int = 200) -> dict:
+    """The paper's own benchmark shape: N^3 cubes (standard problem #3 material: Ms 1000 kA/m,
+    A 1e-11 J/m, H_anis 100 kA/m, large damping), explicit Euler + renormalisation, ms per
+    step in FP32 and FP64; the paper's GTX 650 Ti / Xeon E5410 numbers beside them."""
+    import torch
+
+    import paper_1501_07293_amd as mm
+    from synthetic import random_unit_m
+    Ms = 1.0e6
+    Ku = 4e-7 * np.pi * Ms * 1.0e5 / 2
+    rows = []
+    for n in (8, 16, 32, 64, 128):
+        row = {"N": n}
+        for prec in ("f32", "f64"):
+            sim = mm.Sim(n, n, n, 34e-9 / n, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0, precision=prec)
+            sim.set_m(random_unit_m((3, n, n, n), seed=n))
+            sim.step_euler(5, 1e-14)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step_euler(steps, 1e-14)
+            torch.cuda.synchronize()
+            row[f"ms_per_step_{prec}"] = 1e3 * (time.perf_counter() - t0) / steps
+            sim.close()
+        if n in PAPER_TABLE1_MS:
+            cpu, g64, g32 = PAPER_TABLE1_MS[n]
+            row["paper_ms_cpu_fp64_fp32"] = [cpu, g64, g32]
+        rows.append(row)
+    return {"workload": "N^3 cube, explicit Euler + renormalisation (context: paper Table 1, "
+                        "other hardware, MATLAB)", "rows": rows}
+
+
 def field_error_sampled(sim, cfg, pb, nsamp: int, seed: int = 1):
     import oracle
     rng = np.random.default_rng(seed)
@@ -224,6 +259,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
+    ap.add_argument("--no-cube-leg", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--samples", type=int, default=64)
     args = ap.parse_args()
@@ -297,6 +333,8 @@ def main():
         out["batched"] = batched_leg(max(10, args.steps // 10))
     if not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg()
+    if not args.no_cube_leg:
+        out["paper_table1_shape"] = cube_sweep_leg()
     print(json.dumps(out), flush=True)
 
 

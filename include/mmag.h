@@ -140,6 +140,11 @@ mm_status mm_set_ku_map(mm_sim* sim, const void* ku, int on_device);
  * Asynchronous on the handle's stream.  MM_ESTATE before mm_set_m. */
 mm_status mm_step(mm_sim* sim, int64_t nsteps, double dt);
 
+/* The paper's own integrator (its appendix script): nsteps explicit Euler steps,
+ * m <- (m + dt f(m)) / |m + dt f(m)| per cell, one field evaluation per step.
+ * Asynchronous on the handle's stream. */
+mm_status mm_step_euler(mm_sim* sim, int64_t nsteps, double dt);
+
 /* One term of the effective field at the current m, A/m, [3][nz][ny][nx]. */
 mm_status mm_get_field(mm_sim* sim, int32_t term, void* out, int on_device);
 

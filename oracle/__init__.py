@@ -66,9 +66,10 @@ def _load():
         lib.or_energy.argtypes = [pp, dp, dp, dp]
         lib.or_mean_m.argtypes = [pp, dp, dp]
         lib.or_rk4_adjoint.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
+        lib.or_euler.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64]
         for f in ("or_tensor_point", "or_tensor_table", "or_demag", "or_exchange",
                   "or_anisotropy", "or_heff", "or_llg_rhs", "or_rk4", "or_energy", "or_mean_m",
-                  "or_rk4_adjoint"):
+                  "or_rk4_adjoint", "or_euler"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -206,6 +207,15 @@ def rk4(pb: Problem, m, dt: float, nsteps: int) -> np.ndarray:
     tab = pb.table() if pb.demag else np.zeros(1)
     p = pb._params()
     _load().or_rk4(ctypes.byref(p), _dptr(m), _dptr(tab), float(dt), int(nsteps))
+    return m
+
+
+def euler(pb: Problem, m, dt: float, nsteps: int) -> np.ndarray:
+    """Explicit Euler with per-step renormalisation (the appendix script's update)."""
+    m = _m(pb, m).copy()
+    tab = pb.table() if pb.demag else np.zeros(1)
+    p = pb._params()
+    _load().or_euler(ctypes.byref(p), _dptr(m), _dptr(tab), float(dt), int(nsteps))
     return m
 
 

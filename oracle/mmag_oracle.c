@@ -443,3 +443,24 @@ void or_rk4_adjoint(const or_params *p, const double *m0, const double *table, d
     free(acc);
     free(mstar);
 }
+
+/* Explicit Euler with renormalisation, the integrator of the appendix script:
+ * m <- (m + dt f(m)) / |m + dt f(m)| per cell, nsteps times. */
+void or_euler(const or_params *p, double *m, const double *table, double dt, int64_t nsteps)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz, L = 3 * N;
+    double *k = (double *)malloc(sizeof(double) * L);
+    double *h = (double *)malloc(sizeof(double) * L);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        rhs_of(p, m, table, h, k);
+        for (int64_t q = 0; q < L; ++q) m[q] += dt * k[q];
+        for (int64_t c = 0; c < N; ++c) {
+            double nrm = sqrt(m[c] * m[c] + m[N + c] * m[N + c] + m[2 * N + c] * m[2 * N + c]);
+            m[c] /= nrm;
+            m[N + c] /= nrm;
+            m[2 * N + c] /= nrm;
+        }
+    }
+    free(k);
+    free(h);
+}

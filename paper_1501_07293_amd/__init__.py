@@ -26,7 +26,7 @@ TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
 EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
-           "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_get_field",
+           "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_step_euler", "mm_get_field",
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_set_alpha": [vp, dbl],
         "mm_set_ku_map": [vp, vp, ctypes.c_int],
         "mm_step": [vp, i64, dbl],
+        "mm_step_euler": [vp, i64, dbl],
         "mm_get_field": [vp, i32, vp, ctypes.c_int],
         "mm_get_energy": [vp, ctypes.POINTER(dbl)],
         "mm_get_mean_m": [vp, ctypes.POINTER(dbl)],
@@ -219,6 +220,11 @@ class Sim:
     def step(self, nsteps: int, dt: float):
         self._sync_stream()
         _check(self._lib.mm_step(self._h, int(nsteps), float(dt)), "mm_step")
+
+    def step_euler(self, nsteps: int, dt: float):
+        """The paper's explicit Euler + renormalisation, nsteps steps."""
+        self._sync_stream()
+        _check(self._lib.mm_step_euler(self._h, int(nsteps), float(dt)), "mm_step_euler")
 
     # --------------------------------------------------------------- readout
     def field(self, term: str = "eff"):

@@ -584,6 +584,35 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
     return MM_OK;
 }
 
+// Explicit Euler + renormalisation (the paper's integrator): ping-pong between
+// m_n and m_a, one field evaluation per step; the result ends in m_n.
+template <typename T>
+mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt)
+{
+    const Plan& p = s->p;
+    hipStream_t st = s->stream;
+    T* bufs[2] = {s->at<T>(p.o_mn), s->at<T>(p.o_ma)};
+    T* hd = s->at<T>(p.o_hd);
+    LlgArgs<T> a = llg_args<T>(s, dt);
+    a.stage = 0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        T* src = bufs[n & 1];
+        T* dst = bufs[(n + 1) & 1];
+        if (!(s->flags & MM_NO_DEMAG)) {
+            mm_status r = demag<T>(s, src, hd, st);
+            if (r != MM_OK) return r;
+        }
+        a.ms = src;
+        a.mn = src;
+        a.acc = s->at<T>(p.o_acc);
+        a.out = dst;
+        LAUNCH(KLLG, launch_llg_stage<T>(a, st));
+    }
+    if (nsteps & 1)
+        HIP_TRY(hipMemcpyAsync(bufs[0], bufs[1], 3 * (size_t)p.N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return MM_OK;
+}
+
 void drop_graph(mm_sim* s)
 {
     if (s->gexec) hipGraphExecDestroy(s->gexec);
@@ -1419,6 +1448,15 @@ mm_status mm_step(mm_sim* s, int64_t nsteps, double dt)
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_step before mm_set_m");
     return s->p.prec == MM_F32 ? step_impl<float>(s, nsteps, dt) : step_impl<double>(s, nsteps, dt);
+}
+
+mm_status mm_step_euler(mm_sim* s, int64_t nsteps, double dt)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!s->has_m) return fail(MM_ESTATE, "mm_step_euler before mm_set_m");
+    return s->p.prec == MM_F32 ? euler_impl<float>(s, nsteps, dt) : euler_impl<double>(s, nsteps, dt);
 }
 
 mm_status mm_get_field(mm_sim* s, int32_t term, void* out, int on_device)

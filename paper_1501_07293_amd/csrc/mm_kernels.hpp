@@ -184,7 +184,7 @@ struct LlgArgs {
     T hx, hy, hz;    // reduced applied field H_ext / Ms
     T alpha;
     T gdt;           // gamma Ms dt / (1 + alpha^2)
-    int stage;       // 1..4
+    int stage;       // 1..4 (RK4 stages), 0 (explicit Euler with renormalisation)
 };
 // the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes
 constexpr int kLlgZ = 4;

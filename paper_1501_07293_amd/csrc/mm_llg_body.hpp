@@ -83,7 +83,14 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t t)
         const T dz = m[0] * ty - m[1] * tx;
         const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
                         -a.gdt * (tz + a.alpha * dz)};
-        if (a.stage == 1) {
+        if (a.stage == 0) {  // explicit Euler with renormalisation
+            T v[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[d] = m[d] + F[d];
+            const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
+        } else if (a.stage == 1) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 a.acc[d * N + c] = F[d];

@@ -247,3 +247,21 @@ def test_autotuner_picks_a_schedule_that_matches_the_oracle():
     q = again.plan()
     assert q["tuned"] == 1 and q["candidates"] == 0
     assert (q["px"], q["py"], q["pz"], q["generic_fft"]) == (p["px"], p["py"], p["pz"], p["generic_fft"])
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8), (13, 6, 1), (10, 7, 3)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_euler_matches_oracle(dims, precision):
+    # The paper's explicit Euler + renormalisation on standard-problem-#3-like material
+    # (Ms 1000 kA/m, A 1e-11 J/m, H_anis 100 kA/m along x, large damping).
+    Ms = 1.0e6
+    Ku = 4e-7 * np.pi * Ms * 1.0e5 / 2
+    pb = problem(*dims, cell=4e-9, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0)
+    m0 = random_unit_m(pb.shape, seed=31)
+    sim = make_sim(pb, precision)
+    sim.set_m(m0)
+    m_used = to_np(sim.get_m())
+    sim.step_euler(25, 2e-14)
+    ref = oracle.euler(pb, m_used, 2e-14, 25)
+    err = np.abs(to_np(sim.get_m()) - ref).max()
+    assert err <= (1e-11 if precision == "f64" else 2e-5), err

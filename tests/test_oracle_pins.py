@@ -407,3 +407,19 @@ def test_oracle_adjoint_matches_finite_differences():
         fdm = (_loss(pb, m0 + em * vm, dt, n, w) - _loss(pb, m0 - em * vm, dt, n, w)) / (2 * em)
         adm = float((dm0 * vm).sum())
         assert abs(fdm - adm) <= 1e-6 * abs(adm), (trial, fdm, adm)
+
+
+def test_macrospin_euler_first_order():
+    # The appendix script's explicit Euler + renormalisation converges at first order to
+    # the closed-form macrospin trajectory (halving dt halves the error).
+    H, alpha = 2.0e5, 0.1
+    pb = oracle.Problem(1, 1, 1, 5e-9, Ku=0.0, alpha=alpha, hext=(0.0, 0.0, H))
+    th0, ph0 = 2.5, 0.3
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    T = 1e-10
+    errs = []
+    for nsteps in (2000, 4000, 8000):
+        m = oracle.euler(pb, m0.reshape(3, 1, 1, 1), T / nsteps, nsteps).reshape(3)
+        errs.append(np.abs(m - macrospin_closed_form(th0, ph0, H, alpha, pb.gamma, T)).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.8 < r1 < 2.2 and 1.8 < r2 < 2.2, errs
