@@ -88,6 +88,8 @@ typedef struct {
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
     uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
+    int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
+                            0 = automatic (8), 4 or 8 */
 } mm_options;
 
 typedef struct {
@@ -102,6 +104,7 @@ typedef struct {
     int32_t tuned;       /* 1 when the schedule came from the autotuner */
     int32_t candidates;  /* schedules the autotuner timed (0 if cached or not tuned) */
     double tuned_demag_ms; /* the chosen schedule's time per demag evaluation, ms (0 if not tuned) */
+    int32_t x_lines;     /* row pairs per work-group of the specialised x passes */
 } mm_plan_info;
 
 typedef struct mm_sim mm_sim;

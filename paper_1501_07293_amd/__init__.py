@@ -53,7 +53,8 @@ class Material(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
-                ("pz", ctypes.c_int32), ("flags", ctypes.c_uint32), ("threads", ctypes.c_int32)]
+                ("pz", ctypes.c_int32), ("flags", ctypes.c_uint32), ("threads", ctypes.c_int32),
+                ("x_lines", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -62,7 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("spectrum_elems", ctypes.c_int64), ("passes", ctypes.c_int32),
                 ("kernel_imag_ratio", ctypes.c_double), ("generic_fft", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("tuned_demag_ms", ctypes.c_double)]
+                ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32)]
 
 
 _lib = None
@@ -153,7 +154,7 @@ class Sim:
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
-                 autotune: bool = False, device: str = "cuda:0"):
+                 autotune: bool = False, x_lines: int = 0, device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch = torch
@@ -168,7 +169,7 @@ class Sim:
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
                  | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
-                            threads)
+                            threads, x_lines)
         nbytes = ctypes.c_size_t()
         _check(lib.mm_workspace_query(ctypes.byref(self._grid), ctypes.byref(self._opt),
                                       ctypes.byref(nbytes)), "mm_workspace_query")
@@ -330,7 +331,7 @@ class BatchSim:
         self._grids = garr
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = (0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-        self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0)
+        self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
         nbytes = ctypes.c_size_t()

@@ -105,6 +105,7 @@ struct Plan {
     size_t esz;        // sizeof(T)
     FftPlan fx, fy, fz;
     int x_lines, y_tw, k_tw;
+    int xl;            // complex lines per work-group of the specialised x passes (4 or 8)
     int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
     int64_t oct_elems;         // per component
     // workspace offsets
@@ -170,6 +171,9 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     if (!fits(nt)) return fail(MM_ENOTSUP, "padded sizes %d x %d x %d exceed the FFT work-group capacity",
                                p->Px, p->Py, p->Pz);
     p->nt = nt;
+    if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8)
+        return fail(MM_EINVAL, "x_lines must be 0, 4 or 8");
+    p->xl = o->x_lines ? o->x_lines : 8;
     if (!make_fft_plan(p->Px, &p->fx) || !make_fft_plan(p->Py, &p->fy) || !make_fft_plan(p->Pz, &p->fz))
         return fail(MM_EINVAL, "padded sizes must be 7-smooth");
     const int cap = kElemsPerThread * nt, ldscap = cap + 64;
@@ -317,7 +321,7 @@ template <typename T>
 hipError_t pass_x_forward(const PassCtx& c, const T* m, hipStream_t st)
 {
     const Plan& p = c.p;
-    XLineArgs xa{m, c.S, c.nplanes, p.ny, p.nx, c.Sy, c.twx};
+    XLineArgs xa{m, c.S, c.nplanes, p.ny, p.nx, c.Sy, c.twx, p.xl};
     if (c.fast && launch_xline<T>(xa, p.Px, 0, st)) return hipGetLastError();
     RowR2CArgs r{};
     r.in = m;
@@ -409,7 +413,7 @@ template <typename T>
 hipError_t pass_x_inverse(const PassCtx& c, T* h, hipStream_t st)
 {
     const Plan& p = c.p;
-    XLineArgs xa{c.S, h, c.nplanes, p.ny, p.nx, c.Sy, c.twx};
+    XLineArgs xa{c.S, h, c.nplanes, p.ny, p.nx, c.Sy, c.twx, p.xl};
     if (c.fast && launch_xline<T>(xa, p.Px, 1, st)) return hipGetLastError();
     RowC2RArgs r{};
     r.in = c.S;
@@ -1098,7 +1102,7 @@ mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
 
 // ---------------------------------------------------------------- autotuner
 struct TuneChoice {
-    int px, py, pz, generic, threads;
+    int px, py, pz, generic, threads, xl;
     double ms;
 };
 
@@ -1122,7 +1126,7 @@ void tune_file_load()
     std::ifstream f(path);
     std::string key;
     TuneChoice c;
-    while (f >> key >> c.px >> c.py >> c.pz >> c.generic >> c.threads >> c.ms) g_tune_cache[key] = c;
+    while (f >> key >> c.px >> c.py >> c.pz >> c.generic >> c.threads >> c.xl >> c.ms) g_tune_cache[key] = c;
 }
 
 void tune_file_append(const std::string& key, const TuneChoice& c)
@@ -1131,7 +1135,7 @@ void tune_file_append(const std::string& key, const TuneChoice& c)
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << key << " " << c.px << " " << c.py << " " << c.pz << " " << c.generic << " " << c.threads << " "
-      << c.ms << "\n";
+      << c.xl << " " << c.ms << "\n";
 }
 
 int next_pow2_at_least(int v)
@@ -1190,13 +1194,16 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
         for (int py : pys)
             for (int pz : pzs)
                 for (int generic = 0; generic < 2; ++generic)
-                    for (int threads : {256, 512}) {
+                    for (int threads : {256, 512})
+                        for (int xl : {8, 4}) {
                         if (!generic && threads == 512) continue;  // the specialised passes fix their shape
+                        if (generic && xl == 4) continue;          // only the specialised x passes use it
                         mm_options c = *o;
                         c.px = px;
                         c.py = py;
                         c.pz = pz;
                         c.threads = threads;
+                        c.x_lines = xl;
                         c.flags = (o->flags & ~(MM_AUTOTUNE | MM_USE_GRAPH | MM_GENERIC_FFT)) |
                                   (generic ? MM_GENERIC_FFT : 0u);
                         Plan p;
@@ -1225,7 +1232,7 @@ mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o
         if (r != MM_OK) continue;
         ++*ncand;
         if (ms < best->ms)
-            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, ms};
+            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms};
     }
     if (*ncand == 0) return fail(MM_ENOTSUP, "no schedule of this grid could be built");
     return MM_OK;
@@ -1287,6 +1294,7 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
         c.py = ch.py;
         c.pz = ch.pz;
         c.threads = ch.threads;
+        c.x_lines = ch.xl;
         c.flags = (opt->flags & ~(MM_AUTOTUNE | MM_GENERIC_FFT)) | (ch.generic ? MM_GENERIC_FFT : 0u);
         mm_status r = mm_create(grid, mat, &c, d_workspace, ws_bytes, stream, out);
         if (r == MM_OK) {
@@ -1516,6 +1524,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->tuned = s->tuned;
     out->candidates = s->tune_candidates;
     out->tuned_demag_ms = s->tuned_ms;
+    out->x_lines = s->p.xl;
     return MM_OK;
 }
 

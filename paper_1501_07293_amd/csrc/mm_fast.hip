@@ -189,20 +189,21 @@ __global__ __launch_bounds__(256) void k_yline(YLineArgs a)
 constexpr int kLdsBudget = 160 * 1024;
 // 8 complex lines (16 consecutive real rows of one (component, z) plane) per
 // work-group; the half spectrum is stored transposed, 16 rows per bin.
-constexpr int kXLines = 8;
+// A work-group of the x passes holds L complex lines = 2L consecutive rows of
+// one plane (L = 8: 128-byte transposed segments in FP32; L = 4: half the LDS,
+// twice the work-groups per CU).
 
-template <typename T, int P>
+template <typename T, int P, int L>
 constexpr int x_lds_bytes()
 {
-    return (int)sizeof(cpx<T>) * ((kXLines * padded_len<P>() > 2 * kXLines * (P / 2 + 1))
-                                      ? kXLines * padded_len<P>()
-                                      : 2 * kXLines * (P / 2 + 1));
+    return (int)sizeof(cpx<T>) * ((L * padded_len<P>() > 2 * L * (P / 2 + 1)) ? L * padded_len<P>()
+                                                                              : 2 * L * (P / 2 + 1));
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(kXLines * (P / Sched<P>::R0)) void k_xfwd(XLineArgs a)
+template <typename T, int P, int L>
+__global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xfwd(XLineArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = kXLines, NT = L * TL, LP = padded_len<P>();
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
     constexpr int HX = P / 2 + 1, ROWS = 2 * L;
     __shared__ cpx<T> lds[L * LP];
     const int tpp = (a.ny + ROWS - 1) / ROWS;
@@ -248,10 +249,10 @@ __global__ __launch_bounds__(kXLines * (P / Sched<P>::R0)) void k_xfwd(XLineArgs
 }
 
 // ------------------------------------------------------------------ x inverse
-template <typename T, int P>
-__global__ __launch_bounds__(kXLines * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
+template <typename T, int P, int L>
+__global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = kXLines, NT = L * TL, LP = padded_len<P>();
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
     constexpr int HX = P / 2 + 1, ROWS = 2 * L;
     constexpr int LDSN = (L * LP > ROWS * HX) ? L * LP : ROWS * HX;
     __shared__ cpx<T> lds[LDSN];
@@ -481,20 +482,20 @@ bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s)
     return inverse ? yline_dispatch<T, true>(a, P, s) : yline_dispatch<T, false>(a, P, s);
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, int L>
 static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
 {
     auto go = [&](auto kern, int tl) {
-        const int rows = 2 * kXLines;
+        const int rows = 2 * L;
         const int grid = a.nplanes * ((a.ny + rows - 1) / rows);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kXLines * tl), 0, s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(L * tl), 0, s, a);
         return true;
     };
 #define MM_XCASE(PP)                                                                  \
     case PP:                                                                          \
-        if constexpr (x_lds_bytes<T, PP>() <= kLdsBudget)                             \
-            return INV ? go(k_xinv<T, PP>, PP / Sched<PP>::R0)                        \
-                       : go(k_xfwd<T, PP>, PP / Sched<PP>::R0);                       \
+        if constexpr (x_lds_bytes<T, PP, L>() <= kLdsBudget)                          \
+            return INV ? go(k_xinv<T, PP, L>, PP / Sched<PP>::R0)                     \
+                       : go(k_xfwd<T, PP, L>, PP / Sched<PP>::R0);                    \
         return false;
     switch (P) {
         MM_XCASE(16)
@@ -516,7 +517,9 @@ bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s)
     if (a.nplanes <= 0 || a.ny <= 0) return true;
     // the padded line must hold at least the valid samples
     if (a.nx > P) return false;
-    return inverse ? xline_dispatch<T, true>(a, P, s) : xline_dispatch<T, false>(a, P, s);
+    if (a.lines == 4)
+        return inverse ? xline_dispatch<T, true, 4>(a, P, s) : xline_dispatch<T, false, 4>(a, P, s);
+    return inverse ? xline_dispatch<T, true, 8>(a, P, s) : xline_dispatch<T, false, 8>(a, P, s);
 }
 
 template <typename T>

@@ -113,6 +113,7 @@ struct XLineArgs {           // x pass over [nplanes][ny][nx] real rows <-> [npl
     int ny, nx;
     int64_t srows;
     const void* tw;
+    int lines;               // complex lines (row pairs) per work-group: 4 or 8
 };
 struct KzArgs {              // z k-space pass, columns (kx, ky) = (c / Py, c % Py)
     void* buf;

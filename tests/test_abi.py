@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(lib):
 
 def q(lib, nx, ny, nz, cell=5e-9, prec=0, pad=(0, 0, 0), threads=0, flags=0):
     g = mm.Grid(nx, ny, nz, cell)
-    o = mm.Options(prec, pad[0], pad[1], pad[2], flags, threads)
+    o = mm.Options(prec, pad[0], pad[1], pad[2], flags, threads, 0)
     b = ctypes.c_size_t()
     st = lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b))
     return st, b.value
@@ -63,7 +63,7 @@ def test_autotune_workspace_covers_every_candidate(lib):
 
 def test_batch_workspace_query(lib):
     grids = (mm.Grid * 3)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(77, 33, 2, 5e-9), mm.Grid(1, 1, 1, 5e-9))
-    o = mm.Options(0, 0, 0, 0, 0, 0)
+    o = mm.Options(0, 0, 0, 0, 0, 0, 0)
     b = ctypes.c_size_t()
     assert lib.mm_batch_workspace_query(3, grids, ctypes.byref(o), ctypes.byref(b)) == 0
     assert b.value > 0
@@ -93,7 +93,7 @@ def test_workspace_query_rejects_bad_options(lib):
 
 def test_create_rejects_bad_material_without_gpu_work(lib):
     g = mm.Grid(8, 8, 1, 5e-9)
-    o = mm.Options(0, 0, 0, 0, 0, 0)
+    o = mm.Options(0, 0, 0, 0, 0, 0, 0)
     h = ctypes.c_void_p()
     for mat in (mm.Material(-1, 1e-11, 0, 0.5, 2.2e5), mm.Material(8e5, -1, 0, 0.5, 2.2e5),
                 mm.Material(8e5, 1e-11, 0, -0.1, 2.2e5), mm.Material(8e5, 1e-11, 0, 0.5, 0.0),
