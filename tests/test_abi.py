@@ -129,3 +129,38 @@ def test_product_has_no_cpu_fallback():
         for f in files:
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 assert "import oracle" not in open(os.path.join(root, f)).read()
+
+
+def test_batch_create_rejects_bad_arguments_without_gpu_work(lib):
+    grids = (mm.Grid * 2)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(40, 33, 2, 5e-9))
+    o = mm.Options(0, 0, 0, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    bad_mat = mm.Material(8e5, 1.3e-11, 0, -1.0, 2.2e5)
+    assert lib.mm_batch_create(2, grids, ctypes.byref(bad_mat), None, ctypes.byref(o), None, 0, None,
+                               ctypes.byref(h)) == -1
+    mat = mm.Material(8e5, 1.3e-11, 500.0, 0.5, 2.2e5)
+    hext = (ctypes.c_double * 6)(0, 0, 0, float("nan"), 0, 0)
+    assert lib.mm_batch_create(2, grids, ctypes.byref(mat), hext, ctypes.byref(o), None, 0, None,
+                               ctypes.byref(h)) == -1
+    assert lib.mm_batch_create(2, grids, ctypes.byref(mat), None, ctypes.byref(o), 256, 16, None,
+                               ctypes.byref(h)) == -1
+    assert b"workspace" in lib.mm_last_error()
+    assert not h.value
+    assert lib.mm_batch_destroy(None) == 0
+    assert lib.mm_batch_step(None, 1, 1e-13) == -1
+
+
+def test_adjoint_and_euler_entry_points_reject_null(lib):
+    assert lib.mm_step_euler(None, 1, 1e-13) == -1
+    assert lib.mm_rollout(None, 10, 1e-13, 5, None) == -1
+    b = ctypes.c_size_t()
+    assert lib.mm_adjoint_workspace_query(None, 5, ctypes.byref(b)) == -1
+    assert lib.mm_backward(None, 10, 1e-13, 5, None, None, None, None, None, 0) == -1
+
+
+def test_x_lines_option_validated(lib):
+    g = mm.Grid(64, 64, 4, 5e-9)
+    b = ctypes.c_size_t()
+    for xl, want in ((0, 0), (4, 0), (8, 0), (6, -1)):
+        o = mm.Options(0, 0, 0, 0, 0, 0, xl)
+        assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b)) == want
