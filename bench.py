@@ -110,7 +110,7 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes * reps / dt / 1e9
 
 
-def batched_leg(steps: int, warmup: int = 2) -> dict:
+def batched_leg(steps: int, pow2: bool, warmup: int = 2) -> dict:
     """512 uneven grids (nx, ny in [32, 128], nz in {1, 2}), FP32, one launch per pass
     over all grids, graph replay; value = total cells * steps / s."""
     import torch
@@ -122,7 +122,7 @@ def batched_leg(steps: int, warmup: int = 2) -> dict:
     grids = [(s.nx, s.ny, s.nz) for s in samples]
     hext = np.array([s.hext for s in samples])
     b = mm.BatchSim(grids, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
-                    hext=hext, precision="f32", graph=True)
+                    hext=hext, precision="f32", graph=True, pow2_pad=pow2)
     b.set_m([synthetic.random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples])
     b.step(warmup, c.dt)
     torch.cuda.synchronize()
@@ -131,7 +131,8 @@ def batched_leg(steps: int, warmup: int = 2) -> dict:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out = {"grids": len(grids), "cells": b.cells, "steps": steps, "ms_per_step": 1e3 * dt / steps,
-           "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32"}
+           "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32",
+           "padding": "power of two (size-specialised passes)" if pow2 else "7-smooth (runtime radix)"}
     b.close()
     return out
 
@@ -330,7 +331,8 @@ def main():
         del sim64
         torch.cuda.empty_cache()
     if not args.no_batched_leg:
-        out["batched"] = batched_leg(max(10, args.steps // 10))
+        out["batched"] = batched_leg(max(10, args.steps // 10), pow2=True)
+        out["batched_7smooth"] = batched_leg(max(10, args.steps // 10), pow2=False)
     if not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg()
     if not args.no_cube_leg:

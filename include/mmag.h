@@ -62,6 +62,10 @@ typedef enum {
 #define MM_USE_GRAPH 0x2u  /* mm_step replays a captured hipGraph of whole RK4 steps */
 #define MM_GENERIC_FFT 0x4u /* use the runtime-radix FFT passes even where a size-specialised
                                pass exists (both give the same result up to rounding) */
+#define MM_POW2_PAD 0x10u  /* automatic padded sizes are the next power of two >= 2n-1 (instead of
+                               the smallest 7-smooth size), so the size-specialised passes apply;
+                               a batch created with it runs those passes, one launch per padded
+                               size per pass */
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                2n-smooth vs power of two, specialised vs runtime-radix passes,
                                256 vs 512 threads) and keeps the fastest; results are cached per
@@ -86,7 +90,7 @@ typedef struct {
     int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
-    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE */
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (8), 4 or 8 */

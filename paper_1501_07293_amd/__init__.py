@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
-MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE = 0x1, 0x2, 0x4, 0x8
+MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE, MM_POW2_PAD = 0x1, 0x2, 0x4, 0x8, 0x10
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
@@ -154,7 +154,8 @@ class Sim:
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
-                 autotune: bool = False, x_lines: int = 0, device: str = "cuda:0"):
+                 autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False,
+                 device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch = torch
@@ -167,7 +168,8 @@ class Sim:
         self._grid = Grid(nx, ny, nz, cell)
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-                 | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0))
+                 | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0)
+                 | (MM_POW2_PAD if pow2_pad else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads, x_lines)
         nbytes = ctypes.c_size_t()
@@ -317,7 +319,7 @@ class BatchSim:
     def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  hext=None, precision: str = "f32", demag: bool = True, graph: bool = False,
-                 device: str = "cuda:0"):
+                 pow2_pad: bool = False, device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch, self._lib = torch, lib
@@ -330,7 +332,8 @@ class BatchSim:
         garr = (Grid * self.n)(*[Grid(int(g[0]), int(g[1]), int(g[2]), cell) for g in grids])
         self._grids = garr
         self._mat = Material(Ms, A, Ku, alpha, gamma)
-        flags = (0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+        flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
+                 | (MM_POW2_PAD if pow2_pad else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())

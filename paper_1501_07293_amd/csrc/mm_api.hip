@@ -132,9 +132,17 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->prec = o->prec;
     p->esz = o->prec == MM_F32 ? 4 : 8;
     p->three_d = g->nz > 1;
-    auto pick = [](int n, int req, bool allow1, int* out) -> mm_status {
+    const bool pow2pad = (o->flags & MM_POW2_PAD) != 0;
+    auto pick = [pow2pad](int n, int req, bool allow1, int* out) -> mm_status {
         if (req == 0) {
-            *out = (allow1 && n == 1) ? 1 : auto_pad(n);
+            if (allow1 && n == 1)
+                *out = 1;
+            else if (pow2pad) {
+                int q = 2;
+                while (q < 2 * n - 1) q <<= 1;
+                *out = q;
+            } else
+                *out = auto_pad(n);
             return MM_OK;
         }
         if (req == 1 && allow1 && n == 1) {
@@ -862,8 +870,30 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
 }
 
 // ---------------------------------------------------------------- batched
+struct BatchClassHost {
+    int kind;  // 0 x passes, 1 y passes, 2 z k-space, 3 y k-space
+    int P;
+    std::vector<int> members, prefix;
+    size_t off;  // element offset of members, then prefix, in the device int array
+};
+
+bool fast_supported(int kind, int P, size_t esz)
+{
+    if (fast_first_radix(P) == 0) return false;
+    switch (kind) {
+    case 0: return P >= 16 && P <= (esz == 8 ? 1024 : 2048);
+    case 1: return P >= 16 && P <= 2048;
+    case 2: return P >= 2 && P <= (esz == 8 ? 32 : 64);
+    default: return P >= 16 && P <= 1024;
+    }
+}
+
 struct BatchLayout {
     std::vector<Plan> plans;
+    bool fast = false;
+    std::vector<BatchClassHost> classes;
+    size_t o_classes = 0;
+    int64_t class_ints = 0;
     std::vector<BatchDesc> desc;
     std::vector<int> prefix[5];   // x forward, y, k-space, x inverse, LLG
     int64_t vec_elems = 0, S_elems = 0, kern_elems = 0, tw_elems = 0, cells = 0;
@@ -931,6 +961,52 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
     }
     L->prec = o.prec;
     L->esz = o.prec == MM_F32 ? 4 : 8;
+    // size classes for the specialised passes (power-of-two padding)
+    L->fast = false;
+    L->classes.clear();
+    if (o.flags & MM_POW2_PAD) {
+        bool ok = true;
+        auto cls = [&](int kind, int P) -> BatchClassHost& {
+            for (auto& c : L->classes)
+                if (c.kind == kind && c.P == P) return c;
+            L->classes.push_back(BatchClassHost{kind, P, {}, {0}, 0});
+            return L->classes.back();
+        };
+        for (int s = 0; s < n && ok; ++s) {
+            const Plan& p = L->plans[s];
+            auto add = [&](int kind, int P, int tiles) {
+                if (!fast_supported(kind, P, L->esz)) {
+                    ok = false;
+                    return;
+                }
+                BatchClassHost& c = cls(kind, P);
+                c.members.push_back(s);
+                c.prefix.push_back(c.prefix.back() + tiles);
+            };
+            add(0, p.Px, 3 * p.nz * ((p.ny + 15) / 16));
+            if (!ok) break;
+            if (p.three_d) {
+                const int Ly = 256 / (p.Py / std::max(1, fast_first_radix(p.Py)));
+                add(1, p.Py, (3 * p.nz * p.hx + Ly - 1) / Ly);
+                if (!ok) break;
+                add(2, p.Pz, (int)((p.hx * (int64_t)p.Py + 63) / 64));
+            } else {
+                const int Lk = std::max(1, fast_ky_lines(p.Py));
+                add(3, p.Py, (p.hx + Lk - 1) / Lk);
+            }
+        }
+        if (ok) {
+            L->fast = true;
+            int64_t at = 0;
+            for (auto& c : L->classes) {
+                c.off = at;
+                at += (int64_t)c.members.size() + (int64_t)c.prefix.size();
+            }
+            L->class_ints = at;
+        } else {
+            L->classes.clear();
+        }
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -949,6 +1025,7 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
     L->o_kern = take((size_t)L->kern_elems * L->esz);
     L->o_tw = take((size_t)L->tw_elems * 2 * L->esz);
     L->o_flags = take(64);
+    L->o_classes = take((size_t)std::max<int64_t>(L->class_ints, 1) * sizeof(int));
     L->o_scratch = take(L->scratch);
     L->total = off;
     return MM_OK;
@@ -1006,8 +1083,36 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
     g.can = (T)(2.0 * b->mat.Ku / (kMu0 * Ms * Ms));
     g.alpha = (T)b->alpha;
     g.gdt = (T)(b->mat.gamma * Ms * dt / (1.0 + b->alpha * b->alpha));
+    BatchClass<T> bc{};
+    bc.d = p.d;
+    bc.S = p.S;
+    bc.kern = p.kern;
+    bc.tw = p.tw;
+    bc.out = hd;
+    const int* cints = b->at<int>(L.o_classes);
+    auto run_classes = [&](int kind, int launch_kind, int inverse) -> mm_status {
+        for (const BatchClassHost& c : L.classes) {
+            if (c.kind != kind) continue;
+            bc.members = cints + c.off;
+            bc.prefix = cints + c.off + c.members.size();
+            bc.nmem = (int)c.members.size();
+            if (!launch_batch_class<T>(launch_kind, c.P, bc, c.prefix.back(), inverse, st))
+                return fail(MM_ENOTSUP, "no specialised pass of length %d", c.P);
+            HIP_TRY(hipGetLastError());
+        }
+        return MM_OK;
+    };
     for (int stg = 0; stg < 4; ++stg) {
-        if (with_demag) {
+        if (with_demag && L.fast) {
+            bc.in = src[stg];
+            mm_status r;
+            if ((r = run_classes(0, 0, 0)) != MM_OK) return r;  // x forward
+            if ((r = run_classes(1, 1, 0)) != MM_OK) return r;  // y forward
+            if ((r = run_classes(2, 2, 0)) != MM_OK) return r;  // z k-space
+            if ((r = run_classes(3, 3, 0)) != MM_OK) return r;  // y k-space
+            if ((r = run_classes(1, 1, 1)) != MM_OK) return r;  // y inverse
+            if ((r = run_classes(0, 4, 0)) != MM_OK) return r;  // x inverse
+        } else if (with_demag) {
             p.in = src[stg];
             p.prefix = pre + 0 * (n + 1);
             HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, nullptr, st));
@@ -1659,6 +1764,14 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
         for (int s = 0; s <= n; ++s) pre[q * (n + 1) + s] = BL.prefix[q][s];
     e = hipMemcpyAsync(b->at<char>(BL.o_prefix), pre.data(), pre.size() * sizeof(int),
                        hipMemcpyHostToDevice, hs);
+    std::vector<int> cints((size_t)std::max<int64_t>(BL.class_ints, 1), 0);
+    for (const BatchClassHost& c : BL.classes) {
+        std::copy(c.members.begin(), c.members.end(), cints.begin() + c.off);
+        std::copy(c.prefix.begin(), c.prefix.end(), cints.begin() + c.off + c.members.size());
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->at<char>(BL.o_classes), cints.data(), cints.size() * sizeof(int),
+                           hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return bail(fail(MM_EHIP, "prefix upload: %s", hipGetErrorString(e)));
     // kernel spectra and twiddles: one single-grid setup per grid on the scratch region

@@ -4,6 +4,7 @@
 // of every grid's tiles, and a work-group finds its grid by binary search in
 // the per-pass tile prefix sums, then runs the same device body as the
 // single-grid runtime-radix kernels with that grid's descriptor.
+#include "mm_fast.hpp"
 #include "mm_generic.hpp"
 #include "mm_llg_body.hpp"
 
@@ -159,6 +160,130 @@ __global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g
     a.stage = g.stage;
     body_llg_stage<T>(a, (int64_t)(tile - p.prefix[s]) * kBatchNT + threadIdx.x);
 }
+
+// ---- size classes: the specialised bodies, one launch per padded length
+template <typename T, int P, int L>
+__global__ __launch_bounds__(L * (P / Sched<P>::R0)) void kbf_xfwd(BatchClass<T> c)
+{
+    __shared__ cpx<T> lds[xfwd_lds_elems<P, L>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const XLineArgs a{c.in + d.moff, c.S + d.soff, 3 * d.nz, d.ny, d.nx, d.Sy, c.tw + d.twx, L};
+    body_xfwd<T, P, L>(a, tile - c.prefix[q], lds);
+}
+
+template <typename T, int P, int L>
+__global__ __launch_bounds__(L * (P / Sched<P>::R0)) void kbf_xinv(BatchClass<T> c)
+{
+    __shared__ cpx<T> lds[xinv_lds_elems<P, L>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const XLineArgs a{c.S + d.soff, c.out + d.moff, 3 * d.nz, d.ny, d.nx, d.Sy, c.tw + d.twx, L};
+    body_xinv<T, P, L>(a, tile - c.prefix[q], lds);
+}
+
+template <typename T, int P, bool INV>
+__global__ __launch_bounds__(256) void kbf_yline(BatchClass<T> c)
+{
+    __shared__ cpx<T> lds[yline_lds_elems<P>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const YLineArgs a{c.S + d.soff, 3 * d.nz * d.hx, d.Sy, INV ? d.Py : d.ny, INV ? d.ny : d.Py,
+                      c.tw + d.twy};
+    body_yline<T, P, INV>(a, tile - c.prefix[q], lds);
+}
+
+template <typename T, int PZ>
+__global__ __launch_bounds__(3 * kZCols) void kbf_kspace_z(BatchClass<T> c)
+{
+    __shared__ cpx<T> sh[kspace_z_lds_elems<PZ>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const int64_t plane = (int64_t)d.hx * d.Py;
+    const KzArgs a{c.S + d.soff, d.nz * plane, (int)plane, d.nz, d.Py, c.tw + d.twz, c.kern + d.koff,
+                   d.oct, (int64_t)d.hx * (d.Py / 2 + 1), d.Py / 2 + 1};
+    body_kspace_z<T, PZ>(a, tile - c.prefix[q], sh);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void kbf_kspace_y(BatchClass<T> c)
+{
+    __shared__ cpx<T> lds[kspace_y_lds_elems<P>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const KyArgs a{c.S + d.soff, (int64_t)d.hx * d.ny, d.ny, d.hx, d.ny, c.tw + d.twy, c.kern + d.koff,
+                   d.oct, d.Py / 2 + 1};
+    body_kspace_y<T, P>(a, tile - c.prefix[q], lds);
+}
+
+template <typename T, int P>
+static bool class_launch(int kind, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s)
+{
+    constexpr int TL = P / Sched<P>::R0;
+    switch (kind) {
+    case 0:
+        if constexpr (P >= 16 && xfwd_lds_elems<P, 8>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
+            hipLaunchKernelGGL((kbf_xfwd<T, P, 8>), dim3(tiles), dim3(8 * TL), 0, s, c);
+            return true;
+        }
+        return false;
+    case 4:
+        if constexpr (P >= 16 && xinv_lds_elems<P, 8>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
+            hipLaunchKernelGGL((kbf_xinv<T, P, 8>), dim3(tiles), dim3(8 * TL), 0, s, c);
+            return true;
+        }
+        return false;
+    case 1:
+        if constexpr (P >= 16) {
+            if (inverse)
+                hipLaunchKernelGGL((kbf_yline<T, P, true>), dim3(tiles), dim3(256), 0, s, c);
+            else
+                hipLaunchKernelGGL((kbf_yline<T, P, false>), dim3(tiles), dim3(256), 0, s, c);
+            return true;
+        }
+        return false;
+    case 2:
+        if constexpr (P <= 64 && kspace_z_lds_elems<P>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
+            hipLaunchKernelGGL((kbf_kspace_z<T, P>), dim3(tiles), dim3(3 * kZCols), 0, s, c);
+            return true;
+        }
+        return false;
+    default:
+        if constexpr (P >= 16 && P <= 1024) {
+            hipLaunchKernelGGL((kbf_kspace_y<T, P>), dim3(tiles), dim3(3 * ky_lines<P>() * TL), 0, s, c);
+            return true;
+        }
+        return false;
+    }
+}
+
+template <typename T>
+bool launch_batch_class(int kind, int P, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s)
+{
+    if (tiles <= 0) return true;
+    switch (P) {
+    case 2: return class_launch<T, 2>(kind, c, tiles, inverse, s);
+    case 4: return class_launch<T, 4>(kind, c, tiles, inverse, s);
+    case 8: return class_launch<T, 8>(kind, c, tiles, inverse, s);
+    case 16: return class_launch<T, 16>(kind, c, tiles, inverse, s);
+    case 32: return class_launch<T, 32>(kind, c, tiles, inverse, s);
+    case 64: return class_launch<T, 64>(kind, c, tiles, inverse, s);
+    case 128: return class_launch<T, 128>(kind, c, tiles, inverse, s);
+    case 256: return class_launch<T, 256>(kind, c, tiles, inverse, s);
+    case 512: return class_launch<T, 512>(kind, c, tiles, inverse, s);
+    case 1024: return class_launch<T, 1024>(kind, c, tiles, inverse, s);
+    case 2048: return class_launch<T, 2048>(kind, c, tiles, inverse, s);
+    default: return false;
+    }
+}
+
+template bool launch_batch_class<float>(int, int, const BatchClass<float>&, int, int, hipStream_t);
+template bool launch_batch_class<double>(int, int, const BatchClass<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,

@@ -1,455 +1,42 @@
-// mm_fast.hip -- FFT passes specialised at compile time for power-of-two
-// padded sizes (the common case: P = 2n with n a power of two).
-//
-// Spectrum layout shared with the generic passes: S = [3][nz][hx][Sy] complex
-// (Sy = Py on 3-D grids, ny on one-cell-thick grids), i.e. the x pass writes
-// its half spectrum transposed so that every y line is contiguous.
-//
-// Line passes (x and y): a line of P points is worked by TL = P / R1 threads.
-// Stage 1 of the Stockham schedule takes its R1 inputs x[u + TL r] straight
-// from global memory (coalesced), stages 2.. go through LDS, and the last
-// stage writes x[i + r P/R] straight to global memory (coalesced).  All
-// radices, spans and strides are compile-time constants.
-//
-// Z pass: one thread per (column, component) holds the whole z line in
-// registers; components meet in LDS for the Eq. 14 product.
-#include "mm_fft.hpp"
-#include "mm_kernels.hpp"
+// mm_fast.hip -- single-grid kernels of the size-specialised FFT passes (bodies
+// in mm_fast.hpp) and their dispatch by padded size.
+#include "mm_fast.hpp"
 
 namespace mm {
 
-template <int P>
-struct Sched;
-template <> struct Sched<2> { static constexpr int NS = 1, R0 = 2, R1 = 0, R2 = 0; };
-template <> struct Sched<4> { static constexpr int NS = 1, R0 = 4, R1 = 0, R2 = 0; };
-template <> struct Sched<8> { static constexpr int NS = 1, R0 = 8, R1 = 0, R2 = 0; };
-template <> struct Sched<16> { static constexpr int NS = 1, R0 = 16, R1 = 0, R2 = 0; };
-template <> struct Sched<32> { static constexpr int NS = 2, R0 = 8, R1 = 4, R2 = 0; };
-template <> struct Sched<64> { static constexpr int NS = 2, R0 = 8, R1 = 8, R2 = 0; };
-template <> struct Sched<128> { static constexpr int NS = 2, R0 = 16, R1 = 8, R2 = 0; };
-template <> struct Sched<256> { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 0; };
-template <> struct Sched<512> { static constexpr int NS = 3, R0 = 8, R1 = 8, R2 = 8; };
-template <> struct Sched<1024> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4; };
-template <> struct Sched<2048> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 8; };
-template <> struct Sched<4096> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 16; };
-
-template <int P, int S>
-constexpr int radix_of() { return S == 0 ? Sched<P>::R0 : (S == 1 ? Sched<P>::R1 : Sched<P>::R2); }
-template <int P, int S>
-constexpr int span_of() { return S == 0 ? 1 : (S == 1 ? Sched<P>::R0 : Sched<P>::R0 * Sched<P>::R1); }
-
-// LDS index with one pad slot every 16 entries (breaks the stride-R1 bank pattern
-// of the first-stage writes).
-__device__ constexpr int pad16(int e) { return e + (e >> 4); }
-// LDS line length: the in-line pad plus one slot so consecutive lines start on
-// different banks.
-template <int P>
-constexpr int padded_len() { return P + P / 16 + 1; }
-
-// Stage S >= 1 on one LDS line: each thread does R0/R butterflies.  Reads all,
-// barrier, writes all, barrier.
-template <typename T, int P, int S>
-__device__ inline void mid_stage(cpx<T>* ln, int u, const cpx<T>* __restrict__ tw)
-{
-    constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R, ts = m / p;
-    cpx<T> v[NB][R];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q, k = i & (p - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = ln[pad16(i + r * m)];
-        if (k != 0) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * ts]);
-        }
-        Dft<T, R>::run(v[q]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q, k = i & (p - 1), j = (i - k) * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) ln[pad16(j + r * p)] = v[q][r];
-    }
-    __syncthreads();
-}
-
-// Last stage: outputs land at natural index i + r * P/R; handed to `put`.
-template <typename T, int P, int S, typename Put>
-__device__ inline void last_stage(const cpx<T>* ln, int u, const cpx<T>* __restrict__ tw, Put put)
-{
-    constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R, ts = m / p;
-    static_assert(p == m, "last stage spans P / R");
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q;
-        cpx<T> v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = ln[pad16(i + r * m)];
-        if (i != 0) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * i * ts]);
-        }
-        Dft<T, R>::run(v);
-#pragma unroll
-        for (int r = 0; r < R; ++r) put(i + r * m, v[r]);
-    }
-}
-
-// Whole line after stage 1 has been computed into v (registers): write to LDS,
-// run the remaining stages, deliver outputs through put.  NS >= 2.
-template <typename T, int P, typename Put>
-__device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const cpx<T>* __restrict__ tw,
-                                   Put put)
-{
-    constexpr int NS = Sched<P>::NS, R0 = Sched<P>::R0;
-#pragma unroll
-    for (int r = 0; r < R0; ++r) ln[pad16(u * R0 + r)] = v[r];
-    __syncthreads();
-    if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, tw);
-    last_stage<T, P, NS - 1>(ln, u, tw, put);
-}
-
-// In-register FFT of N points (N <= 64), all indices compile-time; Stockham
-// order so the output is in natural order.
-template <typename T, int N>
-__device__ inline void fft_reg(cpx<T>* x, const cpx<T>* __restrict__ tw)
-{
-    constexpr int NS = Sched<N>::NS;
-    if constexpr (NS == 1) {
-        Dft<T, N>::run(x);
-    } else {
-        constexpr int R0 = Sched<N>::R0, R1 = Sched<N>::R1;
-        // stage 0 (p = 1): no twiddles
-        cpx<T> y[N];
-        constexpr int m0 = N / R0;
-#pragma unroll
-        for (int i = 0; i < m0; ++i) {
-            cpx<T> u[R0];
-#pragma unroll
-            for (int r = 0; r < R0; ++r) u[r] = x[i + r * m0];
-            Dft<T, R0>::run(u);
-#pragma unroll
-            for (int r = 0; r < R0; ++r) y[i * R0 + r] = u[r];
-        }
-        // stage 1 (p = R0, last): j = i
-        constexpr int m1 = N / R1, ts = m1 / R0;
-        static_assert(m1 == R0, "two-stage register FFT");
-#pragma unroll
-        for (int i = 0; i < m1; ++i) {
-            cpx<T> u[R1];
-#pragma unroll
-            for (int r = 0; r < R1; ++r) u[r] = y[i + r * m1];
-            if (i != 0) {
-#pragma unroll
-                for (int r = 1; r < R1; ++r) u[r] = cmul(u[r], tw[r * i * ts]);
-            }
-            Dft<T, R1>::run(u);
-#pragma unroll
-            for (int r = 0; r < R1; ++r) x[i + r * m1] = u[r];
-        }
-    }
-}
-
-// ------------------------------------------------------------------ y lines
 template <typename T, int P, bool INV>
 __global__ __launch_bounds__(256) void k_yline(YLineArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = 256 / TL, LP = padded_len<P>();
-    __shared__ cpx<T> lds[L * LP];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int l = threadIdx.x / TL, u = threadIdx.x % TL;
-    const int line = tile * L + l;
-    const bool ok = line < a.nlines;
-    cpx<T>* g = (cpx<T>*)a.buf + (int64_t)(ok ? line : 0) * a.line_stride;
-    const cpx<T>* tw = (const cpx<T>*)a.tw;
-    cpx<T> v[R0];
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-        const int e = u + TL * r;
-        cpx<T> x = {(T)0, (T)0};
-        if (ok && e < a.nin) x = g[e];
-        v[r] = INV ? conj(x) : x;
-    }
-    Dft<T, R0>::run(v);
-    auto put = [&](int e, cpx<T> val) {
-        if (ok && e < a.nout) g[e] = INV ? conj(val) : val;
-    };
-    if constexpr (Sched<P>::NS == 1) {
-#pragma unroll
-        for (int r = 0; r < R0; ++r) put(r, v[r]);
-    } else {
-        finish_line<T, P>(lds + l * LP, u, v, tw, put);
-    }
-}
-
-// ------------------------------------------------------------------ x forward
-constexpr int kLdsBudget = 160 * 1024;
-// 8 complex lines (16 consecutive real rows of one (component, z) plane) per
-// work-group; the half spectrum is stored transposed, 16 rows per bin.
-// A work-group of the x passes holds L complex lines = 2L consecutive rows of
-// one plane (L = 8: 128-byte transposed segments in FP32; L = 4: half the LDS,
-// twice the work-groups per CU).
-
-template <typename T, int P, int L>
-constexpr int x_lds_bytes()
-{
-    return (int)sizeof(cpx<T>) * ((L * padded_len<P>() > 2 * L * (P / 2 + 1)) ? L * padded_len<P>()
-                                                                              : 2 * L * (P / 2 + 1));
+    __shared__ cpx<T> lds[yline_lds_elems<P>()];
+    body_yline<T, P, INV>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int P, int L>
 __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xfwd(XLineArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
-    constexpr int HX = P / 2 + 1, ROWS = 2 * L;
-    __shared__ cpx<T> lds[L * LP];
-    const int tpp = (a.ny + ROWS - 1) / ROWS;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int plane = tile / tpp, yb = (tile - plane * tpp) * ROWS;
-    const int l = threadIdx.x / TL, u = threadIdx.x % TL;
-    const int y0 = yb + 2 * l;
-    const T* in = (const T*)a.in + ((int64_t)plane * a.ny + y0) * a.nx;
-    const bool ok0 = y0 < a.ny, ok1 = y0 + 1 < a.ny;
-    const cpx<T>* tw = (const cpx<T>*)a.tw;
-    cpx<T>* ln = lds + l * LP;
-    cpx<T> v[R0];
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-        const int e = u + TL * r;
-        cpx<T> x = {(T)0, (T)0};
-        if (e < a.nx) {
-            if (ok0) x.re = in[e];
-            if (ok1) x.im = in[a.nx + e];
-        }
-        v[r] = x;
-    }
-    Dft<T, R0>::run(v);
-    if constexpr (Sched<P>::NS == 1) {
-#pragma unroll
-        for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
-    } else {
-        // the last stage writes back to LDS in natural order (in place: each thread
-        // rewrites exactly the slots its own butterflies read)
-        finish_line<T, P>(ln, u, v, tw, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
-    }
-    __syncthreads();
-    cpx<T>* out = (cpx<T>*)a.out + (int64_t)plane * HX * a.srows;
-    for (int idx = threadIdx.x; idx < HX * ROWS; idx += NT) {
-        const int rr = idx % ROWS, kx = idx / ROWS, q = rr >> 1;
-        const cpx<T> zk = lds[q * LP + pad16(kx)];
-        const cpx<T> zm = lds[q * LP + pad16(kx == 0 ? 0 : P - kx)];
-        // Z = FFT(a + i b): A = (Z_k + conj Z_-k)/2, B = (Z_k - conj Z_-k)/(2i)
-        const cpx<T> val = (rr & 1) ? scale(mul_mi(zk - conj(zm)), (T)0.5)
-                                    : scale(zk + conj(zm), (T)0.5);
-        if (yb + rr < a.ny) out[(int64_t)kx * a.srows + yb + rr] = val;
-    }
+    __shared__ cpx<T> lds[xfwd_lds_elems<P, L>()];
+    body_xfwd<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-// ------------------------------------------------------------------ x inverse
 template <typename T, int P, int L>
 __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
-    constexpr int HX = P / 2 + 1, ROWS = 2 * L;
-    constexpr int LDSN = (L * LP > ROWS * HX) ? L * LP : ROWS * HX;
-    __shared__ cpx<T> lds[LDSN];
-    const int tpp = (a.ny + ROWS - 1) / ROWS;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int plane = tile / tpp, yb = (tile - plane * tpp) * ROWS;
-    const cpx<T>* src = (const cpx<T>*)a.in + (int64_t)plane * HX * a.srows;
-    // gather the 16 half-spectrum rows of this block: raw[rr][kx]
-    for (int idx = threadIdx.x; idx < HX * ROWS; idx += NT) {
-        const int rr = idx % ROWS, kx = idx / ROWS;
-        cpx<T> x = {(T)0, (T)0};
-        if (yb + rr < a.ny) x = src[(int64_t)kx * a.srows + yb + rr];
-        lds[rr * HX + kx] = x;
-    }
-    __syncthreads();
-    const int l = threadIdx.x / TL, u = threadIdx.x % TL;
-    const cpx<T>* ra = lds + (2 * l) * HX;
-    const cpx<T>* rb = lds + (2 * l + 1) * HX;
-    cpx<T> v[R0];
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-        const int k = u + TL * r;
-        cpx<T> A, B;
-        if (k < HX) {
-            A = ra[k];
-            B = rb[k];
-            if (k == 0 || 2 * k == P) {  // DC and Nyquist bins of a real row are real
-                A.im = (T)0;
-                B.im = (T)0;
-            }
-        } else {
-            A = conj(ra[P - k]);
-            B = conj(rb[P - k]);
-        }
-        v[r] = conj(cpx<T>{A.re - B.im, A.im + B.re});  // conj(A + i B): inverse by conjugation
-    }
-    Dft<T, R0>::run(v);
-    __syncthreads();  // every raw read is done before the FFT reuses the LDS
-    const int y0 = yb + 2 * l;
-    T* out = (T*)a.out + ((int64_t)plane * a.ny + y0) * a.nx;
-    const bool ok0 = y0 < a.ny, ok1 = y0 + 1 < a.ny;
-    auto put = [&](int e, cpx<T> val) {  // result a + i b = conj(val)
-        if (e < a.nx) {
-            if (ok0) out[e] = val.re;
-            if (ok1) out[a.nx + e] = -val.im;
-        }
-    };
-    if constexpr (Sched<P>::NS == 1) {
-#pragma unroll
-        for (int r = 0; r < R0; ++r) put(r, v[r]);
-    } else {
-        finish_line<T, P>(lds + l * LP, u, v, (const cpx<T>*)a.tw, put);
-    }
+    __shared__ cpx<T> lds[xinv_lds_elems<P, L>()];
+    body_xinv<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
-
-// ------------------------------------------------------------------ z k-space
-constexpr int kZCols = 64;
 
 template <typename T, int PZ>
 __global__ __launch_bounds__(3 * kZCols) void k_kspace_z(KzArgs a)
 {
-    __shared__ cpx<T> sh[3 * PZ * kZCols];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int comp = threadIdx.x / kZCols, t = threadIdx.x % kZCols;
-    const int col = tile * kZCols + t;
-    const bool ok = col < a.ncols;
-    // 32-bit element offsets from the uniform base pointers (the spectrum and
-    // the octant both stay below 2^31 elements)
-    const int zs = a.ncols;  // z stride: one (kx, ky) plane
-    const cpx<T>* tw = (const cpx<T>*)a.tw;
-    cpx<T>* buf = (cpx<T>*)a.buf;
-    const int base = comp * (int)a.comp_stride + (ok ? col : 0);
-    cpx<T> v[PZ];
-#pragma unroll
-    for (int z = 0; z < PZ; ++z) {
-        cpx<T> x = {(T)0, (T)0};
-        if (ok && z < a.nz) x = buf[base + z * zs];
-        v[z] = x;
-    }
-    fft_reg<T, PZ>(v, tw);
-#pragma unroll
-    for (int z = 0; z < PZ; ++z) sh[(comp * PZ + z) * kZCols + t] = v[z];
-    __syncthreads();
-    // Eq. 14, row `comp` of the symmetric tensor; negative frequencies mirror with
-    // the component parities (xy odd in y, xz odd in z, yz odd in y and z).
-    const int kx = (ok ? col : 0) / a.Py;
-    int ky = (ok ? col : 0) - kx * a.Py;
-    T sy = (T)1;
-    if (2 * ky > a.Py) {
-        ky = a.Py - ky;
-        sy = (T)-1;
-    }
-    const T* K = (const T*)a.kern;
-    const int ko = kx * (int)a.k_xs + ky, cs = (int)a.k_cs, kzs = (int)a.k_zs;
-    // the three spectra of row `comp` and their parity signs in y
-    const int c0 = comp == 0 ? 0 : (comp == 1 ? 1 : 2);
-    const int c1 = comp == 0 ? 1 : (comp == 1 ? 3 : 4);
-    const int c2 = comp == 0 ? 2 : (comp == 1 ? 4 : 5);
-    const T y0 = comp == 1 ? sy : (T)1, y1 = comp == 0 ? sy : (comp == 2 ? sy : (T)1);
-    const T y2 = comp == 1 ? sy : (T)1;
-    // parity signs in z: xz (c=2) and yz (c=4) are odd
-    const bool z0 = c0 == 2, z1 = c1 == 4, z2 = (c2 == 2 || c2 == 4);
-#pragma unroll
-    for (int z = 0; z < PZ; ++z) {
-        constexpr int H = PZ / 2;
-        const int kz = z <= H ? z : PZ - z;
-        const T sz = (z <= H || 2 * z == PZ) ? (T)1 : (T)-1;
-        const int kk = ko + kz * kzs;
-        const T k0 = y0 * (z0 ? sz : (T)1) * K[c0 * cs + kk];
-        const T k1 = y1 * (z1 ? sz : (T)1) * K[c1 * cs + kk];
-        const T k2 = y2 * (z2 ? sz : (T)1) * K[c2 * cs + kk];
-        const cpx<T> m0 = sh[(0 * PZ + z) * kZCols + t];
-        const cpx<T> m1 = sh[(1 * PZ + z) * kZCols + t];
-        const cpx<T> m2 = sh[(2 * PZ + z) * kZCols + t];
-        const cpx<T> h = {k0 * m0.re + k1 * m1.re + k2 * m2.re, k0 * m0.im + k1 * m1.im + k2 * m2.im};
-        v[z] = conj(h);
-    }
-    fft_reg<T, PZ>(v, tw);
-    if (ok) {
-#pragma unroll
-        for (int z = 0; z < PZ; ++z)
-            if (z < a.nz) buf[base + z * zs] = conj(v[z]);
-    }
+    __shared__ cpx<T> sh[kspace_z_lds_elems<PZ>()];
+    body_kspace_z<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
-
-// ------------------------------------------------------------ y k-space (2-D)
-// One-cell-thick grids: the k-space pass runs along y.  A work-group holds L
-// x-bins, three component lines each: forward FFT (stage 1 from global memory),
-// Eq. 14 product with the four real spectra (xx, xy, yy, zz) in LDS, inverse
-// FFT (stage 1 from LDS, last stage to global memory).
-template <int P>
-constexpr int ky_lines() { return (256 / (3 * (P / Sched<P>::R0))) > 0 ? 256 / (3 * (P / Sched<P>::R0)) : 1; }
 
 template <typename T, int P>
 __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspace_y(KyArgs a)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = ky_lines<P>(), NT = 3 * L * TL;
-    constexpr int LP = padded_len<P>();
-    __shared__ cpx<T> lds[3 * L * LP];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int line = threadIdx.x / TL, u = threadIdx.x % TL;
-    const int comp = line / L, l = line - comp * L;
-    const int kx = tile * L + l;
-    const bool ok = kx < a.hx;
-    cpx<T>* g = (cpx<T>*)a.buf + comp * a.comp_stride + (int64_t)(ok ? kx : 0) * a.line_stride;
-    cpx<T>* ln = lds + line * LP;
-    const cpx<T>* tw = (const cpx<T>*)a.tw;
-    cpx<T> v[R0];
-#pragma unroll
-    for (int r = 0; r < R0; ++r) {
-        const int e = u + TL * r;
-        cpx<T> x = {(T)0, (T)0};
-        if (ok && e < a.ny) x = g[e];
-        v[r] = x;
-    }
-    Dft<T, R0>::run(v);
-    if constexpr (Sched<P>::NS == 1) {
-#pragma unroll
-        for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
-    } else {
-        finish_line<T, P>(ln, u, v, tw, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
-    }
-    __syncthreads();
-    const T* K = (const T*)a.kern;
-    for (int idx = threadIdx.x; idx < L * P; idx += NT) {
-        const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
-        if (kx2 >= a.hx) continue;
-        int ky = e;
-        T sy = (T)1;
-        if (2 * ky > P) {
-            ky = P - ky;
-            sy = (T)-1;
-        }
-        const T* Kp = K + (int64_t)kx2 * a.k_xs + ky;
-        const T kxx = Kp[0], kxy = sy * Kp[a.k_cs], kyy = Kp[2 * a.k_cs], kzz = Kp[3 * a.k_cs];
-        cpx<T>* px = lds + (0 * L + l2) * LP + pad16(e);
-        cpx<T>* py = lds + (1 * L + l2) * LP + pad16(e);
-        cpx<T>* pz = lds + (2 * L + l2) * LP + pad16(e);
-        const cpx<T> mx = *px, my = *py, mz = *pz;
-        *px = conj(cpx<T>{kxx * mx.re + kxy * my.re, kxx * mx.im + kxy * my.im});
-        *py = conj(cpx<T>{kxy * mx.re + kyy * my.re, kxy * mx.im + kyy * my.im});
-        *pz = conj(cpx<T>{kzz * mz.re, kzz * mz.im});
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R0; ++r) v[r] = ln[pad16(u + TL * r)];
-    Dft<T, R0>::run(v);
-    auto put = [&](int e, cpx<T> val) {
-        if (ok && e < a.ny) g[e] = conj(val);
-    };
-    if constexpr (Sched<P>::NS == 1) {
-#pragma unroll
-        for (int r = 0; r < R0; ++r) put(r, v[r]);
-    } else {
-        __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
-        finish_line<T, P>(ln, u, v, tw, put);
-    }
+    __shared__ cpx<T> lds[kspace_y_lds_elems<P>()];
+    body_kspace_y<T, P>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -566,6 +153,38 @@ bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
     default: return false;
     }
 #undef MM_KYCASE
+}
+
+int fast_first_radix(int P)
+{
+    switch (P) {
+    case 2: return Sched<2>::R0;
+    case 4: return Sched<4>::R0;
+    case 8: return Sched<8>::R0;
+    case 16: return Sched<16>::R0;
+    case 32: return Sched<32>::R0;
+    case 64: return Sched<64>::R0;
+    case 128: return Sched<128>::R0;
+    case 256: return Sched<256>::R0;
+    case 512: return Sched<512>::R0;
+    case 1024: return Sched<1024>::R0;
+    case 2048: return Sched<2048>::R0;
+    default: return 0;
+    }
+}
+
+int fast_ky_lines(int P)
+{
+    switch (P) {
+    case 16: return ky_lines<16>();
+    case 32: return ky_lines<32>();
+    case 64: return ky_lines<64>();
+    case 128: return ky_lines<128>();
+    case 256: return ky_lines<256>();
+    case 512: return ky_lines<512>();
+    case 1024: return ky_lines<1024>();
+    default: return 0;
+    }
 }
 
 template bool launch_kspace_y<float>(const KyArgs&, int, hipStream_t);

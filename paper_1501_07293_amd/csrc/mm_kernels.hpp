@@ -262,6 +262,28 @@ struct BatchLlg {
     T can, alpha, gdt;
     int stage;
 };
+// A size class of a batch: the grids whose padded length for one pass is P.
+template <typename T>
+struct BatchClass {
+    const BatchDesc* d;
+    const int* members;  // class-local index -> grid index
+    const int* prefix;   // nmem + 1 tile prefix sums
+    int nmem;
+    const T* in;         // x forward: the stage input m
+    T* out;              // x inverse: the demag field
+    cpx<T>* S;
+    const T* kern;
+    const cpx<T>* tw;
+};
+// kind: 0 x forward, 1 y (inverse flag), 2 z k-space, 3 y k-space (one cell
+// thick), 4 x inverse.  Returns false when no specialised kernel has length P.
+template <typename T>
+bool launch_batch_class(int kind, int P, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s);
+// First radix of the specialised schedule of length P (0 if none), and the
+// lines per work-group of the specialised y k-space pass.
+int fast_first_radix(int P);
+int fast_ky_lines(int P);
+
 // which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse, 4 LLG stage.
 template <typename T>
 hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,

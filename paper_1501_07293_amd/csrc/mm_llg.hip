@@ -59,10 +59,12 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
     }
 }
 
+// XCD-aware: consecutive tiles (neighbouring rows of a plane) run on the same
+// XCD, so the y-neighbour rows one work-group reads are in that XCD's L2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
 {
-    body_llg_stage<T>(a, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+    body_llg_stage<T>(a, xcd_tile(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x);
 }
 
 template <typename T>

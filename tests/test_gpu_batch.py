@@ -21,30 +21,37 @@ def fields_for(n, seed=0):
     return mT_to_Apm(g.uniform(-40, 40, size=(n, 3)))
 
 
-def run_single(grid, hext, m0, precision, nsteps):
+def run_single(grid, hext, m0, precision, nsteps, pow2=False):
     nx, ny, nz = grid
     sim = mmag.Sim(nx, ny, nz, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                   precision=precision, generic_fft=True, threads=256)
+                   precision=precision, generic_fft=not pow2, threads=256, pow2_pad=pow2)
     sim.set_hext(hext)
     sim.set_m(m0)
     sim.step(nsteps, C.dt)
     return to_np(sim.get_m())
 
 
+FAST_MIXED = [g for g in MIXED if min(g[0], g[1]) >= 8]   # power-of-two padding >= 16
+
+
+@pytest.mark.parametrize("pow2", [False, True])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_batch_matches_single_grid_runs(precision):
-    hext = fields_for(len(MIXED))
-    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=100 + i) for i, g in enumerate(MIXED)]
-    b = mmag.BatchSim(MIXED, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                      hext=hext, precision=precision)
+def test_batch_matches_single_grid_runs(precision, pow2):
+    # runtime-radix passes on 7-smooth padding, or size classes of the specialised
+    # passes on power-of-two padding: each grid as if run alone
+    grids = FAST_MIXED if pow2 else MIXED
+    hext = fields_for(len(grids))
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=100 + i) for i, g in enumerate(grids)]
+    b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision=precision, pow2_pad=pow2)
     b.set_m(m0)
     b.step(20, C.dt)
     got = [to_np(x) for x in b.get_m()]
     worst = 0.0
-    for i, g in enumerate(MIXED):
-        ref = run_single(g, hext[i], m0[i], precision, 20)
+    for i, g in enumerate(grids):
+        ref = run_single(g, hext[i], m0[i], precision, 20, pow2=pow2)
         worst = max(worst, float(np.abs(got[i] - ref).max()))
-    print(f"batch vs single-grid runs ({precision}): max |dm| = {worst:.3e}")
+    print(f"batch vs single-grid runs ({precision}, pow2={pow2}): max |dm| = {worst:.3e}")
     assert worst <= (1e-13 if precision == "f64" else 1e-6)
 
 
@@ -80,14 +87,15 @@ def test_batch_graph_replay_matches_eager():
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_full_batched_workload_512_grids():
+@pytest.mark.parametrize("pow2", [False, True])
+def test_full_batched_workload_512_grids(pow2):
     # 512 grids, nx, ny uniform in [32, 128], nz in {1, 2}, fields in a 50 mT ball.
     samples = batch_samples(512, seed=0)
     grids = [(s.nx, s.ny, s.nz) for s in samples]
     hext = np.array([s.hext for s in samples])
     m0 = [random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples]
     b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                      hext=hext, precision="f32", graph=True)
+                      hext=hext, precision="f32", graph=True, pow2_pad=pow2)
     b.set_m(m0)
     b.step(10, C.dt)
     got = [to_np(x) for x in b.get_m()]
@@ -98,5 +106,5 @@ def test_full_batched_workload_512_grids():
     sizes = [g[0] * g[1] * g[2] for g in grids]
     pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 1, 100, 311, 511]))
     for i in pick:
-        ref = run_single(grids[i], hext[i], m0[i], "f32", 10)
+        ref = run_single(grids[i], hext[i], m0[i], "f32", 10, pow2=pow2)
         assert np.abs(got[i] - ref).max() <= 1e-6, (i, grids[i])
