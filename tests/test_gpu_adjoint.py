@@ -96,8 +96,10 @@ def test_adjoint_matches_finite_differences_on_the_128x128_case(precision):
     # forward (Richardson-extrapolated).
     # FP64: |ad - fd| <= 1e-6 |fd| per direction.  FP32: the error is bounded against
     # max(|fd|, rms projection), the rms of <grad, v> over unit-variance directions v,
-    # i.e. |grad|_2 |v|_2 / sqrt(N); FP32 rounding over 500 steps leaves ~1e-4 relative
-    # error in the gradient vector, which a projection that happens to be small inflates.
+    # i.e. |grad|_2 |v|_2 / sqrt(N).  FP32 rounding over 500 steps leaves a gradient error
+    # vector dg with |dg|_2 <= 1e-4 |grad|_2 (test_fp32_adjoint_tracks_fp64_adjoint); its
+    # projection on a Gaussian direction is Gaussian with standard deviation |dg|_2 |v|_2 /
+    # sqrt(N), so 3e-4 of the rms projection is the three-sigma bound.
     c, ku, m0, target = diff_problem()
     nsteps = c.steps
     gku = adjoint_grad(c, ku, m0, target, nsteps, precision)
@@ -114,7 +116,7 @@ def test_adjoint_matches_finite_differences_on_the_128x128_case(precision):
         if precision == "f64":
             assert rel <= 1e-6
         else:
-            assert rel_rms <= 1e-4
+            assert rel_rms <= 3e-4
 
 
 def test_fp32_adjoint_tracks_fp64_adjoint():
