@@ -27,6 +27,75 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_IDS = ["x_fwd", "y_fwd", "kspace", "y_inv", "x_inv", "llg"]
+PROFILES = os.path.join(ROOT, "profiles")
+# counter readings of a plain 1 GiB device copy (1 GiB read, 1 GiB written) under
+# rocprofv3 --pmc on MI355X: FETCH_SIZE reads 524299.5 KiB, WRITE_SIZE 1048576 KiB
+COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+
+
+CSRC = os.path.join(ROOT, "paper_1501_07293_amd", "csrc")
+# translation unit that defines each kernel family
+KERNEL_TU = [("mm::kbf_", "mm_batch.hip"), ("mm::kb_", "mm_batch.hip"),
+             ("mm::k_xfwd", "mm_fast.hip"), ("mm::k_xinv", "mm_fast.hip"),
+             ("mm::k_yline", "mm_fast.hip"), ("mm::k_kspace_z", "mm_fast.hip"),
+             ("mm::k_kspace_y", "mm_fast.hip"), ("mm::k_llg_stage", "mm_llg.hip"),
+             ("mm::k_row_", "mm_passes.hip"), ("mm::k_col_fft", "mm_passes.hip"),
+             ("mm::k_kspace<", "mm_passes.hip")]
+
+
+def tu_digest(tu: str) -> str:
+    """sha256 over a translation unit, the headers it includes (transitively) and
+    the build flags, so that counter readings taken on one build of a kernel are
+    not reported for another."""
+    import hashlib
+    import re
+    seen, todo = [], [tu]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        todo += re.findall(r'#include "(mm_[a-z_]+\.hpp)"', open(os.path.join(CSRC, f)).read())
+    h = hashlib.sha256()
+    for f in sorted(seen) + ["../build.py"]:
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_digest(kernel: str) -> str | None:
+    for prefix, tu in KERNEL_TU:
+        if kernel.startswith(prefix):
+            return tu_digest(tu)
+    return None
+
+
+def recorded_traffic(kernel: str, workload: str) -> dict | None:
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summaries (FETCH_SIZE and WRITE_SIZE, each scaled by the copy calibration);
+    None when no summary covers it or its sources changed since it was taken."""
+    if not os.path.isdir(PROFILES):
+        return None
+    digest = kernel_digest(kernel)
+    for f in sorted(os.listdir(PROFILES)):
+        if not f.endswith(".md"):
+            continue
+        text = open(os.path.join(PROFILES, f)).read()
+        start = text.find("```json\n")
+        if start < 0:
+            continue
+        end = text.find("```", start + 8)
+        try:
+            rec = json.loads(text[start + 8:end])
+        except ValueError:
+            continue
+        if rec.get("workload") != workload:
+            continue
+        k = rec.get("kernels", {}).get(kernel)
+        if k and k.get("hbm_bytes_per_launch") and digest and k.get("sources_sha256") == digest:
+            return {"bytes": k["hbm_bytes_per_launch"], "source": f"profiles/{f}"}
+    return None
 
 
 def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
@@ -296,11 +365,21 @@ def main():
                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": dom_ms,
                            "launches_timed": dom_n}
+        tr = recorded_traffic(out["roofline"]["kernel"], out["config"]["workload"])
+        if tr is not None:
+            # HBM bytes one launch moves (counters), against the algorithmic bytes above
+            out["roofline"]["traffic"] = tr["bytes"]
+            out["roofline"]["traffic_unit"] = "bytes/launch"
+            out["roofline"]["traffic_over_algorithmic"] = tr["bytes"] / ab[dom]
+            out["roofline"]["traffic_source"] = tr["source"]
         step_bytes = 4 * sum(ab.values())
         out["kernels"] = {k: {"avg_ms": v[0], "gbs": ab[k] / (v[0] * 1e-3) / 1e9 if v[0] else None}
                           for k, v in per_kernel.items()}
         out["step_model_bytes_per_cell"] = step_bytes / cfg.N
+        out["algorithmic_bytes"] = ab
+        out["plan"] = {k: plan[k] for k in ("px", "py", "pz", "passes", "threads", "generic_fft", "x_lines")}
         out["effective_gbs"] = step_bytes / (secs / args.steps) / 1e9
+    out["sources_sha256"] = {tu: tu_digest(tu) for tu in sorted({t for _, t in KERNEL_TU})}
     out["energy_J"] = energy.tolist()
     out["copy_gbs_measured"] = copy_bandwidth()
 
@@ -352,7 +431,8 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
     if k == "llg":
         return f"mm::k_llg_stage<{t}>"
     if k in ("x_fwd", "x_inv"):
-        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}>" if x_ok else \
+        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {plan.get('x_lines', 8)}>" \
+            if x_ok else \
             f"mm::k_row_{'r2c' if k == 'x_fwd' else 'c2r'}<{t}, {plan['threads']}>"
     if k in ("y_fwd", "y_inv"):
         return f"mm::k_yline<{t}, {py}, {'true' if k == 'y_inv' else 'false'}>" if y_ok else \
@@ -364,5 +444,110 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
     return f"mm::k_kspace_y<{t}, {py}>" if ky_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
 
 
+def kernel_key(name: str) -> str:
+    """rocprofv3's demangled name without 'void ' and the argument list."""
+    name = name[5:] if name.startswith("void ") else name
+    if not name.endswith(")"):
+        return name
+    # the argument list is the last top-level parenthesis group
+    depth = 0
+    for i in range(len(name) - 1, -1, -1):
+        depth += name[i] == ")"
+        depth -= name[i] == "("
+        if depth == 0:
+            return name[:i]
+    return name
+
+
+def summarize_rocprof(run_dir: str, out_dir: str, command: str) -> str:
+    """Writes a summary of one profiled bench run: kernel-trace statistics
+    (run_dir/kt), FETCH_SIZE (run_dir/pf) and WRITE_SIZE (run_dir/pw) per dispatch,
+    both scaled by what they read for the 1 GiB device copy of the same run, and
+    the bench line of the kernel-trace run (run_dir/kt.log)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(pattern):
+        found = glob.glob(os.path.join(run_dir, pattern), recursive=True)
+        if not found:
+            raise SystemExit(f"no {pattern} under {run_dir}")
+        return found[0]
+
+    stats = list(csv.DictReader(open(one("kt/**/*kernel_stats.csv"))))
+    line = [l for l in open(os.path.join(run_dir, "kt.log")) if l.startswith("{")][-1]
+    b = json.loads(line)
+
+    def counter(pattern, name):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(one(pattern))):
+            if r["Counter_Name"] == name:
+                per[kernel_key(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return per
+
+    fetch = counter("pf/**/*counter_collection.csv", "FETCH_SIZE")
+    write = counter("pw/**/*counter_collection.csv", "WRITE_SIZE")
+    copy = "__amd_rocclr_copyBuffer"
+    scale = {"FETCH_SIZE": (1 << 30) / (max(fetch[copy]) * 1024),
+             "WRITE_SIZE": (1 << 30) / (max(write[copy]) * 1024)}
+    rl = b["roofline"]
+    dom = rl["kernel"]
+    workload = b["config"]["workload"]
+    ab = {mm_kernel_symbol(k, b["dtype"], b["plan"]): v for k, v in b["algorithmic_bytes"].items()}
+    rows, kernels = [], {}
+    for k in sorted(set(fetch) & set(write) - {copy}):
+        f = sum(fetch[k]) / len(fetch[k])
+        w = sum(write[k]) / len(write[k])
+        hbm = 1024 * (f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"])
+        tu = next((t for prefix, t in KERNEL_TU if k.startswith(prefix)), None)
+        kernels[k] = {"dispatches": len(fetch[k]), "fetch_kib": f, "write_kib": w,
+                      "hbm_bytes_per_launch": hbm,
+                      "sources_sha256": b["sources_sha256"].get(tu) if tu else None}
+        if k in ab:
+            kernels[k]["algorithmic_bytes_per_launch"] = ab[k]
+        rows.append((k, len(fetch[k]), f, w, hbm, ab.get(k)))
+    short = dom.split("::")[-1].split("<")[0].replace("k_", "")
+    tag = f"{short}_{b['config']['workload'].split(' cells')[0].replace(' ', '_')}_{b['dtype']}"
+    path = os.path.join(out_dir, tag + ".md")
+    lines = [f"# {dom} and the other kernels of one RK4 step: {workload}", "",
+             "Commands:", "",
+             "```", command.strip(), "```", "",
+             "## Kernel time (`rocprofv3 --kernel-trace --stats`)", "",
+             "| kernel | calls | avg µs | % of GPU time |", "|---|---|---|---|"]
+    for r in stats[:14]:
+        lines.append(f"| `{kernel_key(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} "
+                     f"| {float(r['Percentage']):.1f} |")
+    dom_rows = [r for r in stats if kernel_key(r["Name"]) == dom]
+    if dom_rows:
+        lines += ["", f"Dominant kernel `{dom}`: rocprofv3 average {float(dom_rows[0]['AverageNs']) / 1e3:.1f} µs"
+                      f" over {dom_rows[0]['Calls']} launches; the bench's HIP events in the same run "
+                      f"{1e3 * rl['avg_launch_ms']:.1f} µs over {rl['launches_timed']} launches."]
+    lines += ["", "## HBM traffic per dispatch (`rocprofv3 --pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)", "",
+              f"Calibration on the 1 GiB device copy of the same run: FETCH_SIZE reads "
+              f"{max(fetch[copy]):.1f} KiB (scale {scale['FETCH_SIZE']:.4f}), WRITE_SIZE "
+              f"{max(write[copy]):.1f} KiB (scale {scale['WRITE_SIZE']:.4f}). HBM bytes = 1024 · "
+              f"(FETCH · scale + WRITE · scale).", "",
+              "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM MB | algorithmic MB | HBM / algorithmic |",
+              "|---|---|---|---|---|---|---|"]
+    for k, n, f, w, hbm, a in sorted(rows, key=lambda r: -r[4]):
+        ratio = f"{hbm / a:.3f}" if a else ""
+        am = f"{a / 1e6:.1f}" if a else ""
+        lines.append(f"| `{k}` | {n} | {f:.0f} | {w:.0f} | {hbm / 1e6:.1f} | {am} | {ratio} |")
+    lines += ["", f"Bench line of the kernel-trace run: value {b['value']:.4g} {b['unit']}, "
+                  f"{b['ms_per_step']:.3f} ms per step (profiler attached).", "",
+              "Record read by `bench.py` for `roofline.traffic` (a kernel's entry holds while "
+              "its translation unit and headers hash to its `sources_sha256`):", "", "```json",
+              json.dumps({"workload": workload, "precision": b["dtype"], "copy_scale": scale,
+                          "kernels": kernels}, indent=1), "```", ""]
+    os.makedirs(out_dir, exist_ok=True)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines))
+    return path
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
+        # bench.py --summarize-rocprof RUN_DIR OUT_DIR "COMMANDS"
+        print(summarize_rocprof(sys.argv[2], sys.argv[3], sys.argv[4]))
+    else:
+        main()

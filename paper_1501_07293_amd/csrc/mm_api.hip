@@ -956,7 +956,7 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
             p.three_d ? (3 * p.nz * p.hx + d.y_lines - 1) / d.y_lines : 0,
             p.three_d ? (int)((p.hx * (int64_t)p.Py + p.k_tw - 1) / p.k_tw) : (p.hx + p.k_tw - 1) / p.k_tw,
             (npairs + p.x_lines - 1) / p.x_lines,
-            (int)((p.nx * (int64_t)p.ny * ((p.nz + kLlgZ - 1) / kLlgZ) + 255) / 256)};
+            (int)llg_blocks(p.nx, p.ny, p.nz)};
         for (int q = 0; q < 5; ++q) L->prefix[q][s + 1] = L->prefix[q][s] + tiles[q];
     }
     L->prec = o.prec;

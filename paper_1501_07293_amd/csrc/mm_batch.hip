@@ -11,6 +11,7 @@
 namespace mm {
 
 constexpr int kBatchNT = 256;
+static_assert(kBatchNT == kLlgNT, "the batched LLG pass launches kLlgNT threads per work-group");
 
 __device__ inline int find_sample(const int* prefix, int n, int tile)
 {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g
     a.alpha = g.alpha;
     a.gdt = g.gdt;
     a.stage = g.stage;
-    body_llg_stage<T>(a, (int64_t)(tile - p.prefix[s]) * kBatchNT + threadIdx.x);
+    body_llg_stage<T>(a, tile - p.prefix[s], threadIdx.x);
 }
 
 // ---- size classes: the specialised bodies, one launch per padded length

@@ -187,8 +187,15 @@ struct LlgArgs {
     T gdt;           // gamma Ms dt / (1 + alpha^2)
     int stage;       // 1..4 (RK4 stages), 0 (explicit Euler with renormalisation)
 };
-// the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes
+// the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes;
+// a work-group of kLlgNT threads covers kLlgNT consecutive columns of one chunk,
+// and the chunks of the same columns are consecutive work-groups
 constexpr int kLlgZ = 4;
+constexpr int kLlgNT = 256;
+__host__ __device__ inline int64_t llg_blocks(int nx, int ny, int nz)
+{
+    return ((int64_t)nx * ny + kLlgNT - 1) / kLlgNT * ((nz + kLlgZ - 1) / kLlgZ);
+}
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s);
 

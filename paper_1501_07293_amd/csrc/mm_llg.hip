@@ -62,9 +62,9 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
 // XCD-aware: consecutive tiles (neighbouring rows of a plane) run on the same
 // XCD, so the y-neighbour rows one work-group reads are in that XCD's L2.
 template <typename T>
-__global__ __launch_bounds__(256) void k_llg_stage(LlgArgs<T> a)
+__global__ __launch_bounds__(kLlgNT) void k_llg_stage(LlgArgs<T> a)
 {
-    body_llg_stage<T>(a, xcd_tile(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x);
+    body_llg_stage<T>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 template <typename T>
@@ -199,8 +199,7 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
 {
-    const int64_t threads = (int64_t)a.nx * a.ny * ((a.nz + kLlgZ - 1) / kLlgZ);
-    hipLaunchKernelGGL(k_llg_stage<T>, dim3(blocks_for(threads)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_llg_stage<T>, dim3((int)llg_blocks(a.nx, a.ny, a.nz)), dim3(kLlgNT), 0, s, a);
     return hipGetLastError();
 }
 

@@ -10,25 +10,22 @@ namespace mm {
 // One thread per (x, y) column and chunk of kLlgZ planes.  Every load of the
 // chunk (m of planes k0-1 .. k0+kLlgZ, in-plane neighbours, H_d, Ku, m_n, acc)
 // is issued before the first store, so a thread keeps many loads in flight;
-// the z neighbours come from registers, the x and y neighbours from rows that
-// neighbouring threads load anyway (L1/L2 hits).
+// the z neighbours inside the chunk come from registers, the x and y neighbours
+// from rows that neighbouring threads load anyway.  Work-group b takes chunk
+// b % nzc of the column block b / nzc: the chunks of one column block are
+// consecutive work-groups, so the two planes a chunk shares with its z
+// neighbours are read from HBM once and found in L2 the second time.
 
+// Thread `lane` of work-group `blk` (0 <= blk < llg_blocks, 0 <= lane < kLlgNT).
 template <typename T>
-__device__ inline int64_t llg_threads(const LlgArgs<T>& a)
-{
-    return (int64_t)a.nx * a.ny * ((a.nz + kLlgZ - 1) / kLlgZ);
-}
-
-// Thread t of the stage (0 <= t < llg_threads).
-template <typename T>
-__device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t t)
+__device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane)
 {
     constexpr int KZ = kLlgZ;
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int nzc = (a.nz + KZ - 1) / KZ;
-    if (t >= plane * nzc) return;
-    const int kc = (int)(t / plane);
-    const int64_t pc = t - (int64_t)kc * plane;
+    const int kc = (int)(blk % nzc);
+    const int64_t pc = (blk / nzc) * kLlgNT + lane;
+    if (pc >= plane) return;
     const int i = (int)(pc % a.nx), j = (int)(pc / a.nx);
     const int k0 = kc * KZ;
     const int64_t N = a.N, sy = a.nx;
