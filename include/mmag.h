@@ -152,6 +152,39 @@ mm_status mm_step(mm_sim* sim, int64_t nsteps, double dt);
  * Asynchronous on the handle's stream. */
 mm_status mm_step_euler(mm_sim* sim, int64_t nsteps, double dt);
 
+/* Integrators for mm_run_schedule. */
+typedef enum { MM_RK4 = 0, MM_EULER = 1 } mm_method;
+
+/* One piece of a time-dependent protocol: the switching experiment of Sec. 3
+ * (standard problem #4, field 1) and its appendix script saturate along
+ * (1,1,1), ramp that field down, relax at high damping, then reverse at low
+ * damping while sampling the mean magnetisation.  During step n of the piece
+ * (0 <= n < steps) the applied field is h0 + (h1 - h0) n / steps, A/m
+ * (h1 = h0 holds it constant); alpha is the damping of the whole piece. */
+typedef struct {
+    int64_t steps;  /* >= 0 */
+    double h0[3];   /* finite */
+    double h1[3];   /* finite */
+    double alpha;   /* finite, >= 0 */
+} mm_segment;
+
+/* Runs the pieces in order, `method` steps of dt (RK4 as mm_step, or explicit
+ * Euler as mm_step_euler).  After every `every`-th step (every >= 1, counted
+ * from the start of the call over all pieces) one trace row of 4 doubles
+ * {t, <m_x>, <m_y>, <m_z>} is written: t is the time since the call's start in
+ * seconds, <m> the FP64 mean of the unit vectors.  `trace` is DEVICE memory
+ * of trace_cap rows (row-major), written by the library on the handle's
+ * stream; it may be NULL when no row is due.  The number of rows due,
+ * floor(sum(steps) / every), must fit trace_cap: otherwise MM_EINVAL before
+ * any step.  The pieces are enqueued without host synchronisation between
+ * them; the call returns after the stream has drained, with *rows (may be
+ * NULL) = rows written.  Afterwards the handle's applied field is that of the
+ * last step run and its damping that of the last piece.  Constant-field RK4
+ * pieces use the graph replay of MM_USE_GRAPH when the handle has it. */
+mm_status mm_run_schedule(mm_sim* sim, const mm_segment* segs, int32_t nseg, int32_t method,
+                          double dt, int64_t every, double* trace, int64_t trace_cap,
+                          int64_t* rows);
+
 /* One term of the effective field at the current m, A/m, [3][nz][ny][nx]. */
 mm_status mm_get_field(mm_sim* sim, int32_t term, void* out, int on_device);
 

@@ -219,6 +219,37 @@ def euler(pb: Problem, m, dt: float, nsteps: int) -> np.ndarray:
     return m
 
 
+def schedule(pb: Problem, m0, pieces, dt: float, every: int, method: str = "rk4"):
+    """A time-dependent protocol (Sec. 3, the switching experiment of standard
+    problem #4, and the appendix script that drives it): the pieces
+    (steps, h0, h1, alpha) run in order; during step n of a piece the applied
+    field is h0 + (h1 - h0) n / steps (A/m) and the damping is alpha.  After
+    every `every`-th step (counted over all pieces) a row (t, <m_x>, <m_y>,
+    <m_z>) is recorded, t = steps done * dt.  Returns (rows (k, 4), final m).
+    pb.hext and pb.alpha are restored afterwards."""
+    step = rk4 if method == "rk4" else euler
+    m = _m(pb, m0).copy()
+    rows, done = [], 0
+    keep = (tuple(pb.hext), pb.alpha)
+    try:
+        for steps, h0, h1, alpha in pieces:
+            pb.alpha = float(alpha)
+            ramp = any(float(h0[c]) != float(h1[c]) for c in range(3))
+            n = 0
+            while n < steps:
+                run = 1 if ramp else min(steps - n, every - done % every)
+                f = n / steps
+                pb.hext = tuple(float(h0[c]) + (float(h1[c]) - float(h0[c])) * f for c in range(3))
+                m = step(pb, m, dt, run)
+                n += run
+                done += run
+                if done % every == 0:
+                    rows.append((done * dt, *mean_m(pb, m)))
+    finally:
+        pb.hext, pb.alpha = keep
+    return np.array(rows, dtype=np.float64).reshape(-1, 4), m
+
+
 def energy(pb: Problem, m) -> np.ndarray:
     """[E_exch, E_anis, E_demag, E_zeeman, E_total] in J (Eq. 1 times the cell volume)."""
     m = _m(pb, m)

@@ -22,11 +22,13 @@ LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
 MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE, MM_POW2_PAD = 0x1, 0x2, 0x4, 0x8, 0x10
+MM_RK4, MM_EULER = 0, 1
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
 EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
-           "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_step_euler", "mm_get_field",
+           "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_step_euler", "mm_run_schedule",
+           "mm_get_field",
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
@@ -55,6 +57,11 @@ class Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
                 ("pz", ctypes.c_int32), ("flags", ctypes.c_uint32), ("threads", ctypes.c_int32),
                 ("x_lines", ctypes.c_int32)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("h0", ctypes.c_double * 3), ("h1", ctypes.c_double * 3),
+                ("alpha", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -91,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_set_ku_map": [vp, vp, ctypes.c_int],
         "mm_step": [vp, i64, dbl],
         "mm_step_euler": [vp, i64, dbl],
+        "mm_run_schedule": [vp, ctypes.POINTER(Segment), i32, i32, dbl, i64, vp, i64, ctypes.POINTER(i64)],
         "mm_get_field": [vp, i32, vp, ctypes.c_int],
         "mm_get_energy": [vp, ctypes.POINTER(dbl)],
         "mm_get_mean_m": [vp, ctypes.POINTER(dbl)],
@@ -228,6 +236,32 @@ class Sim:
         """The paper's explicit Euler + renormalisation, nsteps steps."""
         self._sync_stream()
         _check(self._lib.mm_step_euler(self._h, int(nsteps), float(dt)), "mm_step_euler")
+
+    def run_schedule(self, pieces, dt: float, every: int, method: str = "rk4"):
+        """Runs the pieces of a time-dependent protocol; each piece is
+        (steps, h0, h1, alpha) with the applied field ramping linearly from h0
+        (A/m) at the piece's first step towards h1 (h1 = h0: constant).  Returns
+        the trace, a float64 tensor (rows, 4) of {t [s], <m_x>, <m_y>, <m_z>}
+        sampled after every `every`-th step."""
+        torch = self._torch
+        segs = (Segment * max(1, len(pieces)))()
+        total = 0
+        for q, (steps, h0, h1, alpha) in enumerate(pieces):
+            segs[q].steps = int(steps)
+            for c in range(3):
+                segs[q].h0[c] = float(h0[c])
+                segs[q].h1[c] = float(h1[c])
+            segs[q].alpha = float(alpha)
+            total += int(steps)
+        cap = max(1, total // max(1, int(every)))
+        trace = torch.empty((cap, 4), dtype=torch.float64, device=self.device)
+        rows = ctypes.c_int64()
+        self._sync_stream()
+        _check(self._lib.mm_run_schedule(self._h, segs, len(pieces),
+                                         MM_EULER if method == "euler" else MM_RK4, float(dt),
+                                         int(every), trace.data_ptr(), cap, ctypes.byref(rows)),
+               "mm_run_schedule")
+        return trace[:rows.value]
 
     # --------------------------------------------------------------- readout
     def field(self, term: str = "eff"):

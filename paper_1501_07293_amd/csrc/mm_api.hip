@@ -598,8 +598,23 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
 
 // Explicit Euler + renormalisation (the paper's integrator): ping-pong between
 // m_n and m_a, one field evaluation per step; the result ends in m_n.
+// Applied field during step n of a schedule piece: h0 + (h1 - h0) n / steps.
+void piece_field(const mm_segment& g, int64_t n, double h[3])
+{
+    const double f = g.steps > 0 ? (double)n / (double)g.steps : 0.0;
+    for (int c = 0; c < 3; ++c) h[c] = g.h0[c] + (g.h1[c] - g.h0[c]) * f;
+}
+
+bool piece_ramps(const mm_segment& g)
+{
+    return g.h0[0] != g.h1[0] || g.h0[1] != g.h1[1] || g.h0[2] != g.h1[2];
+}
+
+// nsteps explicit Euler steps; with a schedule piece g, step n takes the field of
+// the piece's step n0 + n.
 template <typename T>
-mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt)
+mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt, const mm_segment* g = nullptr,
+                     int64_t n0 = 0)
 {
     const Plan& p = s->p;
     hipStream_t st = s->stream;
@@ -610,6 +625,12 @@ mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt)
     for (int64_t n = 0; n < nsteps; ++n) {
         T* src = bufs[n & 1];
         T* dst = bufs[(n + 1) & 1];
+        if (g) {
+            piece_field(*g, n0 + n, s->hext);
+            a.hx = (T)(s->hext[0] / s->mat.Ms);
+            a.hy = (T)(s->hext[1] / s->mat.Ms);
+            a.hz = (T)(s->hext[2] / s->mat.Ms);
+        }
         if (!(s->flags & MM_NO_DEMAG)) {
             mm_status r = demag<T>(s, src, hd, st);
             if (r != MM_OK) return r;
@@ -671,6 +692,63 @@ mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
         mm_status r = rk4_step<T>(s, dt, st);
         if (r != MM_OK) return r;
     }
+    return MM_OK;
+}
+
+// One row of the mean-magnetisation trace, enqueued on the handle's stream.
+template <typename T>
+mm_status trace_sample(mm_sim* s, double t, double* row)
+{
+    const Plan& p = s->p;
+    LlgArgs<T> a = llg_args<T>(s, 0.0);
+    T* mn = s->at<T>(p.o_mn);
+    a.ms = mn;
+    a.mn = mn;
+    a.hd = nullptr;
+    double* dout = s->at<double>(p.o_redout);
+    HIP_TRY(launch_reduce<T>(a, s->at<double>(p.o_red), reduce_blocks(p.N), dout, s->stream));
+    HIP_TRY(launch_trace_row(dout, 1.0 / (double)p.N, t, row, s->stream));
+    return MM_OK;
+}
+
+// The pieces of a time-dependent protocol, sampled every `every` steps.
+template <typename T>
+mm_status schedule_impl(mm_sim* s, const mm_segment* segs, int nseg, int method, double dt,
+                        int64_t every, double* trace, int64_t* rows)
+{
+    int64_t done = 0, nrow = 0;
+    for (int q = 0; q < nseg; ++q) {
+        const mm_segment& g = segs[q];
+        const bool ramp = piece_ramps(g);
+        s->alpha = g.alpha;
+        s->graph_valid = false;
+        if (!ramp)
+            for (int c = 0; c < 3; ++c) s->hext[c] = g.h0[c];
+        for (int64_t n = 0; n < g.steps;) {
+            const int64_t run = std::min(g.steps - n, every - done % every);
+            mm_status r = MM_OK;
+            if (method == MM_EULER) {
+                r = euler_impl<T>(s, run, dt, ramp ? &g : nullptr, n);
+            } else if (!ramp) {
+                r = step_impl<T>(s, run, dt);
+            } else {
+                for (int64_t k = 0; k < run && r == MM_OK; ++k) {
+                    piece_field(g, n + k, s->hext);
+                    r = rk4_step<T>(s, dt, s->stream);
+                }
+            }
+            if (r != MM_OK) return r;
+            n += run;
+            done += run;
+            if (done % every == 0) {
+                if ((r = trace_sample<T>(s, (double)done * dt, trace + 4 * nrow)) != MM_OK) return r;
+                ++nrow;
+            }
+        }
+        s->graph_valid = false;
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (rows) *rows = nrow;
     return MM_OK;
 }
 
@@ -1570,6 +1648,35 @@ mm_status mm_step_euler(mm_sim* s, int64_t nsteps, double dt)
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_step_euler before mm_set_m");
     return s->p.prec == MM_F32 ? euler_impl<float>(s, nsteps, dt) : euler_impl<double>(s, nsteps, dt);
+}
+
+mm_status mm_run_schedule(mm_sim* s, const mm_segment* segs, int32_t nseg, int32_t method,
+                          double dt, int64_t every, double* trace, int64_t trace_cap, int64_t* rows)
+{
+    if (rows) *rows = 0;
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (nseg < 0 || (nseg > 0 && !segs)) return fail(MM_EINVAL, "segs is NULL or nseg < 0");
+    if (method != MM_RK4 && method != MM_EULER) return fail(MM_EINVAL, "method must be MM_RK4 or MM_EULER");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (every < 1) return fail(MM_EINVAL, "every must be >= 1");
+    int64_t total = 0;
+    for (int q = 0; q < nseg; ++q) {
+        const mm_segment& g = segs[q];
+        if (g.steps < 0 || g.steps > INT64_MAX - total) return fail(MM_EINVAL, "piece %d: bad step count", q);
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(g.h0[c]) || !std::isfinite(g.h1[c]))
+                return fail(MM_EINVAL, "piece %d: applied field must be finite", q);
+        if (!(g.alpha >= 0) || !std::isfinite(g.alpha))
+            return fail(MM_EINVAL, "piece %d: alpha must be finite and >= 0", q);
+        total += g.steps;
+    }
+    const int64_t due = total / every;
+    if (due > 0 && (!trace || trace_cap < due))
+        return fail(MM_EINVAL, "the trace needs %lld rows, trace_cap is %lld", (long long)due,
+                    (long long)trace_cap);
+    if (!s->has_m) return fail(MM_ESTATE, "mm_run_schedule before mm_set_m");
+    return s->p.prec == MM_F32 ? schedule_impl<float>(s, segs, nseg, method, dt, every, trace, rows)
+                               : schedule_impl<double>(s, segs, nseg, method, dt, every, trace, rows);
 }
 
 mm_status mm_get_field(mm_sim* s, int32_t term, void* out, int on_device)

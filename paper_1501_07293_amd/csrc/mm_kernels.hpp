@@ -190,7 +190,10 @@ struct LlgArgs {
 // the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes;
 // a work-group of kLlgNT threads covers kLlgNT consecutive columns of one chunk,
 // and the chunks of the same columns are consecutive work-groups
-constexpr int kLlgZ = 4;
+#ifndef MM_LLG_Z
+#define MM_LLG_Z 4
+#endif
+constexpr int kLlgZ = MM_LLG_Z;
 constexpr int kLlgNT = 256;
 __host__ __device__ inline int64_t llg_blocks(int nx, int ny, int nz)
 {
@@ -207,6 +210,8 @@ hipError_t launch_field_term(const LlgArgs<T>& a, int term, T Ms, T* out, hipStr
 // out[1] = sum ku_red (my^2 + mz^2), out[2] = sum m.hd, out[3] = sum m.hext,
 // out[4..6] = sum m, out[7] = count of non-finite entries.  partial holds
 // nblocks*8 doubles.
+// row = {t, sums[4..6] * inv_n}: one sample of the mean-magnetisation trace
+hipError_t launch_trace_row(const double* sums, double inv_n, double t, double* row, hipStream_t s);
 template <typename T>
 hipError_t launch_reduce(const LlgArgs<T>& a, double* partial, int nblocks, double* out,
                          hipStream_t s);

@@ -217,6 +217,18 @@ int reduce_blocks(int64_t N)
     return (int)(b < 1 ? 1 : b);
 }
 
+__global__ void k_trace_row(const double* sums, double inv_n, double t, double* row)
+{
+    if (threadIdx.x == 0) row[0] = t;
+    else if (threadIdx.x < 4) row[threadIdx.x] = sums[3 + threadIdx.x] * inv_n;
+}
+
+hipError_t launch_trace_row(const double* sums, double inv_n, double t, double* row, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_trace_row, dim3(1), dim3(64), 0, s, sums, inv_n, t, row);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_reduce(const LlgArgs<T>& a, double* partial, int nblocks, double* out,
                          hipStream_t s)

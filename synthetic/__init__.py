@@ -7,8 +7,9 @@ here, so they always see identical m, fields and maps.
 
 Workloads (stand-ins for the paper's muMAG standard problems, Sec. 3, whose
 reference curves are not available): a small strip, a mid-size film driven by
-a step field, a large film, a batch of uneven grids, and a differentiation
-case with a per-cell anisotropy map.
+a step field, a large film, a batch of uneven grids, a differentiation case
+with a per-cell anisotropy map, and the standard-problem-#4 protocol of the
+appendix script.
 """
 from __future__ import annotations
 
@@ -69,6 +70,27 @@ DIFF = Config("differentiation 128x128x1", 128, 128, 1, 5e-9, Ku=500.0, alpha=0.
 # Batched: material of the small strip, delta 5 nm, dt 1e-13 s, 1000 steps.
 BATCH_TEMPLATE = Config("batched sample", 0, 0, 0, 5e-9, Ku=500.0, alpha=0.5, dt=1e-13,
                         steps=1000)
+
+
+# Standard problem #4 (Sec. 3, field 1) as the appendix script sets it up: 166x42x1 cells of
+# 3 nm (500 x 125 x 3 nm), Ms 800 kA/m, A 1.3e-11 J/m, no anisotropy, explicit Euler with
+# dt = 5 fs for 150000 steps, m starting along +x, <m> recorded every 1000 steps.
+SP4 = Config("standard problem 4 film 166x42x1", 166, 42, 1, 3e-9, Ku=0.0, alpha=0.5,
+             dt=5e-15, steps=150000)
+
+
+def sp4_pieces(shrink: int = 1) -> List[tuple]:
+    """The appendix protocol as schedule pieces (steps, h0, h1, alpha), fields in A/m:
+    steps 1..3999 a saturating 100 kA/m along each axis; 4000..5999 that field ramped
+    linearly to zero (the script's step t carries (6000 - t)/20 kA/m on each axis); 6000..50000
+    relaxation without field (alpha 0.5 throughout); 50001..150000 the reversing field
+    (-19.576, 3.422, 0) kA/m = (-24.6, 4.3, 0) mT with alpha 0.02.  `shrink` divides every
+    piece's length (quick variants of the same shape)."""
+    sat = (1.0e5, 1.0e5, 1.0e5)
+    zero = (0.0, 0.0, 0.0)
+    rev = (-19.576e3, 3.422e3, 0.0)
+    return [(3999 // shrink, sat, sat, 0.5), (2000 // shrink, sat, zero, 0.5),
+            (44001 // shrink, zero, zero, 0.5), (100000 // shrink, rev, rev, 0.02)]
 
 
 def rng(seed: int) -> np.random.Generator:

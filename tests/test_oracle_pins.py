@@ -423,3 +423,80 @@ def test_macrospin_euler_first_order():
         errs.append(np.abs(m - macrospin_closed_form(th0, ph0, H, alpha, pb.gamma, T)).max())
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 1.8 < r1 < 2.2 and 1.8 < r2 < 2.2, errs
+
+
+def rot(axis: int, ang: float) -> np.ndarray:
+    """Right-handed rotation by ang about coordinate axis 0, 1 or 2."""
+    c, s = np.cos(ang), np.sin(ang)
+    i, j = [(1, 2), (2, 0), (0, 1)][axis]
+    R = np.eye(3)
+    R[i, i], R[i, j], R[j, i], R[j, j] = c, -s, s, c
+    return R
+
+
+def test_schedule_macrospin_piecewise_fields_closed_form():
+    # Undamped single cell: each piece rotates m about its field by gamma |H| t
+    # (right-handed; the demag field -M/3 is parallel to m).  Pieces along z, then x,
+    # then a ramp along y: within step k of the ramp the field is H0 + (H1 - H0) k / n,
+    # so after n' steps the angle is gamma dt (n' H0 + (H1 - H0) n'(n'-1) / (2 n)).
+    # Rows every 7 steps across the piece boundaries.
+    g = 2.211e5
+    pb = oracle.Problem(1, 1, 1, 5e-9, alpha=0.0, gamma=g)
+    m0 = np.array([0.6, 0.0, 0.8])
+    dt, Hz, Hx, H0, H1 = 2e-14, 3.0e5, 1.5e5, 2.0e5, -1.0e5
+    pieces = [(30, (0, 0, Hz), (0, 0, Hz), 0.0), (25, (Hx, 0, 0), (Hx, 0, 0), 0.0),
+              (40, (0, H0, 0), (0, H1, 0), 0.0)]
+    rows, mf = oracle.schedule(pb, m0.reshape(3, 1, 1, 1), pieces, dt, 7)
+    assert rows.shape == (95 // 7, 4)
+
+    def exact(t_steps):
+        R = np.eye(3)
+        left = t_steps
+        for axis, n, ang in ((2, 30, lambda k: g * dt * Hz * k), (0, 25, lambda k: g * dt * Hx * k),
+                             (1, 40, lambda k: g * dt * (k * H0 + (H1 - H0) * k * (k - 1) / (2 * 40)))):
+            k = min(left, n)
+            R = rot(axis, ang(k)) @ R
+            left -= k
+        return R @ m0
+
+    for r in rows:
+        k = int(round(r[0] / dt))
+        assert np.abs(r[1:] - exact(k)).max() < 1e-9, (k, r[1:], exact(k))
+    assert np.abs(mf.reshape(3) - exact(95)).max() < 1e-9
+    assert pb.hext == (0.0, 0.0, 0.0) and pb.alpha == 0.0
+
+
+def test_schedule_damping_switch_closed_form():
+    # Single cell in H z: alpha 1 for the first piece, 0.02 for the second; the polar
+    # angle follows tan(th/2) = tan(th0/2) exp(-alpha gamma' H t) per piece, the azimuth
+    # gamma' H t (gamma' = gamma / (1 + alpha^2)); rows every 10 steps.
+    g, H, dt = 2.211e5, 2.0e5, 1e-14
+    pb = oracle.Problem(1, 1, 1, 5e-9, gamma=g)
+    th0, ph0 = 2.5, 0.3
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    pieces = [(200, (0, 0, H), (0, 0, H), 1.0), (300, (0, 0, H), (0, 0, H), 0.02)]
+    rows, _ = oracle.schedule(pb, m0.reshape(3, 1, 1, 1), pieces, dt, 10)
+    assert rows.shape == (50, 4)
+    T1 = 200 * dt
+    th1 = macrospin_closed_form(th0, ph0, H, 1.0, g, T1)
+    th1, ph1 = np.arccos(th1[2]), np.arctan2(th1[1], th1[0])
+    for r in rows:
+        t = r[0]
+        want = (macrospin_closed_form(th0, ph0, H, 1.0, g, t) if t <= T1 + 1e-20
+                else macrospin_closed_form(th1, ph1, H, 0.02, g, t - T1))
+        assert np.abs(r[1:] - want).max() < 1e-9, (t, r[1:], want)
+
+
+def test_schedule_euler_rotates_by_arctan():
+    # Explicit Euler + renormalisation of an undamped single cell turns m about H by
+    # exactly atan(gamma |H| dt) per step (m + dt w x m has length sec of that angle for
+    # the in-plane part): a closed form of the appendix update at any dt.
+    g, H, dt = 2.211e5, 4.0e5, 5e-15
+    pb = oracle.Problem(1, 1, 1, 3e-9, alpha=0.0, gamma=g)
+    m0 = np.array([1.0, 0.0, 0.0])
+    rows, _ = oracle.schedule(pb, m0.reshape(3, 1, 1, 1), [(1000, (0, 0, H), (0, 0, H), 0.0)],
+                              dt, 100, method="euler")
+    for r in rows:
+        k = int(round(r[0] / dt))
+        want = rot(2, k * np.arctan(g * H * dt)) @ m0
+        assert np.abs(r[1:] - want).max() < 1e-12, (k, r[1:], want)
