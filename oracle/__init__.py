@@ -22,17 +22,21 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmag_oracle.c")
+_SRC_NEWELL = os.path.join(_HERE, "newell_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MU0 = 4.0e-7 * np.pi
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, IEEE FP64, no fast-math, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (-O2, IEEE FP64 (binary128 for Newell's tensor),
+    no fast-math, OpenMP)."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_NEWELL))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu99",
+                               "-fno-fast-math", "-ffp-contract=off", _SRC, _SRC_NEWELL, "-o", tmp,
+                               "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -57,6 +61,8 @@ def _load():
         pp = ctypes.POINTER(_Params)
         lib.or_tensor_point.argtypes = [ctypes.c_int32] * 3 + [dp]
         lib.or_tensor_table.argtypes = [ctypes.c_int32] * 3 + [dp]
+        lib.or_newell_point.argtypes = [ctypes.c_int32] * 3 + [dp]
+        lib.or_newell_table.argtypes = [ctypes.c_int32] * 3 + [dp]
         lib.or_demag.argtypes = [pp, dp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
         lib.or_exchange.argtypes = [pp, dp, dp]
         lib.or_anisotropy.argtypes = [pp, dp, dp]
@@ -97,6 +103,7 @@ class Problem:
     hext: Sequence[float] = (0.0, 0.0, 0.0)   # A/m
     ku_map: Optional[np.ndarray] = None       # (nz, ny, nx) J/m^3, overrides Ku
     demag: bool = True
+    tensor: str = "point"           # "point": Eqs. 10-11; "newell": cell-averaged (Newell et al.)
     _table: Optional[np.ndarray] = field(default=None, repr=False)
 
     @property
@@ -124,7 +131,8 @@ class Problem:
     def table(self) -> np.ndarray:
         """Demag tensor over all offsets: (6, 2nz-1, 2ny-1, 2nx-1); order xx,xy,xz,yy,yz,zz."""
         if self._table is None:
-            self._table = tensor_table(self.nx, self.ny, self.nz)
+            make = newell_table if self.tensor == "newell" else tensor_table
+            self._table = make(self.nx, self.ny, self.nz)
         return self._table
 
 
@@ -138,6 +146,21 @@ def tensor_point(I: int, J: int, K: int) -> np.ndarray:
 def tensor_table(nx: int, ny: int, nz: int) -> np.ndarray:
     out = np.zeros((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
     _load().or_tensor_table(nx, ny, nz, _dptr(out))
+    return out
+
+
+def newell_point(I: int, J: int, K: int) -> np.ndarray:
+    """Newell's cell-averaged tensor at the integer offset (I,J,K), in the sign
+    convention of Eqs. 12-13 (K = -N; K(0) = -I/3 for a cube); evaluated in
+    binary128 and returned in FP64."""
+    out = np.zeros(6)
+    _load().or_newell_point(int(I), int(J), int(K), _dptr(out))
+    return out
+
+
+def newell_table(nx: int, ny: int, nz: int) -> np.ndarray:
+    out = np.zeros((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
+    _load().or_newell_table(nx, ny, nz, _dptr(out))
     return out
 
 

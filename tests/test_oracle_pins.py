@@ -500,3 +500,79 @@ def test_schedule_euler_rotates_by_arctan():
         k = int(round(r[0] / dt))
         want = rot(2, k * np.arctan(g * H * dt)) @ m0
         assert np.abs(r[1:] - want).max() < 1e-12, (k, r[1:], want)
+
+
+# ------------------------------------------------ Newell's cell-averaged tensor
+def aharoni_dz(a: float, b: float, c: float) -> float:
+    """Magnetometric demagnetising factor along z of a uniformly magnetised
+    rectangular prism of edges 2a x 2b x 2c (Aharoni, J. Appl. Phys. 83, 3432,
+    1998): an independent closed form for the cell sums of the averaged tensor."""
+    r = np.sqrt(a * a + b * b + c * c)
+    ab, bc, ac = np.sqrt(a * a + b * b), np.sqrt(b * b + c * c), np.sqrt(a * a + c * c)
+    s = ((b * b - c * c) / (2 * b * c) * np.log((r - a) / (r + a))
+         + (a * a - c * c) / (2 * a * c) * np.log((r - b) / (r + b))
+         + b / (2 * c) * np.log((ab + a) / (ab - a)) + a / (2 * c) * np.log((ab + b) / (ab - b))
+         + c / (2 * a) * np.log((bc - b) / (bc + b)) + c / (2 * b) * np.log((ac - a) / (ac + a))
+         + 2 * np.arctan(a * b / (c * r)) + (a ** 3 + b ** 3 - 2 * c ** 3) / (3 * a * b * c)
+         + (a * a + b * b - 2 * c * c) / (3 * a * b * c) * r + c / (a * b) * (ac + bc)
+         - (ab ** 3 + bc ** 3 + ac ** 3) / (3 * a * b * c))
+    return s / np.pi
+
+
+def test_aharoni_closed_form_sanity():
+    assert abs(aharoni_dz(1, 1, 1) - 1 / 3) < 1e-14
+    for a, b, c in ((3, 1.5, 1), (1, 2, 3), (5, 1, 0.4)):
+        tot = aharoni_dz(a, b, c) + aharoni_dz(b, c, a) + aharoni_dz(c, a, b)
+        assert abs(tot - 1) < 1e-13
+
+
+def test_newell_origin_trace_and_parity():
+    k0 = oracle.newell_point(0, 0, 0)
+    assert np.abs(k0 - np.array([-1 / 3, 0, 0, -1 / 3, 0, -1 / 3])).max() < 1e-15
+    g = np.random.default_rng(12)
+    offs = [(1, 0, 0), (1, 1, 0), (1, 1, 1), (0, 2, 1)] + [tuple(g.integers(-9, 10, 3)) for _ in range(12)]
+    for d in offs:
+        if d == (0, 0, 0):
+            continue
+        k = oracle.newell_point(*d)
+        # the averaged field of one cell has zero divergence outside it: trace 0 for
+        # every pair of distinct (non-overlapping) cells
+        assert abs(k[0] + k[3] + k[5]) < 1e-15 * max(1.0, np.abs(k).max()), d
+        assert np.array_equal(k, oracle.newell_point(-d[0], -d[1], -d[2])) or \
+            np.abs(k - oracle.newell_point(-d[0], -d[1], -d[2])).max() < 1e-17
+        # xy odd in y alone, xz odd in z alone
+        km = oracle.newell_point(d[0], -d[1], d[2])
+        assert abs(km[1] + k[1]) < 1e-17 and abs(km[0] - k[0]) < 1e-17
+
+
+def test_newell_box_factors_match_aharoni():
+    # Uniform m along each axis in an a x b x c box of cells: the cell average of
+    # sum_j K(r_j - r_i) is minus the prism's demagnetising factor, exactly, because the
+    # averaged tensor integrates the field over every cell.
+    for nx, ny, nz in ((4, 4, 4), (6, 3, 2), (10, 3, 1), (5, 7, 3)):
+        tab = oracle.newell_table(nx, ny, nz)
+        I = np.abs(np.arange(-(nx - 1), nx))
+        J = np.abs(np.arange(-(ny - 1), ny))
+        K = np.abs(np.arange(-(nz - 1), nz))
+        cnt = (nz - K)[:, None, None] * (ny - J)[None, :, None] * (nx - I)[None, None, :]
+        N = nx * ny * nz
+        dxx, dyy, dzz = (-(tab[c] * cnt).sum() / N for c in (0, 3, 5))
+        a, b, c = nx / 2, ny / 2, nz / 2
+        assert abs(dzz - aharoni_dz(a, b, c)) < 1e-12, (nx, ny, nz, dzz, aharoni_dz(a, b, c))
+        assert abs(dxx - aharoni_dz(b, c, a)) < 1e-12
+        assert abs(dyy - aharoni_dz(c, a, b)) < 1e-12
+        assert abs(dxx + dyy + dzz - 1) < 1e-12
+
+
+def test_newell_approaches_point_tensor_at_fourth_order():
+    # Both tensors are cube averages of the dipole kernel (Newell over source and target,
+    # Eqs. 10-11 over the source only); the kernel is harmonic, so the averages differ
+    # from each other by O((delta / r)^4): doubling r divides the gap by ~16.
+    for u in ((1, 0, 0), (2, 1, 0), (3, 2, 1)):
+        gaps = []
+        for s in (4, 8, 16):
+            d = tuple(s * v for v in u)
+            kp, kn = oracle.tensor_point(*d), oracle.newell_point(*d)
+            gaps.append(np.abs(kn - kp).max() / np.abs(kp).max())
+        r1, r2 = gaps[0] / gaps[1], gaps[1] / gaps[2]
+        assert 13 < r1 < 19 and 14 < r2 < 18, (u, gaps)
