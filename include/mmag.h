@@ -66,6 +66,9 @@ typedef enum {
                                the smallest 7-smooth size), so the size-specialised passes apply;
                                a batch created with it runs those passes, one launch per padded
                                size per pass */
+#define MM_NEWELL 0x20u    /* demag with Newell's cell-averaged tensor (Newell, Williams and Dunlop,
+                               J. Geophys. Res. 98, 9551, 1993; cited in Sec. 2.3) instead of the
+                               point-field tensor of Eqs. 10-11; see mm_demag_tensor_newell */
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                2n-smooth vs power of two, specialised vs runtime-radix passes,
                                256 vs 512 threads) and keeps the fastest; results are cached per
@@ -90,7 +93,8 @@ typedef struct {
     int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
-    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD */
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD |
+                            MM_NEWELL */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (8), 4 or 8 */
@@ -206,6 +210,14 @@ mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
  * dimensionless: d_out[6][2nz-1][2ny-1][2nx-1] (device memory, caller-owned),
  * component order xx, xy, xz, yy, yz, zz, offset index (K+nz-1, J+ny-1, I+nx-1). */
 mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream);
+
+/* Newell's cell-averaged tensor (the alternative Sec. 2.3 cites) in the same sign
+ * convention (K = -N, K(0) = -I/3) and the same layout as mm_demag_tensor.  FP64:
+ * the exact 27-point second differences of Newell's f and g within a distance
+ * of 8 cells, beyond it the point field of Eqs. 10-11 averaged over the
+ * observer's cell by 4-point Gauss-Legendre quadrature per axis; relative error
+ * ~2e-10 of the largest entry at any offset. */
+mm_status mm_demag_tensor_newell(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream);
 
 /* ---- batched form --------------------------------------------------------
  * n independent grids of uneven sizes (each its own padding and applied

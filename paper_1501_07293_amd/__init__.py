@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
 MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE, MM_POW2_PAD = 0x1, 0x2, 0x4, 0x8, 0x10
+MM_NEWELL = 0x20
 MM_RK4, MM_EULER = 0, 1
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
@@ -30,7 +31,7 @@ EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm
            "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_step_euler", "mm_run_schedule",
            "mm_get_field",
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
-           "mm_demag_tensor", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
+           "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
            "mm_batch_cells", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
            "mm_profile_begin", "mm_profile_end", "mm_kernel_name", "mm_status_string",
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_get_plan": [vp, ctypes.POINTER(PlanInfo)],
         "mm_get_kernel_spectrum": [vp, vp, ctypes.c_int],
         "mm_demag_tensor": [i32, i32, i32, vp, vp],
+        "mm_demag_tensor_newell": [i32, i32, i32, vp, vp],
         "mm_batch_workspace_query": [i32, ctypes.POINTER(Grid), ctypes.POINTER(Options),
                                      ctypes.POINTER(ctypes.c_size_t)],
         "mm_batch_create": [i32, ctypes.POINTER(Grid), ctypes.POINTER(Material), ctypes.POINTER(dbl),
@@ -163,7 +165,7 @@ class Sim:
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
                  autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False,
-                 device: str = "cuda:0"):
+                 tensor: str = "point", device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch = torch
@@ -177,7 +179,7 @@ class Sim:
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
                  | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0)
-                 | (MM_POW2_PAD if pow2_pad else 0))
+                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads, x_lines)
         nbytes = ctypes.c_size_t()
@@ -353,7 +355,7 @@ class BatchSim:
     def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  hext=None, precision: str = "f32", demag: bool = True, graph: bool = False,
-                 pow2_pad: bool = False, device: str = "cuda:0"):
+                 pow2_pad: bool = False, tensor: str = "point", device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch, self._lib = torch, lib
@@ -367,7 +369,7 @@ class BatchSim:
         self._grids = garr
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-                 | (MM_POW2_PAD if pow2_pad else 0))
+                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
@@ -433,14 +435,21 @@ class BatchSim:
             pass
 
 
-def demag_tensor(nx: int, ny: int, nz: int, device: str = "cuda:0"):
-    """Demag tensor of Eqs. 10-11 on the GPU in FP64: (6, 2nz-1, 2ny-1, 2nx-1)."""
+def demag_tensor(nx: int, ny: int, nz: int, device: str = "cuda:0", tensor: str = "point"):
+    """Demag tensor on the GPU in FP64: (6, 2nz-1, 2ny-1, 2nx-1); tensor "point" is
+    Eqs. 10-11, "newell" the cell-averaged tensor."""
     torch = _torch()
     lib = load_library()
     out = torch.empty((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1), dtype=torch.float64, device=device)
-    _check(lib.mm_demag_tensor(nx, ny, nz, out.data_ptr(), _stream_ptr(torch, torch.device(device))),
-           "mm_demag_tensor")
+    fn = lib.mm_demag_tensor_newell if _tensor_flag(tensor) else lib.mm_demag_tensor
+    _check(fn(nx, ny, nz, out.data_ptr(), _stream_ptr(torch, torch.device(device))), "mm_demag_tensor")
     return out
+
+
+def _tensor_flag(tensor: str) -> int:
+    if tensor not in ("point", "newell"):
+        raise ValueError(f"tensor must be 'point' or 'newell', not {tensor!r}")
+    return MM_NEWELL if tensor == "newell" else 0
 
 
 def kernel_name(k: int) -> str:

@@ -533,7 +533,8 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
     const int nt = p.nt;
     const int cap = kElemsPerThread * nt, ldscap = cap + 64;
     for (int q = 0; q < p.ncomp; ++q) {
-        HIP_TRY(launch_tensor_wrapped(R, comps[q], p.nx, p.ny, p.nz, p.Px, p.Py, p.Pz, st));
+        HIP_TRY(launch_tensor_wrapped(R, (s->flags & MM_NEWELL) ? 1 : 0, comps[q], p.nx, p.ny, p.nz,
+                                      p.Px, p.Py, p.Pz, st));
         RowR2CArgs xr{};
         xr.in = R;
         xr.in_row_stride = p.Px;
@@ -1756,7 +1757,16 @@ mm_status mm_demag_tensor(int32_t nx, int32_t ny, int32_t nz, double* d_out, voi
     if (nx < 1 || ny < 1 || nz < 1 || !d_out) return fail(MM_EINVAL, "dims must be >= 1 and d_out non-NULL");
     if ((int64_t)(2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1) > ((int64_t)1 << 34))
         return fail(MM_ENOTSUP, "tensor table too large");
-    HIP_TRY(launch_tensor_table(d_out, nx, ny, nz, as_stream(stream)));
+    HIP_TRY(launch_tensor_table(d_out, 0, nx, ny, nz, as_stream(stream)));
+    return MM_OK;
+}
+
+mm_status mm_demag_tensor_newell(int32_t nx, int32_t ny, int32_t nz, double* d_out, void* stream)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !d_out) return fail(MM_EINVAL, "dims must be >= 1 and d_out non-NULL");
+    if ((int64_t)(2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1) > ((int64_t)1 << 34))
+        return fail(MM_ENOTSUP, "tensor table too large");
+    HIP_TRY(launch_tensor_table(d_out, 1, nx, ny, nz, as_stream(stream)));
     return MM_OK;
 }
 

@@ -153,12 +153,12 @@ template <typename T>
 hipError_t launch_kspace(const KspArgs& a, int nt, hipStream_t s);
 
 // ---------------------------------------------------------------- setup
-// Demag tensor component `comp` (0..5 = xx,xy,xz,yy,yz,zz) of Eqs. 10-11 in
-// the wrapped layout of a [Pz][Py][Px] FP64 array.
-hipError_t launch_tensor_wrapped(double* out, int comp, int nx, int ny, int nz, int Px, int Py,
-                                 int Pz, hipStream_t s);
+// Demag tensor component `comp` (0..5 = xx,xy,xz,yy,yz,zz) in the wrapped layout
+// of a [Pz][Py][Px] FP64 array; kind 0 = Eqs. 10-11, 1 = Newell's averaged tensor.
+hipError_t launch_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
+                                 int Py, int Pz, hipStream_t s);
 // All six components on the offset table [6][2nz-1][2ny-1][2nx-1] (FP64).
-hipError_t launch_tensor_table(double* out, int nx, int ny, int nz, hipStream_t s);
+hipError_t launch_tensor_table(double* out, int kind, int nx, int ny, int nz, hipStream_t s);
 // tw[t] = exp(-2 pi i t / P), computed in FP64, stored in T.
 template <typename T>
 hipError_t launch_twiddles(void* tw, int P, hipStream_t s);

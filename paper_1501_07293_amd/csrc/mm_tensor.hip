@@ -12,11 +12,12 @@ __device__ inline double log_z_plus_r(double X, double Y, double Z, double r)
     return Z >= 0.0 ? log(Z + r) : log((X * X + Y * Y) / (r - Z));
 }
 
-// Component comp (0..5 = xx, xy, xz, yy, yz, zz) at integer offset
-// (I,J,K) = source - observer, in units of the cell edge: the eight-corner
-// alternating sums of Eq. 10 (atan terms, diagonal) and Eq. 11 (log terms,
-// off-diagonal, with the minus sign), over corners i,j,k in {0,1}.
-__device__ double tensor_component(int comp, int I, int J, int K)
+// Component comp (0..5 = xx, xy, xz, yy, yz, zz) at offset (I,J,K) = source -
+// observer, in units of the cell edge: the eight-corner alternating sums of
+// Eq. 10 (atan terms, diagonal) and Eq. 11 (log terms, off-diagonal, with the
+// minus sign), over corners i,j,k in {0,1}.  Integer offsets give the paper's
+// tensor; real ones the point field at a shifted observer (used below).
+__device__ double tensor_component(int comp, double I, double J, double K)
 {
     double s = 0.0;
 #pragma unroll
@@ -42,6 +43,94 @@ __device__ double tensor_component(int comp, int I, int J, int K)
     return (comp == 0 || comp == 3 || comp == 5) ? pf * s : -pf * s;
 }
 
+// ---- Newell's cell-averaged tensor (Newell, Williams and Dunlop 1993; the
+// alternative Sec. 2.3 cites), in the sign convention above (K = -N).
+// Near the origin: the 27-point second difference of Newell's f (diagonal) and
+// g (off-diagonal) in FP64.  That sum cancels as (r / delta)^6 in relative
+// terms, so from a (Euclidean) distance of kNewellFar cells on, the average of
+// the point field above over the observer's cell is taken instead, by 4-point
+// Gauss-Legendre quadrature per axis; both parts stay within ~2e-10 of the
+// exact averaged tensor.
+constexpr int kNewellFar = 8;
+
+__device__ double newell_f(double x, double y, double z)
+{
+    x = fabs(x);
+    y = fabs(y);
+    z = fabs(z);
+    const double x2 = x * x, y2 = y * y, z2 = z * z, R = sqrt(x2 + y2 + z2);
+    double s = (2.0 * x2 - y2 - z2) * R / 6.0;
+    if (y > 0.0 && x2 + z2 > 0.0) s += 0.5 * y * (z2 - x2) * asinh(y / sqrt(x2 + z2));
+    if (z > 0.0 && x2 + y2 > 0.0) s += 0.5 * z * (y2 - x2) * asinh(z / sqrt(x2 + y2));
+    if (x > 0.0 && y > 0.0 && z > 0.0) s -= x * y * z * atan(y * z / (x * R));
+    return s;
+}
+
+__device__ double newell_g(double x, double y, double z)
+{
+    const double sgn = ((x < 0.0) != (y < 0.0)) ? -1.0 : 1.0;
+    x = fabs(x);
+    y = fabs(y);
+    z = fabs(z);
+    const double x2 = x * x, y2 = y * y, z2 = z * z, R = sqrt(x2 + y2 + z2);
+    double s = -x * y * R / 3.0;
+    if (z > 0.0 && x2 + y2 > 0.0) s += x * y * z * asinh(z / sqrt(x2 + y2));
+    if (x > 0.0 && y2 + z2 > 0.0) s += y / 6.0 * (3.0 * z2 - y2) * asinh(x / sqrt(y2 + z2));
+    if (y > 0.0 && x2 + z2 > 0.0) s += x / 6.0 * (3.0 * z2 - x2) * asinh(y / sqrt(x2 + z2));
+    if (x > 0.0 && y > 0.0 && z > 0.0) {
+        s -= z2 * z / 6.0 * atan(x * y / (z * R));
+        s -= 0.5 * z * y2 * atan(x * z / (y * R));
+        s -= 0.5 * z * x2 * atan(y * z / (x * R));
+    }
+    return sgn * s;
+}
+
+// (1 / 4 pi) sum_{i,j,k in -1..1} w_i w_j w_k F(a+i, b+j, c+k), w = (-1, 2, -1)
+template <bool G>
+__device__ double newell_sum(double a, double b, double c)
+{
+    double s = 0.0;
+    for (int i = -1; i <= 1; ++i)
+        for (int j = -1; j <= 1; ++j)
+            for (int k = -1; k <= 1; ++k) {
+                const double w = (i ? -1.0 : 2.0) * (j ? -1.0 : 2.0) * (k ? -1.0 : 2.0);
+                s += w * (G ? newell_g(a + i, b + j, c + k) : newell_f(a + i, b + j, c + k));
+            }
+    return 0.079577471545947667884 * s;
+}
+
+__device__ double newell_component(int comp, int I, int J, int K)
+{
+    if (I * I + J * J + K * K < kNewellFar * kNewellFar) {
+        const double X = I, Y = J, Z = K;
+        switch (comp) {
+        case 0: return -newell_sum<false>(X, Y, Z);
+        case 1: return -newell_sum<true>(X, Y, Z);
+        case 2: return -newell_sum<true>(X, Z, Y);
+        case 3: return -newell_sum<false>(Y, X, Z);
+        case 4: return -newell_sum<true>(Y, Z, X);
+        default: return -newell_sum<false>(Z, X, Y);
+        }
+    }
+    // nodes and weights of 4-point Gauss-Legendre on [-1/2, 1/2]
+    const double u[4] = {-0.43056815579702629, -0.16999052179242813, 0.16999052179242813,
+                         0.43056815579702629};
+    const double w[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
+                         0.17392742256872693};
+    double s = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c)
+                s += w[a] * w[b] * w[c] * tensor_component(comp, I + u[a], J + u[b], K + u[c]);
+    return s;
+}
+
+// kind 0: Eqs. 10-11 (the paper's tensor); kind 1: Newell's averaged tensor
+__device__ inline double tensor_value(int kind, int comp, int I, int J, int K)
+{
+    return kind ? newell_component(comp, I, J, K) : tensor_component(comp, I, J, K);
+}
+
 // Wrapped offset of padded index q along an axis of n cells padded to P >= 2n-1:
 // q < n -> q; q > P - n -> q - P; otherwise no offset (the entry is zero).
 __device__ inline bool wrap_offset(int q, int n, int P, int* d)
@@ -57,8 +146,8 @@ __device__ inline bool wrap_offset(int q, int n, int P, int* d)
     return false;
 }
 
-__global__ void k_tensor_wrapped(double* out, int comp, int nx, int ny, int nz, int Px, int Py,
-                                 int Pz)
+__global__ void k_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
+                                 int Py, int Pz)
 {
     const int64_t total = (int64_t)Px * Py * Pz;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
@@ -69,12 +158,12 @@ __global__ void k_tensor_wrapped(double* out, int comp, int nx, int ny, int nz, 
         int I, J, K;
         double v = 0.0;
         if (wrap_offset(qx, nx, Px, &I) && wrap_offset(qy, ny, Py, &J) && wrap_offset(qz, nz, Pz, &K))
-            v = tensor_component(comp, I, J, K);
+            v = tensor_value(kind, comp, I, J, K);
         out[q] = v;
     }
 }
 
-__global__ void k_tensor_table(double* out, int nx, int ny, int nz)
+__global__ void k_tensor_table(double* out, int kind, int nx, int ny, int nz)
 {
     const int tx = 2 * nx - 1, ty = 2 * ny - 1, tz = 2 * nz - 1;
     const int64_t plane = (int64_t)tx * ty * tz;
@@ -83,7 +172,7 @@ __global__ void k_tensor_table(double* out, int nx, int ny, int nz)
         const int I = (int)(q % tx) - (nx - 1);
         const int J = (int)((q / tx) % ty) - (ny - 1);
         const int K = (int)(q / ((int64_t)tx * ty)) - (nz - 1);
-        for (int c = 0; c < 6; ++c) out[c * plane + q] = tensor_component(c, I, J, K);
+        for (int c = 0; c < 6; ++c) out[c * plane + q] = tensor_value(kind, c, I, J, K);
     }
 }
 
@@ -139,19 +228,20 @@ static int grid_for(int64_t n, int block)
     return (int)g;
 }
 
-hipError_t launch_tensor_wrapped(double* out, int comp, int nx, int ny, int nz, int Px, int Py,
-                                 int Pz, hipStream_t s)
+hipError_t launch_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
+                                 int Py, int Pz, hipStream_t s)
 {
     const int64_t total = (int64_t)Px * Py * Pz;
-    hipLaunchKernelGGL(k_tensor_wrapped, dim3(grid_for(total, 256)), dim3(256), 0, s, out, comp, nx,
-                       ny, nz, Px, Py, Pz);
+    hipLaunchKernelGGL(k_tensor_wrapped, dim3(grid_for(total, 256)), dim3(256), 0, s, out, kind, comp,
+                       nx, ny, nz, Px, Py, Pz);
     return hipGetLastError();
 }
 
-hipError_t launch_tensor_table(double* out, int nx, int ny, int nz, hipStream_t s)
+hipError_t launch_tensor_table(double* out, int kind, int nx, int ny, int nz, hipStream_t s)
 {
     const int64_t total = (int64_t)(2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1);
-    hipLaunchKernelGGL(k_tensor_table, dim3(grid_for(total, 256)), dim3(256), 0, s, out, nx, ny, nz);
+    hipLaunchKernelGGL(k_tensor_table, dim3(grid_for(total, 256)), dim3(256), 0, s, out, kind, nx, ny,
+                       nz);
     return hipGetLastError();
 }
 
