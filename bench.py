@@ -254,9 +254,10 @@ def cube_sweep_leg(steps: int = 200) -> dict:
     for n in (8, 16, 32, 64, 128):
         row = {"N": n}
         for prec in ("f32", "f64"):
-            sim = mm.Sim(n, n, n, 34e-9 / n, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0, precision=prec)
+            sim = mm.Sim(n, n, n, 34e-9 / n, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0, precision=prec,
+                         graph=True)
             sim.set_m(random_unit_m((3, n, n, n), seed=n))
-            sim.step_euler(5, 1e-14)
+            sim.step_euler(16, 1e-14)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step_euler(steps, 1e-14)
@@ -267,8 +268,37 @@ def cube_sweep_leg(steps: int = 200) -> dict:
             cpu, g64, g32 = PAPER_TABLE1_MS[n]
             row["paper_ms_cpu_fp64_fp32"] = [cpu, g64, g32]
         rows.append(row)
-    return {"workload": "N^3 cube, explicit Euler + renormalisation (context: paper Table 1, "
-                        "other hardware, MATLAB)", "rows": rows}
+    return {"workload": "N^3 cube, explicit Euler + renormalisation, graph replay of 8-step "
+                        "groups (context: paper Table 1, other hardware, MATLAB)", "rows": rows}
+
+
+def sp4_leg() -> dict:
+    """The appendix run of the paper (standard problem #4, field 1): 166x42x1 cells of 3 nm,
+    150000 explicit Euler steps of 5 fs through the saturate / ramp / relax / reverse
+    protocol, <m> every 1000 steps; wall time of the whole protocol in FP32 and FP64."""
+    import torch
+
+    import paper_1501_07293_amd as mm
+    import synthetic
+    c = synthetic.SP4
+    out = {"workload": "standard problem 4 protocol, 166x42x1, 150000 Euler steps (appendix script)"}
+    for prec in ("f32", "f64"):
+        sim = mm.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
+                     gamma=c.gamma, precision=prec, graph=True)
+        m0 = np.zeros(c.shape)
+        m0[0] = 1.0
+        sim.set_m(m0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = sim.run_schedule(synthetic.sp4_pieces(), c.dt, 1000, method="euler")
+        torch.cuda.synchronize()
+        out[f"seconds_{prec}"] = time.perf_counter() - t0
+        t = tr.cpu().numpy()
+        out[f"s_state_m_{prec}"] = t[49, 1:].tolist()
+        out[f"final_m_{prec}"] = t[-1, 1:].tolist()
+        sim.close()
+    out["us_per_step_f32"] = 1e6 * out["seconds_f32"] / c.steps
+    return out
 
 
 def field_error_sampled(sim, cfg, pb, nsamp: int, seed: int = 1):
@@ -330,6 +360,7 @@ def main():
     ap.add_argument("--no-batched-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cube-leg", action="store_true")
+    ap.add_argument("--no-sp4-leg", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--samples", type=int, default=64)
     args = ap.parse_args()
@@ -416,6 +447,8 @@ def main():
         out["adjoint"] = adjoint_leg()
     if not args.no_cube_leg:
         out["paper_table1_shape"] = cube_sweep_leg()
+    if not args.no_sp4_leg:
+        out["paper_appendix_sp4"] = sp4_leg()
     print(json.dumps(out), flush=True)
 
 

@@ -254,6 +254,7 @@ struct mm_sim {
     bool graph_valid;
     double graph_dt;
     int graph_chunk;
+    int graph_method;
     // profiling
     int prof_kernel;
     std::vector<hipEvent_t> ev;
@@ -615,10 +616,10 @@ bool piece_ramps(const mm_segment& g)
 // the piece's step n0 + n.
 template <typename T>
 mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt, const mm_segment* g = nullptr,
-                     int64_t n0 = 0)
+                     int64_t n0 = 0, hipStream_t st = nullptr)
 {
     const Plan& p = s->p;
-    hipStream_t st = s->stream;
+    if (!st) st = s->stream;
     T* bufs[2] = {s->at<T>(p.o_mn), s->at<T>(p.o_ma)};
     T* hd = s->at<T>(p.o_hd);
     LlgArgs<T> a = llg_args<T>(s, dt);
@@ -669,7 +670,7 @@ mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
         return MM_OK;
     }
     const int chunk = 8;
-    if (!s->graph_valid || s->graph_dt != dt) {
+    if (!s->graph_valid || s->graph_dt != dt || s->graph_method != MM_RK4) {
         drop_graph(s);
         HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
         mm_status r = MM_OK;
@@ -686,6 +687,7 @@ mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
         s->graph_valid = true;
         s->graph_dt = dt;
         s->graph_chunk = chunk;
+        s->graph_method = MM_RK4;
     }
     int64_t n = 0;
     for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, st));
@@ -694,6 +696,37 @@ mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
         if (r != MM_OK) return r;
     }
     return MM_OK;
+}
+
+// nsteps Euler steps under the handle's constant field; with MM_USE_GRAPH whole
+// groups of 8 steps replay a captured graph (shared slot with the RK4 graph).
+template <typename T>
+mm_status euler_steps(mm_sim* s, int64_t nsteps, double dt)
+{
+    const bool use_graph = (s->flags & MM_USE_GRAPH) && s->prof_kernel < 0;
+    const int chunk = 8;  // even: the captured steps end in m_n without a copy
+    if (!use_graph || nsteps < chunk) return euler_impl<T>(s, nsteps, dt);
+    if (!s->graph_valid || s->graph_dt != dt || s->graph_method != MM_EULER) {
+        drop_graph(s);
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = euler_impl<T>(s, chunk, dt, nullptr, 0, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (r != MM_OK) {
+            if (g) hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        s->graph = g;
+        HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+        s->graph_valid = true;
+        s->graph_dt = dt;
+        s->graph_chunk = chunk;
+        s->graph_method = MM_EULER;
+    }
+    int64_t n = 0;
+    for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
+    return n < nsteps ? euler_impl<T>(s, nsteps - n, dt) : MM_OK;
 }
 
 // One row of the mean-magnetisation trace, enqueued on the handle's stream.
@@ -729,7 +762,7 @@ mm_status schedule_impl(mm_sim* s, const mm_segment* segs, int nseg, int method,
             const int64_t run = std::min(g.steps - n, every - done % every);
             mm_status r = MM_OK;
             if (method == MM_EULER) {
-                r = euler_impl<T>(s, run, dt, ramp ? &g : nullptr, n);
+                r = ramp ? euler_impl<T>(s, run, dt, &g, n) : euler_steps<T>(s, run, dt);
             } else if (!ramp) {
                 r = step_impl<T>(s, run, dt);
             } else {
@@ -1648,7 +1681,7 @@ mm_status mm_step_euler(mm_sim* s, int64_t nsteps, double dt)
     if (nsteps < 0) return fail(MM_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_step_euler before mm_set_m");
-    return s->p.prec == MM_F32 ? euler_impl<float>(s, nsteps, dt) : euler_impl<double>(s, nsteps, dt);
+    return s->p.prec == MM_F32 ? euler_steps<float>(s, nsteps, dt) : euler_steps<double>(s, nsteps, dt);
 }
 
 mm_status mm_run_schedule(mm_sim* s, const mm_segment* segs, int32_t nseg, int32_t method,

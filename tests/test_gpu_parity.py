@@ -265,3 +265,21 @@ def test_euler_matches_oracle(dims, precision):
     ref = oracle.euler(pb, m_used, 2e-14, 25)
     err = np.abs(to_np(sim.get_m()) - ref).max()
     assert err <= (1e-11 if precision == "f64" else 2e-5), err
+
+
+def test_euler_graph_replay_matches_eager():
+    # 37 Euler steps (four replays of an 8-step graph, then 5 eager steps), twice in a
+    # row, against the same steps without the graph: bitwise.
+    dims = (24, 10, 2)
+    pb = problem(*dims, cell=4e-9, Ku=500.0, alpha=0.5)
+    m0 = random_unit_m(pb.shape, seed=33)
+    out = []
+    for graph in (False, True):
+        sim = mmag.Sim(*dims, 4e-9, Ku=500.0, alpha=0.5, precision="f32", graph=graph)
+        sim.set_m(m0)
+        sim.step_euler(37, 2e-14)
+        sim.step(3, 2e-14)          # an RK4 step in between takes the graph slot back
+        sim.step_euler(37, 2e-14)
+        out.append(to_np(sim.get_m()))
+    assert np.array_equal(out[0], out[1])
+
