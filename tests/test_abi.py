@@ -164,3 +164,14 @@ def test_x_lines_option_validated(lib):
     for xl, want in ((0, 0), (4, 0), (8, 0), (6, -1)):
         o = mm.Options(0, 0, 0, 0, 0, 0, xl)
         assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b)) == want
+
+
+def test_schedule_and_newell_entry_points_reject_bad_arguments(lib):
+    seg = (mm.Segment * 1)()
+    seg[0].steps = 5
+    rows = ctypes.c_int64(7)
+    assert lib.mm_run_schedule(None, seg, 1, mm.MM_RK4, 1e-14, 1, None, 0, ctypes.byref(rows)) == -1
+    assert rows.value == 0
+    assert lib.mm_demag_tensor_newell(0, 1, 1, None, None) == -1
+    assert lib.mm_demag_tensor_newell(2, 2, 2, None, None) == -1
+    assert b"dims" in lib.mm_last_error()
