@@ -258,12 +258,21 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
     const int tpp = (a.ny + ROWS - 1) / ROWS;
     const int plane = tile / tpp, yb = (tile - plane * tpp) * ROWS;
     const cpx<T>* src = (const cpx<T>*)a.in + (int64_t)plane * HX * a.srows;
-    // gather the 16 half-spectrum rows of this block: raw[rr][kx]
-    for (int idx = threadIdx.x; idx < HX * ROWS; idx += NT) {
+    // gather the 2L half-spectrum rows of this block, raw[rr][kx]: every load is
+    // issued before the first LDS store, so the gather costs one memory latency
+    constexpr int NEL = HX * ROWS, ITER = (NEL + NT - 1) / NT;
+    cpx<T> g[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
         const int rr = idx % ROWS, kx = idx / ROWS;
-        cpx<T> x = {(T)0, (T)0};
-        if (yb + rr < a.ny) x = src[(int64_t)kx * a.srows + yb + rr];
-        lds[rr * HX + kx] = x;
+        g[it] = cpx<T>{(T)0, (T)0};
+        if (idx < NEL && yb + rr < a.ny) g[it] = src[(int64_t)kx * a.srows + yb + rr];
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
+        if (idx < NEL) lds[(idx % ROWS) * HX + idx / ROWS] = g[it];
     }
     __syncthreads();
     const int l = threadIdx.x / TL, u = threadIdx.x % TL;

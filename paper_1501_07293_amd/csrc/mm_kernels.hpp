@@ -190,10 +190,7 @@ struct LlgArgs {
 // the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes;
 // a work-group of kLlgNT threads covers kLlgNT consecutive columns of one chunk,
 // and the chunks of the same columns are consecutive work-groups
-#ifndef MM_LLG_Z
-#define MM_LLG_Z 4
-#endif
-constexpr int kLlgZ = MM_LLG_Z;
+constexpr int kLlgZ = 4;
 constexpr int kLlgNT = 256;
 __host__ __device__ inline int64_t llg_blocks(int nx, int ny, int nz)
 {

@@ -64,12 +64,7 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
 template <typename T>
 __global__ __launch_bounds__(kLlgNT) void k_llg_stage(LlgArgs<T> a)
 {
-#if MM_LLG_TILE
-    __shared__ T sh[kLlgZ * 3 * kLlgNT];
-    body_llg_tile<T>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, sh);
-#else
     body_llg_stage<T>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
-#endif
 }
 
 template <typename T>
@@ -204,12 +199,7 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
 {
-#if MM_LLG_TILE
-    const int64_t blocks = llg_tile_blocks(a.nx, a.ny, a.nz);
-#else
-    const int64_t blocks = llg_blocks(a.nx, a.ny, a.nz);
-#endif
-    hipLaunchKernelGGL(k_llg_stage<T>, dim3((int)blocks), dim3(kLlgNT), 0, s, a);
+    hipLaunchKernelGGL(k_llg_stage<T>, dim3((int)llg_blocks(a.nx, a.ny, a.nz)), dim3(kLlgNT), 0, s, a);
     return hipGetLastError();
 }
 

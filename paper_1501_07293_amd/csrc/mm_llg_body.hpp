@@ -5,12 +5,6 @@
 #include "mm_common.hpp"
 #include "mm_kernels.hpp"
 
-#ifndef MM_LLG_XSHFL
-#define MM_LLG_XSHFL 0
-#endif
-#ifndef MM_LLG_TILE
-#define MM_LLG_TILE 0
-#endif
 
 namespace mm {
 
@@ -81,6 +75,9 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
 // neighbours are read from HBM once and found in L2 the second time.
 
 // Thread `lane` of work-group `blk` (0 <= blk < llg_blocks, 0 <= lane < kLlgNT).
+// A neighbour missing at the boundary is the cell itself (Eq. 7): its address
+// is clamped to the cell's own, which adds mc - mc = 0, so every load is issued
+// unconditionally and none waits on a per-lane branch.
 template <typename T>
 __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane)
 {
@@ -98,138 +95,43 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane
 #pragma unroll
     for (int q = 0; q < KZ + 2; ++q) {
         const int k = k0 - 1 + q;
-        const bool in = k >= 0 && k < a.nz;
+        const int kk = k < 0 ? 0 : (k >= a.nz ? a.nz - 1 : k);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) col[q][d] = in ? ms[d * N + pc + k * plane] : (T)0;
+        for (int d = 0; d < 3; ++d) col[q][d] = ms[d * N + pc + kk * plane];
     }
+    const int64_t dxm = i > 0 ? -1 : 0, dxp = i < a.nx - 1 ? 1 : 0;
+    const int64_t dym = j > 0 ? -sy : 0, dyp = j < a.ny - 1 ? sy : 0;
     T lap[KZ][3], hd[KZ][3], mn[KZ][3], ac[KZ][3], kan[KZ];
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
         const int k = k0 + q;
         const bool in = k < a.nz;
-        const int64_t c = pc + (int64_t)(in ? k : 0) * plane;
+        const int64_t c = pc + (int64_t)(in ? k : a.nz - 1) * plane;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const T* u = ms + d * N;
+            const T* u = ms + d * N + c;
             const T mc = col[q + 1][d];
             T acc = (T)0;
-#if MM_LLG_XSHFL
-            // x neighbours from the adjacent lanes; the wave's first and last lanes
-            // load the one value outside the wave
-            const int wl = lane & 63;
-            T left = __shfl_up(mc, 1), right = __shfl_down(mc, 1);
-            const bool edge = (wl == 0 && i > 0) || (wl == 63 && i < a.nx - 1);
-            if (in && edge) {
-                const T e = u[wl == 0 ? c - 1 : c + 1];
-                if (wl == 0) left = e;
-                else right = e;
-            }
-#endif
-            if (in) {
-#if MM_LLG_XSHFL
-                if (i > 0) acc += left - mc;
-                if (i < a.nx - 1) acc += right - mc;
-#else
-                if (i > 0) acc += u[c - 1] - mc;
-                if (i < a.nx - 1) acc += u[c + 1] - mc;
-#endif
-                if (j > 0) acc += u[c - sy] - mc;
-                if (j < a.ny - 1) acc += u[c + sy] - mc;
-                if (k > 0) acc += col[q][d] - mc;
-                if (k < a.nz - 1) acc += col[q + 2][d] - mc;
-            }
+            acc += u[dxm] - mc;
+            acc += u[dxp] - mc;
+            acc += u[dym] - mc;
+            acc += u[dyp] - mc;
+            if (k > 0) acc += col[q][d] - mc;
+            if (k < a.nz - 1) acc += col[q + 2][d] - mc;
             lap[q][d] = acc;
-            hd[q][d] = (in && a.hd) ? a.hd[d * N + c] : (T)0;
-            mn[q][d] = (in && a.stage > 1) ? a.mn[d * N + c] : (T)0;
-            ac[q][d] = (in && a.stage > 1) ? a.acc[d * N + c] : (T)0;
+            hd[q][d] = (T)0;
+            mn[q][d] = (T)0;
+            ac[q][d] = (T)0;
+            if (a.hd) hd[q][d] = a.hd[d * N + c];
+            if (a.stage > 1) {
+                mn[q][d] = a.mn[d * N + c];
+                ac[q][d] = a.acc[d * N + c];
+            }
         }
-        kan[q] = (in && a.ku) ? a.ku[c] : a.can;
+        kan[q] = a.ku ? a.ku[c] : a.can;
     }
     llg_update<T>(a, pc, k0, col, lap, hd, mn, ac, kan);
 }
 
-
-// Tiled variant for one large grid: a work-group takes a tile of kLlgTX x
-// kLlgTY columns (one wave per row of the tile) and one chunk of kLlgZ planes.
-// The x neighbours come from the adjacent lanes (the wave's first and last lane
-// load the value outside the tile), the y neighbours inside the tile from LDS,
-// and only the tile's first and last rows load a halo row from global memory.
-constexpr int kLlgTX = 64, kLlgTY = kLlgNT / kLlgTX;
-__host__ __device__ inline int64_t llg_tile_blocks(int nx, int ny, int nz)
-{
-    return (int64_t)((nx + kLlgTX - 1) / kLlgTX) * ((ny + kLlgTY - 1) / kLlgTY) *
-           ((nz + kLlgZ - 1) / kLlgZ);
-}
-
-// sh: kLlgZ * 3 * kLlgNT elements of LDS.  Every thread of the work-group must call it.
-template <typename T>
-__device__ inline void body_llg_tile(const LlgArgs<T>& a, int64_t blk, int lane, T* sh)
-{
-    constexpr int KZ = kLlgZ;
-    const int64_t plane = (int64_t)a.nx * a.ny, N = a.N, sy = a.nx;
-    const int nzc = (a.nz + KZ - 1) / KZ;
-    const int kc = (int)(blk % nzc);
-    const int64_t t = blk / nzc;
-    const int ntx = (a.nx + kLlgTX - 1) / kLlgTX;
-    const int wx = lane % kLlgTX, wy = lane / kLlgTX;
-    const int i = (int)(t % ntx) * kLlgTX + wx, j = (int)(t / ntx) * kLlgTY + wy;
-    const bool act = i < a.nx && j < a.ny;
-    const int64_t pc = act ? (int64_t)j * a.nx + i : 0;
-    const int k0 = kc * KZ;
-    const T* __restrict__ ms = a.ms;
-    T col[KZ + 2][3];
-#pragma unroll
-    for (int q = 0; q < KZ + 2; ++q) {
-        const int k = k0 - 1 + q;
-        const bool in = act && k >= 0 && k < a.nz;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) col[q][d] = in ? ms[d * N + pc + k * plane] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < KZ; ++q)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) sh[(q * 3 + d) * kLlgNT + lane] = col[q + 1][d];
-    __syncthreads();
-    T lap[KZ][3], hd[KZ][3], mn[KZ][3], ac[KZ][3], kan[KZ];
-#pragma unroll
-    for (int q = 0; q < KZ; ++q) {
-        const int k = k0 + q;
-        const bool in = act && k < a.nz;
-        const int64_t c = pc + (int64_t)(in ? k : 0) * plane;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T* u = ms + d * N;
-            const T mc = col[q + 1][d];
-            T left = __shfl_up(mc, 1), right = __shfl_down(mc, 1);
-            const bool xedge = (wx == 0 && i > 0) || (wx == kLlgTX - 1 && i < a.nx - 1);
-            if (in && xedge) {
-                const T e = u[wx == 0 ? c - 1 : c + 1];
-                if (wx == 0) left = e;
-                else right = e;
-            }
-            const T* row = sh + (q * 3 + d) * kLlgNT;
-            T down = wy > 0 ? row[lane - kLlgTX] : (T)0;
-            T up = wy < kLlgTY - 1 ? row[lane + kLlgTX] : (T)0;
-            if (in && wy == 0 && j > 0) down = u[c - sy];
-            if (in && wy == kLlgTY - 1 && j < a.ny - 1) up = u[c + sy];
-            T acc = (T)0;
-            if (in) {
-                if (i > 0) acc += left - mc;
-                if (i < a.nx - 1) acc += right - mc;
-                if (j > 0) acc += down - mc;
-                if (j < a.ny - 1) acc += up - mc;
-                if (k > 0) acc += col[q][d] - mc;
-                if (k < a.nz - 1) acc += col[q + 2][d] - mc;
-            }
-            lap[q][d] = acc;
-            hd[q][d] = (in && a.hd) ? a.hd[d * N + c] : (T)0;
-            mn[q][d] = (in && a.stage > 1) ? a.mn[d * N + c] : (T)0;
-            ac[q][d] = (in && a.stage > 1) ? a.acc[d * N + c] : (T)0;
-        }
-        kan[q] = (in && a.ku) ? a.ku[c] : a.can;
-    }
-    if (!act) return;
-    llg_update<T>(a, pc, k0, col, lap, hd, mn, ac, kan);
-}
 
 }  // namespace mm
