@@ -284,7 +284,8 @@ def sp4_leg() -> dict:
     out = {"workload": "standard problem 4 protocol, 166x42x1, 150000 Euler steps (appendix script)"}
     for prec in ("f32", "f64"):
         sim = mm.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
-                     gamma=c.gamma, precision=prec, graph=True)
+                     gamma=c.gamma, precision=prec, graph=True, autotune=True)
+        out[f"plan_{prec}"] = {k: sim.plan()[k] for k in ("px", "py", "generic_fft", "x_lines")}
         m0 = np.zeros(c.shape)
         m0[0] = 1.0
         sim.set_m(m0)

@@ -127,18 +127,23 @@ __global__ __launch_bounds__(256) void k_adj_apply(AdjArgs<T> a, T cmu, T ca)
     const int i = (int)(c % a.nx);
     const int j = (int)((c / a.nx) % a.ny);
     const int k = (int)(c / sz);
+    // a neighbour missing at the boundary is the cell itself (Eq. 7): clamped
+    // offsets add uc - uc = 0 and keep every load unconditional
+    const int64_t dxm = i > 0 ? -1 : 0, dxp = i < a.nx - 1 ? 1 : 0;
+    const int64_t dym = j > 0 ? -sy : 0, dyp = j < a.ny - 1 ? sy : 0;
+    const int64_t dzm = k > 0 ? -sz : 0, dzp = k < a.nz - 1 ? sz : 0;
     T out[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T* u = a.nu + d * N;
-        const T uc = u[c];
+        const T* u = a.nu + d * N + c;
+        const T uc = u[0];
         T acc = (T)0;
-        if (i > 0) acc += u[c - 1] - uc;
-        if (i < a.nx - 1) acc += u[c + 1] - uc;
-        if (j > 0) acc += u[c - sy] - uc;
-        if (j < a.ny - 1) acc += u[c + sy] - uc;
-        if (k > 0) acc += u[c - sz] - uc;
-        if (k < a.nz - 1) acc += u[c + sz] - uc;
+        acc += u[dxm] - uc;
+        acc += u[dxp] - uc;
+        acc += u[dym] - uc;
+        acc += u[dyp] - uc;
+        acc += u[dzm] - uc;
+        acc += u[dzp] - uc;
         T v = a.loc[d * N + c] + a.cex * acc;
         if (a.hd) v += a.hd[d * N + c];
         out[d] = v;

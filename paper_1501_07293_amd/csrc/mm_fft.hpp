@@ -233,30 +233,38 @@ __device__ inline void fft_stage(cpx<T>* lds, const LdsGeom g, int P, int p, int
     constexpr int MAXB = (kElemsPerThread + R - 1) / R;
     const int m = P / R;
     const int nbf = g.nlines * m;
-    cpx<T> v[MAXB][R];
+    cpx<T> v[MAXB][R], w[MAXB][R];
     int base[MAXB], iw[MAXB];
+    // every twiddle of the stage is loaded before the first is used (one memory
+    // latency per stage); k = 0 reads tw[0] = 1, whose product is exact
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int b = tid + q * NT;
-        base[q] = -1;
-        if (b < nbf) {
-            int l, i;
-            if (LINE_FAST) {
-                l = b % g.nlines;
-                i = b / g.nlines;
-            } else {
-                i = b % m;
-                l = b / m;
-            }
-            const int lb = (l % g.LI) * g.LSi + (l / g.LI) * g.LSo;
-            base[q] = lb;
-            iw[q] = i;
+        const bool ok = b < nbf;
+        int l, i;
+        if (LINE_FAST) {
+            l = b % g.nlines;
+            i = b / g.nlines;
+        } else {
+            i = b % m;
+            l = b / m;
+        }
+        if (!ok) i = 0;
+        base[q] = ok ? (l % g.LI) * g.LSi + (l / g.LI) * g.LSo : -1;
+        iw[q] = i;
+        const int k = i % p;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[q][r] = tw[r * k * tstride];
+    }
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        if (base[q] >= 0) {
+            const int lb = base[q], i = iw[q];
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = lds[lb + (i + r * m) * g.ES];
-            const int k = i % p;
-            if (k != 0) {
+            if (i % p != 0) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * tstride]);
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r]);
             }
             Dft<T, R>::run(v[q]);
         }

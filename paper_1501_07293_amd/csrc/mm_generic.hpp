@@ -25,6 +25,11 @@ __device__ inline int64_t col_off(int c, int cpr, int64_t row2)
     return (int64_t)r * row2 + (c - r * cpr);
 }
 
+// Global loads of the input loops go through registers in groups of kStage per
+// thread, all issued before the group's LDS stores, so a group costs one
+// memory latency instead of one per element.
+constexpr int kStage = 8;
+
 // ------------------------------------------------------------------ x forward
 template <typename T, int NT>
 __device__ void body_row_r2c(const RowR2CArgs& a, const FftPlan& pl, int tile, cpx<T>* lds)
@@ -33,15 +38,25 @@ __device__ void body_row_r2c(const RowR2CArgs& a, const FftPlan& pl, int tile, c
     const int npairs = (a.nrows + 1) >> 1;
     const int q0 = tile * B;
     const T* in = (const T*)a.in;
-    for (int idx = threadIdx.x; idx < B * P; idx += NT) {
-        const int q = idx / P, x = idx - q * P, pr = q0 + q;
-        cpx<T> v = {(T)0, (T)0};
-        if (pr < npairs && x < a.nvalid) {
-            const int r0 = 2 * pr;
-            v.re = in[(int64_t)r0 * a.in_row_stride + x];
-            if (r0 + 1 < a.nrows) v.im = in[(int64_t)(r0 + 1) * a.in_row_stride + x];
+    const int BP = B * P;
+    for (int i0 = 0; i0 < BP; i0 += kStage * NT) {
+        cpx<T> v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int q = idx / P, x = idx - q * P, pr = q0 + q;
+            v[u] = cpx<T>{(T)0, (T)0};
+            if (idx < BP && pr < npairs && x < a.nvalid) {
+                const int r0 = 2 * pr;
+                v[u].re = in[(int64_t)r0 * a.in_row_stride + x];
+                if (r0 + 1 < a.nrows) v[u].im = in[(int64_t)(r0 + 1) * a.in_row_stride + x];
+            }
         }
-        lds[q * LS + x] = v;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx < BP) lds[(idx / P) * LS + idx % P] = v[u];
+        }
     }
     __syncthreads();
     lds_fft<T, NT, false>(lds, LdsGeom{B, B, LS, 0, 1}, pl, (const cpx<T>*)a.tw, threadIdx.x);
@@ -71,30 +86,42 @@ __device__ void body_row_c2r(const RowC2RArgs& a, const FftPlan& pl, int tile, c
     const int q0 = tile * B;
     const bool evenP = (P & 1) == 0;
     const cpx<T>* in = (const cpx<T>*)a.in;
-    for (int idx = threadIdx.x; idx < B * P; idx += NT) {
-        const int q = idx / P, x = idx - q * P, pr = q0 + q;
-        cpx<T> z = {(T)0, (T)0};
-        if (pr < npairs) {
-            const int r0 = 2 * pr;
-            const bool has1 = r0 + 1 < a.nrows;
-            const int64_t o0 = row_off(r0, a.rows_per_plane, a.in_plane_stride, a.rstride);
-            const int64_t o1 = has1 ? row_off(r0 + 1, a.rows_per_plane, a.in_plane_stride, a.rstride) : 0;
-            const int64_t ks = a.kstride;
-            cpx<T> A, Bv = {(T)0, (T)0};
+    const int BP = B * P;
+    for (int i0 = 0; i0 < BP; i0 += kStage * NT) {
+        cpx<T> A[kStage], Bv[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int q = idx / P, x = idx - q * P, pr = q0 + q;
+            A[u] = Bv[u] = cpx<T>{(T)0, (T)0};
+            if (idx < BP && pr < npairs) {
+                const int r0 = 2 * pr;
+                const bool has1 = r0 + 1 < a.nrows;
+                const int64_t o0 = row_off(r0, a.rows_per_plane, a.in_plane_stride, a.rstride);
+                const int64_t o1 = has1 ? row_off(r0 + 1, a.rows_per_plane, a.in_plane_stride, a.rstride) : 0;
+                const int64_t kk = (int64_t)(x < a.hx ? x : P - x) * a.kstride;
+                A[u] = in[o0 + kk];
+                if (has1) Bv[u] = in[o1 + kk];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx >= BP) continue;
+            const int q = idx / P, x = idx - q * P;
+            cpx<T> a0 = A[u], b0 = Bv[u];
             if (x < a.hx) {
-                A = in[o0 + x * ks];
-                if (has1) Bv = in[o1 + x * ks];
                 if (x == 0 || (evenP && 2 * x == P)) {  // DC and Nyquist bins are real
-                    A.im = (T)0;
-                    Bv.im = (T)0;
+                    a0.im = (T)0;
+                    b0.im = (T)0;
                 }
             } else {
-                A = conj(in[o0 + (P - x) * ks]);
-                if (has1) Bv = conj(in[o1 + (P - x) * ks]);
+                a0 = conj(a0);
+                b0 = conj(b0);
             }
-            z = {A.re - Bv.im, A.im + Bv.re};  // A + i B
+            const cpx<T> z = {a0.re - b0.im, a0.im + b0.re};  // A + i B
+            lds[q * LS + x] = conj(z);
         }
-        lds[q * LS + x] = conj(z);
     }
     __syncthreads();
     lds_fft<T, NT, false>(lds, LdsGeom{B, B, LS, 0, 1}, pl, (const cpx<T>*)a.tw, threadIdx.x);
@@ -118,14 +145,23 @@ __device__ void body_col_fft(const ColArgs& a, const FftPlan& pl, int tile, cpx<
     const int ctiles = (a.ncols + TW - 1) / TW;
     const int plane = tile / ctiles, c0 = (tile - plane * ctiles) * TW;
     cpx<T>* buf = (cpx<T>*)a.buf + (int64_t)plane * a.plane_stride;
-    for (int idx = threadIdx.x; idx < P * TW; idx += NT) {
-        const int e = idx / TW, t = idx - e * TW, col = c0 + t;
-        cpx<T> v = {(T)0, (T)0};
-        if (e < a.nin && col < a.ncols) {
-            v = buf[e * a.es + col_off(col, a.cols_per_row, a.row2_stride)];
-            if (a.inverse) v = conj(v);
+    const int PTW = P * TW;
+    for (int i0 = 0; i0 < PTW; i0 += kStage * NT) {
+        cpx<T> v[kStage];
+        bool ok[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int e = idx / TW, t = idx - e * TW, col = c0 + t;
+            v[u] = cpx<T>{(T)0, (T)0};
+            ok[u] = idx < PTW && e < a.nin && col < a.ncols;
+            if (ok[u]) v[u] = buf[e * a.es + col_off(col, a.cols_per_row, a.row2_stride)];
         }
-        lds[idx] = v;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx < PTW) lds[idx] = (a.inverse && ok[u]) ? conj(v[u]) : v[u];
+        }
     }
     __syncthreads();
     lds_fft<T, NT, true>(lds, LdsGeom{TW, TW, 1, 0, TW}, pl, (const cpx<T>*)a.tw, threadIdx.x);
@@ -148,14 +184,23 @@ __device__ void body_line_c2c(const LineArgs& a, const FftPlan& pl, int tile, cp
     const int P = pl.P, LS = P + 1, B = a.lines_per_wg;
     const int l0 = tile * B;
     cpx<T>* buf = (cpx<T>*)a.buf;
-    for (int idx = threadIdx.x; idx < B * P; idx += NT) {
-        const int q = idx / P, e = idx - q * P, l = l0 + q;
-        cpx<T> v = {(T)0, (T)0};
-        if (l < a.nlines && e < a.nin) {
-            v = buf[(int64_t)l * a.line_stride + e];
-            if (a.inverse) v = conj(v);
+    const int BP = B * P;
+    for (int i0 = 0; i0 < BP; i0 += kStage * NT) {
+        cpx<T> v[kStage];
+        bool ok[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int q = idx / P, e = idx - q * P, l = l0 + q;
+            v[u] = cpx<T>{(T)0, (T)0};
+            ok[u] = idx < BP && l < a.nlines && e < a.nin;
+            if (ok[u]) v[u] = buf[(int64_t)l * a.line_stride + e];
         }
-        lds[q * LS + e] = v;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx < BP) lds[(idx / P) * LS + idx % P] = (a.inverse && ok[u]) ? conj(v[u]) : v[u];
+        }
     }
     __syncthreads();
     lds_fft<T, NT, false>(lds, LdsGeom{B, B, LS, 0, 1}, pl, (const cpx<T>*)a.tw, threadIdx.x);
@@ -176,64 +221,89 @@ __device__ void body_kspace(const KspArgs& a, const FftPlan& pl, int tile, cpx<T
     const int c0 = tile * TW;
     cpx<T>* buf = (cpx<T>*)a.buf;
     const int PT = P * TW;
-    for (int idx = threadIdx.x; idx < 3 * PT; idx += NT) {
-        const int c = idx / PT, rem = idx - c * PT, e = rem / TW, t = rem - e * TW, col = c0 + t;
-        cpx<T> v = {(T)0, (T)0};
-        if (e < a.nvalid && col < a.ncols)
-            v = buf[c * a.comp_stride + e * a.es + col_off(col, a.cols_per_row, a.row2_stride)];
-        lds[idx] = v;
+    for (int i0 = 0; i0 < 3 * PT; i0 += kStage * NT) {
+        cpx<T> v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int c = idx / PT, rem = idx - c * PT, e = rem / TW, t = rem - e * TW, col = c0 + t;
+            v[u] = cpx<T>{(T)0, (T)0};
+            if (idx < 3 * PT && e < a.nvalid && col < a.ncols)
+                v[u] = buf[c * a.comp_stride + e * a.es + col_off(col, a.cols_per_row, a.row2_stride)];
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx < 3 * PT) lds[idx] = v[u];
+        }
     }
     __syncthreads();
     const LdsGeom g{3 * TW, TW, 1, PT, TW};
     lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
     // Eq. 14: H~_a = sum_b K~_ab M~_b with the real, symmetric kernel spectrum.
     const T* K = (const T*)a.kern;
-    for (int idx = threadIdx.x; idx < PT; idx += NT) {
-        const int e = idx / TW, t = idx - e * TW, col = c0 + t;
-        if (col >= a.ncols) continue;
-        int kx, ky, kz;
-        if (a.axis_is_z) {
-            kx = col / a.Py;
-            ky = col - kx * a.Py;
-            kz = e;
-        } else {
-            kx = col;
-            ky = e;
-            kz = 0;
+    constexpr int KS = kStage / 2;  // elements per thread whose spectra load together
+    for (int i0 = 0; i0 < PT; i0 += KS * NT) {
+        T kv[KS][6];
+        bool ok[KS];
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int e = idx / TW, t = idx - e * TW, col = c0 + t;
+            ok[u] = idx < PT && col < a.ncols;
+            int kx, ky, kz;
+            if (a.axis_is_z) {
+                kx = col / a.Py;
+                ky = col - kx * a.Py;
+                kz = e;
+            } else {
+                kx = col;
+                ky = e;
+                kz = 0;
+            }
+            T sy = (T)1, sz = (T)1;
+            if (2 * ky > a.Py) {
+                ky = a.Py - ky;
+                sy = (T)-1;
+            }
+            if (2 * kz > a.Pz) {
+                kz = a.Pz - kz;
+                sz = (T)-1;
+            }
+            const int64_t ko = ok[u] ? kz * a.k_zs + kx * a.k_xs + ky : 0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) kv[u][c] = (T)0;
+            if (ok[u]) {
+                if (a.ncomp == 6) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) kv[u][c] = K[c * a.k_cs + ko];
+                } else {  // xx, xy, yy, zz
+                    kv[u][0] = K[ko];
+                    kv[u][1] = K[a.k_cs + ko];
+                    kv[u][3] = K[2 * a.k_cs + ko];
+                    kv[u][5] = K[3 * a.k_cs + ko];
+                }
+            }
+            // parities of the mirrored octant: xy odd in y, xz odd in z, yz odd in both
+            kv[u][1] *= sy;
+            kv[u][2] *= sz;
+            kv[u][4] *= sy * sz;
         }
-        T sy = (T)1, sz = (T)1;
-        if (2 * ky > a.Py) {
-            ky = a.Py - ky;
-            sy = (T)-1;
+        // Eq. 14: H~_a = sum_b K~_ab M~_b with the real, symmetric kernel spectrum.
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            if (!ok[u]) continue;
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const T kxx = kv[u][0], kxy = kv[u][1], kxz = kv[u][2], kyy = kv[u][3], kyz = kv[u][4],
+                    kzz = kv[u][5];
+            const cpx<T> mx = lds[idx], my = lds[PT + idx], mz = lds[2 * PT + idx];
+            const cpx<T> hx = {kxx * mx.re + kxy * my.re + kxz * mz.re, kxx * mx.im + kxy * my.im + kxz * mz.im};
+            const cpx<T> hy = {kxy * mx.re + kyy * my.re + kyz * mz.re, kxy * mx.im + kyy * my.im + kyz * mz.im};
+            const cpx<T> hz = {kxz * mx.re + kyz * my.re + kzz * mz.re, kxz * mx.im + kyz * my.im + kzz * mz.im};
+            lds[idx] = conj(hx);  // inverse transform by conjugation
+            lds[PT + idx] = conj(hy);
+            lds[2 * PT + idx] = conj(hz);
         }
-        if (2 * kz > a.Pz) {
-            kz = a.Pz - kz;
-            sz = (T)-1;
-        }
-        const int64_t ko = kz * a.k_zs + kx * a.k_xs + ky;
-        T kxx, kxy, kxz, kyy, kyz, kzz;
-        if (a.ncomp == 6) {
-            kxx = K[ko];
-            kxy = sy * K[a.k_cs + ko];
-            kxz = sz * K[2 * a.k_cs + ko];
-            kyy = K[3 * a.k_cs + ko];
-            kyz = sy * sz * K[4 * a.k_cs + ko];
-            kzz = K[5 * a.k_cs + ko];
-        } else {
-            kxx = K[ko];
-            kxy = sy * K[a.k_cs + ko];
-            kxz = (T)0;
-            kyy = K[2 * a.k_cs + ko];
-            kyz = (T)0;
-            kzz = K[3 * a.k_cs + ko];
-        }
-        const cpx<T> mx = lds[idx], my = lds[PT + idx], mz = lds[2 * PT + idx];
-        const cpx<T> hx = {kxx * mx.re + kxy * my.re + kxz * mz.re, kxx * mx.im + kxy * my.im + kxz * mz.im};
-        const cpx<T> hy = {kxy * mx.re + kyy * my.re + kyz * mz.re, kxy * mx.im + kyy * my.im + kyz * mz.im};
-        const cpx<T> hz = {kxz * mx.re + kyz * my.re + kzz * mz.re, kxz * mx.im + kyz * my.im + kzz * mz.im};
-        lds[idx] = conj(hx);  // inverse transform by conjugation
-        lds[PT + idx] = conj(hy);
-        lds[2 * PT + idx] = conj(hz);
     }
     __syncthreads();
     lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
