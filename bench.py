@@ -409,7 +409,8 @@ def main():
                           for k, v in per_kernel.items()}
         out["step_model_bytes_per_cell"] = step_bytes / cfg.N
         out["algorithmic_bytes"] = ab
-        out["plan"] = {k: plan[k] for k in ("px", "py", "pz", "passes", "threads", "generic_fft", "x_lines")}
+        out["plan"] = {k: plan[k] for k in ("px", "py", "pz", "passes", "threads", "generic_fft", "x_lines",
+                                            "x_lines_inv")}
         out["effective_gbs"] = step_bytes / (secs / args.steps) / 1e9
     out["sources_sha256"] = {tu: tu_digest(tu) for tu in sorted({t for _, t in KERNEL_TU})}
     out["energy_J"] = energy.tolist()
@@ -465,7 +466,8 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
     if k == "llg":
         return f"mm::k_llg_stage<{t}>"
     if k in ("x_fwd", "x_inv"):
-        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {plan.get('x_lines', 8)}>" \
+        lines = plan.get("x_lines", 8) if k == "x_fwd" else plan.get("x_lines_inv", 4)
+        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {lines}>" \
             if x_ok else \
             f"mm::k_row_{'r2c' if k == 'x_fwd' else 'c2r'}<{t}, {plan['threads']}>"
     if k in ("y_fwd", "y_inv"):

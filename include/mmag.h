@@ -97,7 +97,9 @@ typedef struct {
                             MM_NEWELL */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
-                            0 = automatic (8), 4 or 8 */
+                            0 = automatic (8 forward, 4 inverse), 4, 8 or 16 (both passes;
+                            16 only where its LDS tile and
+                            work-group fit; otherwise that pass runs the runtime-radix body) */
 } mm_options;
 
 typedef struct {
@@ -112,7 +114,8 @@ typedef struct {
     int32_t tuned;       /* 1 when the schedule came from the autotuner */
     int32_t candidates;  /* schedules the autotuner timed (0 if cached or not tuned) */
     double tuned_demag_ms; /* the chosen schedule's time per demag evaluation, ms (0 if not tuned) */
-    int32_t x_lines;     /* row pairs per work-group of the specialised x passes */
+    int32_t x_lines;     /* row pairs per work-group of the specialised x forward pass */
+    int32_t x_lines_inv; /* ... and of the specialised x inverse pass */
 } mm_plan_info;
 
 typedef struct mm_sim mm_sim;

@@ -71,7 +71,8 @@ class PlanInfo(ctypes.Structure):
                 ("spectrum_elems", ctypes.c_int64), ("passes", ctypes.c_int32),
                 ("kernel_imag_ratio", ctypes.c_double), ("generic_fft", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32)]
+                ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32),
+                ("x_lines_inv", ctypes.c_int32)]
 
 
 _lib = None

@@ -105,7 +105,7 @@ struct Plan {
     size_t esz;        // sizeof(T)
     FftPlan fx, fy, fz;
     int x_lines, y_tw, k_tw;
-    int xl;            // complex lines per work-group of the specialised x passes (4 or 8)
+    int xl, xl_inv;    // complex lines per work-group of the specialised x passes (forward, inverse)
     int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
     int64_t oct_elems;         // per component
     // workspace offsets
@@ -179,9 +179,12 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     if (!fits(nt)) return fail(MM_ENOTSUP, "padded sizes %d x %d x %d exceed the FFT work-group capacity",
                                p->Px, p->Py, p->Pz);
     p->nt = nt;
-    if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8)
-        return fail(MM_EINVAL, "x_lines must be 0, 4 or 8");
+    if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8 && o->x_lines != 16)
+        return fail(MM_EINVAL, "x_lines must be 0, 4, 8 or 16");
+    // automatic: 8 lines forward (128-byte transposed segments), 4 inverse (twice the
+    // work-groups per CU for its gather); an explicit value sets both
     p->xl = o->x_lines ? o->x_lines : 8;
+    p->xl_inv = o->x_lines ? o->x_lines : 4;
     if (!make_fft_plan(p->Px, &p->fx) || !make_fft_plan(p->Py, &p->fy) || !make_fft_plan(p->Pz, &p->fz))
         return fail(MM_EINVAL, "padded sizes must be 7-smooth");
     const int cap = kElemsPerThread * nt, ldscap = cap + 64;
@@ -422,7 +425,7 @@ template <typename T>
 hipError_t pass_x_inverse(const PassCtx& c, T* h, hipStream_t st)
 {
     const Plan& p = c.p;
-    XLineArgs xa{c.S, h, c.nplanes, p.ny, p.nx, c.Sy, c.twx, p.xl};
+    XLineArgs xa{c.S, h, c.nplanes, p.ny, p.nx, c.Sy, c.twx, p.xl_inv};
     if (c.fast && launch_xline<T>(xa, p.Px, 1, st)) return hipGetLastError();
     RowC2RArgs r{};
     r.in = c.S;
@@ -1771,6 +1774,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->candidates = s->tune_candidates;
     out->tuned_demag_ms = s->tuned_ms;
     out->x_lines = s->p.xl;
+    out->x_lines_inv = s->p.xl_inv;
     return MM_OK;
 }
 

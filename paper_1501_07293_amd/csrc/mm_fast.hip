@@ -80,7 +80,8 @@ static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
     };
 #define MM_XCASE(PP)                                                                  \
     case PP:                                                                          \
-        if constexpr (x_lds_bytes<T, PP, L>() <= kLdsBudget)                          \
+        if constexpr (x_lds_bytes<T, PP, L>() <= kLdsBudget &&                        \
+                      L * (PP / Sched<PP>::R0) <= 1024)                               \
             return INV ? go(k_xinv<T, PP, L>, PP / Sched<PP>::R0)                     \
                        : go(k_xfwd<T, PP, L>, PP / Sched<PP>::R0);                    \
         return false;
@@ -106,6 +107,8 @@ bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s)
     if (a.nx > P) return false;
     if (a.lines == 4)
         return inverse ? xline_dispatch<T, true, 4>(a, P, s) : xline_dispatch<T, false, 4>(a, P, s);
+    if (a.lines == 16)
+        return inverse ? xline_dispatch<T, true, 16>(a, P, s) : xline_dispatch<T, false, 16>(a, P, s);
     return inverse ? xline_dispatch<T, true, 8>(a, P, s) : xline_dispatch<T, false, 8>(a, P, s);
 }
 

@@ -113,7 +113,7 @@ struct XLineArgs {           // x pass over [nplanes][ny][nx] real rows <-> [npl
     int ny, nx;
     int64_t srows;
     const void* tw;
-    int lines;               // complex lines (row pairs) per work-group: 4 or 8
+    int lines;               // complex lines (row pairs) per work-group: 4, 8 or 16
 };
 struct KzArgs {              // z k-space pass, columns (kx, ky) = (c / Py, c % Py)
     void* buf;

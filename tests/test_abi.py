@@ -161,7 +161,7 @@ def test_adjoint_and_euler_entry_points_reject_null(lib):
 def test_x_lines_option_validated(lib):
     g = mm.Grid(64, 64, 4, 5e-9)
     b = ctypes.c_size_t()
-    for xl, want in ((0, 0), (4, 0), (8, 0), (6, -1)):
+    for xl, want in ((0, 0), (4, 0), (8, 0), (16, 0), (6, -1), (32, -1)):
         o = mm.Options(0, 0, 0, 0, 0, 0, xl)
         assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(o), ctypes.byref(b)) == want
 
