@@ -181,10 +181,20 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->nt = nt;
     if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8 && o->x_lines != 16)
         return fail(MM_EINVAL, "x_lines must be 0, 4, 8 or 16");
-    // automatic: 8 lines forward (128-byte transposed segments), 4 inverse (twice the
-    // work-groups per CU for its gather); an explicit value sets both
-    p->xl = o->x_lines ? o->x_lines : 8;
-    p->xl_inv = o->x_lines ? o->x_lines : 4;
+    // automatic: work-groups of at least 512 threads forward and 256 inverse (a line of
+    // P points takes P / R0 threads), 4 to 16 lines; at P = 1024 that is 8 lines forward
+    // (128-byte transposed segments) and 4 inverse (more work-groups per CU for its
+    // gather).  An explicit value sets both.
+    {
+        const int r0 = fast_first_radix(p->Px);
+        const int tl = r0 > 0 ? p->Px / r0 : 64;
+        auto lines_for = [&](int threads) {
+            const int l = threads / std::max(1, tl);
+            return l >= 16 ? 16 : (l >= 8 ? 8 : 4);
+        };
+        p->xl = o->x_lines ? o->x_lines : lines_for(512);
+        p->xl_inv = o->x_lines ? o->x_lines : lines_for(256);
+    }
     if (!make_fft_plan(p->Px, &p->fx) || !make_fft_plan(p->Py, &p->fy) || !make_fft_plan(p->Pz, &p->fz))
         return fail(MM_EINVAL, "padded sizes must be 7-smooth");
     const int cap = kElemsPerThread * nt, ldscap = cap + 64;

@@ -233,40 +233,57 @@ __device__ inline void fft_stage(cpx<T>* lds, const LdsGeom g, int P, int p, int
     constexpr int MAXB = (kElemsPerThread + R - 1) / R;
     const int m = P / R;
     const int nbf = g.nlines * m;
-    cpx<T> v[MAXB][R], w[MAXB][R];
+    cpx<T> v[MAXB][R];
     int base[MAXB], iw[MAXB];
-    // every twiddle of the stage is loaded before the first is used (one memory
-    // latency per stage); k = 0 reads tw[0] = 1, whose product is exact
+    if constexpr (LINE_FAST) {
+        // column-wise stages: neighbouring threads read the same twiddle; the
+        // register budget of these kernels is tight, so each butterfly loads its own
 #pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        const int b = tid + q * NT;
-        const bool ok = b < nbf;
-        int l, i;
-        if (LINE_FAST) {
-            l = b % g.nlines;
-            i = b / g.nlines;
-        } else {
-            i = b % m;
-            l = b / m;
-        }
-        if (!ok) i = 0;
-        base[q] = ok ? (l % g.LI) * g.LSi + (l / g.LI) * g.LSo : -1;
-        iw[q] = i;
-        const int k = i % p;
+        for (int q = 0; q < MAXB; ++q) {
+            const int b = tid + q * NT;
+            base[q] = -1;
+            if (b < nbf) {
+                const int l = b % g.nlines, i = b / g.nlines;
+                const int lb = (l % g.LI) * g.LSi + (l / g.LI) * g.LSo;
+                base[q] = lb;
+                iw[q] = i;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[q][r] = tw[r * k * tstride];
-    }
+                for (int r = 0; r < R; ++r) v[q][r] = lds[lb + (i + r * m) * g.ES];
+                const int k = i % p;
+                if (k != 0) {
 #pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        if (base[q] >= 0) {
-            const int lb = base[q], i = iw[q];
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = lds[lb + (i + r * m) * g.ES];
-            if (i % p != 0) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r]);
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * tstride]);
+                }
+                Dft<T, R>::run(v[q]);
             }
-            Dft<T, R>::run(v[q]);
+        }
+    } else {
+        // row-wise stages: every twiddle of the stage is loaded before the first is
+        // used (one memory latency per stage); k = 0 reads tw[0] = 1, product skipped
+        cpx<T> w[MAXB][R];
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            const int b = tid + q * NT;
+            const bool ok = b < nbf;
+            const int i = ok ? b % m : 0, l = b / m;
+            base[q] = ok ? (l % g.LI) * g.LSi + (l / g.LI) * g.LSo : -1;
+            iw[q] = i;
+            const int k = i % p;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[q][r] = tw[r * k * tstride];
+        }
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            if (base[q] >= 0) {
+                const int lb = base[q], i = iw[q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = lds[lb + (i + r * m) * g.ES];
+                if (i % p != 0) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[q][r]);
+                }
+                Dft<T, R>::run(v[q]);
+            }
         }
     }
     __syncthreads();
