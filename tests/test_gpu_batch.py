@@ -108,3 +108,23 @@ def test_full_batched_workload_512_grids(pow2):
     for i in pick:
         ref = run_single(grids[i], hext[i], m0[i], "f32", 10, pow2=pow2)
         assert np.abs(got[i] - ref).max() <= 1e-6, (i, grids[i])
+
+
+def test_batch_with_newell_tensor_matches_single_grid_runs():
+    grids = FAST_MIXED[:4]
+    hext = fields_for(len(grids), seed=9)
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=400 + i) for i, g in enumerate(grids)]
+    b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision="f64", pow2_pad=True, tensor="newell")
+    b.set_m(m0)
+    b.step(10, C.dt)
+    got = [to_np(x) for x in b.get_m()]
+    for i, g in enumerate(grids):
+        nx, ny, nz = g
+        sim = mmag.Sim(nx, ny, nz, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                       precision="f64", threads=256, pow2_pad=True, tensor="newell")
+        sim.set_hext(hext[i])
+        sim.set_m(m0[i])
+        sim.step(10, C.dt)
+        assert np.abs(got[i] - to_np(sim.get_m())).max() <= 1e-13
+

@@ -283,3 +283,24 @@ def test_euler_graph_replay_matches_eager():
         out.append(to_np(sim.get_m()))
     assert np.array_equal(out[0], out[1])
 
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("dims", [(1024, 4, 1), (8, 1024, 1), (128, 128, 32), (2000, 3, 1)])
+def test_largest_lengths_sampled_against_direct_sum(dims, precision):
+    # The longest lines of each pass: x and y padded to 2048 (specialised x pass in FP32,
+    # runtime-radix y k-space beyond 1024), z padded to 64 (specialised z k-space in
+    # FP32), and a 7-smooth x length of 4000.  The demag field at 64 sampled cells plus
+    # the corners against the oracle's direct sum on the same m.
+    pb = problem(*dims, cell=3e-9)
+    sim = make_sim(pb, precision)
+    sim.set_m(random_unit_m(pb.shape, seed=61))
+    m_gpu = to_np(sim.get_m())
+    h = to_np(sim.field("demag")).reshape(3, -1)
+    N = pb.N
+    g = np.random.default_rng(62)
+    obs = np.unique(np.concatenate([[0, pb.nx - 1, N - pb.nx, N - 1], g.integers(0, N, 64)]))
+    ref = oracle.demag(pb, m_gpu, obs.astype(np.int64))
+    err = rel_max(h[:, obs], ref)
+    print(f"{dims} {precision} plan {sim.plan()['px']}x{sim.plan()['py']}x{sim.plan()['pz']}: {err:.2e}")
+    assert err <= FIELD_TOL[precision]
