@@ -40,7 +40,7 @@ KERNEL_TU = [("mm::kbf_", "mm_batch.hip"), ("mm::kb_", "mm_batch.hip"),
              ("mm::k_yline", "mm_fast.hip"), ("mm::k_kspace_z", "mm_fast.hip"),
              ("mm::k_kspace_y", "mm_fast.hip"), ("mm::k_llg_stage", "mm_llg.hip"),
              ("mm::k_row_", "mm_passes.hip"), ("mm::k_col_fft", "mm_passes.hip"),
-             ("mm::k_kspace<", "mm_passes.hip")]
+             ("mm::k_kspace<", "mm_passes.hip"), ("mm::k_kspace_fixed", "mm_passes.hip")]
 
 
 def tu_digest(tu: str) -> str:
@@ -475,7 +475,11 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
             f"mm::k_col_fft<{t}, {plan['threads']}>"
     if plan["passes"] == 5:
         z_ok = fast and pow2(pz) and 2 <= pz <= (64 if t == "float" else 32)
-        return f"mm::k_kspace_z<{t}, {pz}>" if z_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
+        if z_ok:
+            return f"mm::k_kspace_z<{t}, {pz}>"
+        if fast and pz in (128, 256, 512, 1024):
+            return f"mm::k_kspace_fixed<{t}, 256, {pz}>"
+        return f"mm::k_kspace<{t}, {plan['threads']}>"
     ky_ok = fast and pow2(py) and 16 <= py <= 1024
     return f"mm::k_kspace_y<{t}, {py}>" if ky_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
 

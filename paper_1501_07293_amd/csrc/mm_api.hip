@@ -415,6 +415,7 @@ hipError_t pass_kspace(const PassCtx& c, hipStream_t st)
         k.pl = p.fz;
         k.tw = c.twz;
         k.axis_is_z = 1;
+        if (c.fast && launch_kspace_fixed<T>(k, p.Pz, st)) return hipGetLastError();
     } else {
         KyArgs ky{c.S, c.plane, c.Sy, p.hx, p.ny, c.twy, c.kern, p.oct_elems, k_xs};
         if (c.fast && launch_kspace_y<T>(ky, p.Py, st)) return hipGetLastError();

@@ -22,21 +22,6 @@
 
 namespace mm {
 
-template <int P>
-struct Sched;
-template <> struct Sched<2> { static constexpr int NS = 1, R0 = 2, R1 = 0, R2 = 0; };
-template <> struct Sched<4> { static constexpr int NS = 1, R0 = 4, R1 = 0, R2 = 0; };
-template <> struct Sched<8> { static constexpr int NS = 1, R0 = 8, R1 = 0, R2 = 0; };
-template <> struct Sched<16> { static constexpr int NS = 1, R0 = 16, R1 = 0, R2 = 0; };
-template <> struct Sched<32> { static constexpr int NS = 2, R0 = 8, R1 = 4, R2 = 0; };
-template <> struct Sched<64> { static constexpr int NS = 2, R0 = 8, R1 = 8, R2 = 0; };
-template <> struct Sched<128> { static constexpr int NS = 2, R0 = 16, R1 = 8, R2 = 0; };
-template <> struct Sched<256> { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 0; };
-template <> struct Sched<512> { static constexpr int NS = 3, R0 = 8, R1 = 8, R2 = 8; };
-template <> struct Sched<1024> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4; };
-template <> struct Sched<2048> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 8; };
-template <> struct Sched<4096> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 16; };
-
 template <int P, int S>
 constexpr int radix_of() { return S == 0 ? Sched<P>::R0 : (S == 1 ? Sched<P>::R1 : Sched<P>::R2); }
 template <int P, int S>

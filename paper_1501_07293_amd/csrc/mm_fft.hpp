@@ -217,6 +217,24 @@ struct Dft<T, 7> {
     __device__ static inline void run(cpx<T>* v) { dft_odd<T, 7>(v); }
 };
 
+// Radix schedule of the power-of-two lengths compiled per size: stage radices
+// R0, R1, R2 (NS stages), R0 >= the others so the first stage takes the most
+// points per thread.
+template <int P>
+struct Sched;
+template <> struct Sched<2> { static constexpr int NS = 1, R0 = 2, R1 = 0, R2 = 0; };
+template <> struct Sched<4> { static constexpr int NS = 1, R0 = 4, R1 = 0, R2 = 0; };
+template <> struct Sched<8> { static constexpr int NS = 1, R0 = 8, R1 = 0, R2 = 0; };
+template <> struct Sched<16> { static constexpr int NS = 1, R0 = 16, R1 = 0, R2 = 0; };
+template <> struct Sched<32> { static constexpr int NS = 2, R0 = 8, R1 = 4, R2 = 0; };
+template <> struct Sched<64> { static constexpr int NS = 2, R0 = 8, R1 = 8, R2 = 0; };
+template <> struct Sched<128> { static constexpr int NS = 2, R0 = 16, R1 = 8, R2 = 0; };
+template <> struct Sched<256> { static constexpr int NS = 2, R0 = 16, R1 = 16, R2 = 0; };
+template <> struct Sched<512> { static constexpr int NS = 3, R0 = 8, R1 = 8, R2 = 8; };
+template <> struct Sched<1024> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4; };
+template <> struct Sched<2048> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 8; };
+template <> struct Sched<4096> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 16; };
+
 // ---------------------------------------------------------------- LDS geometry
 // Line l, element e sits at (l % LI) * LSi + (l / LI) * LSo + e * ES.
 struct LdsGeom {
@@ -300,6 +318,11 @@ __device__ inline void fft_stage(cpx<T>* lds, const LdsGeom g, int P, int p, int
     __syncthreads();
 }
 
+// As lds_fft for one power-of-two length P fixed at compile time: every radix,
+// span and twiddle stride is a constant.
+template <typename T, int NT, int P, bool LINE_FAST>
+__device__ inline void lds_fft_fixed(cpx<T>* lds, const LdsGeom g, const cpx<T>* __restrict__ tw, int tid);
+
 // Full forward FFT of every line in LDS.  Caller synchronises before the call;
 // the call ends with a barrier.
 template <typename T, int NT, bool LINE_FAST>
@@ -318,6 +341,18 @@ __device__ inline void lds_fft(cpx<T>* lds, const LdsGeom g, const FftPlan& pl,
         default: fft_stage<T, NT, 16, LINE_FAST>(lds, g, pl.P, p, ts, tw, tid); break;
         }
     }
+}
+
+template <typename T, int NT, int P, bool LINE_FAST>
+__device__ inline void lds_fft_fixed(cpx<T>* lds, const LdsGeom g, const cpx<T>* __restrict__ tw, int tid)
+{
+    using S = Sched<P>;
+    // Stockham stage s of radix R over spans p: twiddle stride P / (p R)
+    fft_stage<T, NT, S::R0, LINE_FAST>(lds, g, P, 1, P / S::R0, tw, tid);
+    if constexpr (S::NS > 1)
+        fft_stage<T, NT, S::R1, LINE_FAST>(lds, g, P, S::R0, P / (S::R0 * S::R1), tw, tid);
+    if constexpr (S::NS > 2)
+        fft_stage<T, NT, S::R2, LINE_FAST>(lds, g, P, S::R0 * S::R1, P / (S::R0 * S::R1 * S::R2), tw, tid);
 }
 
 }  // namespace mm

@@ -214,10 +214,11 @@ __device__ void body_line_c2c(const LineArgs& a, const FftPlan& pl, int tile, cp
 }
 
 // ------------------------------------------------------------------ k-space
-template <typename T, int NT>
+// PF > 0: the last-axis length is PF (a power of two), fixed at compile time.
+template <typename T, int NT, int PF = 0>
 __device__ void body_kspace(const KspArgs& a, const FftPlan& pl, int tile, cpx<T>* lds)
 {
-    const int P = pl.P, TW = a.tw_cols;
+    const int P = PF > 0 ? PF : pl.P, TW = a.tw_cols;
     const int c0 = tile * TW;
     cpx<T>* buf = (cpx<T>*)a.buf;
     const int PT = P * TW;
@@ -239,7 +240,10 @@ __device__ void body_kspace(const KspArgs& a, const FftPlan& pl, int tile, cpx<T
     }
     __syncthreads();
     const LdsGeom g{3 * TW, TW, 1, PT, TW};
-    lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
+    if constexpr (PF > 0)
+        lds_fft_fixed<T, NT, PF, true>(lds, g, (const cpx<T>*)a.tw, threadIdx.x);
+    else
+        lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
     // Eq. 14: H~_a = sum_b K~_ab M~_b with the real, symmetric kernel spectrum.
     const T* K = (const T*)a.kern;
     constexpr int KS = kStage / 2;  // elements per thread whose spectra load together
@@ -306,7 +310,10 @@ __device__ void body_kspace(const KspArgs& a, const FftPlan& pl, int tile, cpx<T
         }
     }
     __syncthreads();
-    lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
+    if constexpr (PF > 0)
+        lds_fft_fixed<T, NT, PF, true>(lds, g, (const cpx<T>*)a.tw, threadIdx.x);
+    else
+        lds_fft<T, NT, true>(lds, g, pl, (const cpx<T>*)a.tw, threadIdx.x);
     const int VT = a.nvalid * TW;
     for (int idx = threadIdx.x; idx < 3 * VT; idx += NT) {
         const int c = idx / VT, rem = idx - c * VT, e = rem / TW, t = rem - e * TW, col = c0 + t;

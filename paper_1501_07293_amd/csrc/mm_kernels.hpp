@@ -138,6 +138,10 @@ template <typename T>
 bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s);
 template <typename T>
 bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s);
+// Last-axis k-space pass with the length P fixed at compile time (P = 128 .. 1024);
+// false when P has no such pass.
+template <typename T>
+bool launch_kspace_fixed(const KspArgs& a, int P, hipStream_t s);
 template <typename T>
 bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s);
 template <typename T>

@@ -41,6 +41,43 @@ __global__ __launch_bounds__(NT) void k_kspace(KspArgs a)
     body_kspace<T, NT>(a, a.pl, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
+// The last-axis k-space pass for power-of-two lengths beyond the register-resident
+// z pass (PZ >= 128): the same body with the length fixed at compile time (every
+// radix, span and twiddle stride a constant); a work-group of NT threads holds
+// 16 NT / (3 PZ) columns.
+template <typename T, int NT, int PZ>
+__global__ __launch_bounds__(NT) void k_kspace_fixed(KspArgs a)
+{
+    __shared__ cpx<T> lds[lds_elems(NT)];
+    body_kspace<T, NT, PZ>(a, a.pl, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+template <typename T, int NT, int PZ>
+static bool kspace_fixed_go(KspArgs a, hipStream_t s)
+{
+    constexpr int TW = kElemsPerThread * NT / (3 * PZ);
+    static_assert(TW >= 1 && lds_elems(NT) * sizeof(cpx<T>) <= 160 * 1024, "k-space tile");
+    a.tw_cols = TW;
+    const int grid = (a.ncols + TW - 1) / TW;
+    if (grid > 0) hipLaunchKernelGGL((k_kspace_fixed<T, NT, PZ>), dim3(grid), dim3(NT), 0, s, a);
+    return true;
+}
+
+template <typename T>
+bool launch_kspace_fixed(const KspArgs& a, int P, hipStream_t s)
+{
+    // 256 threads: 5 columns at PZ = 256 and 4 work-groups per CU (FP32) measured
+    // faster than 384 (8 columns) or 768 (16 columns, one work-group per CU)
+    constexpr int NT = 256;
+    switch (P) {
+    case 128: return kspace_fixed_go<T, NT, 128>(a, s);
+    case 256: return kspace_fixed_go<T, NT, 256>(a, s);
+    case 512: return kspace_fixed_go<T, NT, 512>(a, s);
+    case 1024: return kspace_fixed_go<T, NT, 1024>(a, s);
+    default: return false;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 #define MM_LAUNCH_NT(kern, T, grid, nt, s, arg)                                              \
     do {                                                                                     \
@@ -94,6 +131,8 @@ template hipError_t launch_row_c2r<float>(const RowC2RArgs&, int, hipStream_t);
 template hipError_t launch_row_c2r<double>(const RowC2RArgs&, int, hipStream_t);
 template hipError_t launch_col_fft<float>(const ColArgs&, int, hipStream_t);
 template hipError_t launch_col_fft<double>(const ColArgs&, int, hipStream_t);
+template bool launch_kspace_fixed<float>(const KspArgs&, int, hipStream_t);
+template bool launch_kspace_fixed<double>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace<float>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace<double>(const KspArgs&, int, hipStream_t);
 
