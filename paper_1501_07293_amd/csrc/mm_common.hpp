@@ -19,6 +19,12 @@ struct cpx {
     T re, im;
 };
 
+// two adjacent complex values, written by one aligned store
+template <typename T>
+struct alignas(4 * sizeof(T)) cpx2 {
+    cpx<T> a, b;
+};
+
 template <typename T>
 __host__ __device__ inline cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
 template <typename T>

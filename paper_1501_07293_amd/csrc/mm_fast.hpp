@@ -222,14 +222,28 @@ __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
     }
     __syncthreads();
     cpx<T>* out = (cpx<T>*)a.out + (int64_t)plane * HX * a.srows;
-    for (int idx = threadIdx.x; idx < HX * ROWS; idx += NT) {
-        const int rr = idx % ROWS, kx = idx / ROWS, q = rr >> 1;
+    // one thread per (bin, row pair): both rows of a pair come from the same two
+    // entries of its line and are adjacent in the transposed layout.  With an even
+    // row stride (every 3-D grid) and a spectrum that starts on a pair boundary, the
+    // pair starts at an even element (yb and 2q are even) and goes out as one
+    // aligned store; otherwise as two.
+    const bool paired = (a.srows & 1) == 0 &&
+                        (reinterpret_cast<uintptr_t>(a.out) % sizeof(cpx2<T>)) == 0;
+    for (int idx = threadIdx.x; idx < HX * L; idx += NT) {
+        const int q = idx % L, kx = idx / L;
         const cpx<T> zk = lds[q * LP + pad16(kx)];
         const cpx<T> zm = lds[q * LP + pad16(kx == 0 ? 0 : P - kx)];
         // Z = FFT(a + i b): A = (Z_k + conj Z_-k)/2, B = (Z_k - conj Z_-k)/(2i)
-        const cpx<T> val = (rr & 1) ? scale(mul_mi(zk - conj(zm)), (T)0.5)
-                                    : scale(zk + conj(zm), (T)0.5);
-        if (yb + rr < a.ny) out[(int64_t)kx * a.srows + yb + rr] = val;
+        const cpx<T> A = scale(zk + conj(zm), (T)0.5);
+        const cpx<T> B = scale(mul_mi(zk - conj(zm)), (T)0.5);
+        const int y = yb + 2 * q;
+        cpx<T>* o = out + (int64_t)kx * a.srows + y;
+        if (paired && y + 1 < a.ny) {
+            *reinterpret_cast<cpx2<T>*>(o) = cpx2<T>{A, B};
+        } else {
+            if (y < a.ny) o[0] = A;
+            if (y + 1 < a.ny) o[1] = B;
+        }
     }
 }
 
