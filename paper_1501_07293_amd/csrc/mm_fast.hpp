@@ -257,21 +257,38 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
     const int tpp = (a.ny + ROWS - 1) / ROWS;
     const int plane = tile / tpp, yb = (tile - plane * tpp) * ROWS;
     const cpx<T>* src = (const cpx<T>*)a.in + (int64_t)plane * HX * a.srows;
-    // gather the 2L half-spectrum rows of this block, raw[rr][kx]: every load is
-    // issued before the first LDS store, so the gather costs one memory latency
-    constexpr int NEL = HX * ROWS, ITER = (NEL + NT - 1) / NT;
-    cpx<T> g[ITER];
+    // gather the 2L half-spectrum rows of this block, raw[rr][kx]: one thread per
+    // (bin, row pair), the two rows adjacent in the transposed layout (one aligned
+    // 2-element load under the conditions of the forward pass's paired store);
+    // every load is issued before the first LDS store, so the gather costs one
+    // memory latency
+    constexpr int NEL = HX * L, ITER = (NEL + NT - 1) / NT;
+    const bool paired = (a.srows & 1) == 0 &&
+                        (reinterpret_cast<uintptr_t>(a.in) % sizeof(cpx2<T>)) == 0;
+    cpx2<T> g[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
         const int idx = (int)threadIdx.x + it * NT;
-        const int rr = idx % ROWS, kx = idx / ROWS;
-        g[it] = cpx<T>{(T)0, (T)0};
-        if (idx < NEL && yb + rr < a.ny) g[it] = src[(int64_t)kx * a.srows + yb + rr];
+        const int q = idx % L, kx = idx / L, y = yb + 2 * q;
+        const cpx<T>* p = src + (int64_t)kx * a.srows + y;
+        g[it].a = g[it].b = cpx<T>{(T)0, (T)0};
+        if (idx < NEL) {
+            if (paired && y + 1 < a.ny) {
+                g[it] = *reinterpret_cast<const cpx2<T>*>(p);
+            } else {
+                if (y < a.ny) g[it].a = p[0];
+                if (y + 1 < a.ny) g[it].b = p[1];
+            }
+        }
     }
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
         const int idx = (int)threadIdx.x + it * NT;
-        if (idx < NEL) lds[(idx % ROWS) * HX + idx / ROWS] = g[it];
+        if (idx < NEL) {
+            const int q = idx % L, kx = idx / L;
+            lds[(2 * q) * HX + kx] = g[it].a;
+            lds[(2 * q + 1) * HX + kx] = g[it].b;
+        }
     }
     __syncthreads();
     const int l = threadIdx.x / TL, u = threadIdx.x % TL;
