@@ -367,8 +367,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              f"a multi-GPU layout is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: the micromagnetic step runs on one GPU only (got --gpus {args.gpus}); "
+              f"sharding a grid or a batch across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
