@@ -69,6 +69,8 @@ typedef enum {
 #define MM_NEWELL 0x20u    /* demag with Newell's cell-averaged tensor (Newell, Williams and Dunlop,
                                J. Geophys. Res. 98, 9551, 1993; cited in Sec. 2.3) instead of the
                                point-field tensor of Eqs. 10-11; see mm_demag_tensor_newell */
+#define MM_PER_GRID_MATERIAL 0x40u /* mm_batch_create: `mat` points to n materials, one per grid
+                                      (otherwise one material for every grid) */
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                2n-smooth vs power of two, specialised vs runtime-radix passes,
                                256 vs 512 threads) and keeps the fastest; results are cached per
@@ -94,7 +96,7 @@ typedef struct {
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
     uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD |
-                            MM_NEWELL */
+                            MM_NEWELL | MM_PER_GRID_MATERIAL (batches) */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (8 forward, 4 inverse), 4, 8 or 16 (both passes;
@@ -224,7 +226,8 @@ mm_status mm_demag_tensor_newell(int32_t nx, int32_t ny, int32_t nz, double* d_o
 
 /* ---- batched form --------------------------------------------------------
  * n independent grids of uneven sizes (each its own padding and applied
- * field; one material and precision) advanced together: every pass of a field
+ * field, one material for all or, with MM_PER_GRID_MATERIAL, one per grid; one
+ * precision) advanced together: every pass of a field
  * evaluation and every LLG stage is one kernel launch over all grids, and with
  * MM_USE_GRAPH mm_batch_step replays captured RK4 steps.  m arrays are the
  * concatenation, grid by grid, of [3][nz][ny][nx] blocks.  Sizes must fit the

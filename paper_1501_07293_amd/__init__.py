@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmmag.so")
 
 MM_F32, MM_F64 = 0, 1
 MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE, MM_POW2_PAD = 0x1, 0x2, 0x4, 0x8, 0x10
-MM_NEWELL = 0x20
+MM_NEWELL, MM_PER_GRID_MATERIAL = 0x20, 0x40
 MM_RK4, MM_EULER = 0, 1
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
@@ -350,8 +350,9 @@ class Sim:
 
 
 class BatchSim:
-    """Many independent grids (uneven sizes, one material) advanced together:
-    one kernel launch per pass over all grids (handle around mm_batch_*)."""
+    """Many independent grids of uneven sizes advanced together: one kernel launch
+    per pass over all grids (handle around mm_batch_*).  Ms, A, Ku, alpha and gamma
+    are each a number (every grid) or a sequence with one value per grid."""
 
     def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
@@ -368,9 +369,17 @@ class BatchSim:
         self.dtype = torch.float32 if precision == "f32" else torch.float64
         garr = (Grid * self.n)(*[Grid(int(g[0]), int(g[1]), int(g[2]), cell) for g in grids])
         self._grids = garr
-        self._mat = Material(Ms, A, Ku, alpha, gamma)
+        props = [Ms, A, Ku, alpha, gamma]
+        per_grid = any(np.ndim(v) > 0 for v in props)
+        if per_grid:
+            cols = [np.broadcast_to(np.asarray(v, dtype=np.float64), (self.n,)) for v in props]
+            self._mat = (Material * self.n)(*[Material(*(float(c[i]) for c in cols))
+                                              for i in range(self.n)])
+        else:
+            self._mat = (Material * 1)(Material(*(float(v) for v in props)))
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor))
+                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor)
+                 | (MM_PER_GRID_MATERIAL if per_grid else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
@@ -380,7 +389,7 @@ class BatchSim:
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
             hdl = ctypes.c_void_p()
-            _check(lib.mm_batch_create(self.n, garr, ctypes.byref(self._mat), self._hext,
+            _check(lib.mm_batch_create(self.n, garr, self._mat, self._hext,
                                        ctypes.byref(self._opt), self.workspace.data_ptr(), nbytes.value,
                                        _stream_ptr(torch, self.device), ctypes.byref(hdl)),
                    "mm_batch_create")

@@ -1162,13 +1162,13 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
 struct mm_batch {
     BatchLayout L;
     int n;
-    mm_material mat;
+    std::vector<mm_material> mats;  // one per grid
+    double desc_dt;                 // the dt the descriptors' gdt was computed for
     uint32_t flags;
     char* ws;
     bool own_ws;
     hipStream_t stream, cap_stream;
     bool has_m;
-    double alpha;
     hipGraph_t graph;
     hipGraphExec_t gexec;
     bool graph_valid;
@@ -1205,10 +1205,6 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
     g.mn = mn;
     g.acc = acc;
     g.hd = with_demag ? hd : nullptr;
-    const double Ms = b->mat.Ms;
-    g.can = (T)(2.0 * b->mat.Ku / (kMu0 * Ms * Ms));
-    g.alpha = (T)b->alpha;
-    g.gdt = (T)(b->mat.gamma * Ms * dt / (1.0 + b->alpha * b->alpha));
     BatchClass<T> bc{};
     bc.d = p.d;
     bc.S = p.S;
@@ -1269,10 +1265,27 @@ void batch_drop_graph(mm_batch* b)
     b->graph_valid = false;
 }
 
+// Each grid's gamma Ms dt / (1 + alpha^2), evaluated as the single-grid step does,
+// goes into its descriptor when dt changes (before any graph capture).
+mm_status batch_set_dt(mm_batch* b, double dt)
+{
+    if (b->desc_dt == dt) return MM_OK;
+    for (int s = 0; s < b->n; ++s) {
+        const mm_material& m = b->mats[s];
+        b->L.desc[s].gdt = m.gamma * m.Ms * dt / (1.0 + m.alpha * m.alpha);
+    }
+    HIP_TRY(hipMemcpyAsync(b->at<char>(b->L.o_desc), b->L.desc.data(), b->n * sizeof(BatchDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->desc_dt = dt;
+    return MM_OK;
+}
+
 template <typename T>
 mm_status batch_step_impl(mm_batch* b, int64_t nsteps, double dt)
 {
     hipStream_t st = b->stream;
+    if (mm_status r = batch_set_dt(b, dt); r != MM_OK) return r;
     if (!(b->flags & MM_USE_GRAPH)) {
         for (int64_t q = 0; q < nsteps; ++q) {
             mm_status r = batch_rk4_step<T>(b, dt, st);
@@ -1874,11 +1887,18 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
 {
     if (!out) return fail(MM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!check_material(mat))
-        return fail(MM_EINVAL, "material needs Ms > 0, A >= 0, alpha >= 0, gamma > 0, all finite");
+    if (!mat) return fail(MM_EINVAL, "material is NULL");
     BatchLayout L;
     mm_status st = batch_layout(n, grids, opt, &L);
     if (st != MM_OK) return st;
+    const bool per_grid = opt && (opt->flags & MM_PER_GRID_MATERIAL);
+    std::vector<mm_material> mats(n);
+    for (int s = 0; s < n; ++s) {
+        mats[s] = per_grid ? mat[s] : mat[0];
+        if (!check_material(&mats[s]))
+            return fail(MM_EINVAL, "material of grid %d needs Ms > 0, A >= 0, alpha >= 0, gamma > 0, all finite",
+                        s);
+    }
     if (hext)
         for (int q = 0; q < 3 * n; ++q)
             if (!std::isfinite(hext[q])) return fail(MM_EINVAL, "applied fields must be finite");
@@ -1888,15 +1908,19 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
         return fail(MM_EINVAL, "workspace must be 256-byte aligned");
     mm_batch* b = new mm_batch();
     b->n = n;
-    b->mat = *mat;
+    b->mats = mats;
     b->flags = opt ? opt->flags : 0;
     b->stream = as_stream(stream);
-    b->alpha = mat->alpha;
-    const double Ms = mat->Ms;
+    b->desc_dt = 0.0;  // no dt yet: the first step fills gdt
     for (int s = 0; s < n; ++s) {
         BatchDesc& d = L.desc[s];
+        const mm_material& m = mats[s];
+        const double Ms = m.Ms;
         for (int a = 0; a < 3; ++a) d.hred[a] = hext ? hext[3 * s + a] / Ms : 0.0;
-        d.cex = 2.0 * mat->A / (kMu0 * Ms * Ms * grids[s].cell * grids[s].cell);
+        d.cex = 2.0 * m.A / (kMu0 * Ms * Ms * grids[s].cell * grids[s].cell);
+        d.can = 2.0 * m.Ku / (kMu0 * Ms * Ms);
+        d.alpha = m.alpha;
+        d.gdt = 0.0;
     }
     b->L = std::move(L);
     const BatchLayout& BL = b->L;
@@ -1947,7 +1971,7 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
         const Plan& p = BL.plans[s];
         const BatchDesc& d = BL.desc[s];
         mm_sim* t = nullptr;
-        mm_status r = mm_create(&grids[s], mat, &o, b->at<char>(BL.o_scratch), BL.scratch, stream, &t);
+        mm_status r = mm_create(&grids[s], &b->mats[s], &o, b->at<char>(BL.o_scratch), BL.scratch, stream, &t);
         if (r != MM_OK) return bail(r);
         const size_t esz = BL.esz;
         hipError_t ce = hipMemcpyAsync(b->at<char>(BL.o_kern) + d.koff * esz, t->at<char>(p.o_kern),

@@ -152,12 +152,12 @@ __global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g
     a.nz = d.nz;
     a.N = (int64_t)d.nx * d.ny * d.nz;
     a.cex = (T)d.cex;
-    a.can = g.can;
+    a.can = (T)d.can;
     a.hx = (T)d.hred[0];
     a.hy = (T)d.hred[1];
     a.hz = (T)d.hred[2];
-    a.alpha = g.alpha;
-    a.gdt = g.gdt;
+    a.alpha = (T)d.alpha;
+    a.gdt = (T)d.gdt;
     a.stage = g.stage;
     body_llg_stage<T>(a, tile - p.prefix[s], threadIdx.x);
 }

@@ -252,6 +252,9 @@ struct BatchDesc {
     int64_t twx, twy, twz;
     double hred[3];   // H_ext / Ms
     double cex;       // 2 A / (mu0 Ms^2 delta^2) of this grid
+    double can;       // 2 Ku / (mu0 Ms^2) of this grid's material
+    double alpha;     // damping of this grid's material
+    double gdt;       // gamma Ms dt / (1 + alpha^2) for the batch's current dt
     FftPlan fx, fy, fz;
 };
 template <typename T>
@@ -272,7 +275,6 @@ struct BatchLlg {
     T* acc;
     T* out;
     const T* hd;
-    T can, alpha, gdt;
     int stage;
 };
 // A size class of a batch: the grids whose padded length for one pass is P.

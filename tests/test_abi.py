@@ -175,3 +175,14 @@ def test_schedule_and_newell_entry_points_reject_bad_arguments(lib):
     assert lib.mm_demag_tensor_newell(0, 1, 1, None, None) == -1
     assert lib.mm_demag_tensor_newell(2, 2, 2, None, None) == -1
     assert b"dims" in lib.mm_last_error()
+
+
+def test_batch_per_grid_materials_validated_without_gpu_work(lib):
+    grids = (mm.Grid * 2)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(40, 33, 2, 5e-9))
+    o = mm.Options(0, 0, 0, 0, mm.MM_PER_GRID_MATERIAL, 0, 0)
+    mats = (mm.Material * 2)(mm.Material(8e5, 1.3e-11, 0, 0.5, 2.2e5), mm.Material(8e5, 1.3e-11, 0, -0.5, 2.2e5))
+    h = ctypes.c_void_p()
+    assert lib.mm_batch_create(2, grids, mats, None, ctypes.byref(o), None, 0, None, ctypes.byref(h)) == -1
+    assert b"grid 1" in lib.mm_last_error()
+    assert lib.mm_batch_create(2, grids, None, None, ctypes.byref(o), None, 0, None, ctypes.byref(h)) == -1
+
