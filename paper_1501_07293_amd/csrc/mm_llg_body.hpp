@@ -8,6 +8,57 @@
 
 namespace mm {
 
+// The stage update of cell c (Eq. 2 for the field of Eqs. 3-8, then the RK4 stage
+// combine, or the explicit Euler step) from its m, Laplacian, demag field, m_n,
+// RK4 accumulator and reduced anisotropy constant; writes the stage output (and
+// the accumulator) and returns the stage output in res.
+template <typename T>
+__device__ inline void llg_cell(const LlgArgs<T>& a, int64_t c, const T (&m)[3], const T (&lap)[3],
+                                const T (&hd)[3], const T (&mn)[3], const T (&ac)[3], T kan, T (&res)[3])
+{
+    const int64_t N = a.N;
+    const T h[3] = {a.cex * lap[0] + kan * m[0] + a.hx + hd[0], a.cex * lap[1] + a.hy + hd[1],
+                    a.cex * lap[2] + a.hz + hd[2]};
+    const T tx = m[1] * h[2] - m[2] * h[1];
+    const T ty = m[2] * h[0] - m[0] * h[2];
+    const T tz = m[0] * h[1] - m[1] * h[0];
+    const T dx = m[1] * tz - m[2] * ty;
+    const T dy = m[2] * tx - m[0] * tz;
+    const T dz = m[0] * ty - m[1] * tx;
+    const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
+                    -a.gdt * (tz + a.alpha * dz)};
+    if (a.stage == 0) {  // explicit Euler with renormalisation
+        T v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = m[d] + F[d];
+        const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) res[d] = v[d] * inv;
+    } else if (a.stage == 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            a.acc[d * N + c] = F[d];
+            res[d] = m[d] + (T)0.5 * F[d];
+        }
+    } else if (a.stage == 2 || a.stage == 3) {
+        const T w = a.stage == 2 ? (T)0.5 : (T)1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            a.acc[d * N + c] = ac[d] + (T)2 * F[d];
+            res[d] = mn[d] + w * F[d];
+        }
+    } else {
+        T v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = mn[d] + (ac[d] + F[d]) / (T)6;
+        const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) res[d] = v[d] * inv;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.out[d * N + c] = res[d];
+}
+
 // The stage update of the planes k0 .. k0+kLlgZ-1 of column pc from the gathered
 // m (col, planes k0-1 .. k0+kLlgZ), Laplacian, demag field, m_n, RK4 accumulator
 // and reduced anisotropy constant.
@@ -17,51 +68,13 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
                                   const T (&mn)[kLlgZ][3], const T (&ac)[kLlgZ][3], const T (&kan)[kLlgZ])
 {
     constexpr int KZ = kLlgZ;
-    const int64_t plane = (int64_t)a.nx * a.ny, N = a.N;
+    const int64_t plane = (int64_t)a.nx * a.ny;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
         const int k = k0 + q;
         if (k >= a.nz) break;
-        const int64_t c = pc + (int64_t)k * plane;
-        const T* m = col[q + 1];
-        const T h[3] = {a.cex * lap[q][0] + kan[q] * m[0] + a.hx + hd[q][0],
-                        a.cex * lap[q][1] + a.hy + hd[q][1], a.cex * lap[q][2] + a.hz + hd[q][2]};
-        const T tx = m[1] * h[2] - m[2] * h[1];
-        const T ty = m[2] * h[0] - m[0] * h[2];
-        const T tz = m[0] * h[1] - m[1] * h[0];
-        const T dx = m[1] * tz - m[2] * ty;
-        const T dy = m[2] * tx - m[0] * tz;
-        const T dz = m[0] * ty - m[1] * tx;
-        const T F[3] = {-a.gdt * (tx + a.alpha * dx), -a.gdt * (ty + a.alpha * dy),
-                        -a.gdt * (tz + a.alpha * dz)};
-        if (a.stage == 0) {  // explicit Euler with renormalisation
-            T v[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) v[d] = m[d] + F[d];
-            const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
-        } else if (a.stage == 1) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                a.acc[d * N + c] = F[d];
-                a.out[d * N + c] = m[d] + (T)0.5 * F[d];
-            }
-        } else if (a.stage == 2 || a.stage == 3) {
-            const T w = a.stage == 2 ? (T)0.5 : (T)1;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                a.acc[d * N + c] = ac[q][d] + (T)2 * F[d];
-                a.out[d * N + c] = mn[q][d] + w * F[d];
-            }
-        } else {
-            T v[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) v[d] = mn[q][d] + (ac[q][d] + F[d]) / (T)6;
-            const T inv = (T)1 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) a.out[d * N + c] = v[d] * inv;
-        }
+        T res[3];
+        llg_cell<T>(a, pc + (int64_t)k * plane, col[q + 1], lap[q], hd[q], mn[q], ac[q], kan[q], res);
     }
 }
 
