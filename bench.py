@@ -554,8 +554,11 @@ def summarize_rocprof(run_dir: str, out_dir: str, command: str) -> str:
              "```", command.strip(), "```", "",
              "## Kernel time (`rocprofv3 --kernel-trace --stats`)", "",
              "| kernel | calls | avg µs | % of GPU time |", "|---|---|---|---|"]
+    def short(name):
+        return name if len(name) <= 90 else name[:87] + "..."
+
     for r in stats[:14]:
-        lines.append(f"| `{kernel_key(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} "
+        lines.append(f"| `{short(kernel_key(r['Name']))}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} "
                      f"| {float(r['Percentage']):.1f} |")
     dom_rows = [r for r in stats if kernel_key(r["Name"]) == dom]
     if dom_rows:
@@ -572,7 +575,7 @@ def summarize_rocprof(run_dir: str, out_dir: str, command: str) -> str:
     for k, n, f, w, hbm, a in sorted(rows, key=lambda r: -r[4]):
         ratio = f"{hbm / a:.3f}" if a else ""
         am = f"{a / 1e6:.1f}" if a else ""
-        lines.append(f"| `{k}` | {n} | {f:.0f} | {w:.0f} | {hbm / 1e6:.1f} | {am} | {ratio} |")
+        lines.append(f"| `{short(k)}` | {n} | {f:.0f} | {w:.0f} | {hbm / 1e6:.1f} | {am} | {ratio} |")
     lines += ["", f"Bench line of the kernel-trace run: value {b['value']:.4g} {b['unit']}, "
                   f"{b['ms_per_step']:.3f} ms per step (profiler attached).", "",
               "Record read by `bench.py` for `roofline.traffic` (a kernel's entry holds while "
