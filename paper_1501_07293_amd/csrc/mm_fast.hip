@@ -117,6 +117,9 @@ bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
 {
     const int grid = (a.ncols + kZCols - 1) / kZCols;
     if (grid <= 0) return true;
+    // the body indexes the spectrum and the octant with 32-bit offsets: larger
+    // grids take the k-space pass with 64-bit offsets
+    if (3 * a.comp_stride > INT32_MAX || 6 * a.k_cs > INT32_MAX) return false;
     switch (PZ) {
     case 2: hipLaunchKernelGGL((k_kspace_z<T, 2>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
     case 4: hipLaunchKernelGGL((k_kspace_z<T, 4>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
