@@ -323,3 +323,34 @@ def test_long_z_lines_match_oracle(dims, precision):
         err = rel_max(to_np(sim.field("demag")), ref)
         print(f"{dims} {precision} generic={generic} pz={sim.plan()['pz']}: {err:.2e}")
         assert err <= FIELD_TOL[precision], (generic, err)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("cfg_name", ["LARGE", "MID"])
+def test_full_size_configs_sampled_against_direct_sum(cfg_name, precision):
+    # The 512x512x16 film (padded 1024x1024x32) and the 256x64x4 film (512x128x8) at full
+    # size, in the launch configuration the benchmark times (default options): every
+    # field term at 64 sampled cells plus the corners against the oracle, and five RK4
+    # steps keep |m| = 1.
+    import synthetic
+    c = getattr(synthetic, cfg_name)
+    pb = problem(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
+                 hext=c.hext)
+    sim = make_sim(pb, precision)
+    sim.set_hext(c.hext)
+    sim.set_m(random_unit_m(pb.shape, seed=101))
+    m_gpu = to_np(sim.get_m())
+    N = pb.N
+    g = np.random.default_rng(102)
+    obs = np.unique(np.concatenate([[0, pb.nx - 1, N - pb.nx, N - 1], g.integers(0, N, 64)])).astype(np.int64)
+    hd = to_np(sim.field("demag")).reshape(3, -1)[:, obs]
+    err = rel_max(hd, oracle.demag(pb, m_gpu, obs))
+    heff = to_np(sim.field("eff")).reshape(3, -1)[:, obs]
+    ref = oracle.demag(pb, m_gpu, obs) + oracle.exchange(pb, m_gpu).reshape(3, -1)[:, obs] + \
+        oracle.anisotropy(pb, m_gpu).reshape(3, -1)[:, obs] + np.asarray(c.hext).reshape(3, 1)
+    err_eff = rel_max(heff, ref)
+    print(f"{cfg_name} {precision}: demag {err:.2e}, effective {err_eff:.2e}")
+    assert err <= FIELD_TOL[precision] and err_eff <= FIELD_TOL[precision]
+    sim.step(5, c.dt)
+    m = to_np(sim.get_m())
+    assert np.abs(np.sqrt((m * m).sum(axis=0)) - 1).max() < (1e-12 if precision == "f64" else 1e-6)
