@@ -179,9 +179,11 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes * reps / dt / 1e9
 
 
-def batched_leg(steps: int, pow2: bool, warmup: int = 2) -> dict:
+def batched_leg(steps: int, autotune: bool, warmup: int = 2) -> dict:
     """512 uneven grids (nx, ny in [32, 128], nz in {1, 2}), FP32, one launch per pass
-    over all grids, graph replay; value = total cells * steps / s."""
+    over all grids, graph replay; value = total cells * steps / s.  autotune: the
+    layout (padding and pass family) is timed at creation; otherwise 7-smooth
+    padding with the runtime-radix passes."""
     import torch
 
     import paper_1501_07293_amd as mm
@@ -191,7 +193,8 @@ def batched_leg(steps: int, pow2: bool, warmup: int = 2) -> dict:
     grids = [(s.nx, s.ny, s.nz) for s in samples]
     hext = np.array([s.hext for s in samples])
     b = mm.BatchSim(grids, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
-                    hext=hext, precision="f32", graph=True, pow2_pad=pow2)
+                    hext=hext, precision="f32", graph=True, autotune=autotune)
+    info = b.info()
     b.set_m([synthetic.random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples])
     b.step(warmup, c.dt)
     torch.cuda.synchronize()
@@ -201,7 +204,9 @@ def batched_leg(steps: int, pow2: bool, warmup: int = 2) -> dict:
     dt = time.perf_counter() - t0
     out = {"grids": len(grids), "cells": b.cells, "steps": steps, "ms_per_step": 1e3 * dt / steps,
            "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32",
-           "padding": "power of two (size-specialised passes)" if pow2 else "7-smooth (runtime radix)"}
+           "padding": "power of two" if info["pow2_pad"] else "7-smooth",
+           "passes": "size classes" if info["size_classes"] else "runtime radix",
+           "autotuned": bool(info["tuned"]), "layouts_timed": info["candidates"]}
     b.close()
     return out
 
@@ -443,8 +448,8 @@ def main():
         del sim64
         torch.cuda.empty_cache()
     if not args.no_batched_leg:
-        out["batched"] = batched_leg(max(10, args.steps // 10), pow2=True)
-        out["batched_7smooth"] = batched_leg(max(10, args.steps // 10), pow2=False)
+        out["batched"] = batched_leg(max(10, args.steps // 10), autotune=True)
+        out["batched_7smooth"] = batched_leg(max(10, args.steps // 10), autotune=False)
     if not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg()
     if not args.no_cube_leg:

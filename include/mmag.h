@@ -72,10 +72,15 @@ typedef enum {
 #define MM_PER_GRID_MATERIAL 0x40u /* mm_batch_create: `mat` points to n materials, one per grid
                                       (otherwise one material for every grid) */
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
-                               2n-smooth vs power of two, specialised vs runtime-radix passes,
-                               256 vs 512 threads) and keeps the fastest; results are cached per
-                               process and, if MMAG_TUNE_CACHE names a file, across processes.
-                               Explicit px/py/pz/threads are ignored under this flag. */
+                               7-smooth vs power of two, specialised vs runtime-radix passes,
+                               256 vs 512 threads, x lines per work-group) and keeps the fastest;
+                               results are cached per process and, if MMAG_TUNE_CACHE names a
+                               file, across processes.  mm_batch_create times the batch layouts
+                               (7-smooth padding, power-of-two padding with runtime-radix passes,
+                               power-of-two padding with size-class passes) on one field
+                               evaluation each and keeps the fastest (mm_batch_get_info reports
+                               it); MM_POW2_PAD and MM_GENERIC_FFT are then ignored.  Explicit
+                               px/py/pz/threads are ignored under this flag. */
 
 typedef struct {
     int32_t nx, ny, nz; /* cells along x, y, z; each >= 1 */
@@ -246,6 +251,21 @@ mm_status mm_batch_set_m(mm_batch* b, const void* m, int on_device);
 mm_status mm_batch_get_m(mm_batch* b, void* out, int on_device);
 mm_status mm_batch_step(mm_batch* b, int64_t nsteps, double dt);
 mm_status mm_batch_cells(mm_batch* b, int64_t* total_cells);
+
+/* The layout a batch runs on (for MM_AUTOTUNE, the one that won). */
+typedef struct {
+    int64_t cells;           /* cells over all grids */
+    int32_t n;               /* grids */
+    int32_t pow2_pad;        /* 1: padded sizes are powers of two; 0: 7-smooth */
+    int32_t size_classes;    /* 1: the size-class passes (one launch per padded length per
+                                pass); 0: the runtime-radix passes (one launch per pass) */
+    int32_t tuned;           /* 1: chosen by MM_AUTOTUNE */
+    int32_t tune_candidates; /* layouts timed */
+    int32_t reserved;
+    double tuned_ms;         /* the winner's time of one field evaluation of every grid, ms */
+    size_t workspace_bytes;  /* device bytes the layout uses */
+} mm_batch_info;
+mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out);
 
 /* ---- differentiation (adjoint) ------------------------------------------
  * Gradients of a loss of the final state of an RK4 rollout with respect to the

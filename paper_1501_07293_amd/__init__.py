@@ -33,7 +33,7 @@ EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm
            "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
-           "mm_batch_cells", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
+           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
            "mm_profile_begin", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
@@ -73,6 +73,13 @@ class PlanInfo(ctypes.Structure):
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32),
                 ("x_lines_inv", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int64), ("n", ctypes.c_int32), ("pow2_pad", ctypes.c_int32),
+                ("size_classes", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tuned_demag_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -118,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_batch_get_m": [vp, vp, ctypes.c_int],
         "mm_batch_step": [vp, i64, dbl],
         "mm_batch_cells": [vp, ctypes.POINTER(i64)],
+        "mm_batch_get_info": [vp, ctypes.POINTER(BatchInfo)],
         "mm_rollout": [vp, i64, dbl, i64, vp],
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
@@ -357,7 +365,8 @@ class BatchSim:
     def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  hext=None, precision: str = "f32", demag: bool = True, graph: bool = False,
-                 pow2_pad: bool = False, tensor: str = "point", device: str = "cuda:0"):
+                 pow2_pad: bool = False, tensor: str = "point", autotune: bool = False,
+                 device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
         self._torch, self._lib = torch, lib
@@ -379,7 +388,7 @@ class BatchSim:
             self._mat = (Material * 1)(Material(*(float(v) for v in props)))
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
                  | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor)
-                 | (MM_PER_GRID_MATERIAL if per_grid else 0))
+                 | (MM_PER_GRID_MATERIAL if per_grid else 0) | (MM_AUTOTUNE if autotune else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
@@ -401,6 +410,12 @@ class BatchSim:
     def _sync_stream(self):
         _check(self._lib.mm_batch_set_stream(self._h, _stream_ptr(self._torch, self.device)),
                "mm_batch_set_stream")
+
+    def info(self) -> dict:
+        """The layout in use: padding family, pass family, autotune record."""
+        p = BatchInfo()
+        _check(self._lib.mm_batch_get_info(self._h, ctypes.byref(p)), "mm_batch_get_info")
+        return {k: getattr(p, k) for k, _ in BatchInfo._fields_ if k != "reserved"}
 
     def set_m(self, ms):
         """ms: list of per-grid (3, nz, ny, nx) arrays (or one flat array)."""

@@ -1090,7 +1090,7 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
     // size classes for the specialised passes (power-of-two padding)
     L->fast = false;
     L->classes.clear();
-    if (o.flags & MM_POW2_PAD) {
+    if ((o.flags & MM_POW2_PAD) && !(o.flags & MM_GENERIC_FFT)) {
         bool ok = true;
         auto cls = [&](int kind, int P) -> BatchClassHost& {
             for (auto& c : L->classes)
@@ -1174,11 +1174,72 @@ struct mm_batch {
     bool graph_valid;
     double graph_dt;
     int graph_chunk;
+    int tuned, tune_candidates;
+    double tuned_ms;
     template <typename U>
     U* at(size_t off) const { return reinterpret_cast<U*>(ws + off); }
 };
 
 namespace {
+
+// One demag field evaluation of every grid: the passes from m (in) to the
+// field in the hd region, as size-class launches (power-of-two padding) or one
+// runtime-radix launch per pass.
+template <typename T>
+mm_status batch_demag(mm_batch* b, const T* in, hipStream_t st)
+{
+    const BatchLayout& L = b->L;
+    const int* pre = b->at<int>(L.o_prefix);
+    const int n = b->n;
+    if (L.fast) {
+        BatchClass<T> bc{};
+        bc.d = b->at<BatchDesc>(L.o_desc);
+        bc.S = b->at<cpx<T>>(L.o_S);
+        bc.kern = b->at<T>(L.o_kern);
+        bc.tw = b->at<cpx<T>>(L.o_tw);
+        bc.out = b->at<T>(L.o_hd);
+        bc.in = in;
+        const int* cints = b->at<int>(L.o_classes);
+        auto run_classes = [&](int kind, int launch_kind, int inverse) -> mm_status {
+            for (const BatchClassHost& c : L.classes) {
+                if (c.kind != kind) continue;
+                bc.members = cints + c.off;
+                bc.prefix = cints + c.off + c.members.size();
+                bc.nmem = (int)c.members.size();
+                if (!launch_batch_class<T>(launch_kind, c.P, bc, c.prefix.back(), inverse, st))
+                    return fail(MM_ENOTSUP, "no specialised pass of length %d", c.P);
+                HIP_TRY(hipGetLastError());
+            }
+            return MM_OK;
+        };
+        mm_status r;
+        if ((r = run_classes(0, 0, 0)) != MM_OK) return r;  // x forward
+        if ((r = run_classes(1, 1, 0)) != MM_OK) return r;  // y forward
+        if ((r = run_classes(2, 2, 0)) != MM_OK) return r;  // z k-space
+        if ((r = run_classes(3, 3, 0)) != MM_OK) return r;  // y k-space
+        if ((r = run_classes(1, 1, 1)) != MM_OK) return r;  // y inverse
+        return run_classes(0, 4, 0);                         // x inverse
+    }
+    BatchPass<T> p{};
+    p.d = b->at<BatchDesc>(L.o_desc);
+    p.n = n;
+    p.S = b->at<cpx<T>>(L.o_S);
+    p.kern = b->at<T>(L.o_kern);
+    p.tw = b->at<cpx<T>>(L.o_tw);
+    p.out = b->at<T>(L.o_hd);
+    p.in = in;
+    p.prefix = pre + 0 * (n + 1);
+    HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, nullptr, st));
+    p.prefix = pre + 1 * (n + 1);
+    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 0, nullptr, st));
+    p.prefix = pre + 2 * (n + 1);
+    HIP_TRY(launch_batch_pass<T>(2, p, L.prefix[2][n], 0, nullptr, st));
+    p.prefix = pre + 1 * (n + 1);
+    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 1, nullptr, st));
+    p.prefix = pre + 3 * (n + 1);
+    HIP_TRY(launch_batch_pass<T>(3, p, L.prefix[3][n], 0, nullptr, st));
+    return MM_OK;
+}
 
 template <typename T>
 mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
@@ -1197,60 +1258,17 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
     BatchPass<T> p{};
     p.d = b->at<BatchDesc>(L.o_desc);
     p.n = n;
-    p.S = b->at<cpx<T>>(L.o_S);
-    p.kern = b->at<T>(L.o_kern);
-    p.tw = b->at<cpx<T>>(L.o_tw);
-    p.out = hd;
+    p.prefix = pre + 4 * (n + 1);
     BatchLlg<T> g{};
     g.mn = mn;
     g.acc = acc;
     g.hd = with_demag ? hd : nullptr;
-    BatchClass<T> bc{};
-    bc.d = p.d;
-    bc.S = p.S;
-    bc.kern = p.kern;
-    bc.tw = p.tw;
-    bc.out = hd;
-    const int* cints = b->at<int>(L.o_classes);
-    auto run_classes = [&](int kind, int launch_kind, int inverse) -> mm_status {
-        for (const BatchClassHost& c : L.classes) {
-            if (c.kind != kind) continue;
-            bc.members = cints + c.off;
-            bc.prefix = cints + c.off + c.members.size();
-            bc.nmem = (int)c.members.size();
-            if (!launch_batch_class<T>(launch_kind, c.P, bc, c.prefix.back(), inverse, st))
-                return fail(MM_ENOTSUP, "no specialised pass of length %d", c.P);
-            HIP_TRY(hipGetLastError());
-        }
-        return MM_OK;
-    };
     for (int stg = 0; stg < 4; ++stg) {
-        if (with_demag && L.fast) {
-            bc.in = src[stg];
-            mm_status r;
-            if ((r = run_classes(0, 0, 0)) != MM_OK) return r;  // x forward
-            if ((r = run_classes(1, 1, 0)) != MM_OK) return r;  // y forward
-            if ((r = run_classes(2, 2, 0)) != MM_OK) return r;  // z k-space
-            if ((r = run_classes(3, 3, 0)) != MM_OK) return r;  // y k-space
-            if ((r = run_classes(1, 1, 1)) != MM_OK) return r;  // y inverse
-            if ((r = run_classes(0, 4, 0)) != MM_OK) return r;  // x inverse
-        } else if (with_demag) {
-            p.in = src[stg];
-            p.prefix = pre + 0 * (n + 1);
-            HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, nullptr, st));
-            p.prefix = pre + 1 * (n + 1);
-            HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 0, nullptr, st));
-            p.prefix = pre + 2 * (n + 1);
-            HIP_TRY(launch_batch_pass<T>(2, p, L.prefix[2][n], 0, nullptr, st));
-            p.prefix = pre + 1 * (n + 1);
-            HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 1, nullptr, st));
-            p.prefix = pre + 3 * (n + 1);
-            HIP_TRY(launch_batch_pass<T>(3, p, L.prefix[3][n], 0, nullptr, st));
-        }
+        if (with_demag)
+            if (mm_status r = batch_demag<T>(b, src[stg], st); r != MM_OK) return r;
         g.ms = src[stg];
         g.out = dst[stg];
         g.stage = stg + 1;
-        p.prefix = pre + 4 * (n + 1);
         HIP_TRY(launch_batch_pass<T>(4, p, L.prefix[4][n], 0, &g, st));
     }
     return MM_OK;
@@ -1341,6 +1359,70 @@ mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
         return fail(MM_EINVAL, "m has %u zero-length or non-finite cells", nbad);
     }
     b->has_m = true;
+    return MM_OK;
+}
+
+// ---------------------------------------------------------------- batch autotuner
+// Candidate layouts of a batch: 7-smooth padding with the runtime-radix passes
+// (the default), power-of-two padding with the runtime-radix passes, and
+// power-of-two padding with the size-class passes when every padded length has
+// one.  A candidate whose padded sizes equal an earlier one's is dropped.
+std::vector<mm_options> batch_tune_candidates(int32_t n, const mm_grid* grids, const mm_options* opt)
+{
+    const uint32_t base = opt->flags & ~(uint32_t)(MM_AUTOTUNE | MM_POW2_PAD | MM_GENERIC_FFT);
+    const uint32_t variants[3] = {base, base | MM_POW2_PAD | MM_GENERIC_FFT, base | MM_POW2_PAD};
+    std::vector<mm_options> out;
+    std::vector<BatchLayout> kept;
+    for (uint32_t f : variants) {
+        mm_options c = *opt;
+        c.px = c.py = c.pz = 0;
+        c.flags = f;
+        BatchLayout L;
+        if (batch_layout(n, grids, &c, &L) != MM_OK) continue;
+        if ((f & MM_POW2_PAD) && !(f & MM_GENERIC_FFT) && !L.fast) continue;
+        bool dup = false;
+        for (const BatchLayout& K : kept) {
+            if (K.fast != L.fast) continue;
+            bool same = true;
+            for (int s = 0; s < n && same; ++s)
+                same = K.plans[s].Px == L.plans[s].Px && K.plans[s].Py == L.plans[s].Py &&
+                       K.plans[s].Pz == L.plans[s].Pz;
+            dup = dup || same;
+        }
+        if (dup) continue;
+        out.push_back(c);
+        kept.push_back(std::move(L));
+    }
+    return out;
+}
+
+// Mean time of one field evaluation of every grid, on zero-filled state,
+// spectra and twiddles (the passes' cost does not depend on the values).
+template <typename T>
+mm_status time_batch_demag(mm_batch* b, double* ms_out)
+{
+    const BatchLayout& L = b->L;
+    hipStream_t st = b->stream;
+    HIP_TRY(hipMemsetAsync(b->at<char>(L.o_mn), 0, L.o_flags - L.o_mn, st));
+    const T* mn = b->at<T>(L.o_mn);
+    for (int w = 0; w < 2; ++w)
+        if (mm_status r = batch_demag<T>(b, mn, st); r != MM_OK) return r;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int reps = 5;
+    mm_status r = MM_OK;
+    hipError_t e = hipEventRecord(e0, st);
+    for (int q = 0; q < reps && r == MM_OK && e == hipSuccess; ++q) r = batch_demag<T>(b, mn, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r != MM_OK) return r;
+    if (e != hipSuccess) return fail(MM_EHIP, "batch autotune timing: %s", hipGetErrorString(e));
+    *ms_out = ms / reps;
     return MM_OK;
 }
 
@@ -1878,14 +1960,21 @@ mm_status mm_batch_workspace_query(int32_t n, const mm_grid* grids, const mm_opt
     mm_status st = batch_layout(n, grids, opt, &L);
     if (st != MM_OK) return st;
     *bytes = L.total;
+    if (opt && (opt->flags & MM_AUTOTUNE))  // room for whichever layout wins
+        for (const mm_options& c : batch_tune_candidates(n, grids, opt)) {
+            BatchLayout Q;
+            if (batch_layout(n, grids, &c, &Q) == MM_OK) *bytes = std::max(*bytes, Q.total);
+        }
     return MM_OK;
 }
 
-mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* mat,
-                          const double* hext, const mm_options* opt, void* d_workspace,
-                          size_t ws_bytes, void* stream, mm_batch** out)
+// The batch on a layout: descriptors, tile prefix sums and size classes
+// uploaded; with spectra, each grid's kernel spectrum and twiddles too (the
+// timing runs of the autotuner need neither).
+static mm_status batch_build(int32_t n, const mm_grid* grids, const mm_material* mat,
+                             const double* hext, const mm_options* opt, void* d_workspace,
+                             size_t ws_bytes, void* stream, bool spectra, mm_batch** out)
 {
-    if (!out) return fail(MM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!mat) return fail(MM_EINVAL, "material is NULL");
     BatchLayout L;
@@ -1963,6 +2052,10 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
                            hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return bail(fail(MM_EHIP, "prefix upload: %s", hipGetErrorString(e)));
+    if (!spectra) {
+        *out = b;
+        return MM_OK;
+    }
     // kernel spectra and twiddles: one single-grid setup per grid on the scratch region
     mm_options o = opt ? *opt : mm_options{};
     o.threads = 256;
@@ -1990,6 +2083,71 @@ mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* ma
         if (ce != hipSuccess) return bail(fail(MM_EHIP, "spectrum copy: %s", hipGetErrorString(ce)));
     }
     *out = b;
+    return MM_OK;
+}
+
+mm_status mm_batch_create(int32_t n, const mm_grid* grids, const mm_material* mat,
+                          const double* hext, const mm_options* opt, void* d_workspace,
+                          size_t ws_bytes, void* stream, mm_batch** out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!opt || !(opt->flags & MM_AUTOTUNE) || (opt->flags & MM_NO_DEMAG))
+        return batch_build(n, grids, mat, hext, opt, d_workspace, ws_bytes, stream, true, out);
+    // MM_AUTOTUNE: time one field evaluation of every candidate layout on
+    // zero-filled data, then build the fastest with its spectra.  The first
+    // candidate is the default layout: its argument errors go to the caller;
+    // a later candidate that cannot be built (a padded length beyond the
+    // passes, a workspace sized without MM_AUTOTUNE) is skipped.
+    const std::vector<mm_options> cands = batch_tune_candidates(n, grids, opt);
+    if (cands.empty()) {
+        BatchLayout L;
+        mm_status st = batch_layout(n, grids, opt, &L);
+        return st != MM_OK ? st : fail(MM_ENOTSUP, "no layout of this batch could be built");
+    }
+    double best_ms = 1e300;
+    size_t best = 0;
+    int ncand = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        mm_batch* t = nullptr;
+        mm_status r = batch_build(n, grids, mat, hext, &cands[i], d_workspace, ws_bytes, stream, false, &t);
+        if (r != MM_OK) {
+            if (i == 0) return r;
+            continue;
+        }
+        double ms = 0.0;
+        r = t->L.prec == MM_F32 ? time_batch_demag<float>(t, &ms) : time_batch_demag<double>(t, &ms);
+        std::string keep = g_err;
+        mm_batch_destroy(t);
+        g_err = keep;
+        if (r != MM_OK) return r;
+        ++ncand;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = i;
+        }
+    }
+    mm_status r = batch_build(n, grids, mat, hext, &cands[best], d_workspace, ws_bytes, stream, true, out);
+    if (r == MM_OK) {
+        (*out)->tuned = 1;
+        (*out)->tune_candidates = ncand;
+        (*out)->tuned_ms = best_ms;
+    }
+    return r;
+}
+
+mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out)
+{
+    if (!b || !out) return fail(MM_EINVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    out->cells = b->L.cells;
+    out->n = b->n;
+    out->pow2_pad = (b->flags & MM_POW2_PAD) ? 1 : 0;
+    out->size_classes = b->L.fast ? 1 : 0;
+    out->tuned = b->tuned;
+    out->tune_candidates = b->tune_candidates;
+    out->tuned_ms = b->tuned_ms;
+    out->workspace_bytes = b->L.total;
     return MM_OK;
 }
 

@@ -73,6 +73,21 @@ def test_batch_workspace_query(lib):
     assert lib.mm_batch_workspace_query(0, grids, ctypes.byref(o), ctypes.byref(b)) == -1
 
 
+def test_batch_autotune_workspace_covers_every_layout(lib):
+    grids = (mm.Grid * 3)(mm.Grid(33, 47, 1, 5e-9), mm.Grid(77, 33, 2, 5e-9), mm.Grid(20, 20, 3, 5e-9))
+    sizes = {}
+    for name, flags in (("plain", 0), ("pow2", mm.MM_POW2_PAD),
+                        ("pow2_generic", mm.MM_POW2_PAD | mm.MM_GENERIC_FFT), ("tuned", mm.MM_AUTOTUNE)):
+        o = mm.Options(0, 0, 0, 0, flags, 0, 0)
+        b = ctypes.c_size_t()
+        assert lib.mm_batch_workspace_query(3, grids, ctypes.byref(o), ctypes.byref(b)) == 0
+        sizes[name] = b.value
+    assert sizes["tuned"] >= max(sizes["plain"], sizes["pow2"], sizes["pow2_generic"])
+    assert sizes["pow2"] > sizes["plain"]
+    info = mm.BatchInfo()
+    assert lib.mm_batch_get_info(None, ctypes.byref(info)) == -1
+
+
 @pytest.mark.parametrize("args", [(0, 4, 4), (4, -1, 4), (4, 4, 0)])
 def test_workspace_query_rejects_bad_dims(lib, args):
     st, _ = q(lib, *args)

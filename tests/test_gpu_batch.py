@@ -21,10 +21,11 @@ def fields_for(n, seed=0):
     return mT_to_Apm(g.uniform(-40, 40, size=(n, 3)))
 
 
-def run_single(grid, hext, m0, precision, nsteps, pow2=False):
+def run_single(grid, hext, m0, precision, nsteps, pow2=False, generic=None):
     nx, ny, nz = grid
     sim = mmag.Sim(nx, ny, nz, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                   precision=precision, generic_fft=not pow2, threads=256, pow2_pad=pow2)
+                   precision=precision, generic_fft=(not pow2) if generic is None else generic,
+                   threads=256, pow2_pad=pow2)
     sim.set_hext(hext)
     sim.set_m(m0)
     sim.step(nsteps, C.dt)
@@ -158,3 +159,37 @@ def test_batch_with_per_grid_materials_matches_single_grid_runs(precision):
         err = np.abs(got[i] - to_np(sim.get_m())).max()
         assert err <= (1e-13 if precision == "f64" else 1e-6), (i, err)
 
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_autotuned_batch_matches_single_grid_runs_on_its_layout(precision):
+    # MM_AUTOTUNE times the layouts and keeps one; the result is each grid run
+    # alone with that layout's padding and pass family.
+    grids = FAST_MIXED
+    hext = fields_for(len(grids), seed=21)
+    m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=600 + i) for i, g in enumerate(grids)]
+    b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
+                      hext=hext, precision=precision, autotune=True)
+    info = b.info()
+    print(f"autotuned batch ({precision}): {info}")
+    assert info["tuned"] == 1 and 2 <= info["candidates"] <= 3
+    assert info["tuned_demag_ms"] > 0 and info["n"] == len(grids) and info["cells"] == b.cells
+    assert not (info["size_classes"] and not info["pow2_pad"])
+    b.set_m(m0)
+    b.step(20, C.dt)
+    got = [to_np(x) for x in b.get_m()]
+    for i, g in enumerate(grids):
+        ref = run_single(g, hext[i], m0[i], precision, 20, pow2=bool(info["pow2_pad"]),
+                         generic=not info["size_classes"])
+        err = np.abs(got[i] - ref).max()
+        assert err <= (1e-13 if precision == "f64" else 1e-6), (g, err)
+
+
+def test_autotuned_batch_of_tiny_grids_keeps_a_buildable_layout():
+    # grids whose power-of-two padding has no size-class pass: two candidates at most
+    grids = [(5, 3, 2), (1, 1, 1), (70, 3, 2)]
+    b = mmag.BatchSim(grids, C.cell, precision="f32", autotune=True)
+    info = b.info()
+    assert info["tuned"] == 1 and info["size_classes"] == 0 and info["candidates"] <= 2
+    plain = mmag.BatchSim(grids, C.cell, precision="f32")
+    assert plain.info()["tuned"] == 0 and plain.info()["pow2_pad"] == 0
