@@ -35,13 +35,31 @@ __device__ constexpr int pad16(int e) { return e + (e >> 4); }
 template <int P>
 constexpr int padded_len() { return P + P / 16 + 1; }
 
+// Twiddles of stage S >= 1 for one thread: w[q][r - 1] = tw[r k ts] for its
+// q-th butterfly.
+template <typename T, int P, int S>
+struct StageTw {
+    static constexpr int R = radix_of<P, S>(), NB = Sched<P>::R0 / R;
+    cpx<T> w[NB][R - 1];
+    __device__ inline void load(int u, const cpx<T>* __restrict__ tw)
+    {
+        constexpr int TL = P / Sched<P>::R0, p = span_of<P, S>(), m = P / R, ts = m / p;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int k = (u + TL * q) & (p - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r * k * ts];
+        }
+    }
+};
+
 // Stage S >= 1 on one LDS line: each thread does R0/R butterflies.  Reads all,
 // barrier, writes all, barrier.
 template <typename T, int P, int S>
-__device__ inline void mid_stage(cpx<T>* ln, int u, const cpx<T>* __restrict__ tw)
+__device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R, ts = m / p;
+    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R;
     cpx<T> v[NB][R];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -50,7 +68,7 @@ __device__ inline void mid_stage(cpx<T>* ln, int u, const cpx<T>* __restrict__ t
         for (int r = 0; r < R; ++r) v[q][r] = ln[pad16(i + r * m)];
         if (k != 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * ts]);
+            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], W.w[q][r - 1]);
         }
         Dft<T, R>::run(v[q]);
     }
@@ -66,20 +84,20 @@ __device__ inline void mid_stage(cpx<T>* ln, int u, const cpx<T>* __restrict__ t
 
 // Last stage: outputs land at natural index i + r * P/R; handed to `put`.
 template <typename T, int P, int S, typename Put>
-__device__ inline void last_stage(const cpx<T>* ln, int u, const cpx<T>* __restrict__ tw, Put put)
+__device__ inline void last_stage(const cpx<T>* ln, int u, const StageTw<T, P, S>& W, Put put)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R, ts = m / p;
+    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R;
     static_assert(p == m, "last stage spans P / R");
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q;
+        const int i = u + TL * q;  // < m = p, so the twiddle index k of StageTw is i
         cpx<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = ln[pad16(i + r * m)];
         if (i != 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * i * ts]);
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], W.w[q][r - 1]);
         }
         Dft<T, R>::run(v);
 #pragma unroll
@@ -87,18 +105,40 @@ __device__ inline void last_stage(const cpx<T>* ln, int u, const cpx<T>* __restr
     }
 }
 
+// Twiddles of stages 1.. of one thread of a line.  They do not depend on the
+// data, so the passes load them at the start, where their latency overlaps the
+// loads of the line itself.
+template <typename T, int P, int NS = Sched<P>::NS>
+struct LineTw {
+    __device__ inline void load(int, const cpx<T>* __restrict__) {}
+};
+template <typename T, int P>
+struct LineTw<T, P, 2> {
+    StageTw<T, P, 1> wl;
+    __device__ inline void load(int u, const cpx<T>* __restrict__ tw) { wl.load(u, tw); }
+};
+template <typename T, int P>
+struct LineTw<T, P, 3> {
+    StageTw<T, P, 1> wm;
+    StageTw<T, P, 2> wl;
+    __device__ inline void load(int u, const cpx<T>* __restrict__ tw)
+    {
+        wm.load(u, tw);
+        wl.load(u, tw);
+    }
+};
+
 // Whole line after stage 1 has been computed into v (registers): write to LDS,
 // run the remaining stages, deliver outputs through put.  NS >= 2.
 template <typename T, int P, typename Put>
-__device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const cpx<T>* __restrict__ tw,
-                                   Put put)
+__device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const LineTw<T, P>& W, Put put)
 {
     constexpr int NS = Sched<P>::NS, R0 = Sched<P>::R0;
 #pragma unroll
     for (int r = 0; r < R0; ++r) ln[pad16(u * R0 + r)] = v[r];
     __syncthreads();
-    if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, tw);
-    last_stage<T, P, NS - 1>(ln, u, tw, put);
+    if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, W.wm);
+    last_stage<T, P, NS - 1>(ln, u, W.wl, put);
 }
 
 // In-register FFT of N points (N <= 64), all indices compile-time; Stockham
@@ -152,6 +192,8 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
     const bool ok = line < a.nlines;
     cpx<T>* g = (cpx<T>*)a.buf + (int64_t)(ok ? line : 0) * a.line_stride;
     const cpx<T>* tw = (const cpx<T>*)a.tw;
+    LineTw<T, P> W;
+    W.load(u, tw);
     cpx<T> v[R0];
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
@@ -168,7 +210,7 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P>(lds + l * LP, u, v, tw, put);
+        finish_line<T, P>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -218,7 +260,11 @@ __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
     } else {
         // the last stage writes back to LDS in natural order (in place: each thread
         // rewrites exactly the slots its own butterflies read)
-        finish_line<T, P>(ln, u, v, tw, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+        // here the twiddles are loaded after the first stage (measured: loaded
+        // with the row data they lengthen this pass, unlike the other line passes)
+        LineTw<T, P> W;
+        W.load(u, tw);
+        finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
     }
     __syncthreads();
     cpx<T>* out = (cpx<T>*)a.out + (int64_t)plane * HX * a.srows;
@@ -256,6 +302,9 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
     constexpr int LDSN = (L * LP > ROWS * HX) ? L * LP : ROWS * HX;
     const int tpp = (a.ny + ROWS - 1) / ROWS;
     const int plane = tile / tpp, yb = (tile - plane * tpp) * ROWS;
+    const int l = threadIdx.x / TL, u = threadIdx.x % TL;
+    LineTw<T, P> W;
+    W.load(u, (const cpx<T>*)a.tw);
     const cpx<T>* src = (const cpx<T>*)a.in + (int64_t)plane * HX * a.srows;
     // gather the 2L half-spectrum rows of this block, raw[rr][kx]: one thread per
     // (bin, row pair), the two rows adjacent in the transposed layout (one aligned
@@ -291,7 +340,6 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
         }
     }
     __syncthreads();
-    const int l = threadIdx.x / TL, u = threadIdx.x % TL;
     const cpx<T>* ra = lds + (2 * l) * HX;
     const cpx<T>* rb = lds + (2 * l + 1) * HX;
     cpx<T> v[R0];
@@ -327,7 +375,7 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P>(lds + l * LP, u, v, (const cpx<T>*)a.tw, put);
+        finish_line<T, P>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -353,12 +401,10 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
         if (ok && z < a.nz) x = buf[base + z * zs];
         v[z] = x;
     }
-    fft_reg<T, PZ>(v, tw);
-#pragma unroll
-    for (int z = 0; z < PZ; ++z) sh[(comp * PZ + z) * kZCols + t] = v[z];
-    __syncthreads();
     // Eq. 14, row `comp` of the symmetric tensor; negative frequencies mirror with
-    // the component parities (xy odd in y, xz odd in z, yz odd in y and z).
+    // the component parities (xy odd in y, xz odd in z, yz odd in y and z).  The
+    // 3 x (PZ/2 + 1) spectrum values of this column do not depend on the data:
+    // they are loaded before the forward transform, so their latency overlaps it.
     const int kx = (ok ? col : 0) / a.Py;
     int ky = (ok ? col : 0) - kx * a.Py;
     T sy = (T)1;
@@ -368,23 +414,34 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
     }
     const T* K = (const T*)a.kern;
     const int ko = kx * (int)a.k_xs + ky, cs = (int)a.k_cs, kzs = (int)a.k_zs;
-    // the three spectra of row `comp` and their parity signs in y
+    // the three spectra of row `comp`
     const int c0 = comp == 0 ? 0 : (comp == 1 ? 1 : 2);
     const int c1 = comp == 0 ? 1 : (comp == 1 ? 3 : 4);
     const int c2 = comp == 0 ? 2 : (comp == 1 ? 4 : 5);
+    constexpr int H = PZ / 2;
+    T k0v[H + 1], k1v[H + 1], k2v[H + 1];
+#pragma unroll
+    for (int kz = 0; kz <= H; ++kz) {
+        const int kk = ko + kz * kzs;
+        k0v[kz] = K[c0 * cs + kk];
+        k1v[kz] = K[c1 * cs + kk];
+        k2v[kz] = K[c2 * cs + kk];
+    }
+    fft_reg<T, PZ>(v, tw);
+#pragma unroll
+    for (int z = 0; z < PZ; ++z) sh[(comp * PZ + z) * kZCols + t] = v[z];
+    __syncthreads();
+    // parity signs in y and z (xz, c = 2, and yz, c = 4, are odd in z)
     const T y0 = comp == 1 ? sy : (T)1, y1 = comp == 0 ? sy : (comp == 2 ? sy : (T)1);
     const T y2 = comp == 1 ? sy : (T)1;
-    // parity signs in z: xz (c=2) and yz (c=4) are odd
     const bool z0 = c0 == 2, z1 = c1 == 4, z2 = (c2 == 2 || c2 == 4);
 #pragma unroll
     for (int z = 0; z < PZ; ++z) {
-        constexpr int H = PZ / 2;
         const int kz = z <= H ? z : PZ - z;
         const T sz = (z <= H || 2 * z == PZ) ? (T)1 : (T)-1;
-        const int kk = ko + kz * kzs;
-        const T k0 = y0 * (z0 ? sz : (T)1) * K[c0 * cs + kk];
-        const T k1 = y1 * (z1 ? sz : (T)1) * K[c1 * cs + kk];
-        const T k2 = y2 * (z2 ? sz : (T)1) * K[c2 * cs + kk];
+        const T k0 = y0 * (z0 ? sz : (T)1) * k0v[kz];
+        const T k1 = y1 * (z1 ? sz : (T)1) * k1v[kz];
+        const T k2 = y2 * (z2 ? sz : (T)1) * k2v[kz];
         const cpx<T> m0 = sh[(0 * PZ + z) * kZCols + t];
         const cpx<T> m1 = sh[(1 * PZ + z) * kZCols + t];
         const cpx<T> m2 = sh[(2 * PZ + z) * kZCols + t];
@@ -419,6 +476,8 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
     cpx<T>* g = (cpx<T>*)a.buf + comp * a.comp_stride + (int64_t)(ok ? kx : 0) * a.line_stride;
     cpx<T>* ln = lds + line * LP;
     const cpx<T>* tw = (const cpx<T>*)a.tw;
+    LineTw<T, P> W;
+    W.load(u, tw);
     cpx<T> v[R0];
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
@@ -432,7 +491,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
     } else {
-        finish_line<T, P>(ln, u, v, tw, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+        finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
     }
     __syncthreads();
     const T* K = (const T*)a.kern;
@@ -467,7 +526,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
         __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
-        finish_line<T, P>(ln, u, v, tw, put);
+        finish_line<T, P>(ln, u, v, W, put);
     }
 }
 
