@@ -1100,8 +1100,10 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
         };
         for (int s = 0; s < n && ok; ++s) {
             const Plan& p = L->plans[s];
-            auto add = [&](int kind, int P, int tiles) {
-                if (!fast_supported(kind, P, L->esz)) {
+            // n: the valid samples along the axis; the size-class bodies prune the
+            // second half of each line, so they need 2n <= P
+            auto add = [&](int kind, int P, int n, int tiles) {
+                if (!fast_supported(kind, P, L->esz) || 2 * n > P) {
                     ok = false;
                     return;
                 }
@@ -1109,16 +1111,16 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
                 c.members.push_back(s);
                 c.prefix.push_back(c.prefix.back() + tiles);
             };
-            add(0, p.Px, 3 * p.nz * ((p.ny + 15) / 16));
+            add(0, p.Px, p.nx, 3 * p.nz * ((p.ny + 15) / 16));
             if (!ok) break;
             if (p.three_d) {
                 const int Ly = 256 / (p.Py / std::max(1, fast_first_radix(p.Py)));
-                add(1, p.Py, (3 * p.nz * p.hx + Ly - 1) / Ly);
+                add(1, p.Py, p.ny, (3 * p.nz * p.hx + Ly - 1) / Ly);
                 if (!ok) break;
-                add(2, p.Pz, (int)((p.hx * (int64_t)p.Py + 63) / 64));
+                add(2, p.Pz, p.nz, (int)((p.hx * (int64_t)p.Py + 63) / 64));
             } else {
                 const int Lk = std::max(1, fast_ky_lines(p.Py));
-                add(3, p.Py, (p.hx + Lk - 1) / Lk);
+                add(3, p.Py, p.ny, (p.hx + Lk - 1) / Lk);
             }
         }
         if (ok) {

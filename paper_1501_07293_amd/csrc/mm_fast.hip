@@ -66,6 +66,9 @@ template <typename T>
 bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s)
 {
     if (a.nlines <= 0) return true;
+    // the bodies prune the zero half of a forward line and the unused half of an
+    // inverse one: the valid samples must fit the first half
+    if (2 * (inverse ? a.nout : a.nin) > P) return false;
     return inverse ? yline_dispatch<T, true>(a, P, s) : yline_dispatch<T, false>(a, P, s);
 }
 
@@ -103,8 +106,8 @@ template <typename T>
 bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s)
 {
     if (a.nplanes <= 0 || a.ny <= 0) return true;
-    // the padded line must hold at least the valid samples
-    if (a.nx > P) return false;
+    // the valid samples must fit the first half of the padded line (pruning)
+    if (2 * a.nx > P) return false;
     if (a.lines == 4)
         return inverse ? xline_dispatch<T, true, 4>(a, P, s) : xline_dispatch<T, false, 4>(a, P, s);
     if (a.lines == 16)
@@ -140,6 +143,7 @@ template <typename T>
 bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
 {
     if (a.hx <= 0) return true;
+    if (2 * a.ny > P) return false;  // pruning: the valid samples fit the first half
     auto go = [&](auto kern, int L, int nt) {
         const int grid = (a.hx + L - 1) / L;
         hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s, a);

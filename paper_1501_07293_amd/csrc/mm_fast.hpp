@@ -16,6 +16,12 @@
 //
 // Z pass: one thread per (column, component) holds the whole z line in
 // registers; components meet in LDS for the Eq. 14 product.
+//
+// Pruning (line passes): the padded length of every axis is a power of two
+// P >= 2n - 1, so P >= 2n and the n valid samples sit in the first half of a
+// line.  Forward transforms take the second half as literal zeros and inverse
+// transforms never form the outputs of the second half; the launchers refuse
+// n > P / 2.  (The z pass keeps whole lines: pruned there it measured slower.)
 #pragma once
 #include "mm_fft.hpp"
 #include "mm_kernels.hpp"
@@ -82,8 +88,9 @@ __device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
     __syncthreads();
 }
 
-// Last stage: outputs land at natural index i + r * P/R; handed to `put`.
-template <typename T, int P, int S, typename Put>
+// Last stage: outputs land at natural index i + r * P/R; handed to `put`.  HALF:
+// only the outputs below P / 2 (r < R / 2, as i < P / R) are formed.
+template <typename T, int P, int S, bool HALF, typename Put>
 __device__ inline void last_stage(const cpx<T>* ln, int u, const StageTw<T, P, S>& W, Put put)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
@@ -101,7 +108,7 @@ __device__ inline void last_stage(const cpx<T>* ln, int u, const StageTw<T, P, S
         }
         Dft<T, R>::run(v);
 #pragma unroll
-        for (int r = 0; r < R; ++r) put(i + r * m, v[r]);
+        for (int r = 0; r < (HALF ? R / 2 : R); ++r) put(i + r * m, v[r]);
     }
 }
 
@@ -129,8 +136,9 @@ struct LineTw<T, P, 3> {
 };
 
 // Whole line after stage 1 has been computed into v (registers): write to LDS,
-// run the remaining stages, deliver outputs through put.  NS >= 2.
-template <typename T, int P, typename Put>
+// run the remaining stages, deliver outputs through put (HALF: those below
+// P / 2 only).  NS >= 2.
+template <typename T, int P, bool HALF = false, typename Put>
 __device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const LineTw<T, P>& W, Put put)
 {
     constexpr int NS = Sched<P>::NS, R0 = Sched<P>::R0;
@@ -138,7 +146,7 @@ __device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const LineTw<T,
     for (int r = 0; r < R0; ++r) ln[pad16(u * R0 + r)] = v[r];
     __syncthreads();
     if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, W.wm);
-    last_stage<T, P, NS - 1>(ln, u, W.wl, put);
+    last_stage<T, P, NS - 1, HALF>(ln, u, W.wl, put);
 }
 
 // In-register FFT of N points (N <= 64), all indices compile-time; Stockham
@@ -199,7 +207,7 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if (ok && e < a.nin) x = g[e];
+        if ((INV || 2 * r < R0) && ok && e < a.nin) x = g[e];  // forward: e >= P/2 is zero padding
         v[r] = INV ? conj(x) : x;
     }
     Dft<T, R0>::run(v);
@@ -210,7 +218,7 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P>(lds + l * LP, u, v, W, put);
+        finish_line<T, P, INV>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -247,7 +255,7 @@ __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if (e < a.nx) {
+        if (2 * r < R0 && e < a.nx) {  // e >= P/2 is zero padding
             if (ok0) x.re = in[e];
             if (ok1) x.im = in[a.nx + e];
         }
@@ -375,7 +383,7 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P>(lds + l * LP, u, v, W, put);
+        finish_line<T, P, true>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -483,7 +491,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if (ok && e < a.ny) x = g[e];
+        if (2 * r < R0 && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
         v[r] = x;
     }
     Dft<T, R0>::run(v);
@@ -526,7 +534,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
         __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
-        finish_line<T, P>(ln, u, v, W, put);
+        finish_line<T, P, true>(ln, u, v, W, put);
     }
 }
 
