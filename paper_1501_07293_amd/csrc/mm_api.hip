@@ -664,8 +664,8 @@ mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt, const mm_segment* g =
 
 void drop_graph(mm_sim* s)
 {
-    if (s->gexec) hipGraphExecDestroy(s->gexec);
-    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
     s->gexec = nullptr;
     s->graph = nullptr;
     s->graph_valid = false;
@@ -692,7 +692,7 @@ mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
         if (r != MM_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return r;
         }
         if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -727,7 +727,7 @@ mm_status euler_steps(mm_sim* s, int64_t nsteps, double dt)
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
         if (r != MM_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return r;
         }
         if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -1278,8 +1278,8 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
 
 void batch_drop_graph(mm_batch* b)
 {
-    if (b->gexec) hipGraphExecDestroy(b->gexec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
     b->graph_valid = false;
@@ -1322,7 +1322,7 @@ mm_status batch_step_impl(mm_batch* b, int64_t nsteps, double dt)
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
         if (r != MM_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return r;
         }
         if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -1420,8 +1420,8 @@ mm_status time_batch_demag(mm_batch* b, double* ms_out)
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (r != MM_OK) return r;
     if (e != hipSuccess) return fail(MM_EHIP, "batch autotune timing: %s", hipGetErrorString(e));
     *ms_out = ms / reps;
@@ -1497,8 +1497,8 @@ mm_status time_demag(mm_sim* s, hipStream_t st, double* ms_out)
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms_out = ms / reps;
     return MM_OK;
 }
@@ -1556,7 +1556,7 @@ mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o
         double ms = 0;
         if (r == MM_OK) r = p.prec == MM_F32 ? time_demag<float>(t, st, &ms) : time_demag<double>(t, st, &ms);
         if (t) mm_destroy(t);
-        hipFree(w);
+        (void)hipFree(w);
         if (r != MM_OK) continue;
         ++*ncand;
         if (ms < best->ms)
@@ -1664,7 +1664,7 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
     }
     hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        if (s->own_ws) hipFree(s->ws);
+        if (s->own_ws) (void)hipFree(s->ws);
         delete s;
         return fail(MM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
     }
@@ -1683,11 +1683,11 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
 mm_status mm_destroy(mm_sim* s)
 {
     if (!s) return MM_OK;
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
     drop_graph(s);
-    for (hipEvent_t e : s->ev) hipEventDestroy(e);
-    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
-    if (s->own_ws) hipFree(s->ws);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->own_ws) (void)hipFree(s->ws);
     delete s;
     return MM_OK;
 }
@@ -2156,10 +2156,10 @@ mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out)
 mm_status mm_batch_destroy(mm_batch* b)
 {
     if (!b) return MM_OK;
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     batch_drop_graph(b);
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-    if (b->own_ws) hipFree(b->ws);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->own_ws) (void)hipFree(b->ws);
     delete b;
     return MM_OK;
 }
