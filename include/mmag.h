@@ -294,9 +294,13 @@ mm_status mm_backward(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every
 /* Per-kernel timing with HIP events on the handle's stream.  kernel: 0 x-forward,
  * 1 y-forward, 2 k-space, 3 y-inverse, 4 x-inverse, 5 LLG stage.  While a
  * profile is open mm_step launches kernels directly (no graph replay) and
- * brackets every launch of that kernel with an event pair.  mm_profile_end
- * synchronises and returns the summed duration (ms) and the launch count. */
+ * brackets launches of that kernel with an event pair: the first of every
+ * `every` launches (mm_profile_sample, default 1 = each launch; an event pair
+ * costs the stream a few microseconds, so a long timed run samples).
+ * mm_profile_end synchronises and returns the summed duration (ms) and the
+ * number of launches timed. */
 mm_status mm_profile_begin(mm_sim* sim, int32_t kernel);
+mm_status mm_profile_sample(mm_sim* sim, int32_t every);
 mm_status mm_profile_end(mm_sim* sim, double* total_ms, int64_t* launches);
 const char* mm_kernel_name(int32_t kernel);
 

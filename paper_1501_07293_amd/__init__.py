@@ -34,7 +34,7 @@ EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm
            "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
            "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
-           "mm_profile_begin", "mm_profile_end", "mm_kernel_name", "mm_status_string",
+           "mm_profile_begin", "mm_profile_sample", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
 
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
         "mm_profile_begin": [vp, i32],
+        "mm_profile_sample": [vp, i32],
         "mm_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
@@ -335,8 +336,10 @@ class Sim:
         return dku, dm0
 
     # ------------------------------------------------------------- profiling
-    def profile_begin(self, kernel: str):
+    def profile_begin(self, kernel: str, every: int = 1):
+        """Time launches of `kernel` (one in `every`) until profile_end."""
         self._sync_stream()
+        _check(self._lib.mm_profile_sample(self._h, int(every)), "mm_profile_sample")
         _check(self._lib.mm_profile_begin(self._h, KERNELS[kernel]), "mm_profile_begin")
 
     def profile_end(self):

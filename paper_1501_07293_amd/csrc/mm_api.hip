@@ -268,8 +268,11 @@ struct mm_sim {
     double graph_dt;
     int graph_chunk;
     int graph_method;
-    // profiling
+    // profiling: launches of kernel prof_kernel, one in prof_every bracketed by events
     int prof_kernel;
+    int prof_every;
+    int64_t prof_seen;
+    bool prof_armed;
     std::vector<hipEvent_t> ev;
     size_t ev_used;
 
@@ -284,6 +287,8 @@ enum { KX_FWD = 0, KY_FWD = 1, KSPACE = 2, KY_INV = 3, KX_INV = 4, KLLG = 5, KCO
 mm_status prof_pre(mm_sim* s, int kid, hipStream_t st)
 {
     if (s->prof_kernel != kid) return MM_OK;
+    s->prof_armed = s->prof_seen++ % s->prof_every == 0;
+    if (!s->prof_armed) return MM_OK;
     if (s->ev_used + 2 > s->ev.size()) {
         for (int q = 0; q < 256; ++q) {
             hipEvent_t e;
@@ -297,9 +302,10 @@ mm_status prof_pre(mm_sim* s, int kid, hipStream_t st)
 
 mm_status prof_post(mm_sim* s, int kid, hipStream_t st)
 {
-    if (s->prof_kernel != kid) return MM_OK;
+    if (s->prof_kernel != kid || !s->prof_armed) return MM_OK;
     HIP_TRY(hipEventRecord(s->ev[s->ev_used + 1], st));
     s->ev_used += 2;
+    s->prof_armed = false;
     return MM_OK;
 }
 
@@ -1650,6 +1656,7 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
     s->alpha = mat->alpha;
     s->hext[0] = s->hext[1] = s->hext[2] = 0.0;
     s->prof_kernel = -1;
+    s->prof_every = 1;
     if (d_workspace) {
         s->ws = static_cast<char*>(d_workspace);
     } else {
@@ -2209,7 +2216,17 @@ mm_status mm_profile_begin(mm_sim* s, int32_t kernel)
     if (!s) return fail(MM_EINVAL, "sim is NULL");
     if (kernel < 0 || kernel >= KCOUNT) return fail(MM_EINVAL, "kernel id must be 0..5");
     s->prof_kernel = kernel;
+    s->prof_seen = 0;
+    s->prof_armed = false;
     s->ev_used = 0;
+    return MM_OK;
+}
+
+mm_status mm_profile_sample(mm_sim* s, int32_t every)
+{
+    if (!s) return fail(MM_EINVAL, "sim is NULL");
+    if (every < 1) return fail(MM_EINVAL, "every must be >= 1");
+    s->prof_every = every;
     return MM_OK;
 }
 

@@ -165,6 +165,13 @@ def test_batch_create_rejects_bad_arguments_without_gpu_work(lib):
     assert lib.mm_batch_step(None, 1, 1e-13) == -1
 
 
+def test_profile_entry_points_reject_bad_arguments(lib):
+    assert lib.mm_profile_begin(None, 2) == -1
+    assert lib.mm_profile_sample(None, 4) == -1
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.mm_profile_end(None, ctypes.byref(ms), ctypes.byref(n)) == -1
+
+
 def test_adjoint_and_euler_entry_points_reject_null(lib):
     assert lib.mm_step_euler(None, 1, 1e-13) == -1
     assert lib.mm_rollout(None, 10, 1e-13, 5, None) == -1

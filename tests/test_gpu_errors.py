@@ -1,7 +1,7 @@
 """Error paths that need the device: invalid magnetisation is refused at
 mm_set_m (zero-length or non-finite cells, counted by the normalising kernel),
 and a run driven unstable reports MM_ENONFINITE from its reductions instead of
-returning numbers."""
+returning numbers; the per-kernel event profile times the launches it is asked to."""
 import numpy as np
 import pytest
 
@@ -46,3 +46,22 @@ def test_unstable_run_reports_nonfinite(precision):
         with pytest.raises(mmag.MMError) as e:
             call()
         assert e.value.status == -6      # MM_ENONFINITE
+
+
+def test_profile_sampling_counts_launches():
+    # one launch in `every` of the profiled kernel is bracketed by events
+    sim = mmag.Sim(64, 32, 4, 5e-9, Ms=8e5, A=1.3e-11, Ku=0.0, alpha=0.5, precision="f32")
+    sim.set_m(random_unit_m((3, 4, 32, 64), seed=4))
+    sim.step(2, 1e-13)
+    sim.profile_begin("kspace")
+    sim.step(6, 1e-13)
+    ms_all, n_all = sim.profile_end()
+    assert n_all == 24 and ms_all > 0            # four field evaluations per RK4 step
+    sim.profile_begin("kspace", every=5)
+    sim.step(6, 1e-13)
+    ms_s, n_s = sim.profile_end()
+    assert n_s == 5 and ms_s > 0                  # launches 0, 5, 10, 15, 20 of 24
+    assert 0.2 < (ms_s / n_s) / (ms_all / n_all) < 5
+    with pytest.raises(mmag.MMError):
+        sim.profile_begin("llg", every=0)
+    sim.close()
