@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
                 ("cell", ctypes.c_double), ("Ms", ctypes.c_double), ("A", ctypes.c_double),
                 ("Ku", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("hext", ctypes.c_double * 3), ("ku_map", ctypes.POINTER(ctypes.c_double)),
-                ("demag", ctypes.c_int32)]
+                ("demag", ctypes.c_int32), ("periodic", ctypes.c_int32 * 3), ("images", ctypes.c_int32)]
 
 
 def _load():
@@ -63,6 +63,8 @@ def _load():
         lib.or_tensor_table.argtypes = [ctypes.c_int32] * 3 + [dp]
         lib.or_newell_point.argtypes = [ctypes.c_int32] * 3 + [dp]
         lib.or_newell_table.argtypes = [ctypes.c_int32] * 3 + [dp]
+        lib.or_tensor_table_periodic.argtypes = ([ctypes.c_int32] * 3 + [ctypes.POINTER(ctypes.c_int32)]
+                                                 + [ctypes.c_int32] * 2 + [dp])
         lib.or_demag.argtypes = [pp, dp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, dp]
         lib.or_exchange.argtypes = [pp, dp, dp]
         lib.or_anisotropy.argtypes = [pp, dp, dp]
@@ -73,7 +75,8 @@ def _load():
         lib.or_mean_m.argtypes = [pp, dp, dp]
         lib.or_rk4_adjoint.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
         lib.or_euler.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64]
-        for f in ("or_tensor_point", "or_tensor_table", "or_demag", "or_exchange",
+        for f in ("or_tensor_point", "or_tensor_table", "or_tensor_table_periodic", "or_demag",
+                  "or_exchange",
                   "or_anisotropy", "or_heff", "or_llg_rhs", "or_rk4", "or_energy", "or_mean_m",
                   "or_rk4_adjoint", "or_euler"):
             getattr(lib, f).restype = None
@@ -104,6 +107,8 @@ class Problem:
     ku_map: Optional[np.ndarray] = None       # (nz, ny, nx) J/m^3, overrides Ku
     demag: bool = True
     tensor: str = "point"           # "point": Eqs. 10-11; "newell": cell-averaged (Newell et al.)
+    periodic: Sequence[bool] = (False, False, False)   # per axis x, y, z
+    images: int = 0                 # periodic axes: images on each side beyond the minimum image
     _table: Optional[np.ndarray] = field(default=None, repr=False)
 
     @property
@@ -126,13 +131,22 @@ class Problem:
             assert self._ku.size == self.N
             p.ku_map = _dptr(self._ku)
         p.demag = 1 if self.demag else 0
+        for a in range(3):
+            p.periodic[a] = 1 if self.periodic[a] else 0
+        p.images = int(self.images)
         return p
 
     def table(self) -> np.ndarray:
-        """Demag tensor over all offsets: (6, 2nz-1, 2ny-1, 2nx-1); order xx,xy,xz,yy,yz,zz."""
+        """Demag tensor over all offsets: (6, 2nz-1, 2ny-1, 2nx-1); order xx,xy,xz,yy,yz,zz.
+        Along a periodic axis the table has n entries, offsets mod n summed over
+        images (tensor_table_periodic)."""
         if self._table is None:
-            make = newell_table if self.tensor == "newell" else tensor_table
-            self._table = make(self.nx, self.ny, self.nz)
+            if any(self.periodic):
+                self._table = tensor_table_periodic(self.nx, self.ny, self.nz, self.periodic,
+                                                    self.images, self.tensor)
+            else:
+                make = newell_table if self.tensor == "newell" else tensor_table
+                self._table = make(self.nx, self.ny, self.nz)
         return self._table
 
 
@@ -146,6 +160,21 @@ def tensor_point(I: int, J: int, K: int) -> np.ndarray:
 def tensor_table(nx: int, ny: int, nz: int) -> np.ndarray:
     out = np.zeros((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1))
     _load().or_tensor_table(nx, ny, nz, _dptr(out))
+    return out
+
+
+def tensor_table_periodic(nx: int, ny: int, nz: int, periodic, images: int = 0,
+                          tensor: str = "point") -> np.ndarray:
+    """Tensor table with periodic axes (the boundary Sec. 2.3 contrasts with zero
+    padding).  Along a periodic axis of period n the entry t (0 <= t < n) holds
+    the sum of the tensor over the offsets t + j n: the representative of t
+    nearest zero (both t and t - n with weight 1/2 when 2t = n) and `images`
+    further multiples of n on each side; open axes as in tensor_table."""
+    per = (ctypes.c_int32 * 3)(*[1 if p else 0 for p in periodic])
+    dims = [n if p else 2 * n - 1 for n, p in zip((nx, ny, nz), periodic)]
+    out = np.zeros((6, dims[2], dims[1], dims[0]))
+    _load().or_tensor_table_periodic(nx, ny, nz, per, int(images), 1 if tensor == "newell" else 0,
+                                     _dptr(out))
     return out
 
 

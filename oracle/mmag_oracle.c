@@ -13,7 +13,12 @@
  *   - LLG:         Eq. 2 in Landau-Lifshitz form, gamma multiplying H in A/m;
  *   - integrator:  classical RK4 with one renormalisation per step
  *                  (the renormalisation of the appendix script);
- *   - energies:    Eq. 1 term by term.
+ *   - energies:    Eq. 1 term by term;
+ *   - periodic axes (optional): the boundary the paper contrasts with zero
+ *                  padding (Sec. 2.3): the exchange stencil wraps around, and
+ *                  the demag sum runs over the minimum image of each source
+ *                  and `images` further images on each side (see
+ *                  or_tensor_table_periodic for the exact reading).
  *
  * Units are SI: m is a unit vector per cell, M = Ms m, fields in A/m, energy
  * in J.  Layout: planar [3][nz][ny][nx], x fastest.  Cell c = (i,j,k) has
@@ -38,7 +43,11 @@ typedef struct {
     double hext[3];     /* applied field, A/m */
     const double *ku_map; /* optional per-cell Ku, N values, J/m^3 */
     int32_t demag;      /* 0 switches the demag term off */
+    int32_t periodic[3]; /* per axis x, y, z: 1 = periodic */
+    int32_t images;     /* periodic axes: images on each side beyond the minimum image */
 } or_params;
+
+void or_newell_point(int32_t I, int32_t J, int32_t K, double out[6]);
 
 /* ------------------------------------------------------------------------ */
 /* ln(Z + r) with r = |(X,Y,Z)|.  For Z < 0 the sum Z + r cancels; the identity
@@ -98,16 +107,91 @@ void or_tensor_table(int32_t nx, int32_t ny, int32_t nz, double *out)
             }
 }
 
+/* Periodic table.  Along an open axis of n cells the entries are the offsets
+ * d = t - (n - 1), t in [0, 2n - 1), as in or_tensor_table.  Along a periodic
+ * axis of period n the entry t in [0, n) stands for every offset d = t (mod n)
+ * and holds the sum over images: the representative of t nearest to zero
+ * (t if 2t < n, t - n if 2t > n; for 2t = n both t and t - n, each with weight
+ * 1/2, so that the entry keeps the parity of the tensor component) plus
+ * `images` multiples of n on either side of it.  The entry is the weighted sum
+ * of the tensor over the product of the per-axis offset lists.  kind 0: Eqs.
+ * 10-11; kind 1: Newell's cell-averaged tensor.  Output [6][tz][ty][tx].     */
+static int axis_offsets(int n, int periodic, int images, int t, int *off, double *w)
+{
+    if (!periodic) {
+        off[0] = t - (n - 1);
+        w[0] = 1.0;
+        return 1;
+    }
+    int reps[2], nr = 0;
+    double rw = 1.0;
+    if (2 * t < n) {
+        reps[nr++] = t;
+    } else if (2 * t > n) {
+        reps[nr++] = t - n;
+    } else {
+        reps[nr++] = t;
+        reps[nr++] = t - n;
+        rw = 0.5;
+    }
+    int k = 0;
+    for (int r = 0; r < nr; ++r)
+        for (int j = -images; j <= images; ++j) {
+            off[k] = reps[r] + j * n;
+            w[k] = rw;
+            ++k;
+        }
+    return k;
+}
+
+void or_tensor_table_periodic(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                              int32_t images, int32_t kind, double *out)
+{
+    const int64_t tx = periodic[0] ? nx : 2 * nx - 1, ty = periodic[1] ? ny : 2 * ny - 1;
+    const int64_t tz = periodic[2] ? nz : 2 * nz - 1, plane = tx * ty * tz;
+    const int cap = 2 * (2 * images + 1);
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int64_t kk = 0; kk < tz; ++kk)
+        for (int64_t jj = 0; jj < ty; ++jj) {
+            int ox[cap], oy[cap], oz[cap];
+            double wx[cap], wy[cap], wz[cap];
+            int nzo = axis_offsets(nz, periodic[2], images, (int)kk, oz, wz);
+            int nyo = axis_offsets(ny, periodic[1], images, (int)jj, oy, wy);
+            for (int64_t ii = 0; ii < tx; ++ii) {
+                int nxo = axis_offsets(nx, periodic[0], images, (int)ii, ox, wx);
+                double acc[6] = {0, 0, 0, 0, 0, 0};
+                for (int c = 0; c < nzo; ++c)
+                    for (int b = 0; b < nyo; ++b)
+                        for (int a = 0; a < nxo; ++a) {
+                            double v[6];
+                            if (kind == 1) or_newell_point(ox[a], oy[b], oz[c], v);
+                            else or_tensor_point(ox[a], oy[b], oz[c], v);
+                            double w = wx[a] * wy[b] * wz[c];
+                            for (int q = 0; q < 6; ++q) acc[q] += w * v[q];
+                        }
+                int64_t idx = (kk * ty + jj) * tx + ii;
+                for (int q = 0; q < 6; ++q) out[q * plane + idx] = acc[q];
+            }
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Demag field, Eqs. 12-13, direct sum: H_a(o) = Ms sum_s sum_b K_ab(s-o) m_b(s).
- * table: from or_tensor_table for the same grid.  obs: optional list of
- * observation cell indices (nobs of them); H then holds [3][nobs].  With
- * obs == NULL every cell is an observer and H is [3][N].                    */
+ * table: from or_tensor_table for the same grid (or_tensor_table_periodic when
+ * an axis is periodic; its entry along a periodic axis is (s - o) mod n).
+ * obs: optional list of observation cell indices (nobs of them); H then holds
+ * [3][nobs].  With obs == NULL every cell is an observer and H is [3][N].    */
+static int64_t table_index(int64_t d, int64_t n, int periodic)
+{
+    return periodic ? ((d % n) + n) % n : d + n - 1;
+}
+
 void or_demag(const or_params *p, const double *m, const double *table,
               const int64_t *obs, int64_t nobs, double *H)
 {
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
-    const int64_t tx = 2 * nx - 1, ty = 2 * ny - 1, tz = 2 * nz - 1;
+    const int px = p->periodic[0], py = p->periodic[1], pz = p->periodic[2];
+    const int64_t tx = px ? nx : 2 * nx - 1, ty = py ? ny : 2 * ny - 1, tz = pz ? nz : 2 * nz - 1;
     const int64_t plane = tx * ty * tz;
     const double *mx = m, *my = m + N, *mz = m + 2 * N;
     int64_t nout = obs ? nobs : N;
@@ -120,8 +204,8 @@ void or_demag(const or_params *p, const double *m, const double *table,
             for (int64_t sj = 0; sj < ny; ++sj)
                 for (int64_t si = 0; si < nx; ++si) {
                     int64_t s = (sk * ny + sj) * nx + si;
-                    int64_t t = ((sk - ok + nz - 1) * ty + (sj - oj + ny - 1)) * tx
-                              + (si - oi + nx - 1);
+                    int64_t t = (table_index(sk - ok, nz, pz) * ty + table_index(sj - oj, ny, py)) * tx
+                              + table_index(si - oi, nx, px);
                     double kxx = table[t], kxy = table[plane + t], kxz = table[2 * plane + t];
                     double kyy = table[3 * plane + t], kyz = table[4 * plane + t];
                     double kzz = table[5 * plane + t];
@@ -137,11 +221,14 @@ void or_demag(const or_params *p, const double *m, const double *table,
 }
 
 /* Exchange field, Eq. 5 with Eqs. 6-7: a missing neighbour is the cell itself,
- * so it contributes nothing; H = 2A/(mu0 Ms delta^2) sum_nb (m_nb - m_c).    */
+ * so it contributes nothing; H = 2A/(mu0 Ms delta^2) sum_nb (m_nb - m_c).
+ * Along a periodic axis no neighbour is missing: the first and last cells are
+ * neighbours.                                                                */
 void or_exchange(const or_params *p, const double *m, double *H)
 {
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
     const double pref = 2.0 * p->A / (OR_MU0 * p->Ms * p->cell * p->cell);
+    const int px = p->periodic[0], py = p->periodic[1], pz = p->periodic[2];
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
         int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
@@ -149,11 +236,17 @@ void or_exchange(const or_params *p, const double *m, double *H)
             const double *u = m + a * N;
             double mc = u[c], acc = 0.0;
             if (i > 0) acc += u[c - 1] - mc;
+            else if (px) acc += u[c + nx - 1] - mc;
             if (i < nx - 1) acc += u[c + 1] - mc;
+            else if (px) acc += u[c - (nx - 1)] - mc;
             if (j > 0) acc += u[c - nx] - mc;
+            else if (py) acc += u[c + nx * (ny - 1)] - mc;
             if (j < ny - 1) acc += u[c + nx] - mc;
+            else if (py) acc += u[c - nx * (ny - 1)] - mc;
             if (k > 0) acc += u[c - nx * ny] - mc;
+            else if (pz) acc += u[c + nx * ny * (nz - 1)] - mc;
             if (k < nz - 1) acc += u[c + nx * ny] - mc;
+            else if (pz) acc += u[c - nx * ny * (nz - 1)] - mc;
             H[a * N + c] = pref * acc;
         }
     }
