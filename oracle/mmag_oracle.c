@@ -359,10 +359,14 @@ void or_energy(const or_params *p, const double *m, const double *table, double 
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz, N = nx * ny * nz;
     const double V = p->cell * p->cell * p->cell;
     double eex = 0, ean = 0, ed = 0, ez = 0;
+    const int px = p->periodic[0], py = p->periodic[1], pz = p->periodic[2];
     for (int64_t c = 0; c < N; ++c) {
         int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
-        int64_t nb[3] = {i < nx - 1 ? c + 1 : -1, j < ny - 1 ? c + nx : -1,
-                         k < nz - 1 ? c + nx * ny : -1};
+        /* each neighbour pair once, towards +x, +y, +z; along a periodic axis the
+         * last cell pairs with the first (the pairs of the wrapped stencil)     */
+        int64_t nb[3] = {i < nx - 1 ? c + 1 : (px ? c - (nx - 1) : -1),
+                         j < ny - 1 ? c + nx : (py ? c - nx * (ny - 1) : -1),
+                         k < nz - 1 ? c + nx * ny : (pz ? c - nx * ny * (nz - 1) : -1)};
         for (int d = 0; d < 3; ++d) {
             if (nb[d] < 0) continue;
             for (int a = 0; a < 3; ++a) {

@@ -12,6 +12,9 @@ Sec. 2.3; the image window is the reading stated in oracle.tensor_table_periodic
   with eigenvalue 2 cos(2 pi k / n) - 2.
 - Cyclic shifts along periodic axes commute with the demag field, and the
   periodic table keeps the parity of every component.
+- The exchange energy (Eq. 1, summed over neighbour pairs) equals
+  -(mu0/2) delta^3 sum M . H_ex of the wrapped field, and the demag energy
+  -(mu0/2) delta^3 sum M . H_d.
 """
 import itertools
 
@@ -145,3 +148,18 @@ def test_periodic_table_keeps_component_parities(n):
         assert np.allclose(tc[:, :, rev], sx * tc, atol=1e-15)
         assert np.allclose(tc[:, rev, :], sy * tc, atol=1e-15)
         assert np.allclose(tc[rev, :, :], sz * tc, atol=1e-15)
+
+
+@pytest.mark.parametrize("periodic", [(True, False, False), (True, True, False), (False, True, True),
+                                      (True, True, True)])
+def test_periodic_energy_matches_its_fields(periodic):
+    pb = oracle.Problem(5, 2, 3, 4e-9, Ms=MS, A=1.3e-11, Ku=2e3, periodic=periodic, images=1)
+    g = np.random.default_rng(8)
+    m = g.standard_normal(pb.shape)
+    m /= np.linalg.norm(m, axis=0)
+    e = oracle.energy(pb, m)
+    V = pb.cell ** 3
+    e_ex = -0.5 * oracle.MU0 * V * MS * (m * oracle.exchange(pb, m)).sum()
+    e_d = -0.5 * oracle.MU0 * V * MS * (m * oracle.demag(pb, m)).sum()
+    assert abs(e[0] - e_ex) <= 1e-12 * abs(e_ex)
+    assert abs(e[2] - e_d) <= 1e-12 * abs(e_d)
