@@ -71,6 +71,20 @@ typedef enum {
                                point-field tensor of Eqs. 10-11; see mm_demag_tensor_newell */
 #define MM_PER_GRID_MATERIAL 0x40u /* mm_batch_create: `mat` points to n materials, one per grid
                                       (otherwise one material for every grid) */
+/* Periodic boundary along an axis (the alternative to zero padding named in
+ * Sec. 2.3): that axis is not padded (its FFT length is n, which must be
+ * 7-smooth, and a power of two for the size-specialised passes), the exchange
+ * stencil wraps around (the first and last cells are neighbours), and the
+ * demag sum takes every source at the image nearest the observer plus
+ * mm_options.images further images on each side (with an even period the two
+ * images at distance n/2 count one half each, so the tensor keeps its
+ * parities and its spectrum stays real).  The paper defines no periodic
+ * tensor; this image window is the reading taken.  Setup cost grows as
+ * (2 images + 1)^(periodic axes).  Single-grid handles only: mm_batch_create
+ * and the adjoint entry points return MM_ENOTSUP for periodic grids. */
+#define MM_PERIODIC_X 0x80u
+#define MM_PERIODIC_Y 0x100u
+#define MM_PERIODIC_Z 0x200u
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                7-smooth vs power of two, specialised vs runtime-radix passes,
                                256 vs 512 threads, x lines per work-group) and keeps the fastest;
@@ -99,14 +113,16 @@ typedef struct {
     int32_t prec;        /* mm_precision */
     int32_t px, py, pz;  /* padded FFT sizes; 0 = automatic (2n if 7-smooth, else the
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
-                            size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1). */
+                            size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1).
+                            A periodic axis takes n (0 or n accepted). */
     uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD |
-                            MM_NEWELL | MM_PER_GRID_MATERIAL (batches) */
+                            MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (8 forward, 4 inverse), 4, 8 or 16 (both passes;
                             16 only where its LDS tile and
                             work-group fit; otherwise that pass runs the runtime-radix body) */
+    int32_t images;      /* periodic axes: images on each side beyond the nearest, 0..64 */
 } mm_options;
 
 typedef struct {

@@ -107,6 +107,8 @@ struct Plan {
     int x_lines, y_tw, k_tw;
     int xl, xl_inv;    // complex lines per work-group of the specialised x passes (forward, inverse)
     int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
+    int per;                   // periodic axes: bit 0 x, bit 1 y, bit 2 z
+    int images;                // images on each side beyond the nearest (periodic axes)
     int64_t oct_elems;         // per component
     // workspace offsets
     size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_kern, o_twx, o_twy, o_twz;
@@ -133,7 +135,18 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->esz = o->prec == MM_F32 ? 4 : 8;
     p->three_d = g->nz > 1;
     const bool pow2pad = (o->flags & MM_POW2_PAD) != 0;
-    auto pick = [pow2pad](int n, int req, bool allow1, int* out) -> mm_status {
+    p->per = ((o->flags & MM_PERIODIC_X) ? 1 : 0) | ((o->flags & MM_PERIODIC_Y) ? 2 : 0) |
+             ((o->flags & MM_PERIODIC_Z) ? 4 : 0);
+    if (o->images < 0 || o->images > 64) return fail(MM_EINVAL, "images must be in 0..64");
+    p->images = o->images;
+    auto pick = [pow2pad](int n, int req, bool allow1, bool periodic, int* out) -> mm_status {
+        if (periodic) {  // no zero padding: the FFT runs over the period itself
+            if (req != 0 && req != n)
+                return fail(MM_EINVAL, "a periodic axis of %d cells takes padded size %d (got %d)", n, n, req);
+            if (!smooth7(n)) return fail(MM_ENOTSUP, "a periodic axis needs a 7-smooth length (got %d)", n);
+            *out = n;
+            return MM_OK;
+        }
         if (req == 0) {
             if (allow1 && n == 1)
                 *out = 1;
@@ -155,9 +168,9 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
         return MM_OK;
     };
     mm_status st;
-    if ((st = pick(g->nx, o->px, false, &p->Px)) != MM_OK) return st;
-    if ((st = pick(g->ny, o->py, false, &p->Py)) != MM_OK) return st;
-    if ((st = pick(g->nz, o->pz, true, &p->Pz)) != MM_OK) return st;
+    if ((st = pick(g->nx, o->px, false, p->per & 1, &p->Px)) != MM_OK) return st;
+    if ((st = pick(g->ny, o->py, false, p->per & 2, &p->Py)) != MM_OK) return st;
+    if ((st = pick(g->nz, o->pz, true, p->per & 4, &p->Pz)) != MM_OK) return st;
     if (p->Pz == 1 && g->nz != 1) return fail(MM_EINVAL, "pz = 1 needs nz = 1");
     // a padded z axis with nz == 1 still works through the 3-D schedule
     p->three_d = p->Pz > 1;
@@ -461,7 +474,8 @@ hipError_t pass_x_inverse(const PassCtx& c, T* h, hipStream_t st)
     return launch_row_c2r<T>(r, p.nt, st);
 }
 
-// Demag field (reduced, h = H/Ms) of msrc into hd: Eq. 14 with zero padding.
+// Demag field (reduced, h = H/Ms) of msrc into hd: Eq. 14 with zero padding
+// (none along periodic axes).
 template <typename T>
 mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
 {
@@ -484,6 +498,7 @@ LlgArgs<T> llg_args(const mm_sim* s, double dt)
     a.ny = p.ny;
     a.nz = p.nz;
     a.N = p.N;
+    a.per = p.per;
     a.cex = (T)(2.0 * s->mat.A / (kMu0 * Ms * Ms * s->cell * s->cell));
     a.can = (T)(2.0 * s->mat.Ku / (kMu0 * Ms * Ms));
     a.hx = (T)(s->hext[0] / Ms);
@@ -555,7 +570,7 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
     const int cap = kElemsPerThread * nt, ldscap = cap + 64;
     for (int q = 0; q < p.ncomp; ++q) {
         HIP_TRY(launch_tensor_wrapped(R, (s->flags & MM_NEWELL) ? 1 : 0, comps[q], p.nx, p.ny, p.nz,
-                                      p.Px, p.Py, p.Pz, st));
+                                      p.Px, p.Py, p.Pz, p.per, p.images, st));
         RowR2CArgs xr{};
         xr.in = R;
         xr.in_row_stride = p.Px;
@@ -1039,6 +1054,8 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
 {
     if (n < 1) return fail(MM_EINVAL, "batch needs at least one grid");
     if (!grids) return fail(MM_EINVAL, "grids is NULL");
+    if (opt && (opt->flags & (MM_PERIODIC_X | MM_PERIODIC_Y | MM_PERIODIC_Z)))
+        return fail(MM_ENOTSUP, "batches take open boundaries only (periodic axes set)");
     mm_options o = opt ? *opt : mm_options{};
     o.threads = 256;
     L->plans.resize(n);
@@ -1447,7 +1464,8 @@ bool g_tune_file_loaded = false;
 std::string tune_key(const mm_grid* g, const mm_options* o)
 {
     std::ostringstream k;
-    k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1);
+    k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1)
+      << ":b" << ((o->flags >> 7) & 7) << "i" << o->images << ":t" << ((o->flags & MM_NEWELL) ? 1 : 0);
     return k.str();
 }
 
@@ -1514,15 +1532,18 @@ mm_status time_demag(mm_sim* s, hipStream_t st, double* ms_out)
 // passes, and the runtime-radix work-group size.
 std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
 {
-    std::vector<int> pxs{auto_pad(g->nx)}, pys{auto_pad(g->ny)};
-    std::vector<int> pzs{g->nz == 1 ? 1 : auto_pad(g->nz)};
+    // a periodic axis has one size, its period (requested as 0)
+    const bool perx = o->flags & MM_PERIODIC_X, pery = o->flags & MM_PERIODIC_Y;
+    const bool perz = o->flags & MM_PERIODIC_Z;
+    std::vector<int> pxs{perx ? 0 : auto_pad(g->nx)}, pys{pery ? 0 : auto_pad(g->ny)};
+    std::vector<int> pzs{perz ? 0 : (g->nz == 1 ? 1 : auto_pad(g->nz))};
     auto add_pow2 = [](std::vector<int>& v, int n) {
         const int q = next_pow2_at_least(2 * n - 1);
         if (q != v[0] && q <= 4096) v.push_back(q);
     };
-    add_pow2(pxs, g->nx);
-    add_pow2(pys, g->ny);
-    if (g->nz > 1) add_pow2(pzs, g->nz);
+    if (!perx) add_pow2(pxs, g->nx);
+    if (!pery) add_pow2(pys, g->ny);
+    if (g->nz > 1 && !perz) add_pow2(pzs, g->nz);
     std::vector<mm_options> out;
     for (int px : pxs)
         for (int py : pys)
@@ -1928,6 +1949,7 @@ mm_status mm_rollout(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, v
     if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_rollout before mm_set_m");
+    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     return s->p.prec == MM_F32 ? rollout_impl<float>(s, nsteps, dt, ckpt_every, (float*)d_ckpt)
                                : rollout_impl<double>(s, nsteps, dt, ckpt_every, (double*)d_ckpt);
 }
@@ -1936,6 +1958,7 @@ mm_status mm_adjoint_workspace_query(mm_sim* s, int64_t ckpt_every, size_t* byte
 {
     if (!s || !bytes) return fail(MM_EINVAL, "sim or bytes is NULL");
     if (ckpt_every < 1) return fail(MM_EINVAL, "ckpt_every must be >= 1");
+    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     *bytes = adj_bytes(s->p, ckpt_every);
     return MM_OK;
 }
@@ -1949,6 +1972,7 @@ mm_status mm_backward(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, 
     if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_backward before mm_set_m");
+    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     if (adj_ws_bytes < adj_bytes(s->p, ckpt_every))
         return fail(MM_EINVAL, "adjoint workspace of %zu bytes is smaller than the %zu needed", adj_ws_bytes,
                     adj_bytes(s->p, ckpt_every));

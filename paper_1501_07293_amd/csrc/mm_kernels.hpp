@@ -159,8 +159,10 @@ hipError_t launch_kspace(const KspArgs& a, int nt, hipStream_t s);
 // ---------------------------------------------------------------- setup
 // Demag tensor component `comp` (0..5 = xx,xy,xz,yy,yz,zz) in the wrapped layout
 // of a [Pz][Py][Px] FP64 array; kind 0 = Eqs. 10-11, 1 = Newell's averaged tensor.
+// per: periodic axes (bit 0 x, 1 y, 2 z; there P = n), summed over the image
+// nearest zero and `images` further images on each side.
 hipError_t launch_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
-                                 int Py, int Pz, hipStream_t s);
+                                 int Py, int Pz, int per, int images, hipStream_t s);
 // All six components on the offset table [6][2nz-1][2ny-1][2nx-1] (FP64).
 hipError_t launch_tensor_table(double* out, int kind, int nx, int ny, int nz, hipStream_t s);
 // tw[t] = exp(-2 pi i t / P), computed in FP64, stored in T.
@@ -190,6 +192,7 @@ struct LlgArgs {
     T alpha;
     T gdt;           // gamma Ms dt / (1 + alpha^2)
     int stage;       // 1..4 (RK4 stages), 0 (explicit Euler with renormalisation)
+    int per;         // periodic axes (bit 0 x, 1 y, 2 z): the exchange stencil wraps
 };
 // the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes;
 // a work-group of kLlgNT threads covers kLlgNT consecutive columns of one chunk,

@@ -3,7 +3,8 @@
 //
 // Local field (reduced units h = H / Ms) of cell c with unit vector m:
 //   exchange   Sec. 2.1 Eq. 5 with the Neumann rule of Eqs. 6-7: a missing
-//              neighbour equals the cell itself and adds nothing;
+//              neighbour equals the cell itself and adds nothing (along a
+//              periodic axis the first and last cells are neighbours);
 //   anisotropy Sec. 2.2 Eq. 8, easy axis x, x component only;
 //   applied    H_ext / Ms;   demag  the FFT result (already reduced).
 // LLG right-hand side, Eq. 2 in Landau-Lifshitz form for unit m:
@@ -35,11 +36,17 @@ __device__ inline void exchange_at(const LlgArgs<T>& a, int64_t c, int i, int j,
         const T mc = u[c];
         T acc = (T)0;
         if (i > 0) acc += u[c - 1] - mc;
+        else if (a.per & 1) acc += u[c + (a.nx - 1)] - mc;
         if (i < a.nx - 1) acc += u[c + 1] - mc;
+        else if (a.per & 1) acc += u[c - (a.nx - 1)] - mc;
         if (j > 0) acc += u[c - sy] - mc;
+        else if (a.per & 2) acc += u[c + (a.ny - 1) * sy] - mc;
         if (j < a.ny - 1) acc += u[c + sy] - mc;
+        else if (a.per & 2) acc += u[c - (a.ny - 1) * sy] - mc;
         if (k > 0) acc += u[c - sz] - mc;
+        else if (a.per & 4) acc += u[c + (a.nz - 1) * sz] - mc;
         if (k < a.nz - 1) acc += u[c + sz] - mc;
+        else if (a.per & 4) acc += u[c - (a.nz - 1) * sz] - mc;
         o.m[d] = mc;
         o.hex[d] = a.cex * acc;
     }
@@ -123,9 +130,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(LlgArgs<T> a, do
         double m[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) m[d] = (double)a.ms[d * N + c];
-        // exchange: each neighbour pair once (towards +x, +y, +z)
-        const int64_t nb[3] = {i < a.nx - 1 ? c + 1 : -1, j < a.ny - 1 ? c + sy : -1,
-                               k < a.nz - 1 ? c + sz : -1};
+        // exchange: each neighbour pair once (towards +x, +y, +z; across the
+        // boundary of a periodic axis towards its first cell)
+        const int64_t nb[3] = {i < a.nx - 1 ? c + 1 : ((a.per & 1) ? c - (a.nx - 1) : -1),
+                               j < a.ny - 1 ? c + sy : ((a.per & 2) ? c - (int64_t)(a.ny - 1) * sy : -1),
+                               k < a.nz - 1 ? c + sz : ((a.per & 4) ? c - (int64_t)(a.nz - 1) * sz : -1)};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (nb[q] < 0) continue;

@@ -90,7 +90,8 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
 // Thread `lane` of work-group `blk` (0 <= blk < llg_blocks, 0 <= lane < kLlgNT).
 // A neighbour missing at the boundary is the cell itself (Eq. 7): its address
 // is clamped to the cell's own, which adds mc - mc = 0, so every load is issued
-// unconditionally and none waits on a per-lane branch.
+// unconditionally and none waits on a per-lane branch.  Along a periodic axis
+// (a.per) the neighbour across the boundary is the cell at the other end.
 template <typename T>
 __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane)
 {
@@ -104,16 +105,18 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane
     const int k0 = kc * KZ;
     const int64_t N = a.N, sy = a.nx;
     const T* __restrict__ ms = a.ms;
+    const bool px = a.per & 1, py = a.per & 2, pz = a.per & 4;
     T col[KZ + 2][3];
 #pragma unroll
     for (int q = 0; q < KZ + 2; ++q) {
-        const int k = k0 - 1 + q;
-        const int kk = k < 0 ? 0 : (k >= a.nz ? a.nz - 1 : k);
+        const int k = k0 - 1 + q;  // planes beyond the far neighbour are loaded but unused
+        const int kk = k < 0 ? (pz ? a.nz - 1 : 0) : (k >= a.nz ? (pz ? 0 : a.nz - 1) : k);
 #pragma unroll
         for (int d = 0; d < 3; ++d) col[q][d] = ms[d * N + pc + kk * plane];
     }
-    const int64_t dxm = i > 0 ? -1 : 0, dxp = i < a.nx - 1 ? 1 : 0;
-    const int64_t dym = j > 0 ? -sy : 0, dyp = j < a.ny - 1 ? sy : 0;
+    const int64_t dxm = i > 0 ? -1 : (px ? a.nx - 1 : 0), dxp = i < a.nx - 1 ? 1 : (px ? 1 - a.nx : 0);
+    const int64_t dym = j > 0 ? -sy : (py ? (a.ny - 1) * sy : 0);
+    const int64_t dyp = j < a.ny - 1 ? sy : (py ? (1 - a.ny) * sy : 0);
     T lap[KZ][3], hd[KZ][3], mn[KZ][3], ac[KZ][3], kan[KZ];
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
@@ -129,8 +132,8 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane
             acc += u[dxp] - mc;
             acc += u[dym] - mc;
             acc += u[dyp] - mc;
-            if (k > 0) acc += col[q][d] - mc;
-            if (k < a.nz - 1) acc += col[q + 2][d] - mc;
+            if (k > 0 || pz) acc += col[q][d] - mc;
+            if (k < a.nz - 1 || pz) acc += col[q + 2][d] - mc;
             lap[q][d] = acc;
             hd[q][d] = (T)0;
             mn[q][d] = (T)0;

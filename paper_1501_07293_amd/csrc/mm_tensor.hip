@@ -146,8 +146,42 @@ __device__ inline bool wrap_offset(int q, int n, int P, int* d)
     return false;
 }
 
+// Offsets one padded index stands for along an axis.  Open axis: the wrapped
+// offset (or none).  Periodic axis (P = n): index t stands for every offset
+// t + j n; the representative nearest zero is t (2t < n) or t - n (2t > n);
+// at 2t = n both, weight 1/2 each, which keeps the parity of each tensor
+// component under t -> n - t.  `images` multiples of n on either side of each
+// representative are added.
+struct AxisSet {
+    int rep[2];
+    int nrep;
+    double w;
+    int period, images;
+};
+
+__device__ inline bool axis_set(int q, int n, int P, bool periodic, int images, AxisSet* a)
+{
+    a->period = n;
+    a->w = 1.0;
+    a->nrep = 1;
+    a->images = 0;
+    if (!periodic) return wrap_offset(q, n, P, &a->rep[0]);
+    a->images = images;
+    if (2 * q < n) {
+        a->rep[0] = q;
+    } else if (2 * q > n) {
+        a->rep[0] = q - n;
+    } else {
+        a->rep[0] = q;
+        a->rep[1] = q - n;
+        a->nrep = 2;
+        a->w = 0.5;
+    }
+    return true;
+}
+
 __global__ void k_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
-                                 int Py, int Pz)
+                                 int Py, int Pz, int per, int images)
 {
     const int64_t total = (int64_t)Px * Py * Pz;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
@@ -155,10 +189,21 @@ __global__ void k_tensor_wrapped(double* out, int kind, int comp, int nx, int ny
         const int qx = (int)(q % Px);
         const int qy = (int)((q / Px) % Py);
         const int qz = (int)(q / ((int64_t)Px * Py));
-        int I, J, K;
+        AxisSet ax, ay, az;
         double v = 0.0;
-        if (wrap_offset(qx, nx, Px, &I) && wrap_offset(qy, ny, Py, &J) && wrap_offset(qz, nz, Pz, &K))
-            v = tensor_value(kind, comp, I, J, K);
+        if (axis_set(qx, nx, Px, per & 1, images, &ax) && axis_set(qy, ny, Py, per & 2, images, &ay) &&
+            axis_set(qz, nz, Pz, per & 4, images, &az)) {
+            const double w = ax.w * ay.w * az.w;
+            for (int rz = 0; rz < az.nrep; ++rz)
+                for (int jz = -az.images; jz <= az.images; ++jz)
+                    for (int ry = 0; ry < ay.nrep; ++ry)
+                        for (int jy = -ay.images; jy <= ay.images; ++jy)
+                            for (int rx = 0; rx < ax.nrep; ++rx)
+                                for (int jx = -ax.images; jx <= ax.images; ++jx)
+                                    v += w * tensor_value(kind, comp, ax.rep[rx] + jx * ax.period,
+                                                          ay.rep[ry] + jy * ay.period,
+                                                          az.rep[rz] + jz * az.period);
+        }
         out[q] = v;
     }
 }
@@ -229,11 +274,11 @@ static int grid_for(int64_t n, int block)
 }
 
 hipError_t launch_tensor_wrapped(double* out, int kind, int comp, int nx, int ny, int nz, int Px,
-                                 int Py, int Pz, hipStream_t s)
+                                 int Py, int Pz, int per, int images, hipStream_t s)
 {
     const int64_t total = (int64_t)Px * Py * Pz;
     hipLaunchKernelGGL(k_tensor_wrapped, dim3(grid_for(total, 256)), dim3(256), 0, s, out, kind, comp,
-                       nx, ny, nz, Px, Py, Pz);
+                       nx, ny, nz, Px, Py, Pz, per, images);
     return hipGetLastError();
 }
 

@@ -165,6 +165,28 @@ def test_batch_create_rejects_bad_arguments_without_gpu_work(lib):
     assert lib.mm_batch_step(None, 1, 1e-13) == -1
 
 
+def test_periodic_options_validated_without_gpu_work(lib):
+    b = ctypes.c_size_t()
+    g = mm.Grid(64, 48, 4, 5e-9)
+    per = mm.MM_PERIODIC_X | mm.MM_PERIODIC_Y
+    ok = mm.Options(0, 0, 0, 0, per, 0, 0, 2)
+    assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(ok), ctypes.byref(b)) == 0
+    padded = mm.Options(0, 0, 0, 0, 0, 0, 0, 0)
+    b2 = ctypes.c_size_t()
+    assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(padded), ctypes.byref(b2)) == 0
+    assert b.value < b2.value                          # no zero padding along x and y
+    bad_size = mm.Options(0, 128, 0, 0, mm.MM_PERIODIC_X, 0, 0, 0)
+    assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(bad_size), ctypes.byref(b)) == -1
+    assert lib.mm_workspace_query(ctypes.byref(mm.Grid(22, 8, 1, 5e-9)),
+                                  ctypes.byref(mm.Options(0, 0, 0, 0, mm.MM_PERIODIC_X, 0, 0, 0)),
+                                  ctypes.byref(b)) == -5          # 22 = 2 x 11 is not 7-smooth
+    assert lib.mm_workspace_query(ctypes.byref(g), ctypes.byref(mm.Options(0, 0, 0, 0, per, 0, 0, 65)),
+                                  ctypes.byref(b)) == -1
+    grids = (mm.Grid * 2)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(40, 33, 2, 5e-9))
+    assert lib.mm_batch_workspace_query(2, grids, ctypes.byref(mm.Options(0, 0, 0, 0, per, 0, 0, 0)),
+                                        ctypes.byref(b)) == -5
+
+
 def test_profile_entry_points_reject_bad_arguments(lib):
     assert lib.mm_profile_begin(None, 2) == -1
     assert lib.mm_profile_sample(None, 4) == -1

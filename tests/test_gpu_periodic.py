@@ -1,0 +1,143 @@
+"""Periodic boundaries (MM_PERIODIC_X/Y/Z, the alternative to zero padding named in
+Sec. 2.3) on the GPU against the oracle's direct sum over the same image window,
+and the uniformly magnetised periodic box against the union-prism closed form."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import random_unit_m
+from tests.gpu_util import rel_max, to_np
+from tests.test_oracle_periodic import apply, axis_windows, prism_tensor
+
+pytestmark = pytest.mark.gpu
+
+mmag = pytest.importorskip("paper_1501_07293_amd")
+
+FIELD_TOL = {"f64": 1e-11, "f32": 1e-5}
+
+CASES = [
+    # dims, periodic (x, y, z), images
+    ((16, 12, 3), (True, True, False), 0),
+    ((20, 15, 4), (True, True, True), 1),
+    ((32, 8, 1), (True, False, False), 2),
+    ((24, 10, 1), (False, True, False), 0),
+    ((9, 7, 5), (False, False, True), 3),
+    ((64, 64, 2), (True, True, False), 1),
+]
+
+
+def problem(dims, periodic, images, tensor="point", **kw):
+    nx, ny, nz = dims
+    return oracle.Problem(nx, ny, nz, 4e-9, Ms=8e5, A=1.3e-11, Ku=3e3, alpha=0.3,
+                          hext=(1.2e4, -3e3, 5e3), periodic=periodic, images=images, tensor=tensor,
+                          **kw)
+
+
+def make_sim(pb, precision, **kw):
+    s = mmag.Sim(pb.nx, pb.ny, pb.nz, pb.cell, Ms=pb.Ms, A=pb.A, Ku=pb.Ku, alpha=pb.alpha,
+                 gamma=pb.gamma, precision=precision, periodic=pb.periodic, images=pb.images,
+                 tensor=pb.tensor, **kw)
+    s.set_hext(pb.hext)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("dims,periodic,images", CASES)
+def test_periodic_fields_match_oracle(dims, periodic, images, precision):
+    pb = problem(dims, periodic, images)
+    sim = make_sim(pb, precision)
+    plan = sim.plan()
+    for a, n, p in zip("xyz", dims, periodic):   # no padding along periodic axes
+        if p:
+            assert plan["p" + a] == n
+    sim.set_m(random_unit_m(pb.shape, seed=sum(dims) + images))
+    m = to_np(sim.get_m())
+    ref = oracle.heff_terms(pb, m)
+    for term in ("demag", "exch", "eff"):
+        err = rel_max(to_np(sim.field(term)), ref[term])
+        print(dims, periodic, images, precision, term, f"{err:.2e}")
+        assert err <= FIELD_TOL[precision], (term, err)
+    e_gpu, e_ref = sim.energy(), oracle.energy(pb, m)
+    assert np.abs(e_gpu - e_ref).max() <= (1e-10 if precision == "f64" else 1e-5) * np.abs(e_ref).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_periodic_newell_fields_match_oracle(precision):
+    pb = problem((16, 16, 2), (True, True, False), 1, tensor="newell")
+    sim = make_sim(pb, precision)
+    sim.set_m(random_unit_m(pb.shape, seed=77))
+    m = to_np(sim.get_m())
+    err = rel_max(to_np(sim.field("demag")), oracle.demag(pb, m))
+    assert err <= FIELD_TOL[precision], err
+    sim.close()
+
+
+@pytest.mark.parametrize("method", ["rk4", "euler"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_periodic_trajectory_matches_oracle(method, precision):
+    pb = problem((12, 10, 3), (True, True, False), 1)
+    sim = make_sim(pb, precision)
+    sim.set_m(random_unit_m(pb.shape, seed=5))
+    m0 = to_np(sim.get_m())
+    dt, n = 1e-13, 12
+    if method == "rk4":
+        sim.step(n, dt)
+        ref = oracle.rk4(pb, m0, dt, n)
+    else:
+        sim.step_euler(n, dt)
+        ref = oracle.euler(pb, m0, dt, n)
+    err = np.abs(to_np(sim.get_m()) - ref).max()
+    assert err <= (1e-11 if precision == "f64" else 2e-5), err
+    sim.close()
+
+
+@pytest.mark.parametrize("dims,periodic,images", [((16, 12, 3), (True, True, False), 2),
+                                                  ((15, 8, 4), (True, False, True), 1)])
+def test_uniform_periodic_box_on_gpu_is_the_union_prism(dims, periodic, images):
+    nx, ny, nz = dims
+    sim = mmag.Sim(nx, ny, nz, 5e-9, Ms=8e5, precision="f64", periodic=periodic, images=images)
+    u = np.array([0.6, -0.48, 0.64])
+    sim.set_m(np.broadcast_to(u.reshape(3, 1, 1, 1), (3, nz, ny, nx)).copy())
+    h = to_np(sim.field("demag"))
+    worst = 0.0
+    for k, j, i in itertools.product(range(nz), range(ny), range(nx)):
+        ref = np.zeros(3)
+        for (lx, hx, wx) in axis_windows(nx, periodic[0], images, i):
+            for (ly, hy, wy) in axis_windows(ny, periodic[1], images, j):
+                for (lz, hz, wz) in axis_windows(nz, periodic[2], images, k):
+                    ref += wx * wy * wz * 8e5 * apply(prism_tensor((lx, ly, lz), (hx, hy, hz)), u)
+        worst = max(worst, np.abs(h[:, k, j, i] - ref).max() / 8e5)
+    assert worst < 1e-11, worst
+    sim.close()
+
+
+def test_periodic_film_full_size_sampled():
+    # 512 x 512 x 16, periodic in x and y (FFT 512 x 512 x 32), FP32, default launch
+    # configuration: demag and effective field at sampled cells against the oracle
+    pb = oracle.Problem(512, 512, 16, 3e-9, Ms=8e5, A=1.3e-11, periodic=(True, True, False))
+    sim = make_sim(pb, "f32")
+    sim.set_m(random_unit_m(pb.shape, seed=11))
+    m = to_np(sim.get_m())
+    g = np.random.default_rng(12)
+    obs = np.unique(np.concatenate([[0, 511, pb.N - 512, pb.N - 1], g.integers(0, pb.N, 48)]))
+    err = rel_max(to_np(sim.field("demag")).reshape(3, -1)[:, obs], oracle.demag(pb, m, obs))
+    ex = oracle.exchange(pb, m).reshape(3, -1)[:, obs]
+    err_ex = rel_max(to_np(sim.field("exch")).reshape(3, -1)[:, obs], ex)
+    print(f"periodic film: demag {err:.2e}, exchange {err_ex:.2e}")
+    assert err <= FIELD_TOL["f32"] and err_ex <= FIELD_TOL["f32"]
+    sim.step(5, 5e-14)
+    mm = to_np(sim.get_m())
+    assert np.abs(np.sqrt((mm * mm).sum(axis=0)) - 1).max() < 1e-6
+    sim.close()
+
+
+def test_periodic_grids_refuse_the_adjoint():
+    sim = mmag.Sim(16, 16, 1, 5e-9, precision="f32", periodic=(True, True, False))
+    sim.set_m(random_unit_m((3, 1, 16, 16), seed=1))
+    with pytest.raises(mmag.MMError) as e:
+        sim.rollout_ckpt(10, 1e-13, 5)
+    assert e.value.status == -5 and "open boundaries" in str(e.value)
+    sim.close()
