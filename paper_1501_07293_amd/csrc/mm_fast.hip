@@ -4,25 +4,26 @@
 
 namespace mm {
 
-template <typename T, int P, bool INV>
+// FULL: whole lines (a periodic axis, n = P); otherwise the padding half is pruned
+template <typename T, int P, bool INV, bool FULL>
 __global__ __launch_bounds__(256) void k_yline(YLineArgs a)
 {
     __shared__ cpx<T> lds[yline_lds_elems<P>()];
-    body_yline<T, P, INV>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_yline<T, P, INV, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool FULL>
 __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xfwd(XLineArgs a)
 {
     __shared__ cpx<T> lds[xfwd_lds_elems<P, L>()];
-    body_xfwd<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_xfwd<T, P, L, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool FULL>
 __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
 {
     __shared__ cpx<T> lds[xinv_lds_elems<P, L>()];
-    body_xinv<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_xinv<T, P, L, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int PZ>
@@ -32,15 +33,15 @@ __global__ __launch_bounds__(3 * kZCols) void k_kspace_z(KzArgs a)
     body_kspace_z<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
-template <typename T, int P>
+template <typename T, int P, bool FULL>
 __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspace_y(KyArgs a)
 {
     __shared__ cpx<T> lds[kspace_y_lds_elems<P>()];
-    body_kspace_y<T, P>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+    body_kspace_y<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 // ------------------------------------------------------------------ dispatch
-template <typename T, bool INV>
+template <typename T, bool INV, bool FULL>
 static bool yline_dispatch(const YLineArgs& a, int P, hipStream_t s)
 {
     auto go = [&](auto kern, int tl) {
@@ -50,14 +51,14 @@ static bool yline_dispatch(const YLineArgs& a, int P, hipStream_t s)
         return true;
     };
     switch (P) {
-    case 16: return go(k_yline<T, 16, INV>, 16 / Sched<16>::R0);
-    case 32: return go(k_yline<T, 32, INV>, 32 / Sched<32>::R0);
-    case 64: return go(k_yline<T, 64, INV>, 64 / Sched<64>::R0);
-    case 128: return go(k_yline<T, 128, INV>, 128 / Sched<128>::R0);
-    case 256: return go(k_yline<T, 256, INV>, 256 / Sched<256>::R0);
-    case 512: return go(k_yline<T, 512, INV>, 512 / Sched<512>::R0);
-    case 1024: return go(k_yline<T, 1024, INV>, 1024 / Sched<1024>::R0);
-    case 2048: return go(k_yline<T, 2048, INV>, 2048 / Sched<2048>::R0);
+    case 16: return go(k_yline<T, 16, INV, FULL>, 16 / Sched<16>::R0);
+    case 32: return go(k_yline<T, 32, INV, FULL>, 32 / Sched<32>::R0);
+    case 64: return go(k_yline<T, 64, INV, FULL>, 64 / Sched<64>::R0);
+    case 128: return go(k_yline<T, 128, INV, FULL>, 128 / Sched<128>::R0);
+    case 256: return go(k_yline<T, 256, INV, FULL>, 256 / Sched<256>::R0);
+    case 512: return go(k_yline<T, 512, INV, FULL>, 512 / Sched<512>::R0);
+    case 1024: return go(k_yline<T, 1024, INV, FULL>, 1024 / Sched<1024>::R0);
+    case 2048: return go(k_yline<T, 2048, INV, FULL>, 2048 / Sched<2048>::R0);
     default: return false;
     }
 }
@@ -67,12 +68,16 @@ bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s)
 {
     if (a.nlines <= 0) return true;
     // the bodies prune the zero half of a forward line and the unused half of an
-    // inverse one: the valid samples must fit the first half
-    if (2 * (inverse ? a.nout : a.nin) > P) return false;
-    return inverse ? yline_dispatch<T, true>(a, P, s) : yline_dispatch<T, false>(a, P, s);
+    // inverse one when the valid samples fit the first half; whole lines (a
+    // periodic axis) take the FULL instantiation
+    const int n = inverse ? a.nout : a.nin;
+    if (n > P) return false;
+    if (2 * n > P)
+        return inverse ? yline_dispatch<T, true, true>(a, P, s) : yline_dispatch<T, false, true>(a, P, s);
+    return inverse ? yline_dispatch<T, true, false>(a, P, s) : yline_dispatch<T, false, false>(a, P, s);
 }
 
-template <typename T, bool INV, int L>
+template <typename T, bool INV, int L, bool FULL>
 static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
 {
     auto go = [&](auto kern, int tl) {
@@ -85,8 +90,8 @@ static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
     case PP:                                                                          \
         if constexpr (x_lds_bytes<T, PP, L>() <= kLdsBudget &&                        \
                       L * (PP / Sched<PP>::R0) <= 1024)                               \
-            return INV ? go(k_xinv<T, PP, L>, PP / Sched<PP>::R0)                     \
-                       : go(k_xfwd<T, PP, L>, PP / Sched<PP>::R0);                    \
+            return INV ? go(k_xinv<T, PP, L, FULL>, PP / Sched<PP>::R0)               \
+                       : go(k_xfwd<T, PP, L, FULL>, PP / Sched<PP>::R0);              \
         return false;
     switch (P) {
         MM_XCASE(16)
@@ -102,17 +107,24 @@ static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
 #undef MM_XCASE
 }
 
+template <typename T, bool FULL>
+static bool xline_lines(const XLineArgs& a, int P, int inverse, hipStream_t s)
+{
+    if (a.lines == 4)
+        return inverse ? xline_dispatch<T, true, 4, FULL>(a, P, s) : xline_dispatch<T, false, 4, FULL>(a, P, s);
+    if (a.lines == 16)
+        return inverse ? xline_dispatch<T, true, 16, FULL>(a, P, s)
+                       : xline_dispatch<T, false, 16, FULL>(a, P, s);
+    return inverse ? xline_dispatch<T, true, 8, FULL>(a, P, s) : xline_dispatch<T, false, 8, FULL>(a, P, s);
+}
+
 template <typename T>
 bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s)
 {
     if (a.nplanes <= 0 || a.ny <= 0) return true;
-    // the valid samples must fit the first half of the padded line (pruning)
-    if (2 * a.nx > P) return false;
-    if (a.lines == 4)
-        return inverse ? xline_dispatch<T, true, 4>(a, P, s) : xline_dispatch<T, false, 4>(a, P, s);
-    if (a.lines == 16)
-        return inverse ? xline_dispatch<T, true, 16>(a, P, s) : xline_dispatch<T, false, 16>(a, P, s);
-    return inverse ? xline_dispatch<T, true, 8>(a, P, s) : xline_dispatch<T, false, 8>(a, P, s);
+    if (a.nx > P) return false;
+    // valid samples in the first half: pruned bodies; whole lines (periodic x): FULL
+    return 2 * a.nx > P ? xline_lines<T, true>(a, P, inverse, s) : xline_lines<T, false>(a, P, inverse, s);
 }
 
 template <typename T>
@@ -139,11 +151,9 @@ bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
     }
 }
 
-template <typename T>
-bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
+template <typename T, bool FULL>
+static bool kspace_y_dispatch(const KyArgs& a, int P, hipStream_t s)
 {
-    if (a.hx <= 0) return true;
-    if (2 * a.ny > P) return false;  // pruning: the valid samples fit the first half
     auto go = [&](auto kern, int L, int nt) {
         const int grid = (a.hx + L - 1) / L;
         hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s, a);
@@ -151,7 +161,7 @@ bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
     };
 #define MM_KYCASE(PP)                                                                          \
     case PP:                                                                                   \
-        return go(k_kspace_y<T, PP>, ky_lines<PP>(), 3 * ky_lines<PP>() * (PP / Sched<PP>::R0));
+        return go(k_kspace_y<T, PP, FULL>, ky_lines<PP>(), 3 * ky_lines<PP>() * (PP / Sched<PP>::R0));
     switch (P) {
         MM_KYCASE(16)
         MM_KYCASE(32)
@@ -163,6 +173,16 @@ bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
     default: return false;
     }
 #undef MM_KYCASE
+}
+
+template <typename T>
+bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
+{
+    if (a.hx <= 0) return true;
+    if (a.ny > P) return false;
+    // valid samples in the first half: pruned body; whole lines (periodic y): FULL
+    if (2 * a.ny > P) return kspace_y_dispatch<T, true>(a, P, s);
+    return kspace_y_dispatch<T, false>(a, P, s);
 }
 
 int fast_first_radix(int P)

@@ -17,11 +17,13 @@
 // Z pass: one thread per (column, component) holds the whole z line in
 // registers; components meet in LDS for the Eq. 14 product.
 //
-// Pruning (line passes): the padded length of every axis is a power of two
+// Pruning (line passes): a zero-padded axis has a power-of-two length
 // P >= 2n - 1, so P >= 2n and the n valid samples sit in the first half of a
 // line.  Forward transforms take the second half as literal zeros and inverse
-// transforms never form the outputs of the second half; the launchers refuse
-// n > P / 2.  (The z pass keeps whole lines: pruned there it measured slower.)
+// transforms never form the outputs of the second half.  A periodic axis
+// (n = P) takes the FULL instantiation, which transforms whole lines; the
+// launchers pick it when 2n > P.  (The z pass keeps whole lines: pruned there
+// it measured slower.)
 #pragma once
 #include "mm_fft.hpp"
 #include "mm_kernels.hpp"
@@ -191,7 +193,7 @@ __device__ inline void fft_reg(cpx<T>* x, const cpx<T>* __restrict__ tw)
 }
 
 // ------------------------------------------------------------------ y lines
-template <typename T, int P, bool INV>
+template <typename T, int P, bool INV, bool FULL = false>
 __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, L = 256 / TL, LP = padded_len<P>();
@@ -207,7 +209,7 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if ((INV || 2 * r < R0) && ok && e < a.nin) x = g[e];  // forward: e >= P/2 is zero padding
+        if ((INV || FULL || 2 * r < R0) && ok && e < a.nin) x = g[e];  // forward: e >= P/2 is padding
         v[r] = INV ? conj(x) : x;
     }
     Dft<T, R0>::run(v);
@@ -218,7 +220,7 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P, INV>(lds + l * LP, u, v, W, put);
+        finish_line<T, P, INV && !FULL>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -237,7 +239,7 @@ constexpr int x_lds_bytes()
                                                                               : 2 * L * (P / 2 + 1));
 }
 
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool FULL = false>
 __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
@@ -255,7 +257,7 @@ __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if (2 * r < R0 && e < a.nx) {  // e >= P/2 is zero padding
+        if ((FULL || 2 * r < R0) && e < a.nx) {  // e >= P/2 is zero padding
             if (ok0) x.re = in[e];
             if (ok1) x.im = in[a.nx + e];
         }
@@ -302,7 +304,7 @@ __device__ inline void body_xfwd(const XLineArgs& a, int tile, cpx<T>* lds)
 }
 
 // ------------------------------------------------------------------ x inverse
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool FULL = false>
 __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = L * TL, LP = padded_len<P>();
@@ -383,7 +385,7 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
 #pragma unroll
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
-        finish_line<T, P, true>(lds + l * LP, u, v, W, put);
+        finish_line<T, P, !FULL>(lds + l * LP, u, v, W, put);
     }
 }
 
@@ -472,7 +474,7 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
 template <int P>
 constexpr int ky_lines() { return (256 / (3 * (P / Sched<P>::R0))) > 0 ? 256 / (3 * (P / Sched<P>::R0)) : 1; }
 
-template <typename T, int P>
+template <typename T, int P, bool FULL = false>
 __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, L = ky_lines<P>(), NT = 3 * L * TL;
@@ -491,7 +493,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
     for (int r = 0; r < R0; ++r) {
         const int e = u + TL * r;
         cpx<T> x = {(T)0, (T)0};
-        if (2 * r < R0 && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
+        if ((FULL || 2 * r < R0) && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
         v[r] = x;
     }
     Dft<T, R0>::run(v);
@@ -534,7 +536,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
         for (int r = 0; r < R0; ++r) put(r, v[r]);
     } else {
         __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
-        finish_line<T, P, true>(ln, u, v, W, put);
+        finish_line<T, P, !FULL>(ln, u, v, W, put);
     }
 }
 

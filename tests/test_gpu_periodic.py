@@ -25,6 +25,8 @@ CASES = [
     ((24, 10, 1), (False, True, False), 0),
     ((9, 7, 5), (False, False, True), 3),
     ((64, 64, 2), (True, True, False), 1),
+    ((24, 32, 1), (False, True, False), 1),     # one cell thick, periodic y: whole-line y k-space
+    ((32, 16, 4), (True, True, True), 0),       # every axis periodic, powers of two
 ]
 
 
