@@ -214,6 +214,42 @@ def batched_leg(steps: int, autotune: bool, warmup: int = 2) -> dict:
     return out
 
 
+def periodic_leg(steps: int, warmup: int = 3) -> dict:
+    """The 512x512x16 film with periodic x and y (no zero padding: FFT 512x512x32),
+    FP32, RK4: whole-job rate, per-kernel launch times and their algorithmic
+    bandwidth."""
+    import torch
+
+    import paper_1501_07293_amd as mm
+    import synthetic
+    c = synthetic.LARGE
+    sim = mm.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
+                 precision="f32", periodic=(True, True, False), device="cuda:0")
+    sim.set_hext(c.hext)
+    sim.set_m(synthetic.random_unit_m(c.shape, seed=0))
+    plan = sim.plan()
+    sim.step(warmup, c.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, c.dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ab = algorithmic_bytes(plan, c.nx, c.ny, c.nz, 4)
+    kernels = {}
+    for k in KERNEL_IDS:
+        sim.profile_begin(k)
+        sim.step(2, c.dt)
+        ms, n = sim.profile_end()
+        if n:
+            kernels[k] = {"avg_us": 1e3 * ms / n, "gbs": ab[k] / (ms / n * 1e-3) / 1e9}
+    sim.close()
+    return {"workload": f"large film {c.nx}x{c.ny}x{c.nz} periodic in x and y, RK4 dt={c.dt} s, "
+                        f"FFT {plan['px']}x{plan['py']}x{plan['pz']}",
+            "steps": steps, "ms_per_step": 1e3 * secs / steps, "value": c.N * steps / secs,
+            "unit": "cell-updates/s", "dtype": "f32", "kernels": kernels,
+            "step_model_bytes_per_cell": 4 * sum(ab.values()) / c.N}
+
+
 def adjoint_leg() -> dict:
     """128x128x1 Ku-map rollout of 500 RK4 steps (checkpoint every 50) and its
     hand-written adjoint, FP32: forward and backward wall time."""
@@ -370,6 +406,7 @@ def main():
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cube-leg", action="store_true")
     ap.add_argument("--no-sp4-leg", action="store_true")
+    ap.add_argument("--no-periodic-leg", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--samples", type=int, default=64)
     args = ap.parse_args()
@@ -457,6 +494,8 @@ def main():
         out["adjoint"] = adjoint_leg()
     if not args.no_cube_leg:
         out["paper_table1_shape"] = cube_sweep_leg()
+    if not args.no_periodic_leg:
+        out["periodic"] = periodic_leg(max(10, args.steps // 5))
     if not args.no_sp4_leg:
         out["paper_appendix_sp4"] = sp4_leg()
     print(json.dumps(out), flush=True)
