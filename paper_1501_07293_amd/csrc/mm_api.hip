@@ -1140,7 +1140,8 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
                 const int Ly = 256 / (p.Py / std::max(1, fast_first_radix(p.Py)));
                 add(1, p.Py, p.ny, (3 * p.nz * p.hx + Ly - 1) / Ly);
                 if (!ok) break;
-                add(2, p.Pz, p.nz, (int)((p.hx * (int64_t)p.Py + 63) / 64));
+                const int zc = kspace_z_cols_for(L->esz);
+                add(2, p.Pz, p.nz, (int)((p.hx * (int64_t)p.Py + zc - 1) / zc));
             } else {
                 const int Lk = std::max(1, fast_ky_lines(p.Py));
                 add(3, p.Py, p.ny, (p.hx + Lk - 1) / Lk);

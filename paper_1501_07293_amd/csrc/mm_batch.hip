@@ -198,9 +198,9 @@ __global__ __launch_bounds__(256) void kbf_yline(BatchClass<T> c)
 }
 
 template <typename T, int PZ>
-__global__ __launch_bounds__(3 * kZCols) void kbf_kspace_z(BatchClass<T> c)
+__global__ __launch_bounds__(3 * kspace_z_cols<T>()) void kbf_kspace_z(BatchClass<T> c)
 {
-    __shared__ cpx<T> sh[kspace_z_lds_elems<PZ>()];
+    __shared__ cpx<T> sh[kspace_z_lds_elems<T, PZ>()];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int q = find_sample(c.prefix, c.nmem, tile);
     const BatchDesc& d = c.d[c.members[q]];
@@ -249,8 +249,8 @@ static bool class_launch(int kind, const BatchClass<T>& c, int tiles, int invers
         }
         return false;
     case 2:
-        if constexpr (P <= 64 && kspace_z_lds_elems<P>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
-            hipLaunchKernelGGL((kbf_kspace_z<T, P>), dim3(tiles), dim3(3 * kZCols), 0, s, c);
+        if constexpr (P <= 64 && kspace_z_lds_elems<T, P>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
+            hipLaunchKernelGGL((kbf_kspace_z<T, P>), dim3(tiles), dim3(3 * kspace_z_cols<T>()), 0, s, c);
             return true;
         }
         return false;

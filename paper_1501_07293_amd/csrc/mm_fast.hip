@@ -27,9 +27,9 @@ __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
 }
 
 template <typename T, int PZ>
-__global__ __launch_bounds__(3 * kZCols) void k_kspace_z(KzArgs a)
+__global__ __launch_bounds__(3 * kspace_z_cols<T>()) void k_kspace_z(KzArgs a)
 {
-    __shared__ cpx<T> sh[kspace_z_lds_elems<PZ>()];
+    __shared__ cpx<T> sh[kspace_z_lds_elems<T, PZ>()];
     body_kspace_z<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
@@ -130,20 +130,21 @@ bool launch_xline(const XLineArgs& a, int P, int inverse, hipStream_t s)
 template <typename T>
 bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
 {
-    const int grid = (a.ncols + kZCols - 1) / kZCols;
+    constexpr int ZC = kspace_z_cols<T>();
+    const int grid = (a.ncols + ZC - 1) / ZC;
     if (grid <= 0) return true;
     // the body indexes the spectrum and the octant with 32-bit offsets: larger
     // grids take the k-space pass with 64-bit offsets
     if (3 * a.comp_stride > INT32_MAX || 6 * a.k_cs > INT32_MAX) return false;
     switch (PZ) {
-    case 2: hipLaunchKernelGGL((k_kspace_z<T, 2>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
-    case 4: hipLaunchKernelGGL((k_kspace_z<T, 4>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
-    case 8: hipLaunchKernelGGL((k_kspace_z<T, 8>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
-    case 16: hipLaunchKernelGGL((k_kspace_z<T, 16>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
-    case 32: hipLaunchKernelGGL((k_kspace_z<T, 32>), dim3(grid), dim3(3 * kZCols), 0, s, a); return true;
+    case 2: hipLaunchKernelGGL((k_kspace_z<T, 2>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
+    case 4: hipLaunchKernelGGL((k_kspace_z<T, 4>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
+    case 8: hipLaunchKernelGGL((k_kspace_z<T, 8>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
+    case 16: hipLaunchKernelGGL((k_kspace_z<T, 16>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
+    case 32: hipLaunchKernelGGL((k_kspace_z<T, 32>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
     case 64:
         if constexpr (sizeof(T) == 4) {
-            hipLaunchKernelGGL((k_kspace_z<T, 64>), dim3(grid), dim3(3 * kZCols), 0, s, a);
+            hipLaunchKernelGGL((k_kspace_z<T, 64>), dim3(grid), dim3(3 * ZC), 0, s, a);
             return true;
         }
         return false;

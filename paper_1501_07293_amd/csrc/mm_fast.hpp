@@ -390,13 +390,13 @@ __device__ inline void body_xinv(const XLineArgs& a, int tile, cpx<T>* lds)
 }
 
 // ------------------------------------------------------------------ z k-space
-constexpr int kZCols = 64;
 
 template <typename T, int PZ>
 __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
 {
-    const int comp = threadIdx.x / kZCols, t = threadIdx.x % kZCols;
-    const int col = tile * kZCols + t;
+    constexpr int ZC = kspace_z_cols<T>();
+    const int comp = threadIdx.x / ZC, t = threadIdx.x % ZC;
+    const int col = tile * ZC + t;
     const bool ok = col < a.ncols;
     // 32-bit element offsets from the uniform base pointers (the spectrum and
     // the octant both stay below 2^31 elements)
@@ -439,7 +439,7 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
     }
     fft_reg<T, PZ>(v, tw);
 #pragma unroll
-    for (int z = 0; z < PZ; ++z) sh[(comp * PZ + z) * kZCols + t] = v[z];
+    for (int z = 0; z < PZ; ++z) sh[(comp * PZ + z) * ZC + t] = v[z];
     __syncthreads();
     // parity signs in y and z (xz, c = 2, and yz, c = 4, are odd in z)
     const T y0 = comp == 1 ? sy : (T)1, y1 = comp == 0 ? sy : (comp == 2 ? sy : (T)1);
@@ -452,9 +452,9 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
         const T k0 = y0 * (z0 ? sz : (T)1) * k0v[kz];
         const T k1 = y1 * (z1 ? sz : (T)1) * k1v[kz];
         const T k2 = y2 * (z2 ? sz : (T)1) * k2v[kz];
-        const cpx<T> m0 = sh[(0 * PZ + z) * kZCols + t];
-        const cpx<T> m1 = sh[(1 * PZ + z) * kZCols + t];
-        const cpx<T> m2 = sh[(2 * PZ + z) * kZCols + t];
+        const cpx<T> m0 = sh[(0 * PZ + z) * ZC + t];
+        const cpx<T> m1 = sh[(1 * PZ + z) * ZC + t];
+        const cpx<T> m2 = sh[(2 * PZ + z) * ZC + t];
         const cpx<T> h = {k0 * m0.re + k1 * m1.re + k2 * m2.re, k0 * m0.im + k1 * m1.im + k2 * m2.im};
         v[z] = conj(h);
     }
@@ -550,8 +550,8 @@ constexpr int xinv_lds_elems()
 {
     return (L * padded_len<P>() > 2 * L * (P / 2 + 1)) ? L * padded_len<P>() : 2 * L * (P / 2 + 1);
 }
-template <int PZ>
-constexpr int kspace_z_lds_elems() { return 3 * PZ * kZCols; }
+template <typename T, int PZ>
+constexpr int kspace_z_lds_elems() { return 3 * PZ * kspace_z_cols<T>(); }
 template <int P>
 constexpr int kspace_y_lds_elems() { return 3 * ky_lines<P>() * padded_len<P>(); }
 
