@@ -119,7 +119,8 @@ typedef struct {
                             MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
-                            0 = automatic (8 forward, 4 inverse), 4, 8 or 16 (both passes;
+                            0 = automatic (FP32 8 forward, 4 inverse; FP64 4 and 4 at
+                            1024 points), 4, 8 or 16 (both passes;
                             16 only where its LDS tile and
                             work-group fit; otherwise that pass runs the runtime-radix body) */
     int32_t images;      /* periodic axes: images on each side beyond the nearest, 0..64 */
