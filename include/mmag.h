@@ -79,7 +79,8 @@ typedef enum {
  * mm_options.images further images on each side (with an even period the two
  * images at distance n/2 count one half each, so the tensor keeps its
  * parities and its spectrum stays real).  The paper defines no periodic
- * tensor; this image window is the reading taken.  Setup cost grows as
+ * tensor; this image window is the reading taken.  A periodic x or y axis needs
+ * at least 2 cells (MM_ENOTSUP otherwise).  Setup cost grows as
  * (2 images + 1)^(periodic axes).  Single-grid handles only: mm_batch_create
  * and the adjoint entry points return MM_ENOTSUP for periodic grids. */
 #define MM_PERIODIC_X 0x80u

@@ -141,6 +141,9 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->images = o->images;
     auto pick = [pow2pad](int n, int req, bool allow1, bool periodic, int* out) -> mm_status {
         if (periodic) {  // no zero padding: the FFT runs over the period itself
+            // a one-cell period along x or y would need one-point transforms on those
+            // axes, which no pass takes; along z the one-cell-thick schedule serves it
+            if (n == 1 && !allow1) return fail(MM_ENOTSUP, "a periodic x or y axis needs at least 2 cells");
             if (req != 0 && req != n)
                 return fail(MM_EINVAL, "a periodic axis of %d cells takes padded size %d (got %d)", n, n, req);
             if (!smooth7(n)) return fail(MM_ENOTSUP, "a periodic axis needs a 7-smooth length (got %d)", n);

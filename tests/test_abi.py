@@ -185,6 +185,12 @@ def test_periodic_options_validated_without_gpu_work(lib):
     grids = (mm.Grid * 2)(mm.Grid(32, 40, 1, 5e-9), mm.Grid(40, 33, 2, 5e-9))
     assert lib.mm_batch_workspace_query(2, grids, ctypes.byref(mm.Options(0, 0, 0, 0, per, 0, 0, 0)),
                                         ctypes.byref(b)) == -5
+    for dims in ((1, 16, 4), (8, 1, 3)):          # one-cell periods along x or y
+        assert lib.mm_workspace_query(ctypes.byref(mm.Grid(*dims, 5e-9)), ctypes.byref(ok),
+                                      ctypes.byref(b)) == -5
+    assert lib.mm_workspace_query(ctypes.byref(mm.Grid(6, 5, 1, 5e-9)),
+                                  ctypes.byref(mm.Options(0, 0, 0, 0, mm.MM_PERIODIC_Z, 0, 0, 2)),
+                                  ctypes.byref(b)) == 0
 
 
 def test_profile_entry_points_reject_bad_arguments(lib):

@@ -143,3 +143,38 @@ def test_periodic_grids_refuse_the_adjoint():
         sim.rollout_ckpt(10, 1e-13, 5)
     assert e.value.status == -5 and "open boundaries" in str(e.value)
     sim.close()
+
+
+def test_periodic_with_autotune_graph_and_schedule():
+    # the autotuner keeps the period as the FFT length; graph replay and a
+    # piecewise schedule run the same periodic step as plain stepping
+    pb = problem((32, 24, 2), (True, False, False), 1)
+    tuned = make_sim(pb, "f64", autotune=True)
+    assert tuned.plan()["px"] == 32
+    plain = make_sim(pb, "f64", graph=True)
+    m0 = random_unit_m(pb.shape, seed=21)
+    for s in (tuned, plain):
+        s.set_m(m0)
+        s.step(16, 1e-13)
+    ref = oracle.rk4(pb, m0 / np.linalg.norm(m0, axis=0), 1e-13, 16)
+    for s in (tuned, plain):
+        assert np.abs(to_np(s.get_m()) - ref).max() <= 1e-11
+    rows = plain.run_schedule([(8, pb.hext, (0.0, 0.0, 0.0), 0.3)], 1e-13, 4)
+    _, m_ref = oracle.schedule(pb, ref, [(8, pb.hext, (0.0, 0.0, 0.0), 0.3)], 1e-13, 4)
+    assert np.abs(to_np(plain.get_m()) - m_ref).max() <= 1e-11
+    assert len(rows) == 2
+    tuned.close()
+    plain.close()
+
+
+def test_periodic_z_of_one_cell():
+    # a one-cell period along z: the cell is its own z neighbour (no exchange along
+    # z) and every image of a source sits in the same plane stack
+    pb = problem((6, 5, 1), (False, False, True), 2)
+    sim = make_sim(pb, "f64")
+    sim.set_m(random_unit_m(pb.shape, seed=31))
+    m = to_np(sim.get_m())
+    ref = oracle.heff_terms(pb, m)
+    for term in ("demag", "exch"):
+        assert rel_max(to_np(sim.field(term)), ref[term]) <= FIELD_TOL["f64"], term
+    sim.close()
