@@ -83,6 +83,13 @@ typedef enum {
  * at least 2 cells (MM_ENOTSUP otherwise).  Setup cost grows as
  * (2 images + 1)^(periodic axes).  Single-grid handles only: mm_batch_create
  * and the adjoint entry points return MM_ENOTSUP for periodic grids. */
+/* 3-D grids whose [3][Pz][Py] spectrum plane of one x bin fits a work-group
+ * (3 Py Pz <= 16 x threads, e.g. 256x64x4): run the y forward, z k-space and y
+ * inverse passes as one fused pass (three passes per field evaluation instead of
+ * five).  Off by default: with one work-group per x bin it measured slower than
+ * the five passes on such films (256x64x4 FP32: 0.17 against 0.10 ms per RK4
+ * step); MM_AUTOTUNE times both schedules where the fused one applies. */
+#define MM_FUSED_YZ 0x400u
 #define MM_PERIODIC_X 0x80u
 #define MM_PERIODIC_Y 0x100u
 #define MM_PERIODIC_Z 0x200u
@@ -133,7 +140,8 @@ typedef struct {
     int32_t ncomp;       /* 6 kernel spectra, or 4 (xx, xy, yy, zz) when nz == 1 */
     int32_t threads;     /* FFT work-group size in use */
     int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*hx*(py/2+1) */
-    int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1, else 5) */
+    int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1 or the fused y-z
+                            pass, else 5) */
     double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
     int32_t generic_fft; /* 1 when the runtime-radix passes are forced */
     int32_t tuned;       /* 1 when the schedule came from the autotuner */

@@ -108,6 +108,7 @@ struct Plan {
     int xl, xl_inv;    // complex lines per work-group of the specialised x passes (forward, inverse)
     int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
     int per;                   // periodic axes: bit 0 x, bit 1 y, bit 2 z
+    bool yz;                   // 3-D: the fused y-z pass replaces y forward, z k-space, y inverse
     int images;                // images on each side beyond the nearest (periodic axes)
     int64_t oct_elems;         // per component
     // workspace offsets
@@ -195,6 +196,7 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     if (!fits(nt)) return fail(MM_ENOTSUP, "padded sizes %d x %d x %d exceed the FFT work-group capacity",
                                p->Px, p->Py, p->Pz);
     p->nt = nt;
+    p->yz = p->three_d && (o->flags & MM_FUSED_YZ) && 3LL * p->Py * p->Pz <= (int64_t)kElemsPerThread * nt;
     if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8 && o->x_lines != 16)
         return fail(MM_EINVAL, "x_lines must be 0, 4, 8 or 16");
     // automatic: work-groups of at least 512 threads forward and 256 inverse (a line of
@@ -479,12 +481,43 @@ hipError_t pass_x_inverse(const PassCtx& c, T* h, hipStream_t st)
     return launch_row_c2r<T>(r, p.nt, st);
 }
 
+template <typename T>
+hipError_t pass_kspace_yz(const PassCtx& c, hipStream_t st)
+{
+    const Plan& p = c.p;
+    KyzArgs a{};
+    a.buf = c.S;
+    a.comp_stride = (int64_t)p.nz * c.plane;
+    a.zs = c.plane;
+    a.Sy = (int)c.Sy;
+    a.hx = p.hx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.Py = p.Py;
+    a.Pz = p.Pz;
+    a.ply = p.fy;
+    a.plz = p.fz;
+    a.twy = c.twy;
+    a.twz = c.twz;
+    a.kern = c.kern;
+    a.k_cs = p.oct_elems;
+    a.k_zs = (int64_t)p.hx * (p.Py / 2 + 1);
+    a.k_xs = p.Py / 2 + 1;
+    return launch_kspace_yz<T>(a, p.nt, st);
+}
+
 // Demag field (reduced, h = H/Ms) of msrc into hd: Eq. 14 with zero padding
-// (none along periodic axes).
+// (none along periodic axes); five passes, or three with the fused y-z pass.
 template <typename T>
 mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
 {
     const PassCtx c = pass_ctx(s);
+    if (c.p.yz) {
+        LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
+        LAUNCH(KSPACE, pass_kspace_yz<T>(c, st));
+        LAUNCH(KX_INV, pass_x_inverse<T>(c, hd, st));
+        return MM_OK;
+    }
     LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
     if (c.p.three_d) LAUNCH(KY_FWD, pass_y<T>(c, 0, st));
     LAUNCH(KSPACE, pass_kspace<T>(c, st));
@@ -1461,6 +1494,7 @@ mm_status time_batch_demag(mm_batch* b, double* ms_out)
 struct TuneChoice {
     int px, py, pz, generic, threads, xl;
     double ms;
+    int fused;  // 1: the fused y-z pass
 };
 
 std::mutex g_tune_mu;
@@ -1471,7 +1505,8 @@ std::string tune_key(const mm_grid* g, const mm_options* o)
 {
     std::ostringstream k;
     k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1)
-      << ":b" << ((o->flags >> 7) & 7) << "i" << o->images << ":t" << ((o->flags & MM_NEWELL) ? 1 : 0);
+      << ":b" << ((o->flags >> 7) & 7) << "i" << o->images << ":t" << ((o->flags & MM_NEWELL) ? 1 : 0)
+      << ":f" << ((o->flags & MM_FUSED_YZ) ? 1 : 0);
     return k.str();
 }
 
@@ -1484,7 +1519,8 @@ void tune_file_load()
     std::ifstream f(path);
     std::string key;
     TuneChoice c;
-    while (f >> key >> c.px >> c.py >> c.pz >> c.generic >> c.threads >> c.xl >> c.ms) g_tune_cache[key] = c;
+    while (f >> key >> c.px >> c.py >> c.pz >> c.generic >> c.threads >> c.xl >> c.ms >> c.fused)
+        g_tune_cache[key] = c;
 }
 
 void tune_file_append(const std::string& key, const TuneChoice& c)
@@ -1493,7 +1529,7 @@ void tune_file_append(const std::string& key, const TuneChoice& c)
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << key << " " << c.px << " " << c.py << " " << c.pz << " " << c.generic << " " << c.threads << " "
-      << c.xl << " " << c.ms << "\n";
+      << c.xl << " " << c.ms << " " << c.fused << "\n";
 }
 
 int next_pow2_at_least(int v)
@@ -1568,7 +1604,11 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
                         c.flags = (o->flags & ~(MM_AUTOTUNE | MM_USE_GRAPH | MM_GENERIC_FFT)) |
                                   (generic ? MM_GENERIC_FFT : 0u);
                         Plan p;
-                        if (build_plan(g, &c, &p) == MM_OK) out.push_back(c);
+                        if (build_plan(g, &c, &p) != MM_OK) continue;
+                        out.push_back(c);
+                        mm_options f = c;  // the same schedule with the fused y-z pass, where it applies
+                        f.flags |= MM_FUSED_YZ;
+                        if (!(c.flags & MM_FUSED_YZ) && build_plan(g, &f, &p) == MM_OK && p.yz) out.push_back(f);
                     }
     return out;
 }
@@ -1593,7 +1633,8 @@ mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o
         if (r != MM_OK) continue;
         ++*ncand;
         if (ms < best->ms)
-            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms};
+            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms,
+                               (c.flags & MM_FUSED_YZ) ? 1 : 0};
     }
     if (*ncand == 0) return fail(MM_ENOTSUP, "no schedule of this grid could be built");
     return MM_OK;
@@ -1656,7 +1697,8 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
         c.pz = ch.pz;
         c.threads = ch.threads;
         c.x_lines = ch.xl;
-        c.flags = (opt->flags & ~(MM_AUTOTUNE | MM_GENERIC_FFT)) | (ch.generic ? MM_GENERIC_FFT : 0u);
+        c.flags = (opt->flags & ~(MM_AUTOTUNE | MM_GENERIC_FFT)) | (ch.generic ? MM_GENERIC_FFT : 0u) |
+                  (ch.fused ? MM_FUSED_YZ : 0u);
         mm_status r = mm_create(grid, mat, &c, d_workspace, ws_bytes, stream, out);
         if (r == MM_OK) {
             (*out)->tuned = 1;
@@ -1909,7 +1951,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->ncomp = s->p.ncomp;
     out->threads = s->p.nt;
     out->spectrum_elems = (int64_t)s->p.ncomp * s->p.oct_elems;
-    out->passes = s->p.three_d ? 5 : 3;
+    out->passes = (s->p.three_d && !s->p.yz) ? 5 : 3;
     out->kernel_imag_ratio = s->imag_ratio;
     out->generic_fft = (s->flags & MM_GENERIC_FFT) ? 1 : 0;
     out->tuned = s->tuned;

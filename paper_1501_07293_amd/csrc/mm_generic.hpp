@@ -323,4 +323,73 @@ __device__ void body_kspace(const KspArgs& a, const FftPlan& pl, int tile, cpx<T
     }
 }
 
+// Fused y-z pass: x bin `tile`; LDS element (c, z, y) at c Py Pz + z Py + y.
+// The y lines of the nz valid planes are transformed (the others are zero),
+// then every z line; after the product (written conjugated) every z line and
+// the y lines of the nz planes that are kept go back through the forward
+// transform, and the conjugate of the valid window is stored.
+template <typename T, int NT>
+__device__ void body_kspace_yz(const KyzArgs& a, int tile, cpx<T>* lds)
+{
+    const int kx = tile, Py = a.Py, Pz = a.Pz, PP = Py * Pz;
+    cpx<T>* buf = (cpx<T>*)a.buf;
+    const int64_t col = (int64_t)kx * a.Sy;
+    for (int i0 = 0; i0 < 3 * PP; i0 += kStage * NT) {
+        cpx<T> v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            const int c = idx / PP, rem = idx - c * PP, z = rem / Py, y = rem - z * Py;
+            v[u] = cpx<T>{(T)0, (T)0};
+            if (idx < 3 * PP && z < a.nz && y < a.ny) v[u] = buf[c * a.comp_stride + z * a.zs + col + y];
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int idx = i0 + (int)threadIdx.x + u * NT;
+            if (idx < 3 * PP) lds[idx] = v[u];
+        }
+    }
+    __syncthreads();
+    // y lines (c, z < nz): element y at c PP + z Py + y;  z lines (c, y): at c PP + y + z Py
+    const LdsGeom gy{3 * a.nz, a.nz, Py, PP, 1};
+    const LdsGeom gz{3 * Py, Py, 1, PP, Py};
+    const cpx<T>* twy = (const cpx<T>*)a.twy;
+    const cpx<T>* twz = (const cpx<T>*)a.twz;
+    lds_fft<T, NT, false>(lds, gy, a.ply, twy, threadIdx.x);
+    lds_fft<T, NT, true>(lds, gz, a.plz, twz, threadIdx.x);
+    // Eq. 14: H~_a = sum_b K~_ab M~_b; negative ky and kz mirror into the octant
+    // with the parities of the components (xy odd in y, xz odd in z, yz odd in both)
+    const T* K = (const T*)a.kern;
+    for (int idx = threadIdx.x; idx < PP; idx += NT) {
+        int kz = idx / Py, ky = idx - kz * Py;
+        T sy = (T)1, sz = (T)1;
+        if (2 * ky > Py) {
+            ky = Py - ky;
+            sy = (T)-1;
+        }
+        if (2 * kz > Pz) {
+            kz = Pz - kz;
+            sz = (T)-1;
+        }
+        const int64_t ko = kz * a.k_zs + kx * a.k_xs + ky;
+        const T kxx = K[ko], kxy = sy * K[a.k_cs + ko], kxz = sz * K[2 * a.k_cs + ko];
+        const T kyy = K[3 * a.k_cs + ko], kyz = sy * sz * K[4 * a.k_cs + ko], kzz = K[5 * a.k_cs + ko];
+        const cpx<T> mx = lds[idx], my = lds[PP + idx], mz = lds[2 * PP + idx];
+        const cpx<T> hx = {kxx * mx.re + kxy * my.re + kxz * mz.re, kxx * mx.im + kxy * my.im + kxz * mz.im};
+        const cpx<T> hy = {kxy * mx.re + kyy * my.re + kyz * mz.re, kxy * mx.im + kyy * my.im + kyz * mz.im};
+        const cpx<T> hz = {kxz * mx.re + kyz * my.re + kzz * mz.re, kxz * mx.im + kyz * my.im + kzz * mz.im};
+        lds[idx] = conj(hx);  // inverse transform by conjugation
+        lds[PP + idx] = conj(hy);
+        lds[2 * PP + idx] = conj(hz);
+    }
+    __syncthreads();
+    lds_fft<T, NT, true>(lds, gz, a.plz, twz, threadIdx.x);
+    lds_fft<T, NT, false>(lds, gy, a.ply, twy, threadIdx.x);
+    const int VV = a.nz * a.ny;
+    for (int idx = threadIdx.x; idx < 3 * VV; idx += NT) {
+        const int c = idx / VV, rem = idx - c * VV, z = rem / a.ny, y = rem - z * a.ny;
+        buf[c * a.comp_stride + z * a.zs + col + y] = conj(lds[c * PP + z * Py + y]);
+    }
+}
+
 }  // namespace mm

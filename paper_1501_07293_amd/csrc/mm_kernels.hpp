@@ -97,6 +97,24 @@ struct KspArgs {
     int64_t k_cs, k_zs, k_xs;  // octant strides for component, kz, kx (ky is contiguous)
 };
 
+// Fused y-z pass (3-pass schedule): one work-group per x bin holds the whole
+// [3][Pz][Py] plane of that bin in LDS: y forward, z forward, Eq. 14 product,
+// z inverse, y inverse, in place in S = [3][nz][hx][Sy].  For 3-D grids whose
+// plane fits a work-group (3 Py Pz <= kElemsPerThread x threads).
+struct KyzArgs {
+    void* buf;
+    int64_t comp_stride;     // nz * hx * Sy
+    int64_t zs;              // hx * Sy: one z plane of S
+    int Sy, hx, ny, nz, Py, Pz;
+    FftPlan ply, plz;
+    const void* twy;
+    const void* twz;
+    const void* kern;        // octant [6][Pz/2+1][hx][Py/2+1]
+    int64_t k_cs, k_zs, k_xs;
+};
+template <typename T>
+hipError_t launch_kspace_yz(const KyzArgs& a, int nt, hipStream_t s);
+
 // Compile-time specialised passes for power-of-two sizes (mm_fast.hip).  Each
 // launcher returns false (and launches nothing) when no specialisation fits.
 struct YLineArgs {           // contiguous lines, transformed in place

@@ -35,6 +35,13 @@ __global__ __launch_bounds__(NT) void k_col_fft(ColArgs a)
 }
 
 template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_kspace_yz(KyzArgs a)
+{
+    __shared__ cpx<T> lds[lds_elems(NT)];
+    body_kspace_yz<T, NT>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_kspace(KspArgs a)
 {
     __shared__ cpx<T> lds[lds_elems(NT)];
@@ -125,6 +132,14 @@ hipError_t launch_kspace(const KspArgs& a, int nt, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_kspace_yz(const KyzArgs& a, int nt, hipStream_t s)
+{
+    if (a.hx <= 0) return hipSuccess;
+    MM_LAUNCH_NT(k_kspace_yz, T, a.hx, nt, s, a);
+    return hipGetLastError();
+}
+
 template hipError_t launch_row_r2c<float>(const RowR2CArgs&, int, hipStream_t);
 template hipError_t launch_row_r2c<double>(const RowR2CArgs&, int, hipStream_t);
 template hipError_t launch_row_c2r<float>(const RowC2RArgs&, int, hipStream_t);
@@ -135,5 +150,7 @@ template bool launch_kspace_fixed<float>(const KspArgs&, int, hipStream_t);
 template bool launch_kspace_fixed<double>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace<float>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace<double>(const KspArgs&, int, hipStream_t);
+template hipError_t launch_kspace_yz<float>(const KyzArgs&, int, hipStream_t);
+template hipError_t launch_kspace_yz<double>(const KyzArgs&, int, hipStream_t);
 
 }  // namespace mm
