@@ -33,6 +33,13 @@ __global__ __launch_bounds__(3 * kspace_z_cols<T>()) void k_kspace_z(KzArgs a)
     body_kspace_z<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
+template <typename T, int PZ>
+__global__ __launch_bounds__(6 * kspace_z_split_cols()) void k_kspace_z_split(KzArgs a)
+{
+    __shared__ cpx<T> sh[3 * PZ * kspace_z_split_cols()];
+    body_kspace_z_split<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
+}
+
 template <typename T, int P, bool FULL>
 __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspace_y(KyArgs a)
 {
@@ -136,6 +143,18 @@ bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
     // the body indexes the spectrum and the octant with 32-bit offsets: larger
     // grids take the k-space pass with 64-bit offsets
     if (3 * a.comp_stride > INT32_MAX || 6 * a.k_cs > INT32_MAX) return false;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 with the upper half of each z line zero: two lanes per line
+        if ((PZ == 16 || PZ == 32) && 2 * a.nz <= PZ) {
+            constexpr int SC = kspace_z_split_cols();
+            const int sgrid = (a.ncols + SC - 1) / SC;
+            if (PZ == 16)
+                hipLaunchKernelGGL((k_kspace_z_split<T, 16>), dim3(sgrid), dim3(6 * SC), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_kspace_z_split<T, 32>), dim3(sgrid), dim3(6 * SC), 0, s, a);
+            return true;
+        }
+    }
     switch (PZ) {
     case 2: hipLaunchKernelGGL((k_kspace_z<T, 2>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;
     case 4: hipLaunchKernelGGL((k_kspace_z<T, 4>), dim3(grid), dim3(3 * ZC), 0, s, a); return true;

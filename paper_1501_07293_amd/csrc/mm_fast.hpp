@@ -466,6 +466,104 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
     }
 }
 
+// Split z lines (FP64, nz <= PZ / 2): two adjacent lanes share a (column,
+// component) line, so each holds PZ / 2 values instead of PZ.  With the upper
+// half of the input zero, the even outputs are FFT_{PZ/2}(x) and the odd ones
+// FFT_{PZ/2}(x_n w^n) (w = exp(-2 pi i / PZ)): lane h = 0 forms the even, lane
+// h = 1 the odd, from the same loaded values.  After the product (conjugated),
+// the kept outputs n < PZ / 2 are x_n = A_n + w^-n B_n, A and B the inverse
+// half transforms of the even and odd products; lane 0 keeps n < PZ / 4, lane 1
+// the rest, trading PZ / 4 values across the lane pair.
+template <typename T, int PZ>
+__device__ inline void body_kspace_z_split(const KzArgs& a, int tile, cpx<T>* sh)
+{
+    constexpr int ZC = kspace_z_split_cols(), H2 = PZ / 2, Q = PZ / 4;
+    static_assert(PZ == 16 || PZ == 32, "half lines of 8 or 16 points: one radix stage");
+    const int comp = threadIdx.x / (2 * ZC), rem = threadIdx.x % (2 * ZC);
+    const int t = rem >> 1, h = rem & 1;
+    const int col = tile * ZC + t;
+    const bool ok = col < a.ncols;
+    const int zs = a.ncols;
+    const cpx<T>* tw = (const cpx<T>*)a.tw;  // length PZ
+    cpx<T>* buf = (cpx<T>*)a.buf;
+    const int base = comp * (int)a.comp_stride + (ok ? col : 0);
+    cpx<T> v[H2];
+#pragma unroll
+    for (int z = 0; z < H2; ++z) {
+        cpx<T> x = {(T)0, (T)0};
+        if (ok && z < a.nz) x = buf[base + z * zs];
+        v[z] = x;
+    }
+    const int kx = (ok ? col : 0) / a.Py;
+    int ky = (ok ? col : 0) - kx * a.Py;
+    T sy = (T)1;
+    if (2 * ky > a.Py) {
+        ky = a.Py - ky;
+        sy = (T)-1;
+    }
+    const T* K = (const T*)a.kern;
+    const int ko = kx * (int)a.k_xs + ky, cs = (int)a.k_cs, kzs = (int)a.k_zs;
+    const int c0 = comp == 0 ? 0 : (comp == 1 ? 1 : 2);
+    const int c1 = comp == 0 ? 1 : (comp == 1 ? 3 : 4);
+    const int c2 = comp == 0 ? 2 : (comp == 1 ? 4 : 5);
+    // this lane's kz values 2k + h mirror into the octant rows j = kzm / 2 of its parity
+    constexpr int NJ = H2 / 2 + 1;
+    T k0v[NJ], k1v[NJ], k2v[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int kzm = 2 * j + h, kk = ko + (kzm <= H2 ? kzm : 0) * kzs;
+        k0v[j] = K[c0 * cs + kk];
+        k1v[j] = K[c1 * cs + kk];
+        k2v[j] = K[c2 * cs + kk];
+    }
+    if (h) {
+#pragma unroll
+        for (int z = 0; z < H2; ++z) v[z] = cmul(v[z], tw[z]);
+    }
+    Dft<T, H2>::run(v);  // v[k] = X(2k + h)
+#pragma unroll
+    for (int k = 0; k < H2; ++k) sh[(comp * PZ + 2 * k + h) * ZC + t] = v[k];
+    __syncthreads();
+    const T y0 = comp == 1 ? sy : (T)1, y1 = comp == 0 ? sy : (comp == 2 ? sy : (T)1);
+    const T y2 = comp == 1 ? sy : (T)1;
+    const bool z0 = c0 == 2, z1 = c1 == 4, z2 = (c2 == 2 || c2 == 4);
+#pragma unroll
+    for (int k = 0; k < H2; ++k) {
+        const int kz = 2 * k + h, kzm = kz <= H2 ? kz : PZ - kz, j = kzm >> 1;
+        const T sz = kz <= H2 ? (T)1 : (T)-1;
+        const T k0 = y0 * (z0 ? sz : (T)1) * k0v[j];
+        const T k1 = y1 * (z1 ? sz : (T)1) * k1v[j];
+        const T k2 = y2 * (z2 ? sz : (T)1) * k2v[j];
+        const cpx<T> m0 = sh[(0 * PZ + kz) * ZC + t];
+        const cpx<T> m1 = sh[(1 * PZ + kz) * ZC + t];
+        const cpx<T> m2 = sh[(2 * PZ + kz) * ZC + t];
+        const cpx<T> hh = {k0 * m0.re + k1 * m1.re + k2 * m2.re, k0 * m0.im + k1 * m1.im + k2 * m2.im};
+        v[k] = conj(hh);  // inverse transform by conjugation
+    }
+    Dft<T, H2>::run(v);  // conj(A) (h = 0) or conj(B) (h = 1)
+    if (h) {
+#pragma unroll
+        for (int n = 0; n < H2; ++n) v[n] = cmul(v[n], tw[n]);  // conj(w^-n B_n)
+    }
+    // lane 0 keeps n < Q and takes w^-n B_n from lane 1; lane 1 keeps n >= Q and takes A_n
+    cpx<T> o[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const cpx<T> send = h ? v[q] : v[Q + q];
+        cpx<T> recv;
+        recv.re = __shfl_xor(send.re, 1);
+        recv.im = __shfl_xor(send.im, 1);
+        o[q] = h ? recv + v[Q + q] : v[q] + recv;
+    }
+    if (ok) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int n = h * Q + q;
+            if (n < a.nz) buf[base + n * zs] = conj(o[q]);
+        }
+    }
+}
+
 // ------------------------------------------------------------ y k-space (2-D)
 // One-cell-thick grids: the k-space pass runs along y.  A work-group holds L
 // x-bins, three component lines each: forward FFT (stage 1 from global memory),

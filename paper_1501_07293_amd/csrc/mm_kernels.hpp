@@ -325,6 +325,10 @@ int fast_first_radix(int P);
 constexpr int kspace_z_cols_for(size_t esz) { return esz == 8 ? 16 : 64; }
 template <typename T>
 constexpr int kspace_z_cols() { return kspace_z_cols_for(sizeof(T)); }
+// Columns per work-group of the split-line z pass (FP64, two lanes per line):
+// 32 (512-byte segments per plane; measured on the 512x512x16 film: 16 columns
+// 255 us, 32 columns 240 us, 64 columns 325 us per launch)
+constexpr int kspace_z_split_cols() { return 32; }
 int fast_ky_lines(int P);
 
 // which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse, 4 LLG stage.
