@@ -81,8 +81,8 @@ typedef enum {
  * parities and its spectrum stays real).  The paper defines no periodic
  * tensor; this image window is the reading taken.  A periodic x or y axis needs
  * at least 2 cells (MM_ENOTSUP otherwise).  Setup cost grows as
- * (2 images + 1)^(periodic axes).  Single-grid handles only: mm_batch_create
- * and the adjoint entry points return MM_ENOTSUP for periodic grids. */
+ * (2 images + 1)^(periodic axes).  Single-grid handles (including the
+ * adjoint): mm_batch_create returns MM_ENOTSUP for periodic grids. */
 /* 3-D grids whose [3][Pz][Py] spectrum plane of one x bin fits a work-group
  * (3 Py Pz <= 16 x threads, e.g. 256x64x4): run the y forward, z k-space and y
  * inverse passes as one fused pass (three passes per field evaluation instead of

@@ -128,10 +128,14 @@ __global__ __launch_bounds__(256) void k_adj_apply(AdjArgs<T> a, T cmu, T ca)
     const int j = (int)((c / a.nx) % a.ny);
     const int k = (int)(c / sz);
     // a neighbour missing at the boundary is the cell itself (Eq. 7): clamped
-    // offsets add uc - uc = 0 and keep every load unconditional
-    const int64_t dxm = i > 0 ? -1 : 0, dxp = i < a.nx - 1 ? 1 : 0;
-    const int64_t dym = j > 0 ? -sy : 0, dyp = j < a.ny - 1 ? sy : 0;
-    const int64_t dzm = k > 0 ? -sz : 0, dzp = k < a.nz - 1 ? sz : 0;
+    // offsets add uc - uc = 0 and keep every load unconditional; along a
+    // periodic axis the neighbour across the boundary is the cell at the other end
+    const bool px = a.per & 1, py = a.per & 2, pz = a.per & 4;
+    const int64_t dxm = i > 0 ? -1 : (px ? a.nx - 1 : 0), dxp = i < a.nx - 1 ? 1 : (px ? 1 - a.nx : 0);
+    const int64_t dym = j > 0 ? -sy : (py ? (a.ny - 1) * sy : 0);
+    const int64_t dyp = j < a.ny - 1 ? sy : (py ? (1 - a.ny) * sy : 0);
+    const int64_t dzm = k > 0 ? -sz : (pz ? (a.nz - 1) * sz : 0);
+    const int64_t dzp = k < a.nz - 1 ? sz : (pz ? (1 - a.nz) * sz : 0);
     T out[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {

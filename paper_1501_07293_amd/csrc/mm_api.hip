@@ -998,6 +998,7 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
     aa.alpha = la.alpha;
     aa.dku = dku;
     aa.kfac = 2.0 / (kMu0 * s->mat.Ms * s->mat.Ms);
+    aa.per = s->p.per;
     T* ms_of[4] = {nullptr, m2, m3, m4};
     T* hs_of[4] = {h1, h2, h3, h4};
 
@@ -1997,7 +1998,6 @@ mm_status mm_rollout(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, v
     if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_rollout before mm_set_m");
-    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     return s->p.prec == MM_F32 ? rollout_impl<float>(s, nsteps, dt, ckpt_every, (float*)d_ckpt)
                                : rollout_impl<double>(s, nsteps, dt, ckpt_every, (double*)d_ckpt);
 }
@@ -2006,7 +2006,6 @@ mm_status mm_adjoint_workspace_query(mm_sim* s, int64_t ckpt_every, size_t* byte
 {
     if (!s || !bytes) return fail(MM_EINVAL, "sim or bytes is NULL");
     if (ckpt_every < 1) return fail(MM_EINVAL, "ckpt_every must be >= 1");
-    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     *bytes = adj_bytes(s->p, ckpt_every);
     return MM_OK;
 }
@@ -2020,7 +2019,6 @@ mm_status mm_backward(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, 
     if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
     if (!s->has_m) return fail(MM_ESTATE, "mm_backward before mm_set_m");
-    if (s->p.per) return fail(MM_ENOTSUP, "the adjoint takes open boundaries only (periodic axes set)");
     if (adj_ws_bytes < adj_bytes(s->p, ckpt_every))
         return fail(MM_EINVAL, "adjoint workspace of %zu bytes is smaller than the %zu needed", adj_ws_bytes,
                     adj_bytes(s->p, ckpt_every));

@@ -253,6 +253,7 @@ struct AdjArgs {
     T can, cex, G, alpha;        // G = gamma Ms dt / (1 + alpha^2)
     double* dku;                 // dLoss/dKu accumulator (FP64) or nullptr
     double kfac;                 // 2 / (mu0 Ms^2)
+    int per;                     // periodic axes (bit 0 x, 1 y, 2 z): the stencil wraps
 };
 template <typename T>
 hipError_t launch_adj_renorm(const AdjArgs<T>& a, hipStream_t s);

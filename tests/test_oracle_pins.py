@@ -382,14 +382,17 @@ def _loss(pb, m0, dt, n, w):
     return float((oracle.rk4(pb, m0, dt, n) * w).sum())
 
 
-def test_oracle_adjoint_matches_finite_differences():
+@pytest.mark.parametrize("periodic", [(False, False, False), (True, True, False), (True, False, True)])
+def test_oracle_adjoint_matches_finite_differences(periodic):
     # The discrete adjoint (dLoss/dKu, dLoss/dm0) of n RK4 steps against central
-    # differences of the forward run in FP64, for a linear loss sum(w * m_n).
+    # differences of the forward run in FP64, for a linear loss sum(w * m_n); also
+    # with periodic axes (wrapped exchange, image-summed demag).
     g = np.random.default_rng(21)
     nx, ny, nz = 5, 4, 2
     ku = 500.0 + 50.0 * g.standard_normal((nz, ny, nx))
+    kw = dict(periodic=periodic, images=1)
     pb = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku,
-                        hext=tuple(mT_to_Apm([8.0, -3.0, 5.0])))
+                        hext=tuple(mT_to_Apm([8.0, -3.0, 5.0])), **kw)
     m0 = random_unit_m(pb.shape, 22)
     w = g.standard_normal(pb.shape)
     dt, n = 1e-13, 6
@@ -397,8 +400,8 @@ def test_oracle_adjoint_matches_finite_differences():
     for trial in range(3):
         v = g.standard_normal(ku.shape)
         eps = 2.0
-        pb_p = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku + eps * v, hext=pb.hext)
-        pb_m = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku - eps * v, hext=pb.hext)
+        pb_p = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku + eps * v, hext=pb.hext, **kw)
+        pb_m = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.3, ku_map=ku - eps * v, hext=pb.hext, **kw)
         fd = (_loss(pb_p, m0, dt, n, w) - _loss(pb_m, m0, dt, n, w)) / (2 * eps)
         ad = float((dku * v).sum())
         assert abs(fd - ad) <= 1e-6 * abs(ad), (trial, fd, ad)
