@@ -96,8 +96,10 @@ typedef enum {
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                7-smooth vs power of two, specialised vs runtime-radix passes,
                                256 vs 512 threads, x lines per work-group) and keeps the fastest;
-                               results are cached per process and, if MMAG_TUNE_CACHE names a
-                               file, across processes.  mm_batch_create times the batch layouts
+                               each candidate runs in a temporary workspace that mm_create
+                               allocates and frees on the device (a candidate whose workspace
+                               cannot be allocated is skipped); results are cached per process
+                               and, if MMAG_TUNE_CACHE names a file, across processes.  mm_batch_create times the batch layouts
                                (7-smooth padding, power-of-two padding with runtime-radix passes,
                                power-of-two padding with size-class passes) on one field
                                evaluation each and keeps the fastest (mm_batch_get_info reports
