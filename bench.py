@@ -443,7 +443,8 @@ def main():
     if dom is not None:
         ab = algorithmic_bytes(plan, cfg.nx, cfg.ny, cfg.nz, esz)
         achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": mm_kernel_symbol(dom, args.precision, plan),
+        out["roofline"] = {"bound": "hbm",
+                           "kernel": mm_kernel_symbol(dom, args.precision, plan, (cfg.nx, cfg.ny, cfg.nz)),
                            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                            "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": dom_ms,
@@ -462,6 +463,7 @@ def main():
         out["algorithmic_bytes"] = ab
         out["plan"] = {k: plan[k] for k in ("px", "py", "pz", "passes", "threads", "generic_fft", "x_lines",
                                             "x_lines_inv")}
+        out["plan"]["n"] = [cfg.nx, cfg.ny, cfg.nz]
         out["effective_gbs"] = step_bytes / (secs / args.steps) / 1e9
     out["sources_sha256"] = {tu: tu_digest(tu) for tu in sorted({t for _, t in KERNEL_TU})}
     out["energy_J"] = energy.tolist()
@@ -507,34 +509,52 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mm_kernel_symbol(k: str, precision: str, plan: dict) -> str:
+def grid_cells(plan: dict, workload: str = "") -> tuple | None:
+    """(nx, ny, nz) from the plan, else from a workload name ('... NXxNYxNZ cells=...')."""
+    if plan.get("n"):
+        return tuple(plan["n"])
+    import re
+    mt = re.search(r"(\d+)x(\d+)x(\d+) cells", workload)
+    return tuple(int(v) for v in mt.groups()) if mt else None
+
+
+def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None) -> str:
     """Symbol of the kernel the library launches for pass k under this plan (the
-    size-specialised one where it exists, as the library's dispatch decides)."""
+    size-specialised one where it exists, as the library's dispatch decides).
+    n = (nx, ny, nz): an axis whose cells fill more than half its FFT length (a
+    periodic axis) takes the whole-line instantiation; without n none is assumed."""
     t = "float" if precision == "f32" else "double"
     fast = not plan.get("generic_fft", 0)
     px, py, pz = plan["px"], plan["py"], plan["pz"]
+    nx, ny, nz = n if n else (0, 0, 0)
     pow2 = lambda v: v & (v - 1) == 0
+    b = lambda v: "true" if v else "false"
     x_ok = fast and pow2(px) and 16 <= px <= (2048 if t == "float" else 1024)
     y_ok = fast and pow2(py) and 16 <= py <= 2048
     if k == "llg":
         return f"mm::k_llg_stage<{t}>"
     if k in ("x_fwd", "x_inv"):
         lines = plan.get("x_lines", 8) if k == "x_fwd" else plan.get("x_lines_inv", 4)
-        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {lines}>" \
+        return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {lines}, {b(2 * nx > px)}>" \
             if x_ok else \
             f"mm::k_row_{'r2c' if k == 'x_fwd' else 'c2r'}<{t}, {plan['threads']}>"
     if k in ("y_fwd", "y_inv"):
-        return f"mm::k_yline<{t}, {py}, {'true' if k == 'y_inv' else 'false'}>" if y_ok else \
+        return f"mm::k_yline<{t}, {py}, {b(k == 'y_inv')}, {b(2 * ny > py)}>" if y_ok else \
             f"mm::k_col_fft<{t}, {plan['threads']}>"
     if plan["passes"] == 5:
         z_ok = fast and pow2(pz) and 2 <= pz <= (64 if t == "float" else 32)
         if z_ok:
+            # FP64 lines whose upper half is zero: two lanes per line
+            if t == "double" and pz in (16, 32) and 2 * nz <= pz:
+                return f"mm::k_kspace_z_split<{t}, {pz}>"
             return f"mm::k_kspace_z<{t}, {pz}>"
         if fast and pz in (128, 256, 512, 1024):
             return f"mm::k_kspace_fixed<{t}, 256, {pz}>"
         return f"mm::k_kspace<{t}, {plan['threads']}>"
+    if pz > 1:  # three passes on a 3-D grid: the fused y-z pass
+        return f"mm::k_kspace_yz<{t}, {plan['threads']}>"
     ky_ok = fast and pow2(py) and 16 <= py <= 1024
-    return f"mm::k_kspace_y<{t}, {py}>" if ky_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
+    return f"mm::k_kspace_y<{t}, {py}, {b(2 * ny > py)}>" if ky_ok else f"mm::k_kspace<{t}, {plan['threads']}>"
 
 
 def kernel_key(name: str) -> str:
@@ -586,7 +606,8 @@ def summarize_rocprof(run_dir: str, out_dir: str, command: str) -> str:
     rl = b["roofline"]
     dom = rl["kernel"]
     workload = b["config"]["workload"]
-    ab = {mm_kernel_symbol(k, b["dtype"], b["plan"]): v for k, v in b["algorithmic_bytes"].items()}
+    cells = grid_cells(b["plan"], workload)
+    ab = {mm_kernel_symbol(k, b["dtype"], b["plan"], cells): v for k, v in b["algorithmic_bytes"].items()}
     rows, kernels = [], {}
     for k in sorted(set(fetch) & set(write) - {copy}):
         f = sum(fetch[k]) / len(fetch[k])

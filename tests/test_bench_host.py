@@ -1,0 +1,105 @@
+"""Host logic of bench.py (no GPU): the per-kernel byte model of one RK4 step, the
+kernel symbols it names for the library's dispatch, the counter record it reports
+as roofline.traffic, and its refusal of several GPUs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+FILM = {"px": 1024, "py": 1024, "pz": 32, "hx": 513, "passes": 5, "threads": 256, "generic_fft": 0,
+        "x_lines": 8, "x_lines_inv": 4, "spectrum_elems": 6 * 17 * 513 * 513}
+FILM_N = (512, 512, 16)
+WORKLOAD = ("large film 512x512x16 cells=4194304 cell=3e-09 m, RK4 dt=5e-14 s, "
+            "padded FFT 1024x1024x32")
+
+
+def test_film_step_moves_1605_bytes_per_cell():
+    # per cell of the 512x512x16 film in FP32: x passes 3*4 B of m plus 3 complex
+    # values of 8 B for each of 513/512 x bins; y passes those plus 1024/512 y bins;
+    # k-space two full-y spectra and the 6 x 17 x 513 x 513 octant; LLG 21/4 vectors
+    N = 512 * 512 * 16
+    b = bench.algorithmic_bytes(FILM, *FILM_N, 4)
+    per = {k: v / N for k, v in b.items()}
+    assert per["x_fwd"] == pytest.approx(12 + 24 * 513 / 512)
+    assert per["y_fwd"] == pytest.approx(24 * 513 / 512 * 3)
+    assert per["kspace"] == pytest.approx(96 * 513 / 512 + 6 * 17 * 513 * 513 * 4 / N)
+    assert per["llg"] == pytest.approx(63.0)
+    assert b["y_inv"] == b["y_fwd"] and b["x_inv"] == b["x_fwd"]
+    assert 4 * sum(b.values()) / N == pytest.approx(1604.65, abs=0.01)
+
+
+def test_periodic_film_step_moves_759_bytes_per_cell():
+    plan = dict(FILM, px=512, py=512, hx=257, spectrum_elems=6 * 17 * 257 * 257)
+    N = 512 * 512 * 16
+    b = bench.algorithmic_bytes(plan, *FILM_N, 4)
+    assert 4 * sum(b.values()) / N == pytest.approx(759.2, abs=0.05)
+
+
+def test_kernel_symbols_follow_the_dispatch():
+    sym = lambda k, p="f32", plan=FILM, n=FILM_N: bench.mm_kernel_symbol(k, p, plan, n)
+    assert sym("x_fwd") == "mm::k_xfwd<float, 1024, 8, false>"
+    assert sym("x_inv") == "mm::k_xinv<float, 1024, 4, false>"
+    assert sym("y_fwd") == "mm::k_yline<float, 1024, false, false>"
+    assert sym("y_inv") == "mm::k_yline<float, 1024, true, false>"
+    assert sym("kspace") == "mm::k_kspace_z<float, 32>"
+    assert sym("llg") == "mm::k_llg_stage<float>"
+    # FP64 lines with a zero upper half take the two-lane z pass
+    assert sym("kspace", "f64") == "mm::k_kspace_z_split<double, 32>"
+    # periodic x and y: whole lines
+    per = dict(FILM, px=512, py=512, hx=257)
+    assert sym("x_fwd", plan=per) == "mm::k_xfwd<float, 512, 8, true>"
+    assert sym("y_inv", plan=per) == "mm::k_yline<float, 512, true, true>"
+    # runtime-radix passes, longer z lines, one cell thick, the fused y-z pass
+    gen = dict(FILM, generic_fft=1)
+    assert sym("x_fwd", plan=gen) == "mm::k_row_r2c<float, 256>"
+    assert sym("kspace", plan=gen) == "mm::k_kspace<float, 256>"
+    cube = dict(FILM, px=256, py=256, pz=256)
+    assert sym("kspace", plan=cube, n=(128, 128, 128)) == "mm::k_kspace_fixed<float, 256, 256>"
+    thin = dict(FILM, pz=1, passes=3)
+    assert sym("kspace", plan=thin, n=(512, 512, 1)) == "mm::k_kspace_y<float, 1024, false>"
+    fused = dict(FILM, px=512, py=128, pz=8, passes=3)
+    assert sym("kspace", plan=fused, n=(256, 64, 4)) == "mm::k_kspace_yz<float, 256>"
+
+
+def current_record():
+    rec = bench.recorded_traffic("mm::k_kspace_z<float, 32>", WORKLOAD)
+    if rec is None:
+        pytest.skip("the committed counter record predates the current kernel sources")
+    return rec
+
+
+def test_every_profiled_kernel_has_its_byte_model():
+    # the committed summary lists each per-step kernel under the symbol the model names
+    rec = current_record()
+    assert rec["source"].startswith("profiles/")
+    text = open(os.path.join(ROOT, rec["source"])).read()
+    for k in ("x_fwd", "y_fwd", "kspace", "y_inv", "x_inv", "llg"):
+        assert f"`{bench.mm_kernel_symbol(k, 'f32', FILM, FILM_N)}`" in text, k
+
+
+def test_traffic_record_is_dropped_when_sources_change(monkeypatch):
+    rec = current_record()
+    alg = bench.algorithmic_bytes(FILM, *FILM_N, 4)["kspace"]
+    assert 0.99 < rec["bytes"] / alg < 1.1
+    assert bench.recorded_traffic("mm::k_kspace_z<float, 32>", "another workload") is None
+    monkeypatch.setattr(bench, "tu_digest", lambda tu: "0" * 64)
+    assert bench.recorded_traffic("mm::k_kspace_z<float, 32>", WORKLOAD) is None
+
+
+def test_grid_cells_from_plan_or_workload():
+    assert bench.grid_cells({"n": [3, 4, 5]}) == (3, 4, 5)
+    assert bench.grid_cells({}, WORKLOAD) == FILM_N
+    assert bench.grid_cells({}, "no sizes here") is None
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout + r.stderr
