@@ -107,7 +107,10 @@ def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
     cz = 2 * esz                           # one complex value
     real3 = 3 * N * esz                    # m or H, three components
     half_x = 3 * nz * ny * hx * cz         # after the x pass
-    if plan["passes"] == 5:
+    if plan["passes"] == 1:                # one work-group: m in, field out, octant
+        b = {"x_fwd": 0, "y_fwd": 0, "kspace": 2 * real3 + plan["spectrum_elems"] * esz, "y_inv": 0,
+             "x_inv": 0}
+    elif plan["passes"] == 5:
         full_y = 3 * nz * Py * hx * cz     # after the y pass
         kern = plan["spectrum_elems"] * esz
         b = {"x_fwd": real3 + half_x, "y_fwd": half_x + full_y, "kspace": 2 * full_y + kern,
@@ -533,6 +536,8 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
     y_ok = fast and pow2(py) and 16 <= py <= 2048
     if k == "llg":
         return f"mm::k_llg_stage<{t}>"
+    if plan["passes"] == 1:
+        return f"mm::k_demag_1wg<{t}, {plan['threads']}>"
     if k in ("x_fwd", "x_inv"):
         lines = plan.get("x_lines", 8) if k == "x_fwd" else plan.get("x_lines_inv", 4)
         return f"mm::k_{'xfwd' if k == 'x_fwd' else 'xinv'}<{t}, {px}, {lines}, {b(2 * nx > px)}>" \

@@ -90,6 +90,16 @@ typedef enum {
  * the five passes on such films (256x64x4 FP32: 0.17 against 0.10 ms per RK4
  * step); MM_AUTOTUNE times both schedules where the fused one applies. */
 #define MM_FUSED_YZ 0x400u
+/* Grids whose padded volume of the three components fits one work-group's LDS
+ * (3 px py pz <= 16 x threads, e.g. 32x8x1 at 64x16 points): one work-group runs
+ * the whole demag evaluation (every x, y and z transform of the padded volume,
+ * the Eq. 14 product and the inverse) in a single launch instead of three or
+ * five.  Off by default: it measured slower than the multi-pass schedules (the
+ * 32x8x1 strip, FP32: 116 against 61 us per RK4 step), since one work-group runs
+ * every stage back to back.  Ignored where the volume does not fit or MM_NO_DEMAG
+ * is set; takes precedence over MM_FUSED_YZ; MM_AUTOTUNE times it where it
+ * applies. */
+#define MM_ONE_WG 0x800u
 #define MM_PERIODIC_X 0x80u
 #define MM_PERIODIC_Y 0x100u
 #define MM_PERIODIC_Z 0x200u
@@ -126,7 +136,8 @@ typedef struct {
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1).
                             A periodic axis takes n (0 or n accepted). */
     uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD |
-                            MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z */
+                            MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z |
+                            MM_FUSED_YZ | MM_ONE_WG (single-grid handles) */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (FP32 8 forward, 4 inverse; FP64 4 and 4 at
@@ -142,8 +153,8 @@ typedef struct {
     int32_t ncomp;       /* 6 kernel spectra, or 4 (xx, xy, yy, zz) when nz == 1 */
     int32_t threads;     /* FFT work-group size in use */
     int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*hx*(py/2+1) */
-    int32_t passes;      /* FFT passes per field evaluation (3 for nz == 1 or the fused y-z
-                            pass, else 5) */
+    int32_t passes;      /* FFT passes per field evaluation (1 with MM_ONE_WG in use, 3 for
+                            nz == 1 or the fused y-z pass, else 5) */
     double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
     int32_t generic_fft; /* 1 when the runtime-radix passes are forced */
     int32_t tuned;       /* 1 when the schedule came from the autotuner */

@@ -25,6 +25,7 @@ MM_NO_DEMAG, MM_USE_GRAPH, MM_GENERIC_FFT, MM_AUTOTUNE, MM_POW2_PAD = 0x1, 0x2, 
 MM_NEWELL, MM_PER_GRID_MATERIAL = 0x20, 0x40
 MM_PERIODIC_X, MM_PERIODIC_Y, MM_PERIODIC_Z = 0x80, 0x100, 0x200
 MM_FUSED_YZ = 0x400
+MM_ONE_WG = 0x800
 MM_RK4, MM_EULER = 0, 1
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
@@ -178,7 +179,8 @@ class Sim:
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
                  autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False,
                  tensor: str = "point", periodic: Sequence[bool] = (False, False, False),
-                 images: int = 0, fused_yz: bool = False, device: str = "cuda:0"):
+                 images: int = 0, fused_yz: bool = False, one_wg: bool = False,
+                 device: str = "cuda:0"):
         """periodic: per axis x, y, z, no zero padding and a wrapped exchange
         stencil; images: images on each side beyond the nearest one in the
         periodic demag sum (MM_PERIODIC_X/Y/Z)."""
@@ -197,7 +199,8 @@ class Sim:
                  | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0)
                  | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor)
                  | (MM_PERIODIC_X if periodic[0] else 0) | (MM_PERIODIC_Y if periodic[1] else 0)
-                 | (MM_PERIODIC_Z if periodic[2] else 0) | (MM_FUSED_YZ if fused_yz else 0))
+                 | (MM_PERIODIC_Z if periodic[2] else 0) | (MM_FUSED_YZ if fused_yz else 0)
+                 | (MM_ONE_WG if one_wg else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads, x_lines, images)
         nbytes = ctypes.c_size_t()

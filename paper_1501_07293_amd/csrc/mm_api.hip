@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mmag.h"
+#include "mm_demag1.hpp"
 #include "mm_kernels.hpp"
 
 using namespace mm;
@@ -109,6 +110,7 @@ struct Plan {
     int64_t S_planes, S_rows;  // spectrum [3][S_planes][hx][S_rows]
     int per;                   // periodic axes: bit 0 x, bit 1 y, bit 2 z
     bool yz;                   // 3-D: the fused y-z pass replaces y forward, z k-space, y inverse
+    bool wg1;                  // one work-group runs the whole demag evaluation (small grids)
     int images;                // images on each side beyond the nearest (periodic axes)
     int64_t oct_elems;         // per component
     // workspace offsets
@@ -197,6 +199,9 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
                                p->Px, p->Py, p->Pz);
     p->nt = nt;
     p->yz = p->three_d && (o->flags & MM_FUSED_YZ) && 3LL * p->Py * p->Pz <= (int64_t)kElemsPerThread * nt;
+    p->wg1 = (o->flags & MM_ONE_WG) && !(o->flags & MM_NO_DEMAG) &&
+             3LL * p->Px * p->Py * p->Pz <= (int64_t)kElemsPerThread * nt;
+    if (p->wg1) p->yz = false;
     if (o->x_lines != 0 && o->x_lines != 4 && o->x_lines != 8 && o->x_lines != 16)
         return fail(MM_EINVAL, "x_lines must be 0, 4, 8 or 16");
     // automatic: work-groups of at least 512 threads forward and 256 inverse (a line of
@@ -506,12 +511,45 @@ hipError_t pass_kspace_yz(const PassCtx& c, hipStream_t st)
     return launch_kspace_yz<T>(a, p.nt, st);
 }
 
+template <typename T>
+hipError_t pass_demag_1wg(const PassCtx& c, const T* m, T* hd, hipStream_t st)
+{
+    const Plan& p = c.p;
+    Demag1Args a{};
+    a.m = m;
+    a.hd = hd;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.Px = p.Px;
+    a.Py = p.Py;
+    a.Pz = p.Pz;
+    a.hx = p.hx;
+    a.plx = p.fx;
+    a.ply = p.fy;
+    a.plz = p.fz;
+    a.twx = c.twx;
+    a.twy = c.twy;
+    a.twz = c.twz;
+    a.kern = c.kern;
+    a.ncomp = p.ncomp;
+    a.k_cs = p.oct_elems;
+    a.k_zs = (int64_t)p.hx * (p.Py / 2 + 1);
+    a.k_xs = p.Py / 2 + 1;
+    return launch_demag_1wg<T>(a, p.nt, st);
+}
+
 // Demag field (reduced, h = H/Ms) of msrc into hd: Eq. 14 with zero padding
-// (none along periodic axes); five passes, or three with the fused y-z pass.
+// (none along periodic axes); five passes, three with the fused y-z pass, or one
+// work-group for the whole evaluation of a small grid.
 template <typename T>
 mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
 {
     const PassCtx c = pass_ctx(s);
+    if (c.p.wg1) {
+        LAUNCH(KSPACE, pass_demag_1wg<T>(c, msrc, hd, st));
+        return MM_OK;
+    }
     if (c.p.yz) {
         LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
         LAUNCH(KSPACE, pass_kspace_yz<T>(c, st));
@@ -1495,7 +1533,7 @@ mm_status time_batch_demag(mm_batch* b, double* ms_out)
 struct TuneChoice {
     int px, py, pz, generic, threads, xl;
     double ms;
-    int fused;  // 1: the fused y-z pass
+    int fused;  // 1: the fused y-z pass, 2: one work-group for the whole evaluation
 };
 
 std::mutex g_tune_mu;
@@ -1507,7 +1545,7 @@ std::string tune_key(const mm_grid* g, const mm_options* o)
     std::ostringstream k;
     k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1)
       << ":b" << ((o->flags >> 7) & 7) << "i" << o->images << ":t" << ((o->flags & MM_NEWELL) ? 1 : 0)
-      << ":f" << ((o->flags & MM_FUSED_YZ) ? 1 : 0);
+      << ":f" << ((o->flags & MM_FUSED_YZ) ? 1 : 0) << ((o->flags & MM_ONE_WG) ? 1 : 0);
     return k.str();
 }
 
@@ -1610,6 +1648,9 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
                         mm_options f = c;  // the same schedule with the fused y-z pass, where it applies
                         f.flags |= MM_FUSED_YZ;
                         if (!(c.flags & MM_FUSED_YZ) && build_plan(g, &f, &p) == MM_OK && p.yz) out.push_back(f);
+                        mm_options w = c;  // one work-group for the whole evaluation, where it fits
+                        w.flags = (w.flags & ~MM_FUSED_YZ) | MM_ONE_WG;
+                        if (!(c.flags & MM_ONE_WG) && build_plan(g, &w, &p) == MM_OK && p.wg1) out.push_back(w);
                     }
     return out;
 }
@@ -1635,7 +1676,7 @@ mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o
         ++*ncand;
         if (ms < best->ms)
             *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms,
-                               (c.flags & MM_FUSED_YZ) ? 1 : 0};
+                               (c.flags & MM_ONE_WG) ? 2 : ((c.flags & MM_FUSED_YZ) ? 1 : 0)};
     }
     if (*ncand == 0) return fail(MM_ENOTSUP, "no schedule of this grid could be built");
     return MM_OK;
@@ -1699,7 +1740,7 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
         c.threads = ch.threads;
         c.x_lines = ch.xl;
         c.flags = (opt->flags & ~(MM_AUTOTUNE | MM_GENERIC_FFT)) | (ch.generic ? MM_GENERIC_FFT : 0u) |
-                  (ch.fused ? MM_FUSED_YZ : 0u);
+                  (ch.fused == 1 ? MM_FUSED_YZ : 0u) | (ch.fused == 2 ? MM_ONE_WG : 0u);
         mm_status r = mm_create(grid, mat, &c, d_workspace, ws_bytes, stream, out);
         if (r == MM_OK) {
             (*out)->tuned = 1;
@@ -1952,7 +1993,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->ncomp = s->p.ncomp;
     out->threads = s->p.nt;
     out->spectrum_elems = (int64_t)s->p.ncomp * s->p.oct_elems;
-    out->passes = (s->p.three_d && !s->p.yz) ? 5 : 3;
+    out->passes = s->p.wg1 ? 1 : ((s->p.three_d && !s->p.yz) ? 5 : 3);
     out->kernel_imag_ratio = s->imag_ratio;
     out->generic_fft = (s->flags & MM_GENERIC_FFT) ? 1 : 0;
     out->tuned = s->tuned;

@@ -5,6 +5,7 @@
 // the radix schedule (by reference, so a schedule held in memory is indexed in
 // place rather than copied into registers).
 #pragma once
+#include "mm_demag1.hpp"
 #include "mm_fft.hpp"
 #include "mm_kernels.hpp"
 
@@ -389,6 +390,85 @@ __device__ void body_kspace_yz(const KyzArgs& a, int tile, cpx<T>* lds)
     for (int idx = threadIdx.x; idx < 3 * VV; idx += NT) {
         const int c = idx / VV, rem = idx - c * VV, z = rem / a.ny, y = rem - z * a.ny;
         buf[c * a.comp_stride + z * a.zs + col + y] = conj(lds[c * PP + z * Py + y]);
+    }
+}
+
+// Eq. 14 for a whole small grid in one work-group: the padded volume
+// [3][Pz][Py][Px] (x fastest) of complex values sits in LDS; m enters as the real
+// part (zero padding around it), every x, y and z line is transformed, the
+// product with the real symmetric spectrum is taken at every (kx, ky, kz) with
+// negative frequencies mirrored into the octant (xy odd in x and y, xz in x and z,
+// yz in y and z), and the conjugated product goes back through the forward
+// transforms; the real part of the valid window is the field.
+template <typename T, int NT>
+__device__ void body_demag_1wg(const Demag1Args& a, cpx<T>* lds)
+{
+    const int Px = a.Px, Py = a.Py, Pz = a.Pz;
+    const int A = Px * Py, V = A * Pz;
+    const T* m = (const T*)a.m;
+    const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+    for (int idx = threadIdx.x; idx < 3 * V; idx += NT) {
+        const int c = idx / V, r = idx - c * V, z = r / A, r2 = r - z * A, y = r2 / Px, x = r2 - y * Px;
+        T v = (T)0;
+        if (x < a.nx && y < a.ny && z < a.nz) v = m[c * N + ((int64_t)z * a.ny + y) * a.nx + x];
+        lds[idx] = cpx<T>{v, (T)0};
+    }
+    __syncthreads();
+    // x lines: 3 Pz Py of them, contiguous; y lines: (c, z, x), stride Px;
+    // z lines: (c, y, x), stride Px Py
+    const LdsGeom gx{3 * Pz * Py, 3 * Pz * Py, Px, 0, 1};
+    const LdsGeom gy{3 * Pz * Px, Px, 1, A, Px};
+    const LdsGeom gz{3 * A, A, 1, V, A};
+    const cpx<T>* twx = (const cpx<T>*)a.twx;
+    const cpx<T>* twy = (const cpx<T>*)a.twy;
+    const cpx<T>* twz = (const cpx<T>*)a.twz;
+    lds_fft<T, NT, false>(lds, gx, a.plx, twx, threadIdx.x);
+    lds_fft<T, NT, true>(lds, gy, a.ply, twy, threadIdx.x);
+    if (Pz > 1) lds_fft<T, NT, true>(lds, gz, a.plz, twz, threadIdx.x);
+    const T* K = (const T*)a.kern;
+    const bool six = a.ncomp == 6;
+    for (int idx = threadIdx.x; idx < V; idx += NT) {
+        int kz = idx / A;
+        const int r2 = idx - kz * A;
+        int ky = r2 / Px, kx = r2 - ky * Px;
+        T sx = (T)1, sy = (T)1, sz = (T)1;
+        if (2 * kx > Px) {
+            kx = Px - kx;
+            sx = (T)-1;
+        }
+        if (2 * ky > Py) {
+            ky = Py - ky;
+            sy = (T)-1;
+        }
+        if (2 * kz > Pz) {
+            kz = Pz - kz;
+            sz = (T)-1;
+        }
+        const int64_t ko = kz * a.k_zs + kx * a.k_xs + ky;
+        const T kxx = K[ko];
+        const T kxy = sx * sy * K[a.k_cs + ko];
+        const T kxz = six ? sx * sz * K[2 * a.k_cs + ko] : (T)0;
+        const T kyy = K[(six ? 3 : 2) * a.k_cs + ko];
+        const T kyz = six ? sy * sz * K[4 * a.k_cs + ko] : (T)0;
+        const T kzz = K[(six ? 5 : 3) * a.k_cs + ko];
+        const cpx<T> mx = lds[idx], my = lds[V + idx], mz = lds[2 * V + idx];
+        const cpx<T> hx = {kxx * mx.re + kxy * my.re + kxz * mz.re, kxx * mx.im + kxy * my.im + kxz * mz.im};
+        const cpx<T> hy = {kxy * mx.re + kyy * my.re + kyz * mz.re, kxy * mx.im + kyy * my.im + kyz * mz.im};
+        const cpx<T> hz = {kxz * mx.re + kyz * my.re + kzz * mz.re, kxz * mx.im + kyz * my.im + kzz * mz.im};
+        lds[idx] = conj(hx);  // inverse transform by conjugation
+        lds[V + idx] = conj(hy);
+        lds[2 * V + idx] = conj(hz);
+    }
+    __syncthreads();
+    if (Pz > 1) lds_fft<T, NT, true>(lds, gz, a.plz, twz, threadIdx.x);
+    lds_fft<T, NT, true>(lds, gy, a.ply, twy, threadIdx.x);
+    lds_fft<T, NT, false>(lds, gx, a.plx, twx, threadIdx.x);
+    // Re(conj(w)) = Re(w): the real part of the valid window is the field
+    T* hd = (T*)a.hd;
+    for (int64_t idx = threadIdx.x; idx < 3 * N; idx += NT) {
+        const int64_t c = idx / N, r = idx - c * N;
+        const int x = (int)(r % a.nx), y = (int)((r / a.nx) % a.ny), z = (int)(r / ((int64_t)a.nx * a.ny));
+        hd[idx] = lds[c * V + (z * Py + y) * Px + x].re;
     }
 }
 

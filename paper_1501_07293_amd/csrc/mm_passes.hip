@@ -42,6 +42,13 @@ __global__ __launch_bounds__(NT) void k_kspace_yz(KyzArgs a)
 }
 
 template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_demag_1wg(Demag1Args a)
+{
+    __shared__ cpx<T> lds[lds_elems(NT)];
+    body_demag_1wg<T, NT>(a, lds);
+}
+
+template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_kspace(KspArgs a)
 {
     __shared__ cpx<T> lds[lds_elems(NT)];
@@ -140,6 +147,15 @@ hipError_t launch_kspace_yz(const KyzArgs& a, int nt, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_demag_1wg(const Demag1Args& a, int nt, hipStream_t s)
+{
+    // the padded volume of the three components must fit the work-group's LDS
+    if (3LL * a.Px * a.Py * a.Pz > (int64_t)kElemsPerThread * nt) return hipErrorInvalidValue;
+    MM_LAUNCH_NT(k_demag_1wg, T, 1, nt, s, a);
+    return hipGetLastError();
+}
+
 template hipError_t launch_row_r2c<float>(const RowR2CArgs&, int, hipStream_t);
 template hipError_t launch_row_r2c<double>(const RowR2CArgs&, int, hipStream_t);
 template hipError_t launch_row_c2r<float>(const RowC2RArgs&, int, hipStream_t);
@@ -152,5 +168,7 @@ template hipError_t launch_kspace<float>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace<double>(const KspArgs&, int, hipStream_t);
 template hipError_t launch_kspace_yz<float>(const KyzArgs&, int, hipStream_t);
 template hipError_t launch_kspace_yz<double>(const KyzArgs&, int, hipStream_t);
+template hipError_t launch_demag_1wg<float>(const Demag1Args&, int, hipStream_t);
+template hipError_t launch_demag_1wg<double>(const Demag1Args&, int, hipStream_t);
 
 }  // namespace mm

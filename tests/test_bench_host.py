@@ -65,6 +65,15 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("kspace", plan=thin, n=(512, 512, 1)) == "mm::k_kspace_y<float, 1024, false>"
     fused = dict(FILM, px=512, py=128, pz=8, passes=3)
     assert sym("kspace", plan=fused, n=(256, 64, 4)) == "mm::k_kspace_yz<float, 256>"
+    one = dict(FILM, px=64, py=16, pz=1, hx=33, passes=1)
+    assert sym("kspace", plan=one, n=(32, 8, 1)) == "mm::k_demag_1wg<float, 256>"
+
+
+def test_one_work_group_model_reads_m_and_octant_once():
+    plan = dict(FILM, px=64, py=16, pz=1, hx=33, passes=1, spectrum_elems=4 * 1 * 33 * 9)
+    b = bench.algorithmic_bytes(plan, 32, 8, 1, 4)
+    assert b["kspace"] == 2 * 3 * 256 * 4 + 4 * 33 * 9 * 4
+    assert b["x_fwd"] == b["y_fwd"] == b["y_inv"] == b["x_inv"] == 0
 
 
 def current_record():
