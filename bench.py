@@ -125,6 +125,47 @@ def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
     return b
 
 
+def smooth7(v: int) -> bool:
+    for f in (2, 3, 5, 7):
+        while v % f == 0:
+            v //= f
+    return v == 1
+
+
+def pad_length(n: int, pow2: bool) -> int:
+    """The library's automatic padded length of an open axis of n > 1 cells: the
+    smallest power of two >= 2n - 1, or 2n if 7-smooth, else the smallest
+    7-smooth length >= 2n - 1."""
+    if pow2:
+        p = 1
+        while p < 2 * n - 1:
+            p *= 2
+        return p
+    if smooth7(2 * n):
+        return 2 * n
+    p = 2 * n - 1
+    while not smooth7(p):
+        p += 1
+    return p
+
+
+def grid_plan(nx: int, ny: int, nz: int, pow2: bool) -> dict:
+    """Padded sizes, stored x bins, schedule and octant size of one open-boundary grid."""
+    px, py = pad_length(nx, pow2), pad_length(ny, pow2)
+    pz = 1 if nz == 1 else pad_length(nz, pow2)
+    hx = px // 2 + 1
+    ncomp = 6 if pz > 1 else 4
+    return {"px": px, "py": py, "pz": pz, "hx": hx, "passes": 5 if pz > 1 else 3,
+            "spectrum_elems": ncomp * (pz // 2 + 1) * hx * (py // 2 + 1)}
+
+
+def batch_step_bytes(grids, pow2: bool, esz: int = 4) -> int:
+    """Algorithmic bytes of one RK4 step of a batch: every grid's passes and LLG
+    stage by the single-grid model, four field evaluations each."""
+    return sum(4 * sum(algorithmic_bytes(grid_plan(nx, ny, nz, pow2), nx, ny, nz, esz).values())
+               for nx, ny, nz in grids)
+
+
 def run_gpu(args, cfg, precision: str, steps: int, warmup: int, profile: bool):
     import torch
 
@@ -208,8 +249,10 @@ def batched_leg(steps: int, autotune: bool, warmup: int = 2) -> dict:
     b.step(steps, c.dt)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_bytes = batch_step_bytes(grids, bool(info["pow2_pad"]))
     out = {"grids": len(grids), "cells": b.cells, "steps": steps, "ms_per_step": 1e3 * dt / steps,
            "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32",
+           "step_model_bytes": step_bytes, "effective_gbs": step_bytes / (dt / steps) / 1e9,
            "padding": "power of two" if info["pow2_pad"] else "7-smooth",
            "passes": "size classes" if info["size_classes"] else "runtime radix",
            "autotuned": bool(info["tuned"]), "layouts_timed": info["candidates"]}

@@ -112,3 +112,19 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout + r.stderr
+
+
+def test_batch_step_model_sums_the_single_grid_model():
+    # 32x8x1 with power-of-two padding: 64 x 16 points, 33 x bins, 4 kernel spectra
+    N = 256
+    real3, half_x, kern = 3 * N * 4, 3 * 8 * 33 * 8, 4 * 33 * 9 * 4
+    one = (real3 + half_x) * 2 + (2 * half_x + kern) + 21 * 3 * N * 4 // 4
+    assert bench.batch_step_bytes([(32, 8, 1)], pow2=True) == 4 * one
+    # a two-cell-thick grid takes the five-pass model with pz = 4
+    p = bench.grid_plan(33, 47, 2, pow2=True)
+    assert (p["px"], p["py"], p["pz"], p["passes"]) == (128, 128, 4, 5)
+    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], pow2=True) == \
+        4 * one + 4 * sum(bench.algorithmic_bytes(p, 33, 47, 2, 4).values())
+    # 7-smooth padding: 2n when 7-smooth (2 x 33 = 66 = 2 3 11 is not: 65 = 5 13 no, 66..70: 70)
+    assert bench.pad_length(33, False) == 70 and bench.pad_length(32, False) == 64
+    assert bench.pad_length(47, True) == 128 and bench.pad_length(2, True) == 4
