@@ -236,3 +236,46 @@ def test_batch_per_grid_materials_validated_without_gpu_work(lib):
     assert b"grid 1" in lib.mm_last_error()
     assert lib.mm_batch_create(2, grids, None, None, ctypes.byref(o), None, 0, None, ctypes.byref(h)) == -1
 
+
+
+def test_binding_constants_match_the_header():
+    # every MM_ flag and enum value the header defines, the binding defines alike;
+    # the option flags are distinct single bits
+    text = open(HEADER).read()
+    flags = {k: int(v, 16) for k, v in re.findall(r"#define (MM_[A-Z0-9_]+) (0x[0-9a-fA-F]+)u", text)}
+    assert len(flags) >= 12
+    for k, v in flags.items():
+        assert getattr(mm, k) == v, k
+        assert v & (v - 1) == 0, k
+    assert len(set(flags.values())) == len(flags)
+    enums = dict(re.findall(r"\b(MM_F32|MM_F64|MM_RK4|MM_EULER)\s*=\s*(\d+)", text))
+    assert {k: getattr(mm, k) for k in enums} == {k: int(v) for k, v in enums.items()}
+
+
+def test_option_and_plan_structs_match_the_header():
+    # the ctypes mirrors list the C structs' fields in order, with the same widths
+    text = open(HEADER).read()
+
+    def fields(name):
+        end = text.index("} " + name + ";")
+        body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        out = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            typ, names = decl.split(None, 1)
+            for n in names.split(","):
+                n = n.strip()
+                m = re.match(r"(\w+)(?:\[(\d+)\])?", n)
+                out.append((m.group(1), typ))
+        return out
+
+    width = {"int32_t": 4, "uint32_t": 4, "int64_t": 8, "double": 8, "size_t": 8}
+    for cname, py in (("mm_options", mm.Options), ("mm_plan_info", mm.PlanInfo),
+                      ("mm_grid", mm.Grid), ("mm_material", mm.Material)):
+        c = fields(cname)
+        assert [n for n, _ in c] == [n for n, _ in py._fields_], cname
+        for (n, typ), (_, ct) in zip(c, py._fields_):
+            assert ctypes.sizeof(ct) == width[typ], (cname, n)
