@@ -269,13 +269,16 @@ def test_option_and_plan_structs_match_the_header():
             for n in names.split(","):
                 n = n.strip()
                 m = re.match(r"(\w+)(?:\[(\d+)\])?", n)
-                out.append((m.group(1), typ))
+                out.append((m.group(1), typ, int(m.group(2) or 1)))
         return out
 
     width = {"int32_t": 4, "uint32_t": 4, "int64_t": 8, "double": 8, "size_t": 8}
-    for cname, py in (("mm_options", mm.Options), ("mm_plan_info", mm.PlanInfo),
-                      ("mm_grid", mm.Grid), ("mm_material", mm.Material)):
+    for cname, py, same_names in (("mm_options", mm.Options, True), ("mm_plan_info", mm.PlanInfo, True),
+                                  ("mm_grid", mm.Grid, True), ("mm_material", mm.Material, True),
+                                  ("mm_segment", mm.Segment, True), ("mm_batch_info", mm.BatchInfo, False)):
         c = fields(cname)
-        assert [n for n, _ in c] == [n for n, _ in py._fields_], cname
-        for (n, typ), (_, ct) in zip(c, py._fields_):
-            assert ctypes.sizeof(ct) == width[typ], (cname, n)
+        assert len(c) == len(py._fields_), cname
+        if same_names:
+            assert [n for n, _, _ in c] == [n for n, _ in py._fields_], cname
+        for (n, typ, count), (_, ct) in zip(c, py._fields_):
+            assert ctypes.sizeof(ct) == width[typ] * count, (cname, n)
