@@ -73,6 +73,8 @@ def _load():
         lib.or_rk4.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64]
         lib.or_energy.argtypes = [pp, dp, dp, dp]
         lib.or_mean_m.argtypes = [pp, dp, dp]
+        lib.or_max_torque.argtypes = [pp, dp, dp]
+        lib.or_max_torque.restype = ctypes.c_double
         lib.or_rk4_adjoint.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64, dp, dp, dp]
         lib.or_euler.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int64]
         for f in ("or_tensor_point", "or_tensor_table", "or_tensor_table_periodic", "or_demag",
@@ -318,6 +320,14 @@ def mean_m(pb: Problem, m) -> np.ndarray:
     out = np.zeros(3)
     _load().or_mean_m(ctypes.byref(p), _dptr(m), _dptr(out))
     return out
+
+
+def max_torque(pb: Problem, m) -> float:
+    """max over cells of |m x H_eff| in A/m (H_eff of Eq. 3 at m)."""
+    m = _m(pb, m)
+    tab = pb.table() if pb.demag else np.zeros(1)
+    p = pb._params()
+    return float(_load().or_max_torque(ctypes.byref(p), _dptr(m), _dptr(tab)))
 
 
 def rk4_adjoint(pb: Problem, m0, dt: float, nsteps: int, lam_final):

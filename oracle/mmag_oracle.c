@@ -402,6 +402,26 @@ void or_mean_m(const or_params *p, const double *m, double out[3])
     }
 }
 
+/* Largest torque over the cells: max_c |m_c x H_eff,c| in A/m, with H_eff the
+ * full effective field of Eq. 3 at m (the quantity whose vanishing marks an
+ * equilibrium of Eq. 2; used as a relaxation criterion).                     */
+double or_max_torque(const or_params *p, const double *m, const double *table)
+{
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double *h = (double *)malloc(sizeof(double) * 3 * N);
+    or_heff(p, m, table, NULL, NULL, NULL, h);
+    double best = 0.0;
+    for (int64_t c = 0; c < N; ++c) {
+        double mx = m[c], my = m[N + c], mz = m[2 * N + c];
+        double hx = h[c], hy = h[N + c], hz = h[2 * N + c];
+        double tx = my * hz - mz * hy, ty = mz * hx - mx * hz, tz = mx * hy - my * hx;
+        double t = sqrt(tx * tx + ty * ty + tz * tz);
+        if (t > best) best = t;
+    }
+    free(h);
+    return best;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint of nsteps RK4 steps with renormalisation (test infrastructure
  * for the gradient of a loss of the final state).  With the effective field

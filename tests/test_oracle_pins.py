@@ -579,3 +579,63 @@ def test_newell_approaches_point_tensor_at_fourth_order():
             gaps.append(np.abs(kn - kp).max() / np.abs(kp).max())
         r1, r2 = gaps[0] / gaps[1], gaps[1] / gaps[2]
         assert 13 < r1 < 19 and 14 < r2 < 18, (u, gaps)
+
+
+# ------------------------------------------------------- mean of m on many cells
+def test_mean_m_of_a_plane_wave_along_x_vanishes():
+    # m = (cos 2 pi i/nx, sin 2 pi i/nx, 0): the roots of unity sum to zero along every
+    # row, so <m> = 0 on any ny x nz (a cell counted twice or a wrong stride breaks it).
+    nx, ny, nz = 6, 5, 3
+    pb = oracle.Problem(nx, ny, nz, 3e-9)
+    th = 2 * np.pi * np.arange(nx) / nx
+    m = np.zeros(pb.shape)
+    m[0] = np.cos(th)[None, None, :]
+    m[1] = np.sin(th)[None, None, :]
+    assert np.abs(oracle.mean_m(pb, m)).max() < 1e-15
+
+
+def test_mean_m_of_cell_blocks_counts_every_cell_once():
+    # 4 x 3 x 2 cells: plane k = 0 along +z (12 cells), plane k = 1 along +x for
+    # i < 2 (6 cells) and along -y for i >= 2 (6 cells): <m> = (1/4, -1/4, 1/2).
+    # Each component has its own value, so a planar/interleaved mix-up or a
+    # divisor of one plane instead of all cells gives a different result.
+    nx, ny, nz = 4, 3, 2
+    pb = oracle.Problem(nx, ny, nz, 3e-9)
+    m = np.zeros(pb.shape)
+    m[2, 0] = 1.0
+    m[0, 1, :, :2] = 1.0
+    m[1, 1, :, 2:] = -1.0
+    assert np.array_equal(oracle.mean_m(pb, m), np.array([0.25, -0.25, 0.5]))
+
+
+# ------------------------------------------------------------ max torque |m x H|
+def test_max_torque_of_cells_in_a_uniform_field():
+    # No exchange, no anisotropy, no demag: the torque of cell c is |H| sin(theta_c),
+    # theta_c its angle to H_ext; the largest angle below pi/2 wins.
+    H = 3.0e4
+    pb = oracle.Problem(5, 2, 1, 3e-9, A=0.0, Ku=0.0, demag=False, hext=(0.0, 0.0, H))
+    th = np.array([0.1, 0.4, 1.2, 0.7, 2.9, 0.0, 3.1, 0.2, 1.0, 0.5]).reshape(1, 2, 5)
+    m = np.stack([np.sin(th), np.zeros_like(th), np.cos(th)])
+    assert np.isclose(oracle.max_torque(pb, m), H * np.sin(1.2), rtol=1e-14)
+
+
+def test_max_torque_of_a_single_cell_ignores_its_own_demag():
+    # One cell: H_d = -M/3 is parallel to m (torque-free), so only H_ext acts.
+    H = 5.0e4
+    pb = oracle.Problem(1, 1, 1, 5e-9, Ku=0.0, hext=(H, 0.0, 0.0))
+    th = 0.83
+    m = np.array([np.cos(th), np.sin(th), 0.0]).reshape(3, 1, 1, 1)
+    assert np.isclose(oracle.max_torque(pb, m), H * np.sin(th), rtol=1e-12)
+
+
+def test_max_torque_sets_the_largest_llg_rate():
+    # For a unit m the two terms of Eq. 2 are orthogonal and of equal size, so
+    # |dm/dt| = gamma / sqrt(1 + alpha^2) |m x H| cell by cell, with every term of
+    # the effective field present.
+    pb = oracle.Problem(7, 5, 3, 4e-9, Ku=3.0e4, alpha=0.35,
+                        hext=tuple(mT_to_Apm([8.0, -3.0, 5.0])))
+    m = random_unit_m(pb.shape, 12)
+    f = oracle.llg_rhs(pb, m, oracle.heff_terms(pb, m)["eff"])
+    rate = np.sqrt((f * f).sum(axis=0)).max()
+    assert np.isclose(oracle.max_torque(pb, m) * pb.gamma / np.sqrt(1 + pb.alpha ** 2), rate,
+                      rtol=1e-12)
