@@ -66,6 +66,13 @@ typedef enum {
                                the smallest 7-smooth size), so the size-specialised passes apply;
                                a batch created with it runs those passes, one launch per padded
                                size per pass */
+/* Automatic padded sizes are the smallest length >= 2n-1 that has a
+ * size-specialised pass: along x and y the powers of two and 96, 160, 192, 224
+ * (mixed-radix 32 q, q = 3, 5, 6, 7), along z the powers of two.  Any such
+ * length gives the same linear convolution (it is >= 2n-1); for grids of 33 to
+ * 112 cells it pads less than MM_POW2_PAD (e.g. 33 -> 96 instead of 128), and a
+ * batch created with it runs the size-class passes.  Excludes MM_POW2_PAD. */
+#define MM_FAST_PAD 0x1000u
 #define MM_NEWELL 0x20u    /* demag with Newell's cell-averaged tensor (Newell, Williams and Dunlop,
                                J. Geophys. Res. 98, 9551, 1993; cited in Sec. 2.3) instead of the
                                point-field tensor of Eqs. 10-11; see mm_demag_tensor_newell */
@@ -105,11 +112,15 @@ typedef enum {
 #define MM_PERIODIC_Z 0x200u
 #define MM_AUTOTUNE 0x8u    /* mm_create times the candidate schedules of this grid (padded sizes
                                7-smooth vs power of two, specialised vs runtime-radix passes,
-                               256 vs 512 threads, x lines per work-group) and keeps the fastest;
-                               each candidate runs in a temporary workspace that mm_create
-                               allocates and frees on the device (a candidate whose workspace
-                               cannot be allocated is skipped); results are cached per process
-                               and, if MMAG_TUNE_CACHE names a file, across processes.  mm_batch_create times the batch layouts
+                               256 vs 512 threads, x lines per work-group, fused y-z pass, one
+                               work-group) and keeps the fastest.  The candidates run in the
+                               caller's workspace when it holds every one of them (the size
+                               mm_workspace_query returns with this flag), else in one temporary
+                               workspace that mm_create allocates and frees; the kernel spectrum
+                               is built once per candidate padded size.  Results are cached per
+                               process and, if MMAG_TUNE_CACHE names a file, across processes,
+                               keyed by the GPU (architecture, name, compute units), the grid
+                               and the options.  mm_batch_create times the batch layouts
                                (7-smooth padding, power-of-two padding with runtime-radix passes,
                                power-of-two padding with size-class passes) on one field
                                evaluation each and keeps the fastest (mm_batch_get_info reports
@@ -135,7 +146,7 @@ typedef struct {
                             smallest 7-smooth size >= 2n-1; pz = 1 when nz = 1).  An explicit
                             size must be 7-smooth and >= 2n-1 (pz = 1 only when nz = 1).
                             A periodic axis takes n (0 or n accepted). */
-    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD |
+    uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD | MM_FAST_PAD |
                             MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z |
                             MM_FUSED_YZ | MM_ONE_WG (single-grid handles) */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
@@ -248,6 +259,14 @@ mm_status mm_get_energy(mm_sim* sim, double out[5]);
 /* Mean of m over the cells (FP64). */
 mm_status mm_get_mean_m(mm_sim* sim, double out[3]);
 
+/* The largest torque over the cells, max |m x H_eff| in A/m (m the unit vector,
+ * H_eff the full effective field of Eq. 3 at the current m), reduced in FP64
+ * from the working-precision state in the same pass as the energies.  It
+ * vanishes exactly at an equilibrium of Eq. 2 and serves as a relaxation
+ * criterion (e.g. max |m x H_eff| / Ms < 1e-5).  Synchronises.  MM_ENONFINITE
+ * if m holds NaN or Inf. */
+mm_status mm_get_max_torque(mm_sim* sim, double* out);
+
 mm_status mm_get_plan(mm_sim* sim, mm_plan_info* out);
 
 /* Kernel-spectrum octant [ncomp][pz/2+1][hx][py/2+1] (ky fastest), working
@@ -289,6 +308,10 @@ mm_status mm_batch_set_stream(mm_batch* b, void* stream);
 mm_status mm_batch_set_m(mm_batch* b, const void* m, int on_device);
 mm_status mm_batch_get_m(mm_batch* b, void* out, int on_device);
 mm_status mm_batch_step(mm_batch* b, int64_t nsteps, double dt);
+/* One term of every grid's effective field (Eq. 3; terms as mm_get_field) at
+ * the current m, A/m, laid out grid by grid like m.  The demag term runs the
+ * batch's own passes (the layout mm_batch_step uses). */
+mm_status mm_batch_get_field(mm_batch* b, int32_t term, void* out, int on_device);
 mm_status mm_batch_cells(mm_batch* b, int64_t* total_cells);
 
 /* The layout a batch runs on (for MM_AUTOTUNE, the one that won). */
@@ -300,7 +323,7 @@ typedef struct {
                                 pass); 0: the runtime-radix passes (one launch per pass) */
     int32_t tuned;           /* 1: chosen by MM_AUTOTUNE */
     int32_t tune_candidates; /* layouts timed */
-    int32_t reserved;
+    int32_t fast_pad;        /* 1: padded sizes from the specialised set (MM_FAST_PAD) */
     double tuned_ms;         /* the winner's time of one field evaluation of every grid, ms */
     size_t workspace_bytes;  /* device bytes the layout uses */
 } mm_batch_info;
@@ -316,19 +339,35 @@ mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out);
  * mm_rollout: nsteps RK4 steps of dt from the current m, like mm_step, and
  *   stores the state at the start of every segment of ckpt_every steps into
  *   d_ckpt (device, caller-owned, ceil(nsteps/ckpt_every) x [3][nz][ny][nx]).
- * mm_adjoint_workspace_query: device bytes mm_backward needs for ckpt_every.
+ *   The steps replay captured hipGraphs (whatever MM_USE_GRAPH says).
+ * mm_adjoint_workspace_query: device bytes mm_backward needs for ckpt_every:
+ *   8 state-sized vectors per step of a segment (its stage states and stage
+ *   fields, stored while the segment is recomputed from its checkpoint), 7
+ *   working vectors and N doubles, so memory grows with ckpt_every (about
+ *   8 ckpt_every x 12 N bytes in FP32) and compute does not.
  * mm_backward: given d_lam_final = dLoss/dm at the final state ([3][nz][ny][nx],
- *   working precision, device), recomputes each segment from its checkpoint and
- *   runs the reverse sweep; writes d_dku = dLoss/dKu per cell (FP64, device, N
- *   values; loss units per J/m^3) and, if d_dm0 is not NULL, dLoss/dm0
- *   ([3][nz][ny][nx], working precision, device).  nsteps, dt and ckpt_every
- *   must be those of the rollout, with m, Ku map, alpha and H_ext unchanged.
- *   The handle's m is preserved.  Uses the caller's adjoint workspace. */
+ *   working precision, device), recomputes each segment from its checkpoint once
+ *   and runs the reverse sweep over it (each segment one replay of a captured
+ *   hipGraph, kept on the handle for the next call with the same segment length,
+ *   dt, workspace, damping, applied field and Ku-map presence); writes d_dku =
+ *   dLoss/dKu per cell (FP64, device, N values; loss units per J/m^3) and, if
+ *   d_dm0 is not NULL, dLoss/dm0 with respect to the normalised initial state
+ *   ([3][nz][ny][nx], working precision, device; mm_normalize_backward carries it
+ *   to the raw state given to mm_set_m).  nsteps, dt and ckpt_every must be those
+ *   of the rollout, with Ku map, alpha and H_ext unchanged.  The handle's m is
+ *   not touched.  Uses the caller's adjoint workspace. */
 mm_status mm_rollout(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every, void* d_ckpt);
 mm_status mm_adjoint_workspace_query(mm_sim* sim, int64_t ckpt_every, size_t* bytes);
 mm_status mm_backward(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every,
                       const void* d_ckpt, const void* d_lam_final, double* d_dku, void* d_dm0,
                       void* d_adj_ws, size_t adj_ws_bytes);
+
+/* The gradient through the normalisation that mm_set_m applies: given a raw
+ * initial state v ([3][nz][ny][nx], device, working precision, every cell
+ * nonzero) and g_u = dLoss/du for u = v/|v| (e.g. mm_backward's d_dm0), writes
+ * g_v = dLoss/dv = (g_u - u (u . g_u)) / |v| per cell into d_gv (device; may
+ * alias d_gu).  Asynchronous on the handle's stream. */
+mm_status mm_normalize_backward(mm_sim* sim, const void* d_v, const void* d_gu, void* d_gv);
 
 /* Per-kernel timing with HIP events on the handle's stream.  kernel: 0 x-forward,
  * 1 y-forward, 2 k-space, 3 y-inverse, 4 x-inverse, 5 LLG stage.  While a

@@ -26,6 +26,7 @@ MM_NEWELL, MM_PER_GRID_MATERIAL = 0x20, 0x40
 MM_PERIODIC_X, MM_PERIODIC_Y, MM_PERIODIC_Z = 0x80, 0x100, 0x200
 MM_FUSED_YZ = 0x400
 MM_ONE_WG = 0x800
+MM_FAST_PAD = 0x1000
 MM_RK4, MM_EULER = 0, 1
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
@@ -33,10 +34,10 @@ KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5
 EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm_set_m", "mm_get_m",
            "mm_set_hext", "mm_set_alpha", "mm_set_ku_map", "mm_step", "mm_step_euler", "mm_run_schedule",
            "mm_get_field",
-           "mm_get_energy", "mm_get_mean_m", "mm_get_plan", "mm_get_kernel_spectrum",
+           "mm_get_energy", "mm_get_mean_m", "mm_get_max_torque", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
-           "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step",
-           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward",
+           "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step", "mm_batch_get_field",
+           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward", "mm_normalize_backward",
            "mm_profile_begin", "mm_profile_sample", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
@@ -81,7 +82,7 @@ class PlanInfo(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_int64), ("n", ctypes.c_int32), ("pow2_pad", ctypes.c_int32),
                 ("size_classes", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("fast_pad", ctypes.c_int32),
                 ("tuned_demag_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_get_field": [vp, i32, vp, ctypes.c_int],
         "mm_get_energy": [vp, ctypes.POINTER(dbl)],
         "mm_get_mean_m": [vp, ctypes.POINTER(dbl)],
+        "mm_get_max_torque": [vp, ctypes.POINTER(dbl)],
         "mm_get_plan": [vp, ctypes.POINTER(PlanInfo)],
         "mm_get_kernel_spectrum": [vp, vp, ctypes.c_int],
         "mm_demag_tensor": [i32, i32, i32, vp, vp],
@@ -127,11 +129,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_batch_set_m": [vp, vp, ctypes.c_int],
         "mm_batch_get_m": [vp, vp, ctypes.c_int],
         "mm_batch_step": [vp, i64, dbl],
+        "mm_batch_get_field": [vp, i32, vp, ctypes.c_int],
         "mm_batch_cells": [vp, ctypes.POINTER(i64)],
         "mm_batch_get_info": [vp, ctypes.POINTER(BatchInfo)],
         "mm_rollout": [vp, i64, dbl, i64, vp],
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
+        "mm_normalize_backward": [vp, vp, vp, vp],
         "mm_profile_begin": [vp, i32],
         "mm_profile_sample": [vp, i32],
         "mm_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
@@ -177,7 +181,7 @@ class Sim:
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  precision: str = "f32", pad: Sequence[int] = (0, 0, 0), demag: bool = True,
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
-                 autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False,
+                 autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False, fast_pad: bool = False,
                  tensor: str = "point", periodic: Sequence[bool] = (False, False, False),
                  images: int = 0, fused_yz: bool = False, one_wg: bool = False,
                  device: str = "cuda:0"):
@@ -197,8 +201,8 @@ class Sim:
         self._mat = Material(Ms, A, Ku, alpha, gamma)
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
                  | (MM_GENERIC_FFT if generic_fft else 0) | (MM_AUTOTUNE if autotune else 0)
-                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor)
-                 | (MM_PERIODIC_X if periodic[0] else 0) | (MM_PERIODIC_Y if periodic[1] else 0)
+                 | (MM_POW2_PAD if pow2_pad else 0) | (MM_FAST_PAD if fast_pad else 0)
+                 | _tensor_flag(tensor) | (MM_PERIODIC_X if periodic[0] else 0) | (MM_PERIODIC_Y if periodic[1] else 0)
                  | (MM_PERIODIC_Z if periodic[2] else 0) | (MM_FUSED_YZ if fused_yz else 0)
                  | (MM_ONE_WG if one_wg else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
@@ -214,6 +218,10 @@ class Sim:
                                  _stream_ptr(torch, self.device), ctypes.byref(h)), "mm_create")
         self._h = h
         self._lib = lib
+        # the applied field and damping the handle holds (None after run_schedule,
+        # which leaves those of its last step)
+        self._hext_now = (0.0, 0.0, 0.0)
+        self._alpha_now = float(alpha)
 
     # ---------------------------------------------------------------- state
     def _sync_stream(self):
@@ -236,9 +244,11 @@ class Sim:
     def set_hext(self, h: Sequence[float]):
         arr = (ctypes.c_double * 3)(*[float(v) for v in h])
         _check(self._lib.mm_set_hext(self._h, arr), "mm_set_hext")
+        self._hext_now = tuple(arr[:])
 
     def set_alpha(self, alpha: float):
         _check(self._lib.mm_set_alpha(self._h, float(alpha)), "mm_set_alpha")
+        self._alpha_now = float(alpha)
 
     def set_ku_map(self, ku):
         if ku is None:
@@ -280,6 +290,7 @@ class Sim:
         trace = torch.empty((cap, 4), dtype=torch.float64, device=self.device)
         rows = ctypes.c_int64()
         self._sync_stream()
+        self._hext_now = self._alpha_now = None
         _check(self._lib.mm_run_schedule(self._h, segs, len(pieces),
                                          MM_EULER if method == "euler" else MM_RK4, float(dt),
                                          int(every), trace.data_ptr(), cap, ctypes.byref(rows)),
@@ -304,6 +315,13 @@ class Sim:
         self._sync_stream()
         _check(self._lib.mm_get_mean_m(self._h, out), "mm_get_mean_m")
         return np.array(out[:])
+
+    def max_torque(self) -> float:
+        """max over cells of |m x H_eff|, A/m (FP64 reduction on the GPU)."""
+        out = ctypes.c_double()
+        self._sync_stream()
+        _check(self._lib.mm_get_max_torque(self._h, ctypes.byref(out)), "mm_get_max_torque")
+        return out.value
 
     def plan(self) -> dict:
         p = PlanInfo()
@@ -346,6 +364,18 @@ class Sim:
                                      nbytes.value), "mm_backward")
         return dku, dm0
 
+    def normalize_backward(self, v, g_u):
+        """dLoss/dv for u = v / |v| per cell (the normalisation set_m applies),
+        given dLoss/du; both (3, nz, ny, nx) in the handle's precision."""
+        torch = self._torch
+        vv = v.to(device=self.device, dtype=self.dtype).contiguous()
+        gu = g_u.to(device=self.device, dtype=self.dtype).contiguous()
+        out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_normalize_backward(self._h, vv.data_ptr(), gu.data_ptr(), out.data_ptr()),
+               "mm_normalize_backward")
+        return out
+
     # ------------------------------------------------------------- profiling
     def profile_begin(self, kernel: str, every: int = 1):
         """Time launches of `kernel` (one in `every`) until profile_end."""
@@ -379,7 +409,8 @@ class BatchSim:
     def __init__(self, grids: Sequence[Sequence[int]], cell: float, Ms: float = 8.0e5,
                  A: float = 1.3e-11, Ku: float = 0.0, alpha: float = 0.5, gamma: float = 2.211e5,
                  hext=None, precision: str = "f32", demag: bool = True, graph: bool = False,
-                 pow2_pad: bool = False, tensor: str = "point", autotune: bool = False,
+                 pow2_pad: bool = False, fast_pad: bool = False, tensor: str = "point",
+                 autotune: bool = False,
                  device: str = "cuda:0"):
         torch = _torch()
         lib = load_library()
@@ -401,8 +432,8 @@ class BatchSim:
         else:
             self._mat = (Material * 1)(Material(*(float(v) for v in props)))
         flags = ((0 if demag else MM_NO_DEMAG) | (MM_USE_GRAPH if graph else 0)
-                 | (MM_POW2_PAD if pow2_pad else 0) | _tensor_flag(tensor)
-                 | (MM_PER_GRID_MATERIAL if per_grid else 0) | (MM_AUTOTUNE if autotune else 0))
+                 | (MM_POW2_PAD if pow2_pad else 0) | (MM_FAST_PAD if fast_pad else 0)
+                 | _tensor_flag(tensor) | (MM_PER_GRID_MATERIAL if per_grid else 0) | (MM_AUTOTUNE if autotune else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, 0, 0, 0, flags, 0, 0)
         h = np.zeros((self.n, 3)) if hext is None else np.ascontiguousarray(hext, dtype=np.float64)
         self._hext = (ctypes.c_double * (3 * self.n))(*h.reshape(-1).tolist())
@@ -429,7 +460,7 @@ class BatchSim:
         """The layout in use: padding family, pass family, autotune record."""
         p = BatchInfo()
         _check(self._lib.mm_batch_get_info(self._h, ctypes.byref(p)), "mm_batch_get_info")
-        return {k: getattr(p, k) for k, _ in BatchInfo._fields_ if k != "reserved"}
+        return {k: getattr(p, k) for k, _ in BatchInfo._fields_}
 
     def set_m(self, ms):
         """ms: list of per-grid (3, nz, ny, nx) arrays (or one flat array)."""
@@ -461,6 +492,18 @@ class BatchSim:
     def step(self, nsteps: int, dt: float):
         self._sync_stream()
         _check(self._lib.mm_batch_step(self._h, int(nsteps), float(dt)), "mm_batch_step")
+
+    def field(self, term: str = "eff"):
+        """One effective-field term of every grid, A/m: list of (3, nz, ny, nx)."""
+        flat = self._torch.empty(sum(self.sizes), dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _check(self._lib.mm_batch_get_field(self._h, TERMS[term], flat.data_ptr(), 1),
+               "mm_batch_get_field")
+        out, off = [], 0
+        for shp, sz in zip(self.shapes, self.sizes):
+            out.append(flat[off:off + sz].reshape(shp))
+            off += sz
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
@@ -499,28 +542,42 @@ def _rollout_function():
     import torch
 
     class Rollout(torch.autograd.Function):
-        """m_final = RK4^nsteps(m0; Ku map) on the GPU, with the hand-written
+        """m_final = RK4^nsteps(m0 / |m0|; Ku map) on the GPU, with the hand-written
         adjoint (checkpoint every ckpt_every steps, segments recomputed in the
         backward pass).  Gradients flow to the Ku map (J/m^3, per cell) and to m0
-        (taken as the normalised initial state)."""
+        as given (through the per-cell normalisation the forward applies).  The
+        Ku map, applied field and damping of the forward are kept and restored on
+        the handle before the reverse sweep, so other rollouts or parameter
+        changes on the same handle between forward and backward do not alter
+        the gradient; the handle keeps them afterwards."""
 
         @staticmethod
         def forward(ctx, ku, m0, sim, nsteps, dt, ckpt_every):
-            sim.set_ku_map(ku.detach())
-            sim.set_m(m0.detach())
+            if sim._hext_now is None or sim._alpha_now is None:
+                raise RuntimeError("rollout: set the applied field and damping (set_hext, set_alpha) "
+                                   "after run_schedule")
+            ku_used = ku.detach().to(device=sim.device, dtype=sim.dtype).contiguous().clone()
+            m0_used = m0.detach().to(device=sim.device, dtype=sim.dtype).contiguous().clone()
+            sim.set_ku_map(ku_used)
+            sim.set_m(m0_used)
             ck = sim.rollout_ckpt(nsteps, dt, ckpt_every)
             ctx.sim, ctx.nsteps, ctx.dt, ctx.ckpt_every = sim, nsteps, dt, ckpt_every
-            ctx.save_for_backward(ck)
+            ctx.hext, ctx.alpha = sim._hext_now, sim._alpha_now
+            ctx.save_for_backward(ck, ku_used, m0_used)
             ctx.ku_dtype, ctx.m0_dtype = ku.dtype, m0.dtype
             return sim.get_m()
 
         @staticmethod
         def backward(ctx, grad_m):
-            (ck,) = ctx.saved_tensors
-            dku, dm0 = ctx.sim.backward(ctx.nsteps, ctx.dt, ctx.ckpt_every, ck, grad_m,
-                                        want_dm0=ctx.needs_input_grad[1])
+            ck, ku_used, m0_used = ctx.saved_tensors
+            sim = ctx.sim
+            sim.set_ku_map(ku_used)
+            sim.set_hext(ctx.hext)
+            sim.set_alpha(ctx.alpha)
+            dku, dm0 = sim.backward(ctx.nsteps, ctx.dt, ctx.ckpt_every, ck, grad_m,
+                                    want_dm0=ctx.needs_input_grad[1])
             gku = dku.to(ctx.ku_dtype) if ctx.needs_input_grad[0] else None
-            gm0 = dm0.to(ctx.m0_dtype) if dm0 is not None else None
+            gm0 = sim.normalize_backward(m0_used, dm0).to(ctx.m0_dtype) if dm0 is not None else None
             return gku, gm0, None, None, None, None
 
     return Rollout

@@ -183,6 +183,33 @@ hipError_t launch_adj_apply(const AdjArgs<T>& a, T cmu, T ca, hipStream_t s)
     return hipGetLastError();
 }
 
+// Vector-Jacobian product of the normalisation u = v / |v| applied when m is set:
+// g_v = (g_u - u (u . g_u)) / |v|, per cell.
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize_vjp(const T* v, const T* gu, T* gv, int64_t N)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    T x[3], g[3];
+    ld3(v, N, c, x);
+    ld3(gu, N, c, g);
+    const T inv = (T)1 / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const T u[3] = {x[0] * inv, x[1] * inv, x[2] * inv};
+    const T ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+    const T o[3] = {(g[0] - u[0] * ug) * inv, (g[1] - u[1] * ug) * inv, (g[2] - u[2] * ug) * inv};
+    st3(gv, N, c, o);
+}
+
+template <typename T>
+hipError_t launch_normalize_vjp(const T* v, const T* gu, T* gv, int64_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_normalize_vjp<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, v, gu, gv, N);
+    return hipGetLastError();
+}
+
+template hipError_t launch_normalize_vjp<float>(const float*, const float*, float*, int64_t, hipStream_t);
+template hipError_t launch_normalize_vjp<double>(const double*, const double*, double*, int64_t,
+                                                 hipStream_t);
 template hipError_t launch_adj_renorm<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adj_renorm<double>(const AdjArgs<double>&, hipStream_t);
 template hipError_t launch_adj_nu<float>(const AdjArgs<float>&, const float*, const float*, hipStream_t);

@@ -93,6 +93,18 @@ bool make_fft_plan(int P, FftPlan* pl)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The smallest padded length >= v that has size-specialised passes: powers of
+// two, and along x and y also 96, 160, 192 and 224 (32 q, q = 3, 5, 6, 7).
+int fast_pad_length(int v, bool line_axis)
+{
+    int q = 2;
+    while (q < v) q <<= 1;
+    if (line_axis)
+        for (int m : {96, 160, 192, 224})
+            if (m >= v && m < q) return m;
+    return q;
+}
+
 struct Plan {
     int nx, ny, nz;
     int64_t N;
@@ -138,11 +150,13 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->esz = o->prec == MM_F32 ? 4 : 8;
     p->three_d = g->nz > 1;
     const bool pow2pad = (o->flags & MM_POW2_PAD) != 0;
+    const bool fastpad = (o->flags & MM_FAST_PAD) != 0;
+    if (pow2pad && fastpad) return fail(MM_EINVAL, "MM_POW2_PAD and MM_FAST_PAD exclude each other");
     p->per = ((o->flags & MM_PERIODIC_X) ? 1 : 0) | ((o->flags & MM_PERIODIC_Y) ? 2 : 0) |
              ((o->flags & MM_PERIODIC_Z) ? 4 : 0);
     if (o->images < 0 || o->images > 64) return fail(MM_EINVAL, "images must be in 0..64");
     p->images = o->images;
-    auto pick = [pow2pad](int n, int req, bool allow1, bool periodic, int* out) -> mm_status {
+    auto pick = [pow2pad, fastpad](int n, int req, bool allow1, bool periodic, int* out) -> mm_status {
         if (periodic) {  // no zero padding: the FFT runs over the period itself
             // a one-cell period along x or y would need one-point transforms on those
             // axes, which no pass takes; along z the one-cell-thick schedule serves it
@@ -160,6 +174,8 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
                 int q = 2;
                 while (q < 2 * n - 1) q <<= 1;
                 *out = q;
+            } else if (fastpad) {
+                *out = fast_pad_length(2 * n - 1, !allow1);
             } else
                 *out = auto_pad(n);
             return MM_OK;
@@ -252,8 +268,8 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->o_twxd = take((size_t)p->Px * 16);
     p->o_twyd = take((size_t)p->Py * 16);
     p->o_twzd = take((size_t)p->Pz * 16);
-    p->o_red = take(1024 * 8 * sizeof(double));
-    p->o_redout = take(8 * sizeof(double));
+    p->o_red = take(1024 * kRedSlots * sizeof(double));
+    p->o_redout = take(kRedSlots * sizeof(double));
     p->o_flags = take(64);
     p->o_setR = take((size_t)p->Px * p->Py * p->Pz * sizeof(double));
     p->o_setS = take((size_t)p->Pz * p->Py * p->sxd * 16);
@@ -293,6 +309,16 @@ struct mm_sim {
     double graph_dt;
     int graph_chunk;
     int graph_method;
+    // reverse-sweep graphs: one per segment length (a full segment and the
+    // shorter last one), valid while the baked-in arguments are unchanged
+    struct BwdGraph {
+        hipGraphExec_t exec = nullptr;
+        int64_t len = 0;
+        double dt = 0, alpha = 0, hext[3] = {0, 0, 0};
+        bool ku_map = false;
+        const char* ws = nullptr;
+    };
+    BwdGraph bwd[2];
     // profiling: launches of kernel prof_kernel, one in prof_every bracketed by events
     int prof_kernel;
     int prof_every;
@@ -768,11 +794,19 @@ void drop_graph(mm_sim* s)
     s->graph_valid = false;
 }
 
+void drop_bwd_graphs(mm_sim* s)
+{
+    for (auto& g : s->bwd) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = mm_sim::BwdGraph{};
+    }
+}
+
 template <typename T>
-mm_status step_impl(mm_sim* s, int64_t nsteps, double dt)
+mm_status step_impl(mm_sim* s, int64_t nsteps, double dt, bool force_graph = false)
 {
     hipStream_t st = s->stream;
-    const bool use_graph = (s->flags & MM_USE_GRAPH) && s->prof_kernel < 0;
+    const bool use_graph = ((s->flags & MM_USE_GRAPH) || force_graph) && s->prof_kernel < 0;
     if (!use_graph) {
         for (int64_t n = 0; n < nsteps; ++n) {
             mm_status r = rk4_step<T>(s, dt, st);
@@ -920,7 +954,7 @@ mm_status field_impl(mm_sim* s, int term, void* out, int on_device)
 }
 
 template <typename T>
-mm_status reduce_impl(mm_sim* s, double out8[8])
+mm_status reduce_impl(mm_sim* s, double out[kRedSlots])
 {
     const Plan& p = s->p;
     hipStream_t st = s->stream;
@@ -934,7 +968,7 @@ mm_status reduce_impl(mm_sim* s, double out8[8])
     }
     double* dout = s->at<double>(p.o_redout);
     HIP_TRY(launch_reduce<T>(a, s->at<double>(p.o_red), reduce_blocks(p.N), dout, st));
-    HIP_TRY(hipMemcpyAsync(out8, dout, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(out, dout, kRedSlots * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return MM_OK;
 }
@@ -962,25 +996,173 @@ mm_status set_m_impl(mm_sim* s, const void* m, int on_device)
 }
 
 // ---------------------------------------------------------------- adjoint
+// Adjoint workspace: per step of a segment its start state, the three later
+// stage states and the four stage fields (8 vectors, stored while the segment is
+// recomputed from its checkpoint), 7 working vectors, and the FP64 dLoss/dKu
+// accumulator.
+constexpr int kAdjPerStep = 8, kAdjWork = 7;
+
 size_t adj_bytes(const Plan& p, int64_t ck)
 {
     const size_t vec = align256(3 * (size_t)p.N * p.esz);
-    return (size_t)ck * vec + 15 * vec;
+    return ((size_t)ck * kAdjPerStep + kAdjWork) * vec + align256((size_t)p.N * sizeof(double));
 }
 
+// nsteps RK4 steps; the state at the start of every segment of ck steps goes to
+// its checkpoint slot, and the steps of a segment replay captured graphs.
 template <typename T>
 mm_status rollout_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, T* ckpt)
 {
     const Plan& p = s->p;
     const size_t vec = 3 * (size_t)p.N;
     T* mn = s->at<T>(p.o_mn);
-    for (int64_t n = 0; n < nsteps; ++n) {
-        if (n % ck == 0)
-            HIP_TRY(hipMemcpyAsync(ckpt + (n / ck) * vec, mn, vec * sizeof(T), hipMemcpyDeviceToDevice,
-                                   s->stream));
-        mm_status r = rk4_step<T>(s, dt, s->stream);
+    for (int64_t n = 0; n < nsteps; n += ck) {
+        HIP_TRY(hipMemcpyAsync(ckpt + (n / ck) * vec, mn, vec * sizeof(T), hipMemcpyDeviceToDevice,
+                               s->stream));
+        mm_status r = step_impl<T>(s, std::min(ck, nsteps - n), dt, true);
         if (r != MM_OK) return r;
     }
+    return MM_OK;
+}
+
+// Buffers of the reverse sweep, carved from the caller's adjoint workspace.
+template <typename T>
+struct AdjBufs {
+    T* slot;  // [ck][8][3N]: per step m_n, m_2, m_3, m_4, h_1 .. h_4
+    T *lam, *accl, *mu, *dF, *nu, *loc, *scr;
+    double* dku;
+    size_t vbytes;
+    T* at(int64_t n, int q) const
+    {
+        return reinterpret_cast<T*>(reinterpret_cast<char*>(slot) + ((size_t)n * kAdjPerStep + q) * vbytes);
+    }
+};
+
+// One segment of `len` steps whose start state is already in slot 0: the forward
+// recompute, storing every stage state and stage field, then the reverse sweep
+// from the covector in b.lam (left in b.lam on return).  Enqueued on st; every
+// pointer it uses is fixed for a given workspace, so it can be captured.
+template <typename T>
+mm_status backward_segment(mm_sim* s, const AdjBufs<T>& b, int64_t len, double dt, hipStream_t st)
+{
+    const Plan& p = s->p;
+    const bool with_demag = !(s->flags & MM_NO_DEMAG);
+    T* hd = s->at<T>(p.o_hd);
+    LlgArgs<T> la = llg_args<T>(s, dt);
+    la.acc = b.scr;
+    for (int64_t n = 0; n < len; ++n) {
+        la.mn = b.at(n, 0);
+        for (int stg = 0; stg < 4; ++stg) {
+            la.ms = b.at(n, stg);
+            if (with_demag) {
+                mm_status r = demag<T>(s, la.ms, hd, st);
+                if (r != MM_OK) return r;
+            }
+            HIP_TRY(launch_field_term<T>(la, 4, (T)1, b.at(n, 4 + stg), st));
+            if (stg == 3 && n == len - 1) break;  // the next segment starts from its checkpoint
+            la.out = stg < 3 ? b.at(n, stg + 1) : b.at(n + 1, 0);
+            la.stage = stg + 1;
+            HIP_TRY(launch_llg_stage<T>(la, st));
+        }
+    }
+    AdjArgs<T> aa{};
+    aa.nx = p.nx;
+    aa.ny = p.ny;
+    aa.nz = p.nz;
+    aa.N = p.N;
+    aa.mu = b.mu;
+    aa.dF = b.dF;
+    aa.nu = b.nu;
+    aa.loc = b.loc;
+    aa.hd = with_demag ? hd : nullptr;
+    aa.ku = la.ku;
+    aa.can = la.can;
+    aa.cex = la.cex;
+    aa.G = la.gdt;
+    aa.alpha = la.alpha;
+    aa.dku = b.dku;
+    aa.kfac = 2.0 / (kMu0 * s->mat.Ms * s->mat.Ms);
+    aa.per = p.per;
+    T* lam = b.lam;
+    T* accl = b.accl;
+    const T cmu[4] = {(T)0, (T)(1.0 / 6.0), (T)(2.0 / 6.0), (T)(2.0 / 6.0)};
+    const T ca[4] = {(T)0, (T)0.5, (T)0.5, (T)1};
+    for (int64_t n = len - 1; n >= 0; --n) {
+        aa.mn = b.at(n, 0);
+        aa.m2 = b.at(n, 1);
+        aa.m3 = b.at(n, 2);
+        aa.m4 = b.at(n, 3);
+        aa.h1 = b.at(n, 4);
+        aa.h2 = b.at(n, 5);
+        aa.h3 = b.at(n, 6);
+        aa.h4 = b.at(n, 7);
+        aa.lam = lam;
+        aa.accl = accl;
+        // reverse: renormalisation, then stages 4..1
+        HIP_TRY(launch_adj_renorm<T>(aa, st));
+        for (int stg = 3; stg >= 0; --stg) {
+            HIP_TRY(launch_adj_nu<T>(aa, b.at(n, stg), b.at(n, 4 + stg), st));
+            if (with_demag) {
+                mm_status r = demag<T>(s, b.nu, hd, st);
+                if (r != MM_OK) return r;
+            }
+            HIP_TRY(launch_adj_apply<T>(aa, cmu[stg], ca[stg], st));
+        }
+        std::swap(lam, accl);
+    }
+    if (lam != b.lam)  // an odd number of steps: the covector ends in the other buffer
+        HIP_TRY(hipMemcpyAsync(b.lam, lam, 3 * (size_t)p.N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return MM_OK;
+}
+
+// Runs backward_segment for `len` steps, replaying a captured graph when one for
+// the same length, workspace and step parameters exists, else capturing one
+// (eagerly while a profile is open).
+template <typename T>
+mm_status backward_segment_graph(mm_sim* s, const AdjBufs<T>& b, int64_t len, double dt, const char* ws)
+{
+    if (s->prof_kernel >= 0) return backward_segment<T>(s, b, len, dt, s->stream);
+    auto same = [&](const mm_sim::BwdGraph& g) {
+        return g.exec && g.len == len && g.dt == dt && g.alpha == s->alpha && g.ws == ws &&
+               g.ku_map == s->has_ku_map && g.hext[0] == s->hext[0] && g.hext[1] == s->hext[1] &&
+               g.hext[2] == s->hext[2];
+    };
+    mm_sim::BwdGraph* hit = nullptr;
+    for (auto& g : s->bwd)
+        if (same(g)) hit = &g;
+    if (!hit) {
+        // replace a slot of another length if there is one, else the first
+        hit = &s->bwd[0];
+        for (auto& g : s->bwd)
+            if (!g.exec || g.len != len) {
+                hit = &g;
+                break;
+            }
+        if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
+        *hit = mm_sim::BwdGraph{};
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = backward_segment<T>(s, b, len, dt, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (r != MM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&hit->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            hit->exec = nullptr;
+            return fail(MM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        hit->len = len;
+        hit->dt = dt;
+        hit->alpha = s->alpha;
+        hit->ws = ws;
+        hit->ku_map = s->has_ku_map;
+        for (int c = 0; c < 3; ++c) hit->hext[c] = s->hext[c];
+    }
+    HIP_TRY(hipGraphLaunch(hit->exec, s->stream));
     return MM_OK;
 }
 
@@ -991,105 +1173,34 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
     const Plan& p = s->p;
     hipStream_t st = s->stream;
     const size_t vec = 3 * (size_t)p.N, vbytes = align256(vec * sizeof(T));
-    T* seg = reinterpret_cast<T*>(ws);
-    char* q = ws + (size_t)ck * vbytes;
+    AdjBufs<T> b{};
+    b.vbytes = vbytes;
+    b.slot = reinterpret_cast<T*>(ws);
+    char* q = ws + (size_t)ck * kAdjPerStep * vbytes;
     auto take = [&]() {
         T* r = reinterpret_cast<T*>(q);
         q += vbytes;
         return r;
     };
-    T *m2 = take(), *m3 = take(), *m4 = take(), *h1 = take(), *h2 = take(), *h3 = take(),
-      *h4 = take();
-    T *lam = take(), *accl = take(), *mu = take(), *dF = take(), *nu = take(), *loc = take(),
-      *scr = take(), *msave = take();
-    T* mn_sim = s->at<T>(p.o_mn);
-    T* hd = s->at<T>(p.o_hd);
-    const bool with_demag = !(s->flags & MM_NO_DEMAG);
-    HIP_TRY(hipMemcpyAsync(msave, mn_sim, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(lam, lam_final, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemsetAsync(dku, 0, (size_t)p.N * sizeof(double), st));
-
-    LlgArgs<T> la = llg_args<T>(s, dt);
-    AdjArgs<T> aa{};
-    aa.nx = p.nx;
-    aa.ny = p.ny;
-    aa.nz = p.nz;
-    aa.N = p.N;
-    aa.m2 = m2;
-    aa.m3 = m3;
-    aa.m4 = m4;
-    aa.h1 = h1;
-    aa.h2 = h2;
-    aa.h3 = h3;
-    aa.h4 = h4;
-    aa.lam = lam;
-    aa.mu = mu;
-    aa.dF = dF;
-    aa.accl = accl;
-    aa.nu = nu;
-    aa.loc = loc;
-    aa.hd = with_demag ? hd : nullptr;
-    aa.ku = la.ku;
-    aa.can = la.can;
-    aa.cex = la.cex;
-    aa.G = la.gdt;
-    aa.alpha = la.alpha;
-    aa.dku = dku;
-    aa.kfac = 2.0 / (kMu0 * s->mat.Ms * s->mat.Ms);
-    aa.per = s->p.per;
-    T* ms_of[4] = {nullptr, m2, m3, m4};
-    T* hs_of[4] = {h1, h2, h3, h4};
-
+    b.lam = take();
+    b.accl = take();
+    b.mu = take();
+    b.dF = take();
+    b.nu = take();
+    b.loc = take();
+    b.scr = take();
+    b.dku = reinterpret_cast<double*>(q);
+    HIP_TRY(hipMemcpyAsync(b.lam, lam_final, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(b.dku, 0, (size_t)p.N * sizeof(double), st));
     const int64_t nseg = (nsteps + ck - 1) / ck;
     for (int64_t g = nseg - 1; g >= 0; --g) {
         const int64_t len = std::min(ck, nsteps - g * ck);
-        // recompute the segment's step-start states from its checkpoint
-        HIP_TRY(hipMemcpyAsync(seg, ckpt + g * vec, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(mn_sim, seg, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-        for (int64_t n = 1; n < len; ++n) {
-            mm_status r = rk4_step<T>(s, dt, st);
-            if (r != MM_OK) return r;
-            HIP_TRY(hipMemcpyAsync(seg + n * vec, mn_sim, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-        }
-        for (int64_t n = len - 1; n >= 0; --n) {
-            T* mn = seg + n * vec;
-            ms_of[0] = mn;
-            // stage inputs m_s and fields h_s of this step
-            la.mn = mn;
-            la.acc = scr;
-            for (int stg = 0; stg < 4; ++stg) {
-                la.ms = ms_of[stg];
-                if (with_demag) {
-                    mm_status r = demag<T>(s, ms_of[stg], hd, st);
-                    if (r != MM_OK) return r;
-                }
-                HIP_TRY(launch_field_term<T>(la, 4, (T)1, hs_of[stg], st));
-                if (stg < 3) {
-                    la.out = ms_of[stg + 1];
-                    la.stage = stg + 1;
-                    HIP_TRY(launch_llg_stage<T>(la, st));
-                }
-            }
-            // reverse: renormalisation, then stages 4..1
-            aa.mn = mn;
-            HIP_TRY(launch_adj_renorm<T>(aa, st));
-            const T cmu[4] = {(T)0, (T)(1.0 / 6.0), (T)(2.0 / 6.0), (T)(2.0 / 6.0)};
-            const T ca[4] = {(T)0, (T)0.5, (T)0.5, (T)1};
-            for (int stg = 3; stg >= 0; --stg) {
-                HIP_TRY(launch_adj_nu<T>(aa, ms_of[stg], hs_of[stg], st));
-                if (with_demag) {
-                    mm_status r = demag<T>(s, nu, hd, st);
-                    if (r != MM_OK) return r;
-                }
-                HIP_TRY(launch_adj_apply<T>(aa, cmu[stg], ca[stg], st));
-            }
-            std::swap(lam, accl);
-            aa.lam = lam;
-            aa.accl = accl;
-        }
+        HIP_TRY(hipMemcpyAsync(b.at(0, 0), ckpt + g * vec, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+        mm_status r = backward_segment_graph<T>(s, b, len, dt, ws);
+        if (r != MM_OK) return r;
     }
-    if (dm0) HIP_TRY(hipMemcpyAsync(dm0, lam, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(mn_sim, msave, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dku, b.dku, (size_t)p.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (dm0) HIP_TRY(hipMemcpyAsync(dm0, b.lam, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
     return MM_OK;
 }
 
@@ -1190,7 +1301,7 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
     // size classes for the specialised passes (power-of-two padding)
     L->fast = false;
     L->classes.clear();
-    if ((o.flags & MM_POW2_PAD) && !(o.flags & MM_GENERIC_FFT)) {
+    if ((o.flags & (MM_POW2_PAD | MM_FAST_PAD)) && !(o.flags & MM_GENERIC_FFT)) {
         bool ok = true;
         auto cls = [&](int kind, int P) -> BatchClassHost& {
             for (auto& c : L->classes)
@@ -1465,6 +1576,45 @@ mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
     return MM_OK;
 }
 
+// One term of every grid's effective field at the current m, A/m, written grid
+// by grid like m: the demag passes of the whole batch, then the local terms of
+// each grid.
+template <typename T>
+mm_status batch_field_impl(mm_batch* b, int term, void* out, int on_device)
+{
+    const BatchLayout& L = b->L;
+    hipStream_t st = b->stream;
+    T* mn = b->at<T>(L.o_mn);
+    const bool with_demag = !(b->flags & MM_NO_DEMAG);
+    if (with_demag && (term == MM_H_DEMAG || term == MM_H_EFF))
+        if (mm_status r = batch_demag<T>(b, mn, st); r != MM_OK) return r;
+    T* dst = on_device ? static_cast<T*>(out) : b->at<T>(L.o_mb);
+    T* hd = b->at<T>(L.o_hd);
+    for (int s = 0; s < b->n; ++s) {
+        const Plan& p = L.plans[s];
+        const BatchDesc& d = L.desc[s];
+        LlgArgs<T> a{};
+        a.nx = p.nx;
+        a.ny = p.ny;
+        a.nz = p.nz;
+        a.N = p.N;
+        a.cex = (T)d.cex;
+        a.can = (T)d.can;
+        a.hx = (T)d.hred[0];
+        a.hy = (T)d.hred[1];
+        a.hz = (T)d.hred[2];
+        a.ms = mn + d.moff;
+        a.mn = a.ms;
+        a.hd = with_demag ? hd + d.moff : nullptr;
+        HIP_TRY(launch_field_term<T>(a, term, (T)b->mats[s].Ms, dst + d.moff, st));
+    }
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(out, dst, (size_t)L.vec_elems * sizeof(T), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return MM_OK;
+}
+
 // ---------------------------------------------------------------- batch autotuner
 // Candidate layouts of a batch: 7-smooth padding with the runtime-radix passes
 // (the default), power-of-two padding with the runtime-radix passes, and
@@ -1472,8 +1622,9 @@ mm_status batch_set_m_impl(mm_batch* b, const void* m, int on_device)
 // one.  A candidate whose padded sizes equal an earlier one's is dropped.
 std::vector<mm_options> batch_tune_candidates(int32_t n, const mm_grid* grids, const mm_options* opt)
 {
-    const uint32_t base = opt->flags & ~(uint32_t)(MM_AUTOTUNE | MM_POW2_PAD | MM_GENERIC_FFT);
-    const uint32_t variants[3] = {base, base | MM_POW2_PAD | MM_GENERIC_FFT, base | MM_POW2_PAD};
+    const uint32_t base = opt->flags & ~(uint32_t)(MM_AUTOTUNE | MM_POW2_PAD | MM_FAST_PAD | MM_GENERIC_FFT);
+    const uint32_t variants[4] = {base, base | MM_POW2_PAD | MM_GENERIC_FFT, base | MM_POW2_PAD,
+                                  base | MM_FAST_PAD};
     std::vector<mm_options> out;
     std::vector<BatchLayout> kept;
     for (uint32_t f : variants) {
@@ -1482,7 +1633,7 @@ std::vector<mm_options> batch_tune_candidates(int32_t n, const mm_grid* grids, c
         c.flags = f;
         BatchLayout L;
         if (batch_layout(n, grids, &c, &L) != MM_OK) continue;
-        if ((f & MM_POW2_PAD) && !(f & MM_GENERIC_FFT) && !L.fast) continue;
+        if ((f & (MM_POW2_PAD | MM_FAST_PAD)) && !(f & MM_GENERIC_FFT) && !L.fast) continue;
         bool dup = false;
         for (const BatchLayout& K : kept) {
             if (K.fast != L.fast) continue;
@@ -1540,10 +1691,23 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune_cache;
 bool g_tune_file_loaded = false;
 
+// The GPU the current device is: architecture, name and compute units (a tuned
+// schedule is only reused on the same kind of GPU).
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string tag = std::string(prop.gcnArchName) + "/" + prop.name + "/" + std::to_string(prop.multiProcessorCount);
+    for (char& ch : tag)
+        if (ch == ' ' || ch == '\t') ch = '_';
+    return tag;
+}
+
 std::string tune_key(const mm_grid* g, const mm_options* o)
 {
     std::ostringstream k;
-    k << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1)
+    k << device_tag() << ":" << g->nx << "x" << g->ny << "x" << g->nz << ":p" << o->prec << ":d" << ((o->flags & MM_NO_DEMAG) ? 0 : 1)
       << ":b" << ((o->flags >> 7) & 7) << "i" << o->images << ":t" << ((o->flags & MM_NEWELL) ? 1 : 0)
       << ":f" << ((o->flags & MM_FUSED_YZ) ? 1 : 0) << ((o->flags & MM_ONE_WG) ? 1 : 0);
     return k.str();
@@ -1622,9 +1786,15 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
         const int q = next_pow2_at_least(2 * n - 1);
         if (q != v[0] && q <= 4096) v.push_back(q);
     };
+    auto add_fast = [](std::vector<int>& v, int n) {  // a mixed-radix length with specialised passes
+        const int q = fast_pad_length(2 * n - 1, true);
+        if (std::find(v.begin(), v.end(), q) == v.end() && q <= 4096) v.push_back(q);
+    };
     if (!perx) add_pow2(pxs, g->nx);
     if (!pery) add_pow2(pys, g->ny);
     if (g->nz > 1 && !perz) add_pow2(pzs, g->nz);
+    if (!perx) add_fast(pxs, g->nx);
+    if (!pery) add_fast(pys, g->ny);
     std::vector<mm_options> out;
     for (int px : pxs)
         for (int py : pys)
@@ -1640,7 +1810,8 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
                         c.pz = pz;
                         c.threads = threads;
                         c.x_lines = xl;
-                        c.flags = (o->flags & ~(MM_AUTOTUNE | MM_USE_GRAPH | MM_GENERIC_FFT)) |
+                        c.flags = (o->flags & ~(MM_AUTOTUNE | MM_USE_GRAPH | MM_GENERIC_FFT | MM_POW2_PAD |
+                                                MM_FAST_PAD)) |
                                   (generic ? MM_GENERIC_FFT : 0u);
                         Plan p;
                         if (build_plan(g, &c, &p) != MM_OK) continue;
@@ -1655,29 +1826,60 @@ std::vector<mm_options> tune_candidates(const mm_grid* g, const mm_options* o)
     return out;
 }
 
-// Times every candidate; each gets its own temporary handle and workspace.
+// Times every candidate on one workspace: the caller's when it holds every
+// candidate (mm_workspace_query with MM_AUTOTUNE returns that size), else one
+// allocated here for the largest.  Candidates that share padded sizes share the
+// workspace layout, the twiddles and the kernel spectrum, which are built once
+// per padded size; the schedule options (pass family, work-group size, x lines,
+// fused y-z or one work-group) are then switched on the same handle.
 mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o, hipStream_t st,
-                   TuneChoice* best, int* ncand)
+                   void* d_ws, size_t ws_bytes, TuneChoice* best, int* ncand)
 {
     best->ms = 1e300;
     *ncand = 0;
+    std::vector<mm_options> cands;
+    std::vector<Plan> plans;
+    size_t need = 0;
     for (const mm_options& c : tune_candidates(g, o)) {
         Plan p;
         if (build_plan(g, &c, &p) != MM_OK) continue;
-        void* w = nullptr;
-        if (hipMalloc(&w, p.total) != hipSuccess) continue;
-        mm_sim* t = nullptr;
-        mm_status r = mm_create(g, mat, &c, w, p.total, st, &t);
-        double ms = 0;
-        if (r == MM_OK) r = p.prec == MM_F32 ? time_demag<float>(t, st, &ms) : time_demag<double>(t, st, &ms);
-        if (t) mm_destroy(t);
-        (void)hipFree(w);
-        if (r != MM_OK) continue;
-        ++*ncand;
-        if (ms < best->ms)
-            *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms,
-                               (c.flags & MM_ONE_WG) ? 2 : ((c.flags & MM_FUSED_YZ) ? 1 : 0)};
+        cands.push_back(c);
+        plans.push_back(p);
+        need = std::max(need, p.total);
     }
+    void* w = d_ws;
+    bool own = false;
+    if (!w || ws_bytes < need) {
+        if (hipMalloc(&w, need) != hipSuccess) return fail(MM_ENOMEM, "autotune workspace of %zu bytes", need);
+        own = true;
+    }
+    std::vector<bool> done(cands.size(), false);
+    for (size_t i = 0; i < cands.size(); ++i) {
+        if (done[i]) continue;
+        mm_sim* t = nullptr;
+        mm_status r = mm_create(g, mat, &cands[i], w, need, st, &t);
+        for (size_t j = i; j < cands.size(); ++j) {
+            const Plan& pi = plans[i];
+            const Plan& pj = plans[j];
+            if (done[j] || pj.Px != pi.Px || pj.Py != pi.Py || pj.Pz != pi.Pz || pj.total != pi.total ||
+                pj.o_kern != pi.o_kern || pj.o_S != pi.o_S || pj.o_twz != pi.o_twz)
+                continue;
+            done[j] = true;
+            if (r != MM_OK) continue;
+            t->p = pj;  // same layout, spectrum and twiddles; another schedule
+            t->flags = cands[j].flags;
+            double ms = 0;
+            mm_status rj = pj.prec == MM_F32 ? time_demag<float>(t, st, &ms) : time_demag<double>(t, st, &ms);
+            if (rj != MM_OK) continue;
+            ++*ncand;
+            const mm_options& c = cands[j];
+            if (ms < best->ms)
+                *best = TuneChoice{c.px, c.py, c.pz, (c.flags & MM_GENERIC_FFT) ? 1 : 0, c.threads, c.x_lines, ms,
+                                   (c.flags & MM_ONE_WG) ? 2 : ((c.flags & MM_FUSED_YZ) ? 1 : 0)};
+        }
+        if (t) mm_destroy(t);
+    }
+    if (own) (void)hipFree(w);
     if (*ncand == 0) return fail(MM_ENOTSUP, "no schedule of this grid could be built");
     return MM_OK;
 }
@@ -1727,7 +1929,7 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
             }
         }
         if (!have) {
-            mm_status r = autotune(grid, mat, opt, as_stream(stream), &ch, &ncand);
+            mm_status r = autotune(grid, mat, opt, as_stream(stream), d_workspace, ws_bytes, &ch, &ncand);
             if (r != MM_OK) return r;
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune_cache[key] = ch;
@@ -1803,6 +2005,7 @@ mm_status mm_destroy(mm_sim* s)
     if (!s) return MM_OK;
     (void)hipStreamSynchronize(s->stream);
     drop_graph(s);
+    drop_bwd_graphs(s);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->own_ws) (void)hipFree(s->ws);
@@ -1955,7 +2158,7 @@ mm_status mm_get_energy(mm_sim* s, double out[5])
 {
     if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
     if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
-    double r[8];
+    double r[kRedSlots];
     mm_status st = s->p.prec == MM_F32 ? reduce_impl<float>(s, r) : reduce_impl<double>(s, r);
     if (st != MM_OK) return st;
     if (r[7] != 0.0) return fail(MM_ENONFINITE, "m holds %.0f non-finite cells", r[7]);
@@ -1972,7 +2175,7 @@ mm_status mm_get_mean_m(mm_sim* s, double out[3])
 {
     if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
     if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
-    double r[8];
+    double r[kRedSlots];
     const uint32_t keep = s->flags;
     s->flags |= MM_NO_DEMAG;  // the mean needs no field
     mm_status st = s->p.prec == MM_F32 ? reduce_impl<float>(s, r) : reduce_impl<double>(s, r);
@@ -1980,6 +2183,18 @@ mm_status mm_get_mean_m(mm_sim* s, double out[3])
     if (st != MM_OK) return st;
     if (r[7] != 0.0) return fail(MM_ENONFINITE, "m holds %.0f non-finite cells", r[7]);
     for (int a = 0; a < 3; ++a) out[a] = r[4 + a] / (double)s->p.N;
+    return MM_OK;
+}
+
+mm_status mm_get_max_torque(mm_sim* s, double* out)
+{
+    if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
+    if (!s->has_m) return fail(MM_ESTATE, "m has not been set");
+    double r[kRedSlots];
+    mm_status st = s->p.prec == MM_F32 ? reduce_impl<float>(s, r) : reduce_impl<double>(s, r);
+    if (st != MM_OK) return st;
+    if (r[7] != 0.0) return fail(MM_ENONFINITE, "m holds %.0f non-finite cells", r[7]);
+    *out = s->mat.Ms * r[8];  // reduced torque |m x h| -> A/m
     return MM_OK;
 }
 
@@ -2041,6 +2256,18 @@ mm_status mm_rollout(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, v
     if (!s->has_m) return fail(MM_ESTATE, "mm_rollout before mm_set_m");
     return s->p.prec == MM_F32 ? rollout_impl<float>(s, nsteps, dt, ckpt_every, (float*)d_ckpt)
                                : rollout_impl<double>(s, nsteps, dt, ckpt_every, (double*)d_ckpt);
+}
+
+mm_status mm_normalize_backward(mm_sim* s, const void* d_v, const void* d_gu, void* d_gv)
+{
+    if (!s || !d_v || !d_gu || !d_gv) return fail(MM_EINVAL, "NULL argument");
+    if (s->p.prec == MM_F32)
+        HIP_TRY(launch_normalize_vjp<float>(static_cast<const float*>(d_v), static_cast<const float*>(d_gu),
+                                            static_cast<float*>(d_gv), s->p.N, s->stream));
+    else
+        HIP_TRY(launch_normalize_vjp<double>(static_cast<const double*>(d_v), static_cast<const double*>(d_gu),
+                                             static_cast<double*>(d_gv), s->p.N, s->stream));
+    return MM_OK;
 }
 
 mm_status mm_adjoint_workspace_query(mm_sim* s, int64_t ckpt_every, size_t* bytes)
@@ -2263,6 +2490,7 @@ mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out)
     out->cells = b->L.cells;
     out->n = b->n;
     out->pow2_pad = (b->flags & MM_POW2_PAD) ? 1 : 0;
+    out->fast_pad = (b->flags & MM_FAST_PAD) ? 1 : 0;
     out->size_classes = b->L.fast ? 1 : 0;
     out->tuned = b->tuned;
     out->tune_candidates = b->tune_candidates;
@@ -2297,6 +2525,15 @@ mm_status mm_batch_get_m(mm_batch* b, void* out, int on_device)
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
     if (!on_device) HIP_TRY(hipStreamSynchronize(b->stream));
     return MM_OK;
+}
+
+mm_status mm_batch_get_field(mm_batch* b, int32_t term, void* out, int on_device)
+{
+    if (!b || !out) return fail(MM_EINVAL, "batch or out is NULL");
+    if (term < 0 || term > 4) return fail(MM_EINVAL, "term must be 0..4");
+    if (!b->has_m) return fail(MM_ESTATE, "m has not been set");
+    return b->L.prec == MM_F32 ? batch_field_impl<float>(b, term, out, on_device)
+                               : batch_field_impl<double>(b, term, out, on_device);
 }
 
 mm_status mm_batch_step(mm_batch* b, int64_t nsteps, double dt)

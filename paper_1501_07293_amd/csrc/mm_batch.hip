@@ -186,7 +186,7 @@ __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void kbf_xinv(BatchClass<T>
 }
 
 template <typename T, int P, bool INV>
-__global__ __launch_bounds__(256) void kbf_yline(BatchClass<T> c)
+__global__ __launch_bounds__(yline_lines<P>() * (P / Sched<P>::R0)) void kbf_yline(BatchClass<T> c)
 {
     __shared__ cpx<T> lds[yline_lds_elems<P>()];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -242,9 +242,9 @@ static bool class_launch(int kind, const BatchClass<T>& c, int tiles, int invers
     case 1:
         if constexpr (P >= 16) {
             if (inverse)
-                hipLaunchKernelGGL((kbf_yline<T, P, true>), dim3(tiles), dim3(256), 0, s, c);
+                hipLaunchKernelGGL((kbf_yline<T, P, true>), dim3(tiles), dim3(yline_lines<P>() * TL), 0, s, c);
             else
-                hipLaunchKernelGGL((kbf_yline<T, P, false>), dim3(tiles), dim3(256), 0, s, c);
+                hipLaunchKernelGGL((kbf_yline<T, P, false>), dim3(tiles), dim3(yline_lines<P>() * TL), 0, s, c);
             return true;
         }
         return false;
@@ -274,7 +274,11 @@ bool launch_batch_class(int kind, int P, const BatchClass<T>& c, int tiles, int 
     case 16: return class_launch<T, 16>(kind, c, tiles, inverse, s);
     case 32: return class_launch<T, 32>(kind, c, tiles, inverse, s);
     case 64: return class_launch<T, 64>(kind, c, tiles, inverse, s);
+    case 96: return class_launch<T, 96>(kind, c, tiles, inverse, s);
     case 128: return class_launch<T, 128>(kind, c, tiles, inverse, s);
+    case 160: return class_launch<T, 160>(kind, c, tiles, inverse, s);
+    case 192: return class_launch<T, 192>(kind, c, tiles, inverse, s);
+    case 224: return class_launch<T, 224>(kind, c, tiles, inverse, s);
     case 256: return class_launch<T, 256>(kind, c, tiles, inverse, s);
     case 512: return class_launch<T, 512>(kind, c, tiles, inverse, s);
     case 1024: return class_launch<T, 1024>(kind, c, tiles, inverse, s);

@@ -51,23 +51,29 @@ __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspa
 template <typename T, bool INV, bool FULL>
 static bool yline_dispatch(const YLineArgs& a, int P, hipStream_t s)
 {
-    auto go = [&](auto kern, int tl) {
-        const int L = 256 / tl;
+    auto go = [&](auto kern, int L, int tl) {
         const int grid = (a.nlines + L - 1) / L;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(L * tl), 0, s, a);
         return true;
     };
+#define MM_YCASE(PP) \
+    case PP: return go(k_yline<T, PP, INV, FULL>, yline_lines<PP>(), PP / Sched<PP>::R0);
     switch (P) {
-    case 16: return go(k_yline<T, 16, INV, FULL>, 16 / Sched<16>::R0);
-    case 32: return go(k_yline<T, 32, INV, FULL>, 32 / Sched<32>::R0);
-    case 64: return go(k_yline<T, 64, INV, FULL>, 64 / Sched<64>::R0);
-    case 128: return go(k_yline<T, 128, INV, FULL>, 128 / Sched<128>::R0);
-    case 256: return go(k_yline<T, 256, INV, FULL>, 256 / Sched<256>::R0);
-    case 512: return go(k_yline<T, 512, INV, FULL>, 512 / Sched<512>::R0);
-    case 1024: return go(k_yline<T, 1024, INV, FULL>, 1024 / Sched<1024>::R0);
-    case 2048: return go(k_yline<T, 2048, INV, FULL>, 2048 / Sched<2048>::R0);
+        MM_YCASE(16)
+        MM_YCASE(32)
+        MM_YCASE(64)
+        MM_YCASE(96)
+        MM_YCASE(128)
+        MM_YCASE(160)
+        MM_YCASE(192)
+        MM_YCASE(224)
+        MM_YCASE(256)
+        MM_YCASE(512)
+        MM_YCASE(1024)
+        MM_YCASE(2048)
     default: return false;
     }
+#undef MM_YCASE
 }
 
 template <typename T>
@@ -104,7 +110,11 @@ static bool xline_dispatch(const XLineArgs& a, int P, hipStream_t s)
         MM_XCASE(16)
         MM_XCASE(32)
         MM_XCASE(64)
+        MM_XCASE(96)
         MM_XCASE(128)
+        MM_XCASE(160)
+        MM_XCASE(192)
+        MM_XCASE(224)
         MM_XCASE(256)
         MM_XCASE(512)
         MM_XCASE(1024)
@@ -186,7 +196,11 @@ static bool kspace_y_dispatch(const KyArgs& a, int P, hipStream_t s)
         MM_KYCASE(16)
         MM_KYCASE(32)
         MM_KYCASE(64)
+        MM_KYCASE(96)
         MM_KYCASE(128)
+        MM_KYCASE(160)
+        MM_KYCASE(192)
+        MM_KYCASE(224)
         MM_KYCASE(256)
         MM_KYCASE(512)
         MM_KYCASE(1024)
@@ -214,7 +228,11 @@ int fast_first_radix(int P)
     case 16: return Sched<16>::R0;
     case 32: return Sched<32>::R0;
     case 64: return Sched<64>::R0;
+    case 96: return Sched<96>::R0;
     case 128: return Sched<128>::R0;
+    case 160: return Sched<160>::R0;
+    case 192: return Sched<192>::R0;
+    case 224: return Sched<224>::R0;
     case 256: return Sched<256>::R0;
     case 512: return Sched<512>::R0;
     case 1024: return Sched<1024>::R0;
@@ -229,7 +247,11 @@ int fast_ky_lines(int P)
     case 16: return ky_lines<16>();
     case 32: return ky_lines<32>();
     case 64: return ky_lines<64>();
+    case 96: return ky_lines<96>();
     case 128: return ky_lines<128>();
+    case 160: return ky_lines<160>();
+    case 192: return ky_lines<192>();
+    case 224: return ky_lines<224>();
     case 256: return ky_lines<256>();
     case 512: return ky_lines<512>();
     case 1024: return ky_lines<1024>();

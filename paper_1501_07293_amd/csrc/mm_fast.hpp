@@ -43,64 +43,80 @@ __device__ constexpr int pad16(int e) { return e + (e >> 4); }
 template <int P>
 constexpr int padded_len() { return P + P / 16 + 1; }
 
+// Butterflies per thread in stage S >= 1: a line has P / R butterflies of radix
+// R and TL = P / R0 threads, so R0 / R each when R divides R0 (every power-of-two
+// schedule); otherwise (a stage of radix 3, 5 or 7 after a first radix of 16)
+// the last round is partly idle.
+template <int P, int S>
+constexpr int stage_nb() { return (Sched<P>::R0 + radix_of<P, S>() - 1) / radix_of<P, S>(); }
+
 // Twiddles of stage S >= 1 for one thread: w[q][r - 1] = tw[r k ts] for its
-// q-th butterfly.
+// q-th butterfly (k < p, so an idle butterfly's index stays inside the table).
 template <typename T, int P, int S>
 struct StageTw {
-    static constexpr int R = radix_of<P, S>(), NB = Sched<P>::R0 / R;
+    static constexpr int R = radix_of<P, S>(), NB = stage_nb<P, S>();
     cpx<T> w[NB][R - 1];
     __device__ inline void load(int u, const cpx<T>* __restrict__ tw)
     {
         constexpr int TL = P / Sched<P>::R0, p = span_of<P, S>(), m = P / R, ts = m / p;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const int k = (u + TL * q) & (p - 1);
+            const int k = (int)((unsigned)(u + TL * q) % (unsigned)p);
 #pragma unroll
             for (int r = 1; r < R; ++r) w[q][r - 1] = tw[r * k * ts];
         }
     }
 };
 
-// Stage S >= 1 on one LDS line: each thread does R0/R butterflies.  Reads all,
-// barrier, writes all, barrier.
+// Stage S >= 1 on one LDS line: each thread does up to NB butterflies.  Reads
+// all, barrier, writes all, barrier.
 template <typename T, int P, int S>
 __device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R;
+    constexpr int p = span_of<P, S>(), m = P / R, NB = stage_nb<P, S>();
+    constexpr bool EXACT = NB * TL == m;
     cpx<T> v[NB][R];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q, k = i & (p - 1);
+        const int i = u + TL * q, k = (int)((unsigned)i % (unsigned)p);
+        if (EXACT || i < m) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = ln[pad16(i + r * m)];
-        if (k != 0) {
+            for (int r = 0; r < R; ++r) v[q][r] = ln[pad16(i + r * m)];
+            if (k != 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], W.w[q][r - 1]);
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], W.w[q][r - 1]);
+            }
+            Dft<T, R>::run(v[q]);
         }
-        Dft<T, R>::run(v[q]);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int i = u + TL * q, k = i & (p - 1), j = (i - k) * R + k;
+        const int i = u + TL * q, k = (int)((unsigned)i % (unsigned)p), j = (i - k) * R + k;
+        if (EXACT || i < m) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) ln[pad16(j + r * p)] = v[q][r];
+            for (int r = 0; r < R; ++r) ln[pad16(j + r * p)] = v[q][r];
+        }
     }
     __syncthreads();
 }
 
 // Last stage: outputs land at natural index i + r * P/R; handed to `put`.  HALF:
-// only the outputs below P / 2 (r < R / 2, as i < P / R) are formed.
+// only the outputs below P / 2 are formed (r < R / 2 for an even last radix, as
+// i < P / R).
 template <typename T, int P, int S, bool HALF, typename Put>
 __device__ inline void last_stage(const cpx<T>* ln, int u, const StageTw<T, P, S>& W, Put put)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
-    constexpr int p = span_of<P, S>(), m = P / R, NB = R0 / R;
+    constexpr int p = span_of<P, S>(), m = P / R, NB = stage_nb<P, S>();
+    constexpr bool EXACT = NB * TL == m;
     static_assert(p == m, "last stage spans P / R");
+    static_assert(!HALF || R % 2 == 0, "pruned schedules end on an even radix");
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int i = u + TL * q;  // < m = p, so the twiddle index k of StageTw is i
+        if (!EXACT && i >= m) break;
         cpx<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = ln[pad16(i + r * m)];
@@ -193,13 +209,18 @@ __device__ inline void fft_reg(cpx<T>* x, const cpx<T>* __restrict__ tw)
 }
 
 // ------------------------------------------------------------------ y lines
+// Lines per work-group of the y passes (L * TL <= 256 threads; with a mixed-radix
+// length TL = P / R0 need not divide 256, and the work-group has L * TL threads).
+template <int P>
+constexpr int yline_lines() { return 256 / (P / Sched<P>::R0); }
+
 template <typename T, int P, bool INV, bool FULL = false>
 __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = 256 / TL, LP = padded_len<P>();
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = yline_lines<P>(), LP = padded_len<P>();
     const int l = threadIdx.x / TL, u = threadIdx.x % TL;
     const int line = tile * L + l;
-    const bool ok = line < a.nlines;
+    const bool ok = line < a.nlines;  // launched with L * TL threads
     cpx<T>* g = (cpx<T>*)a.buf + (int64_t)(ok ? line : 0) * a.line_stride;
     const cpx<T>* tw = (const cpx<T>*)a.tw;
     LineTw<T, P> W;
@@ -640,7 +661,7 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
 
 // LDS entries (complex) each body needs.
 template <int P>
-constexpr int yline_lds_elems() { return (256 / (P / Sched<P>::R0)) * padded_len<P>(); }
+constexpr int yline_lds_elems() { return yline_lines<P>() * padded_len<P>(); }
 template <int P, int L>
 constexpr int xfwd_lds_elems() { return L * padded_len<P>(); }
 template <int P, int L>

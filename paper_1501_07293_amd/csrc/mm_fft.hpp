@@ -234,6 +234,13 @@ template <> struct Sched<512> { static constexpr int NS = 3, R0 = 8, R1 = 8, R2 
 template <> struct Sched<1024> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 4; };
 template <> struct Sched<2048> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 8; };
 template <> struct Sched<4096> { static constexpr int NS = 3, R0 = 16, R1 = 16, R2 = 16; };
+// mixed-radix lengths 32 q (q = 3, 5, 6, 7) for the line passes: a first radix of
+// 16, the odd factor in the middle, an even radix last (the pruned inverse keeps
+// the outputs below P / 2 by dropping the upper half of the last butterflies)
+template <> struct Sched<96> { static constexpr int NS = 3, R0 = 16, R1 = 3, R2 = 2; };
+template <> struct Sched<160> { static constexpr int NS = 3, R0 = 16, R1 = 5, R2 = 2; };
+template <> struct Sched<192> { static constexpr int NS = 3, R0 = 16, R1 = 3, R2 = 4; };
+template <> struct Sched<224> { static constexpr int NS = 3, R0 = 16, R1 = 7, R2 = 2; };
 
 // ---------------------------------------------------------------- LDS geometry
 // Line l, element e sits at (l % LI) * LSi + (l / LI) * LSo + e * ES.

@@ -230,8 +230,9 @@ hipError_t launch_field_term(const LlgArgs<T>& a, int term, T Ms, T* out, hipStr
 
 // FP64 reductions over m (and hd): out[0] = sum |dm|^2 over neighbour pairs,
 // out[1] = sum ku_red (my^2 + mz^2), out[2] = sum m.hd, out[3] = sum m.hext,
-// out[4..6] = sum m, out[7] = count of non-finite entries.  partial holds
-// nblocks*8 doubles.
+// out[4..6] = sum m, out[7] = count of non-finite entries, out[8] = max over the
+// cells of |m x h_eff| (reduced units).  partial holds nblocks * kRedSlots doubles.
+constexpr int kRedSlots = 9;
 // row = {t, sums[4..6] * inv_n}: one sample of the mean-magnetisation trace
 hipError_t launch_trace_row(const double* sums, double inv_n, double t, double* row, hipStream_t s);
 template <typename T>
@@ -261,6 +262,9 @@ template <typename T>
 hipError_t launch_adj_nu(const AdjArgs<T>& a, const T* ms, const T* hs, hipStream_t s);
 template <typename T>
 hipError_t launch_adj_apply(const AdjArgs<T>& a, T cmu, T ca, hipStream_t s);
+// g_v = (g_u - u (u . g_u)) / |v| per cell, u = v / |v|: the VJP of the normalisation.
+template <typename T>
+hipError_t launch_normalize_vjp(const T* v, const T* gu, T* gv, int64_t N, hipStream_t s);
 
 // ---------------------------------------------------------------- batched
 // One grid of a batch (device-resident descriptor).  Offsets count elements

@@ -116,12 +116,18 @@ __global__ __launch_bounds__(256) void k_field_term(LlgArgs<T> a, int term, T Ms
 
 constexpr int kRedThreads = 256;
 
+// One thread block's partial sums over its cells (grid-stride loop), FP64 from
+// working-precision inputs: slots 0-3 the energy sums of Eq. 1 (exchange pairs,
+// anisotropy, demag, applied), 4-6 the sum of m, 7 the count of non-finite
+// cells, and slot 8 the largest torque |m x h| over the cells, h the reduced
+// effective field of Eq. 3 (a maximum, not a sum).
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(LlgArgs<T> a, double* partial)
 {
-    __shared__ double sh[8][kRedThreads];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __shared__ double sh[kRedSlots][kRedThreads];
+    double acc[kRedSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t N = a.N, sy = a.nx, sz = (int64_t)a.nx * a.ny;
+    const double cex = (double)a.cex;
     for (int64_t c = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; c < N;
          c += (int64_t)gridDim.x * kRedThreads) {
         const int i = (int)(c % a.nx);
@@ -146,44 +152,78 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(LlgArgs<T> a, do
         }
         const double kan = a.ku ? (double)a.ku[c] : (double)a.can;
         acc[1] += kan * (m[1] * m[1] + m[2] * m[2]);
-        if (a.hd)
-            acc[2] += m[0] * (double)a.hd[c] + m[1] * (double)a.hd[N + c] + m[2] * (double)a.hd[2 * N + c];
+        double hd[3] = {0.0, 0.0, 0.0};
+        if (a.hd) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) hd[d] = (double)a.hd[d * N + c];
+        }
+        acc[2] += m[0] * hd[0] + m[1] * hd[1] + m[2] * hd[2];
         acc[3] += m[0] * (double)a.hx + m[1] * (double)a.hy + m[2] * (double)a.hz;
         acc[4] += m[0];
         acc[5] += m[1];
         acc[6] += m[2];
         if (!isfinite(m[0]) || !isfinite(m[1]) || !isfinite(m[2])) acc[7] += 1.0;
+        // the six neighbours of Eq. 5; a missing one (Eq. 7) is the cell itself
+        const int64_t six[6] = {i > 0 ? c - 1 : ((a.per & 1) ? c + (a.nx - 1) : c),
+                                i < a.nx - 1 ? c + 1 : ((a.per & 1) ? c - (a.nx - 1) : c),
+                                j > 0 ? c - sy : ((a.per & 2) ? c + (int64_t)(a.ny - 1) * sy : c),
+                                j < a.ny - 1 ? c + sy : ((a.per & 2) ? c - (int64_t)(a.ny - 1) * sy : c),
+                                k > 0 ? c - sz : ((a.per & 4) ? c + (int64_t)(a.nz - 1) * sz : c),
+                                k < a.nz - 1 ? c + sz : ((a.per & 4) ? c - (int64_t)(a.nz - 1) * sz : c)};
+        double h[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double lap = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) lap += (double)a.ms[d * N + six[q]] - m[d];
+            h[d] = cex * lap + hd[d];
+        }
+        h[0] += kan * m[0] + (double)a.hx;
+        h[1] += (double)a.hy;
+        h[2] += (double)a.hz;
+        const double tx = m[1] * h[2] - m[2] * h[1];
+        const double ty = m[2] * h[0] - m[0] * h[2];
+        const double tz = m[0] * h[1] - m[1] * h[0];
+        acc[8] = fmax(acc[8], sqrt(tx * tx + ty * ty + tz * tz));
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] = acc[q];
+    for (int q = 0; q < kRedSlots; ++q) sh[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
+        if ((int)threadIdx.x < w) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            for (int q = 0; q < kRedSlots - 1; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            sh[kRedSlots - 1][threadIdx.x] = fmax(sh[kRedSlots - 1][threadIdx.x],
+                                                  sh[kRedSlots - 1][threadIdx.x + w]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x < 8) partial[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < kRedSlots) partial[blockIdx.x * kRedSlots + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* partial, int nb,
                                                               double* out)
 {
-    __shared__ double sh[8][kRedThreads];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+    __shared__ double sh[kRedSlots][kRedThreads];
+    double acc[kRedSlots] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += partial[b * 8 + q];
+        for (int q = 0; q < kRedSlots - 1; ++q) acc[q] += partial[b * kRedSlots + q];
+        acc[kRedSlots - 1] = fmax(acc[kRedSlots - 1], partial[b * kRedSlots + kRedSlots - 1]);
+    }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] = acc[q];
+    for (int q = 0; q < kRedSlots; ++q) sh[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
+        if ((int)threadIdx.x < w) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            for (int q = 0; q < kRedSlots - 1; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            sh[kRedSlots - 1][threadIdx.x] = fmax(sh[kRedSlots - 1][threadIdx.x],
+                                                  sh[kRedSlots - 1][threadIdx.x + w]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x < 8) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < kRedSlots) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 template <typename T>

@@ -173,3 +173,37 @@ def batch_samples(n: int = 512, seed: int = 0, lo: int = 32, hi: int = 128,
         r = radius_mT * g.uniform() ** (1.0 / 3.0)
         out.append(BatchSample(nx, ny, nz, mT_to_Apm(d * r), int(g.integers(0, 2**31 - 1))))
     return out
+
+
+def observation_cells(nx: int, ny: int, nz: int, n: int = 1024, seed: int = 0) -> np.ndarray:
+    """Seeded sorted linear indices of at least n observation cells for sampled field
+    checks: all 8 corners, 4 cells on each of the 12 edges, 16 on each of the 6 faces,
+    the rest uniform over the grid (x fastest: index (k ny + j) nx + i)."""
+    g = rng(seed)
+    pts = []
+    for k in (0, nz - 1):
+        for j in (0, ny - 1):
+            for i in (0, nx - 1):
+                pts.append((i, j, k))
+    ends = {0: (0, nx - 1), 1: (0, ny - 1), 2: (0, nz - 1)}
+    size = (nx, ny, nz)
+    for axis in range(3):                       # edges along `axis`
+        o1, o2 = [a for a in range(3) if a != axis]
+        for e1 in ends[o1]:
+            for e2 in ends[o2]:
+                for t in g.integers(0, size[axis], 4):
+                    p = [0, 0, 0]
+                    p[axis], p[o1], p[o2] = int(t), e1, e2
+                    pts.append(tuple(p))
+    for axis in range(3):                       # faces normal to `axis`
+        o1, o2 = [a for a in range(3) if a != axis]
+        for e in ends[axis]:
+            for _ in range(16):
+                p = [0, 0, 0]
+                p[axis], p[o1], p[o2] = e, int(g.integers(0, size[o1])), int(g.integers(0, size[o2]))
+                pts.append(tuple(p))
+    idx = {(k * ny + j) * nx + i for i, j, k in pts}
+    N = nx * ny * nz
+    while len(idx) < min(n, N):
+        idx.update(int(v) for v in g.integers(0, N, n - len(idx)))
+    return np.array(sorted(idx), dtype=np.int64)

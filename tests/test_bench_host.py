@@ -119,12 +119,18 @@ def test_batch_step_model_sums_the_single_grid_model():
     N = 256
     real3, half_x, kern = 3 * N * 4, 3 * 8 * 33 * 8, 4 * 33 * 9 * 4
     one = (real3 + half_x) * 2 + (2 * half_x + kern) + 21 * 3 * N * 4 // 4
-    assert bench.batch_step_bytes([(32, 8, 1)], pow2=True) == 4 * one
+    assert bench.batch_step_bytes([(32, 8, 1)], "pow2") == 4 * one
     # a two-cell-thick grid takes the five-pass model with pz = 4
-    p = bench.grid_plan(33, 47, 2, pow2=True)
+    p = bench.grid_plan(33, 47, 2, "pow2")
     assert (p["px"], p["py"], p["pz"], p["passes"]) == (128, 128, 4, 5)
-    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], pow2=True) == \
+    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], "pow2") == \
         4 * one + 4 * sum(bench.algorithmic_bytes(p, 33, 47, 2, 4).values())
     # 7-smooth padding: 2n when 7-smooth (2 x 33 = 66 = 2 3 11 is not: 65 = 5 13 no, 66..70: 70)
     assert bench.pad_length(33, False) == 70 and bench.pad_length(32, False) == 64
     assert bench.pad_length(47, True) == 128 and bench.pad_length(2, True) == 4
+    # the specialised set: powers of two and 96, 160, 192, 224 along x and y, powers of
+    # two along z
+    assert [bench.pad_length(n, "fast") for n in (32, 33, 48, 49, 64, 65, 80, 81, 96, 97, 112, 113)] == \
+        [64, 96, 96, 128, 128, 160, 160, 192, 192, 224, 224, 256]
+    q = bench.grid_plan(33, 47, 2, "fast")
+    assert (q["px"], q["py"], q["pz"], q["hx"]) == (96, 96, 4, 49)

@@ -148,4 +148,93 @@ def test_rollout_autograd_matches_direct_backward():
     ckpt = sim2.rollout_ckpt(nsteps, c.dt, ck)
     dku, dm0 = sim2.backward(nsteps, c.dt, ck, ckpt, w)
     assert np.array_equal(to_np(ku_t.grad), to_np(dku.float()))
-    assert np.array_equal(to_np(m0_t.grad), to_np(dm0))
+    # the gradient of the raw m0 passes through the normalisation set_m applies
+    assert np.array_equal(to_np(m0_t.grad), to_np(sim2.normalize_backward(m0_t.detach(), dm0)))
+
+
+def test_fp32_adjoint_rms_error_against_finite_differences():
+    # The FP32 adjoint's error as a statistic of its own: over 32 seeded Gaussian
+    # directions v of the Ku map, (ad - fd) / rms_projection, with fd the Richardson-
+    # extrapolated central difference of the FP64 GPU forward and rms_projection
+    # = |grad|_2 |v|_2 / sqrt(N) (the rms of <grad, v> over such directions).  Its rms
+    # over the directions estimates |dg|_2 / |grad|_2, the relative error of the whole
+    # gradient, which must stay within 1e-4.
+    c, ku, m0, target = diff_problem()
+    gku = adjoint_grad(c, ku, m0, target, c.steps, "f32")
+    g = np.random.default_rng(40)
+    ratios = []
+    for trial in range(32):
+        v = g.standard_normal(ku.shape)
+        fd = fd_richardson(c, ku, m0, target, c.steps, v)
+        ad = float((gku * v).sum())
+        rms = np.sqrt((gku ** 2).sum()) * np.sqrt((v ** 2).sum() / v.size)
+        ratios.append((ad - fd) / rms)
+    err = float(np.sqrt(np.mean(np.square(ratios))))
+    print(f"FP32 adjoint vs FD over 32 directions: rms of (ad - fd)/rms_projection = {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_rollout_gradient_of_m0_matches_finite_differences():
+    # d loss / d m0 for a raw (not unit) m0: the forward normalises it per cell, so the
+    # gradient has no component along m0 and scales as 1/|m0|.  FP64, central
+    # differences of the FP64 forward along a seeded direction.
+    import torch
+    c, ku, m0, target = diff_problem()
+    nsteps = 40
+    scale = 0.5 + np.random.default_rng(41).uniform(size=(1,) + m0.shape[1:])
+    raw = m0 * scale
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                   precision="f64")
+    ku_t = torch.tensor(ku, dtype=torch.float64, device=sim.device)
+    m0_t = torch.tensor(raw, dtype=torch.float64, device=sim.device, requires_grad=True)
+    tgt = torch.tensor(target, dtype=torch.float64, device=sim.device)
+    out = mmag.rollout(sim, ku_t, m0_t, nsteps, c.dt, 16)
+    ((out - tgt) ** 2).sum(dim=0).mean().backward()
+    grad = to_np(m0_t.grad)
+    assert np.abs((grad * m0).sum(axis=0)).max() <= 1e-12 * np.abs(grad).max()
+    v = np.random.default_rng(42).standard_normal(raw.shape)
+    eps = 1e-4
+    fd = (loss_fp64(c, ku, raw + eps * v, target, nsteps)
+          - loss_fp64(c, ku, raw - eps * v, target, nsteps)) / (2 * eps)
+    ad = float((grad * v).sum())
+    print(f"m0 gradient: adjoint {ad:.9e}  fd {fd:.9e}")
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+
+
+def test_two_rollouts_on_one_handle_before_backward():
+    # Each rollout keeps its own Ku map, field and damping: two rollouts on the same
+    # handle (different maps, a field change in between) and one backward give each
+    # map the gradient a handle of its own gives it.
+    import torch
+    c, ku, m0, target = diff_problem()
+    nsteps, ck = 30, 10
+    g = np.random.default_rng(43)
+    ku_b = ku + 30.0 * g.standard_normal(ku.shape)
+    hext_b = mT_to_Apm([3.0, -1.0, 0.5])
+    w_a = g.standard_normal(m0.shape)
+    w_b = g.standard_normal(m0.shape)
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=c.alpha, gamma=c.gamma,
+                   precision="f64")
+    ka = torch.tensor(ku, dtype=torch.float64, device=sim.device, requires_grad=True)
+    kb = torch.tensor(ku_b, dtype=torch.float64, device=sim.device, requires_grad=True)
+    m0_t = torch.tensor(m0, dtype=torch.float64, device=sim.device)
+    out_a = mmag.rollout(sim, ka, m0_t, nsteps, c.dt, ck)
+    sim.set_hext(hext_b)
+    sim.set_alpha(0.3)
+    out_b = mmag.rollout(sim, kb, m0_t, nsteps, c.dt, ck)
+    sim.set_ku_map(None)
+    sim.set_hext((0.0, 0.0, 0.0))
+    loss = (out_a * torch.tensor(w_a, device=sim.device)).sum() + \
+        (out_b * torch.tensor(w_b, device=sim.device)).sum()
+    loss.backward()
+    for kmap, hext, alpha, w, got in ((ku, (0.0, 0.0, 0.0), c.alpha, w_a, ka.grad),
+                                      (ku_b, hext_b, 0.3, w_b, kb.grad)):
+        ref = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=0.0, alpha=alpha, gamma=c.gamma,
+                       precision="f64")
+        ref.set_hext(hext)
+        ref.set_ku_map(kmap)
+        ref.set_m(m0)
+        ckpt = ref.rollout_ckpt(nsteps, c.dt, ck)
+        dku, _ = ref.backward(nsteps, c.dt, ck, ckpt, torch.tensor(w, device=ref.device),
+                              want_dm0=False)
+        assert np.array_equal(to_np(got), to_np(dku))

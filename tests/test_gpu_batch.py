@@ -21,11 +21,12 @@ def fields_for(n, seed=0):
     return mT_to_Apm(g.uniform(-40, 40, size=(n, 3)))
 
 
-def run_single(grid, hext, m0, precision, nsteps, pow2=False, generic=None):
+def run_single(grid, hext, m0, precision, nsteps, pow2=False, generic=None, fast=False):
     nx, ny, nz = grid
     sim = mmag.Sim(nx, ny, nz, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                   precision=precision, generic_fft=(not pow2) if generic is None else generic,
-                   threads=256, pow2_pad=pow2)
+                   precision=precision,
+                   generic_fft=(not (pow2 or fast)) if generic is None else generic,
+                   threads=256, pow2_pad=pow2, fast_pad=fast)
     sim.set_hext(hext)
     sim.set_m(m0)
     sim.step(nsteps, C.dt)
@@ -35,24 +36,26 @@ def run_single(grid, hext, m0, precision, nsteps, pow2=False, generic=None):
 FAST_MIXED = [g for g in MIXED if min(g[0], g[1]) >= 8]   # power-of-two padding >= 16
 
 
-@pytest.mark.parametrize("pow2", [False, True])
+@pytest.mark.parametrize("pad", ["7-smooth", "pow2", "fast"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_batch_matches_single_grid_runs(precision, pow2):
+def test_batch_matches_single_grid_runs(precision, pad):
     # runtime-radix passes on 7-smooth padding, or size classes of the specialised
-    # passes on power-of-two padding: each grid as if run alone
-    grids = FAST_MIXED if pow2 else MIXED
+    # passes on power-of-two or specialised-set padding: each grid as if run alone
+    pow2, fast = pad == "pow2", pad == "fast"
+    grids = FAST_MIXED if (pow2 or fast) else MIXED
     hext = fields_for(len(grids))
     m0 = [random_unit_m((3, g[2], g[1], g[0]), seed=100 + i) for i, g in enumerate(grids)]
     b = mmag.BatchSim(grids, C.cell, Ms=C.Ms, A=C.A, Ku=C.Ku, alpha=C.alpha, gamma=C.gamma,
-                      hext=hext, precision=precision, pow2_pad=pow2)
+                      hext=hext, precision=precision, pow2_pad=pow2, fast_pad=fast)
+    assert b.info()["size_classes"] == int(pow2 or fast)
     b.set_m(m0)
     b.step(20, C.dt)
     got = [to_np(x) for x in b.get_m()]
     worst = 0.0
     for i, g in enumerate(grids):
-        ref = run_single(g, hext[i], m0[i], precision, 20, pow2=pow2)
+        ref = run_single(g, hext[i], m0[i], precision, 20, pow2=pow2, fast=fast)
         worst = max(worst, float(np.abs(got[i] - ref).max()))
-    print(f"batch vs single-grid runs ({precision}, pow2={pow2}): max |dm| = {worst:.3e}")
+    print(f"batch vs single-grid runs ({precision}, {pad}): max |dm| = {worst:.3e}")
     assert worst <= (1e-13 if precision == "f64" else 1e-6)
 
 
@@ -172,15 +175,15 @@ def test_autotuned_batch_matches_single_grid_runs_on_its_layout(precision):
                       hext=hext, precision=precision, autotune=True)
     info = b.info()
     print(f"autotuned batch ({precision}): {info}")
-    assert info["tuned"] == 1 and 2 <= info["candidates"] <= 3
+    assert info["tuned"] == 1 and 2 <= info["candidates"] <= 4
     assert info["tuned_demag_ms"] > 0 and info["n"] == len(grids) and info["cells"] == b.cells
-    assert not (info["size_classes"] and not info["pow2_pad"])
+    assert not (info["size_classes"] and not (info["pow2_pad"] or info["fast_pad"]))
     b.set_m(m0)
     b.step(20, C.dt)
     got = [to_np(x) for x in b.get_m()]
     for i, g in enumerate(grids):
         ref = run_single(g, hext[i], m0[i], precision, 20, pow2=bool(info["pow2_pad"]),
-                         generic=not info["size_classes"])
+                         generic=not info["size_classes"], fast=bool(info["fast_pad"]))
         err = np.abs(got[i] - ref).max()
         assert err <= (1e-13 if precision == "f64" else 1e-6), (g, err)
 
