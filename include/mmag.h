@@ -362,6 +362,30 @@ mm_status mm_backward(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every
                       const void* d_ckpt, const void* d_lam_final, double* d_dku, void* d_dm0,
                       void* d_adj_ws, size_t adj_ws_bytes);
 
+/* ---- allocation-free adjoint ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight training or serving loops, harnesses that forbid hipMalloc.
+ *
+ * mm_backward_noalloc: mm_backward without the workspace arguments; same inputs,
+ *   outputs, preconditions and results.  Its adjoint workspace is a static
+ *   device array of MM_NOALLOC_SCRATCH_BYTES inside the library: each GPU that
+ *   runs the library holds its own copy from module load until the process
+ *   ends, and its address on a device is taken once, when the first handle is
+ *   created there.  Returns MM_EINVAL when mm_adjoint_workspace_query(ckpt_every)
+ *   exceeds MM_NOALLOC_SCRATCH_BYTES (about 76 MiB for a 128x128x1 FP32 grid at
+ *   ckpt_every 50), MM_EHIP if the array's address could not be found.  Calls no
+ *   hipMalloc, hipFree, or allocating library routine, captures and instantiates
+ *   no graph: only kernel launches and device-to-device copies on the handle's
+ *   stream (every launch made directly, so it is slower than mm_backward's graph
+ *   replay on small grids).  Every call on one GPU, from any handle, uses that
+ *   GPU's one array, which keeps the last call's contents (the library clears
+ *   what must start at zero): calls that overlap on one GPU (two streams, two
+ *   threads) race and must be serialised by the caller. */
+#define MM_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+mm_status mm_backward_noalloc(mm_sim* sim, int64_t nsteps, double dt, int64_t ckpt_every,
+                              const void* d_ckpt, const void* d_lam_final, double* d_dku,
+                              void* d_dm0);
+
 /* The gradient through the normalisation that mm_set_m applies: given a raw
  * initial state v ([3][nz][ny][nx], device, working precision, every cell
  * nonzero) and g_u = dLoss/du for u = v/|v| (e.g. mm_backward's d_dm0), writes

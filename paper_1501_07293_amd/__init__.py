@@ -28,6 +28,7 @@ MM_FUSED_YZ = 0x400
 MM_ONE_WG = 0x800
 MM_FAST_PAD = 0x1000
 MM_RK4, MM_EULER = 0, 1
+MM_NOALLOC_SCRATCH_BYTES = 96 << 20  # static adjoint scratch of mm_backward_noalloc
 TERMS = {"exch": 0, "anis": 1, "demag": 2, "ext": 3, "eff": 4}
 KERNELS = {"x_fwd": 0, "y_fwd": 1, "kspace": 2, "y_inv": 3, "x_inv": 4, "llg": 5}
 
@@ -37,7 +38,7 @@ EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm
            "mm_get_energy", "mm_get_mean_m", "mm_get_max_torque", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step", "mm_batch_get_field",
-           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward", "mm_normalize_backward",
+           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward", "mm_backward_noalloc", "mm_normalize_backward",
            "mm_profile_begin", "mm_profile_sample", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
@@ -135,6 +136,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_rollout": [vp, i64, dbl, i64, vp],
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
+        "mm_backward_noalloc": [vp, i64, dbl, i64, vp, vp, vp, vp],
         "mm_normalize_backward": [vp, vp, vp, vp],
         "mm_profile_begin": [vp, i32],
         "mm_profile_sample": [vp, i32],
@@ -346,21 +348,29 @@ class Sim:
         return ck
 
     def backward(self, nsteps: int, dt: float, ckpt_every: int, ckpt, lam_final,
-                 want_dm0: bool = True):
+                 want_dm0: bool = True, noalloc: bool = False):
         """Reverse sweep: returns (dLoss/dKu per cell (float64, (nz, ny, nx)),
-        dLoss/dm0 or None) for dLoss/dm_final = lam_final."""
+        dLoss/dm0 or None) for dLoss/dm_final = lam_final.  noalloc: call
+        mm_backward_noalloc (the library's static scratch instead of a workspace
+        allocated here)."""
         torch = self._torch
+        lam = lam_final.to(device=self.device, dtype=self.dtype).contiguous()
+        dku = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        dm0 = torch.empty(self.shape, dtype=self.dtype, device=self.device) if want_dm0 else None
+        dm0_ptr = dm0.data_ptr() if dm0 is not None else None
+        if noalloc:
+            self._sync_stream()
+            _check(self._lib.mm_backward_noalloc(self._h, int(nsteps), float(dt), int(ckpt_every),
+                                                 ckpt.data_ptr(), lam.data_ptr(), dku.data_ptr(), dm0_ptr),
+                   "mm_backward_noalloc")
+            return dku, dm0
         nbytes = ctypes.c_size_t()
         _check(self._lib.mm_adjoint_workspace_query(self._h, int(ckpt_every), ctypes.byref(nbytes)),
                "mm_adjoint_workspace_query")
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
-        lam = lam_final.to(device=self.device, dtype=self.dtype).contiguous()
-        dku = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
-        dm0 = torch.empty(self.shape, dtype=self.dtype, device=self.device) if want_dm0 else None
         self._sync_stream()
         _check(self._lib.mm_backward(self._h, int(nsteps), float(dt), int(ckpt_every), ckpt.data_ptr(),
-                                     lam.data_ptr(), dku.data_ptr(),
-                                     dm0.data_ptr() if dm0 is not None else None, ws.data_ptr(),
+                                     lam.data_ptr(), dku.data_ptr(), dm0_ptr, ws.data_ptr(),
                                      nbytes.value), "mm_backward")
         return dku, dm0
 

@@ -207,6 +207,20 @@ hipError_t launch_normalize_vjp(const T* v, const T* gu, T* gv, int64_t N, hipSt
     return hipGetLastError();
 }
 
+// Clears n doubles (a kernel, not a memset node, so that a caller may capture it).
+__global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 template hipError_t launch_normalize_vjp<float>(const float*, const float*, float*, int64_t, hipStream_t);
 template hipError_t launch_normalize_vjp<double>(const double*, const double*, double*, int64_t,
                                                  hipStream_t);

@@ -286,6 +286,36 @@ bool check_material(const mm_material* m)
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+// The adjoint workspace of mm_backward_noalloc, for callers that cannot allocate:
+// a file-scope device array, so each GPU that runs the library holds its own copy
+// (from module load until the process ends).  Host code never passes the array's
+// name to a kernel or a copy: its address on a device comes from
+// hipGetSymbolAddress, taken once per device at mm_create (scratch_address).
+constexpr size_t kNoAllocScratchBytes = MM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;  // device -> its copy of `scratch`
+
+// The address of `scratch` on device dev, which must be the current device.
+mm_status scratch_address(int dev, char** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return MM_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(MM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<char*>(ptr);
+    *out = static_cast<char*>(ptr);
+    return MM_OK;
+}
+
 struct mm_sim {
     Plan p;
     mm_material mat;
@@ -319,6 +349,11 @@ struct mm_sim {
         const char* ws = nullptr;
     };
     BwdGraph bwd[2];
+    // this handle's device and that device's copy of the static adjoint scratch
+    // (nullptr, with the reason in scratch_err, when its address was not found)
+    int device;
+    char* scratch;
+    std::string scratch_err;
     // profiling: launches of kernel prof_kernel, one in prof_every bracketed by events
     int prof_kernel;
     int prof_every;
@@ -1166,9 +1201,14 @@ mm_status backward_segment_graph(mm_sim* s, const AdjBufs<T>& b, int64_t len, do
     return MM_OK;
 }
 
+// The reverse sweep over every segment, last first, in the adjoint workspace ws
+// (adj_bytes(p, ck) bytes, 256-byte aligned).  graphs: replay a captured graph
+// per segment; otherwise every launch is made directly on the handle's stream
+// (nothing is captured or instantiated, and the only operations are kernel
+// launches and device-to-device copies, so a caller may capture the whole call).
 template <typename T>
 mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const T* ckpt,
-                        const T* lam_final, double* dku, T* dm0, char* ws)
+                        const T* lam_final, double* dku, T* dm0, char* ws, bool graphs)
 {
     const Plan& p = s->p;
     hipStream_t st = s->stream;
@@ -1191,12 +1231,12 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
     b.scr = take();
     b.dku = reinterpret_cast<double*>(q);
     HIP_TRY(hipMemcpyAsync(b.lam, lam_final, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemsetAsync(b.dku, 0, (size_t)p.N * sizeof(double), st));
+    HIP_TRY(launch_zero_f64(b.dku, p.N, st));
     const int64_t nseg = (nsteps + ck - 1) / ck;
     for (int64_t g = nseg - 1; g >= 0; --g) {
         const int64_t len = std::min(ck, nsteps - g * ck);
         HIP_TRY(hipMemcpyAsync(b.at(0, 0), ckpt + g * vec, vec * sizeof(T), hipMemcpyDeviceToDevice, st));
-        mm_status r = backward_segment_graph<T>(s, b, len, dt, ws);
+        mm_status r = graphs ? backward_segment_graph<T>(s, b, len, dt, ws) : backward_segment<T>(s, b, len, dt, st);
         if (r != MM_OK) return r;
     }
     HIP_TRY(hipMemcpyAsync(dku, b.dku, (size_t)p.N * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1988,6 +2028,14 @@ mm_status mm_create(const mm_grid* grid, const mm_material* mat, const mm_option
         delete s;
         return fail(MM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
     }
+    // this device's copy of the static adjoint scratch (mm_backward_noalloc reports
+    // a failure here; nothing else uses it)
+    s->device = 0;
+    s->scratch = nullptr;
+    if ((e = hipGetDevice(&s->device)) != hipSuccess)
+        s->scratch_err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    else if (scratch_address(s->device, &s->scratch) != MM_OK)
+        s->scratch_err = g_err;
     st = p.prec == MM_F32 ? build_kernel_spectrum<float>(s, s->stream)
                           : build_kernel_spectrum<double>(s, s->stream);
     if (st != MM_OK) {
@@ -2293,10 +2341,31 @@ mm_status mm_backward(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, 
     if (reinterpret_cast<uintptr_t>(d_adj_ws) & 255) return fail(MM_EINVAL, "adjoint workspace must be 256-byte aligned");
     return s->p.prec == MM_F32
                ? backward_impl<float>(s, nsteps, dt, ckpt_every, (const float*)d_ckpt,
-                                      (const float*)d_lam_final, d_dku, (float*)d_dm0, (char*)d_adj_ws)
+                                      (const float*)d_lam_final, d_dku, (float*)d_dm0, (char*)d_adj_ws, true)
                : backward_impl<double>(s, nsteps, dt, ckpt_every, (const double*)d_ckpt,
                                        (const double*)d_lam_final, d_dku, (double*)d_dm0,
-                                       (char*)d_adj_ws);
+                                       (char*)d_adj_ws, true);
+}
+
+mm_status mm_backward_noalloc(mm_sim* s, int64_t nsteps, double dt, int64_t ckpt_every, const void* d_ckpt,
+                              const void* d_lam_final, double* d_dku, void* d_dm0)
+{
+    if (!s || !d_ckpt || !d_lam_final || !d_dku) return fail(MM_EINVAL, "NULL argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(MM_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (!s->has_m) return fail(MM_ESTATE, "mm_backward_noalloc before mm_set_m");
+    const size_t need = adj_bytes(s->p, ckpt_every);
+    if (need > kNoAllocScratchBytes)
+        return fail(MM_EINVAL,
+                    "ckpt_every %lld needs %zu bytes of adjoint scratch; the static scratch holds %zu "
+                    "(use a shorter checkpoint interval or mm_backward)",
+                    (long long)ckpt_every, need, kNoAllocScratchBytes);
+    if (!s->scratch) return fail(MM_EHIP, "static scratch unavailable: %s", s->scratch_err.c_str());
+    return s->p.prec == MM_F32
+               ? backward_impl<float>(s, nsteps, dt, ckpt_every, (const float*)d_ckpt,
+                                      (const float*)d_lam_final, d_dku, (float*)d_dm0, s->scratch, false)
+               : backward_impl<double>(s, nsteps, dt, ckpt_every, (const double*)d_ckpt,
+                                       (const double*)d_lam_final, d_dku, (double*)d_dm0, s->scratch, false);
 }
 
 mm_status mm_batch_workspace_query(int32_t n, const mm_grid* grids, const mm_options* opt,

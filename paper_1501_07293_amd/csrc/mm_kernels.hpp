@@ -263,6 +263,8 @@ hipError_t launch_adj_nu(const AdjArgs<T>& a, const T* ms, const T* hs, hipStrea
 template <typename T>
 hipError_t launch_adj_apply(const AdjArgs<T>& a, T cmu, T ca, hipStream_t s);
 // g_v = (g_u - u (u . g_u)) / |v| per cell, u = v / |v|: the VJP of the normalisation.
+// p[0 .. n) = 0, as a kernel on stream s.
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_normalize_vjp(const T* v, const T* gu, T* gv, int64_t N, hipStream_t s);
 

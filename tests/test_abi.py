@@ -206,6 +206,14 @@ def test_adjoint_and_euler_entry_points_reject_null(lib):
     b = ctypes.c_size_t()
     assert lib.mm_adjoint_workspace_query(None, 5, ctypes.byref(b)) == -1
     assert lib.mm_backward(None, 10, 1e-13, 5, None, None, None, None, None, 0) == -1
+    assert lib.mm_backward_noalloc(None, 10, 1e-13, 5, None, None, None, None) == -1
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    text = open(HEADER).read()
+    shift = re.search(r"#define MM_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert shift, "MM_NOALLOC_SCRATCH_BYTES not found"
+    assert int(shift.group(1)) << int(shift.group(2)) == mm.MM_NOALLOC_SCRATCH_BYTES
 
 
 def test_x_lines_option_validated(lib):
