@@ -159,10 +159,15 @@ def _pad(n: int, pad, line: bool) -> int:
 
 
 def grid_plan(nx: int, ny: int, nz: int, pad) -> dict:
-    """Padded sizes, stored x bins, schedule and octant size of one open-boundary grid."""
+    """Padded sizes, stored x bins, schedule and kernel-spectrum size of one
+    open-boundary grid.  Two cells thick with the specialised passes (power-of-two
+    or fast padding): the two-plane schedule (3 passes, 10 coefficient planes)."""
     px, py = _pad(nx, pad, True), _pad(ny, pad, True)
     pz = 1 if nz == 1 else _pad(nz, pad, False)
     hx = px // 2 + 1
+    if nz == 2 and pz == 4 and pad in (True, "pow2", "fast") and py <= 1024:
+        return {"px": px, "py": py, "pz": pz, "hx": hx, "passes": 3,
+                "spectrum_elems": 10 * hx * (py // 2 + 1)}
     ncomp = 6 if pz > 1 else 4
     return {"px": px, "py": py, "pz": pz, "hx": hx, "passes": 5 if pz > 1 else 3,
             "spectrum_elems": ncomp * (pz // 2 + 1) * hx * (py // 2 + 1)}
@@ -255,11 +260,13 @@ def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
 
 
 def batched_leg(steps: int, autotune: bool, warmup: int = 2, check: bool = False,
-                repeats: int = 5) -> dict:
+                repeats: int = 5, layout: str = "7smooth") -> dict:
     """512 uneven grids (nx, ny in [32, 128], nz in {1, 2}), FP32, one launch per pass
     over all grids, graph replay; value = total cells * steps / s.  autotune: the
-    layout (padding and pass family) is timed at creation; otherwise 7-smooth
-    padding with the runtime-radix passes."""
+    layout (padding and pass family) is timed at creation; otherwise `layout`:
+    "7smooth" (7-smooth padding, runtime-radix passes), "pow2" (power-of-two padding,
+    size-class passes) or "fast" (powers of two and 96, 160, 192, 224, size-class
+    passes)."""
     import torch
 
     import paper_1501_07293_amd as mm
@@ -269,7 +276,9 @@ def batched_leg(steps: int, autotune: bool, warmup: int = 2, check: bool = False
     grids = [(s.nx, s.ny, s.nz) for s in samples]
     hext = np.array([s.hext for s in samples])
     b = mm.BatchSim(grids, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
-                    hext=hext, precision="f32", graph=True, autotune=autotune)
+                    hext=hext, precision="f32", graph=True, autotune=autotune,
+                    pow2_pad=not autotune and layout == "pow2",
+                    fast_pad=not autotune and layout == "fast")
     info = b.info()
     b.set_m([synthetic.random_unit_m((3, s.nz, s.ny, s.nx), seed=s.seed) for s in samples])
     b.step(warmup, c.dt)
@@ -584,6 +593,10 @@ def main():
     ap.add_argument("--no-mid-leg", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--samples", type=int, default=1024)
+    ap.add_argument("--leg", default=None, choices=["batched", "adjoint", "mid"],
+                    help="run only this leg (FP32) and print its JSON record; for profiling")
+    ap.add_argument("--batch-layout", default="auto", choices=["auto", "7smooth", "pow2", "fast"],
+                    help="--leg batched: autotuned layout, or a fixed one")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -593,6 +606,19 @@ def main():
 
     import torch
     import synthetic
+
+    if args.leg is not None:
+        # one leg alone (no headline run): what a profiler wraps to see that leg's kernels
+        if args.leg == "batched":
+            rec = batched_leg(args.steps, autotune=args.batch_layout == "auto", warmup=args.warmup,
+                              check=not args.no_cpu_baseline, repeats=args.repeats,
+                              layout=args.batch_layout)
+        elif args.leg == "adjoint":
+            rec = adjoint_leg(check=not args.no_cpu_baseline)
+        else:
+            rec = mid_leg(args, args.steps)
+        print(json.dumps({"leg": args.leg, **rec}), flush=True)
+        return
 
     cfg = {"large": synthetic.LARGE, "mid": synthetic.MID, "small": synthetic.SMALL}[args.workload]
     esz = 4 if args.precision == "f32" else 8

@@ -163,9 +163,10 @@ typedef struct {
     int32_t hx;          /* px/2 + 1 stored half-spectrum bins along x */
     int32_t ncomp;       /* 6 kernel spectra, or 4 (xx, xy, yy, zz) when nz == 1 */
     int32_t threads;     /* FFT work-group size in use */
-    int64_t spectrum_elems; /* elements of the kernel-spectrum octant, ncomp*(pz/2+1)*hx*(py/2+1) */
+    int64_t spectrum_elems; /* elements of the kernel spectrum: the octant, ncomp*(pz/2+1)*hx*(py/2+1),
+                               or with two_plane the 10*hx*(py/2+1) coefficient planes */
     int32_t passes;      /* FFT passes per field evaluation (1 with MM_ONE_WG in use, 3 for
-                            nz == 1 or the fused y-z pass, else 5) */
+                            nz == 1, the two-plane schedule or the fused y-z pass, else 5) */
     double kernel_imag_ratio; /* max |Im| / max |Re| of the FP64 kernel spectrum (should be ~1e-16) */
     int32_t generic_fft; /* 1 when the runtime-radix passes are forced */
     int32_t tuned;       /* 1 when the schedule came from the autotuner */
@@ -173,6 +174,15 @@ typedef struct {
     double tuned_demag_ms; /* the chosen schedule's time per demag evaluation, ms (0 if not tuned) */
     int32_t x_lines;     /* row pairs per work-group of the specialised x forward pass */
     int32_t x_lines_inv; /* ... and of the specialised x inverse pass */
+    int32_t two_plane;   /* 1: the two-plane schedule of a grid two cells thick (nz == 2, open z,
+                            specialised y passes): the x passes and one y k-space pass that
+                            couples the two planes directly through the tensor planes at z
+                            offsets -1, 0, 1 (Eqs. 12-13 split along z, Eq. 14 in x and y); no
+                            z transform and no py-long spectrum in HBM.  The kernel spectrum is
+                            then 10 real planes [10][hx][py/2+1] scaled by 1/(px py): xx0, xx1,
+                            xy0, xy1, sxz, yy0, yy1, syz, zz0, zz1 (suffix 0: z offset 0; 1: z
+                            offset +1, the observer above the source; at offset +1 the xz and
+                            yz spectra are i sxz and i syz) */
 } mm_plan_info;
 
 typedef struct mm_sim mm_sim;
@@ -271,7 +281,9 @@ mm_status mm_get_plan(mm_sim* sim, mm_plan_info* out);
 
 /* Kernel-spectrum octant [ncomp][pz/2+1][hx][py/2+1] (ky fastest), working
  * precision, already scaled by 1/(px py pz) (the normalisation of the inverse
- * FFT).  Component order xx, xy, xz, yy, yz, zz, or xx, xy, yy, zz when ncomp == 4. */
+ * FFT).  Component order xx, xy, xz, yy, yz, zz, or xx, xy, yy, zz when ncomp == 4.
+ * With the two-plane schedule (mm_plan_info.two_plane) the 10 coefficient
+ * planes described there instead. */
 mm_status mm_get_kernel_spectrum(mm_sim* sim, void* out, int on_device);
 
 /* Demag tensor of Eqs. 10-11 over every offset |I|<nx, |J|<ny, |K|<nz, FP64,

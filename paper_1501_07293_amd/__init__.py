@@ -77,7 +77,7 @@ class PlanInfo(ctypes.Structure):
                 ("kernel_imag_ratio", ctypes.c_double), ("generic_fft", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32),
-                ("x_lines_inv", ctypes.c_int32)]
+                ("x_lines_inv", ctypes.c_int32), ("two_plane", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -335,6 +335,8 @@ class Sim:
         out = self._torch.empty(int(p["spectrum_elems"]), dtype=self.dtype, device=self.device)
         self._sync_stream()
         _check(self._lib.mm_get_kernel_spectrum(self._h, out.data_ptr(), 1), "mm_get_kernel_spectrum")
+        if p["two_plane"]:
+            return out.reshape(10, p["hx"], p["py"] // 2 + 1)
         return out.reshape(p["ncomp"], p["pz"] // 2 + 1, p["hx"], p["py"] // 2 + 1)
 
     # ----------------------------------------------------------- adjoint

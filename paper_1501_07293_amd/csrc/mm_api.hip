@@ -124,7 +124,10 @@ struct Plan {
     bool yz;                   // 3-D: the fused y-z pass replaces y forward, z k-space, y inverse
     bool wg1;                  // one work-group runs the whole demag evaluation (small grids)
     int images;                // images on each side beyond the nearest (periodic axes)
-    int64_t oct_elems;         // per component
+    bool zd;                   // two cells along z: the two-plane y k-space pass replaces y forward,
+                               // z k-space and y inverse (the z coupling taken directly)
+    int64_t oct_elems;         // per component (two-plane schedule: per coefficient plane)
+    int kplanes;               // blocks of oct_elems in the kernel region (ncomp, or 10)
     // workspace offsets
     size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_kern, o_twx, o_twy, o_twz;
     size_t o_twxd, o_twyd, o_twzd, o_red, o_redout, o_flags, o_setR, o_setS, total;
@@ -242,10 +245,21 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->x_lines = std::min(cap / p->Px, ldscap / (p->Px + 1));
     p->y_tw = std::max(1, std::min(64, cap / p->Py));
     p->k_tw = std::max(1, std::min(64, cap / (3 * last)));
+    // two cells along z with an open z axis (Pz = 4) and a specialised two-plane
+    // pass of length Py: no z transform and no Py-long spectrum in HBM
+    p->zd = p->nz == 2 && p->Pz == 4 && !(p->per & 4) && !p->yz && !p->wg1 &&
+            !(o->flags & MM_GENERIC_FFT) && fast_ky2_lines(p->Py) > 0 && p->ny <= p->Py &&
+            !(p->esz == 8 && p->Py > 1024);
     // spectrum [3][nz][hx][S_rows]: the y pass expands ny rows to Py in place on 3-D grids
     p->S_planes = p->nz;
-    p->S_rows = p->three_d ? p->Py : p->ny;
-    p->oct_elems = (int64_t)(p->Pz / 2 + 1) * (p->Py / 2 + 1) * p->hx;
+    p->S_rows = (p->three_d && !p->zd) ? p->Py : p->ny;
+    if (p->zd) {
+        p->oct_elems = (int64_t)(p->Py / 2 + 1) * p->hx;
+        p->kplanes = kTwoPlaneTablePlanes;
+    } else {
+        p->oct_elems = (int64_t)(p->Pz / 2 + 1) * (p->Py / 2 + 1) * p->hx;
+        p->kplanes = p->ncomp;
+    }
     // workspace
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -261,7 +275,7 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->o_hd = take(vec);
     p->o_ku = take((size_t)p->N * p->esz);
     p->o_S = take(3 * (size_t)p->S_planes * p->hx * p->S_rows * 2 * p->esz);
-    p->o_kern = take((size_t)p->ncomp * p->oct_elems * p->esz);
+    p->o_kern = take((size_t)p->kplanes * p->oct_elems * p->esz);
     p->o_twx = take((size_t)p->Px * 2 * p->esz);
     p->o_twy = take((size_t)p->Py * 2 * p->esz);
     p->o_twz = take((size_t)p->Pz * 2 * p->esz);
@@ -573,6 +587,15 @@ hipError_t pass_kspace_yz(const PassCtx& c, hipStream_t st)
 }
 
 template <typename T>
+hipError_t pass_kspace_y2(const PassCtx& c, hipStream_t st)
+{
+    const Plan& p = c.p;
+    const Ky2Args a{c.S, 2 * c.plane, c.plane, c.Sy, p.hx, p.ny, c.twy, c.kern, p.oct_elems, p.Py / 2 + 1};
+    if (!launch_kspace_y2<T>(a, p.Py, st)) return hipErrorInvalidValue;  // the plan checked P
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t pass_demag_1wg(const PassCtx& c, const T* m, T* hd, hipStream_t st)
 {
     const Plan& p = c.p;
@@ -614,6 +637,12 @@ mm_status demag(mm_sim* s, const T* msrc, T* hd, hipStream_t st)
     if (c.p.yz) {
         LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
         LAUNCH(KSPACE, pass_kspace_yz<T>(c, st));
+        LAUNCH(KX_INV, pass_x_inverse<T>(c, hd, st));
+        return MM_OK;
+    }
+    if (c.p.zd) {
+        LAUNCH(KX_FWD, pass_x_forward<T>(c, msrc, st));
+        LAUNCH(KSPACE, pass_kspace_y2<T>(c, st));
         LAUNCH(KX_INV, pass_x_inverse<T>(c, hd, st));
         return MM_OK;
     }
@@ -757,8 +786,16 @@ mm_status build_kernel_spectrum(mm_sim* s, hipStream_t st)
             z.tw = s->at<char>(p.o_twzd);
             HIP_TRY(launch_col_fft<double>(z, nt, st));
         }
-        HIP_TRY(launch_octant<T>(s->at<char>(p.o_kern) + (size_t)q * p.oct_elems * p.esz, Sd, p.hx,
-                                 p.Py, p.Pz, p.sxd, scale, stats, st));
+        if (p.zd) {
+            // planes: xx 0-1, xy 2-3, xz 4, yy 5-6, yz 7, zz 8-9
+            static const int first_plane[6] = {0, 2, 4, 5, 7, 8};
+            HIP_TRY(launch_table_z2<T>(s->at<char>(p.o_kern) + (size_t)first_plane[q] * p.oct_elems * p.esz,
+                                       Sd, comps[q], p.hx, p.Py, p.sxd, 1.0 / ((double)p.Px * p.Py), stats,
+                                       st));
+        } else {
+            HIP_TRY(launch_octant<T>(s->at<char>(p.o_kern) + (size_t)q * p.oct_elems * p.esz, Sd, p.hx,
+                                     p.Py, p.Pz, p.sxd, scale, stats, st));
+        }
     }
     unsigned long long h[2];
     HIP_TRY(hipMemcpyAsync(h, stats, sizeof h, hipMemcpyDeviceToHost, st));
@@ -1246,7 +1283,7 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
 
 // ---------------------------------------------------------------- batched
 struct BatchClassHost {
-    int kind;  // 0 x passes, 1 y passes, 2 z k-space, 3 y k-space
+    int kind;  // 0 x passes, 1 y passes, 2 z k-space, 3 y k-space, 5 two-plane y k-space
     int P;
     std::vector<int> members, prefix;
     size_t off;  // element offset of members, then prefix, in the device int array
@@ -1259,6 +1296,7 @@ bool fast_supported(int kind, int P, size_t esz)
     case 0: return P >= 16 && P <= (esz == 8 ? 1024 : 2048);
     case 1: return P >= 16 && P <= 2048;
     case 2: return P >= 2 && P <= (esz == 8 ? 32 : 64);
+    case 5: return fast_ky2_lines(P) > 0;
     default: return P >= 16 && P <= 1024;
     }
 }
@@ -1276,7 +1314,12 @@ struct BatchLayout {
     size_t o_desc, o_prefix, o_mn, o_ma, o_mb, o_acc, o_hd, o_S, o_kern, o_tw, o_flags, o_scratch, total;
     int prec;
     size_t esz;
+    bool plan_generic = false;  // the plans were built with the runtime-radix passes forced
 };
+
+mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* opt, bool classes,
+                             BatchLayout* L);
+mm_status batch_layout_offsets(int32_t n, BatchLayout* L);
 
 mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, BatchLayout* L)
 {
@@ -1286,7 +1329,30 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
         return fail(MM_ENOTSUP, "batches take open boundaries only (periodic axes set)");
     mm_options o = opt ? *opt : mm_options{};
     o.threads = 256;
-    L->plans.resize(n);
+    // size classes (the specialised passes) are wanted with power-of-two or fast
+    // padding; otherwise every grid runs the runtime-radix passes, whose plans
+    // must not take the two-plane schedule.  If some grid has no size class, the
+    // layout is built again that way.
+    const bool want_fast = (o.flags & (MM_POW2_PAD | MM_FAST_PAD)) && !(o.flags & MM_GENERIC_FFT);
+    for (int attempt = want_fast ? 0 : 1; attempt < 2; ++attempt) {
+        mm_options oa = o;
+        if (attempt == 1) oa.flags |= MM_GENERIC_FFT;
+        L->plan_generic = attempt == 1;
+        mm_status st = batch_layout_plans(n, grids, &oa, want_fast && attempt == 0, L);
+        if (st != MM_OK) return st;
+        if (L->fast || !want_fast) break;
+    }
+    return batch_layout_offsets(n, L);
+}
+
+mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* opt, bool classes,
+                             BatchLayout* L)
+{
+    const mm_options& o = *opt;
+    L->vec_elems = L->S_elems = L->kern_elems = L->tw_elems = L->cells = 0;
+    L->scratch = 0;
+    L->class_ints = 0;
+    L->plans.assign(n, Plan{});
     L->desc.resize(n);
     for (int q = 0; q < 5; ++q) L->prefix[q].assign(n + 1, 0);
     for (int s = 0; s < n; ++s) {
@@ -1323,7 +1389,7 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
         d.fz = p.fz;
         L->vec_elems += 3 * p.N;
         L->S_elems += 3 * (int64_t)p.nz * p.hx * p.S_rows;
-        L->kern_elems += (int64_t)p.ncomp * p.oct_elems;
+        L->kern_elems += (int64_t)p.kplanes * p.oct_elems;
         L->tw_elems += p.Px + p.Py + p.Pz;
         L->cells += p.N;
         L->scratch = std::max(L->scratch, p.total);
@@ -1338,10 +1404,10 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
     }
     L->prec = o.prec;
     L->esz = o.prec == MM_F32 ? 4 : 8;
-    // size classes for the specialised passes (power-of-two padding)
+    // size classes for the specialised passes (power-of-two or fast padding)
     L->fast = false;
     L->classes.clear();
-    if ((o.flags & (MM_POW2_PAD | MM_FAST_PAD)) && !(o.flags & MM_GENERIC_FFT)) {
+    if (classes) {
         bool ok = true;
         auto cls = [&](int kind, int P) -> BatchClassHost& {
             for (auto& c : L->classes)
@@ -1364,7 +1430,10 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
             };
             add(0, p.Px, p.nx, 3 * p.nz * ((p.ny + 15) / 16));
             if (!ok) break;
-            if (p.three_d) {
+            if (p.zd) {
+                const int L2 = fast_ky2_lines(p.Py);
+                add(5, p.Py, p.ny, (p.hx + L2 - 1) / L2);
+            } else if (p.three_d) {
                 const int Ly = 256 / (p.Py / std::max(1, fast_first_radix(p.Py)));
                 add(1, p.Py, p.ny, (3 * p.nz * p.hx + Ly - 1) / Ly);
                 if (!ok) break;
@@ -1387,6 +1456,11 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
             L->classes.clear();
         }
     }
+    return MM_OK;
+}
+
+mm_status batch_layout_offsets(int32_t n, BatchLayout* L)
+{
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -1471,6 +1545,7 @@ mm_status batch_demag(mm_batch* b, const T* in, hipStream_t st)
         if ((r = run_classes(1, 1, 0)) != MM_OK) return r;  // y forward
         if ((r = run_classes(2, 2, 0)) != MM_OK) return r;  // z k-space
         if ((r = run_classes(3, 3, 0)) != MM_OK) return r;  // y k-space
+        if ((r = run_classes(5, 5, 0)) != MM_OK) return r;  // two-plane y k-space
         if ((r = run_classes(1, 1, 1)) != MM_OK) return r;  // y inverse
         return run_classes(0, 4, 0);                         // x inverse
     }
@@ -2255,8 +2330,8 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->hx = s->p.hx;
     out->ncomp = s->p.ncomp;
     out->threads = s->p.nt;
-    out->spectrum_elems = (int64_t)s->p.ncomp * s->p.oct_elems;
-    out->passes = s->p.wg1 ? 1 : ((s->p.three_d && !s->p.yz) ? 5 : 3);
+    out->spectrum_elems = (int64_t)s->p.kplanes * s->p.oct_elems;
+    out->passes = s->p.wg1 ? 1 : ((s->p.three_d && !s->p.yz && !s->p.zd) ? 5 : 3);
     out->kernel_imag_ratio = s->imag_ratio;
     out->generic_fft = (s->flags & MM_GENERIC_FFT) ? 1 : 0;
     out->tuned = s->tuned;
@@ -2264,6 +2339,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->tuned_demag_ms = s->tuned_ms;
     out->x_lines = s->p.xl;
     out->x_lines_inv = s->p.xl_inv;
+    out->two_plane = s->p.zd ? 1 : 0;
     return MM_OK;
 }
 
@@ -2271,7 +2347,7 @@ mm_status mm_get_kernel_spectrum(mm_sim* s, void* out, int on_device)
 {
     if (!s || !out) return fail(MM_EINVAL, "sim or out is NULL");
     if (s->flags & MM_NO_DEMAG) return fail(MM_ESTATE, "handle was created without demag");
-    const size_t bytes = (size_t)s->p.ncomp * s->p.oct_elems * s->p.esz;
+    const size_t bytes = (size_t)s->p.kplanes * s->p.oct_elems * s->p.esz;
     HIP_TRY(hipMemcpyAsync(out, s->at<char>(s->p.o_kern), bytes,
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -2476,6 +2552,7 @@ static mm_status batch_build(int32_t n, const mm_grid* grids, const mm_material*
     mm_options o = opt ? *opt : mm_options{};
     o.threads = 256;
     o.flags &= ~(uint32_t)MM_USE_GRAPH;
+    if (BL.plan_generic) o.flags |= MM_GENERIC_FFT;  // the same plans (no two-plane schedule)
     for (int s = 0; s < n; ++s) {
         const Plan& p = BL.plans[s];
         const BatchDesc& d = BL.desc[s];
@@ -2484,7 +2561,7 @@ static mm_status batch_build(int32_t n, const mm_grid* grids, const mm_material*
         if (r != MM_OK) return bail(r);
         const size_t esz = BL.esz;
         hipError_t ce = hipMemcpyAsync(b->at<char>(BL.o_kern) + d.koff * esz, t->at<char>(p.o_kern),
-                                       (size_t)p.ncomp * p.oct_elems * esz, hipMemcpyDeviceToDevice, hs);
+                                       (size_t)p.kplanes * p.oct_elems * esz, hipMemcpyDeviceToDevice, hs);
         const size_t cz = 2 * esz;
         if (ce == hipSuccess)
             ce = hipMemcpyAsync(b->at<char>(BL.o_tw) + d.twx * cz, t->at<char>(p.o_twx), p.Px * cz,

@@ -223,6 +223,19 @@ __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void kbf_ks
 }
 
 template <typename T, int P>
+__global__ __launch_bounds__(6 * ky2_lines<P>() * (P / Sched<P>::R0)) void kbf_kspace_y2(BatchClass<T> c)
+{
+    __shared__ cpx<T> lds[kspace_y2_lds_elems<P>()];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
+    const int64_t plane = (int64_t)d.hx * d.ny;
+    const Ky2Args a{c.S + d.soff, 2 * plane, plane, d.ny, d.hx, d.ny, c.tw + d.twy, c.kern + d.koff,
+                    d.oct, d.Py / 2 + 1};
+    body_kspace_y2<T, P>(a, tile - c.prefix[q], lds);
+}
+
+template <typename T, int P>
 static bool class_launch(int kind, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s)
 {
     constexpr int TL = P / Sched<P>::R0;
@@ -251,6 +264,12 @@ static bool class_launch(int kind, const BatchClass<T>& c, int tiles, int invers
     case 2:
         if constexpr (P <= 64 && kspace_z_lds_elems<T, P>() * (int)sizeof(cpx<T>) <= 160 * 1024) {
             hipLaunchKernelGGL((kbf_kspace_z<T, P>), dim3(tiles), dim3(3 * kspace_z_cols<T>()), 0, s, c);
+            return true;
+        }
+        return false;
+    case 5:
+        if constexpr (P >= 16 && P <= 1024 && kspace_y2_lds_elems<P>() * (int)sizeof(cpx<T>) <= kLdsBudget) {
+            hipLaunchKernelGGL((kbf_kspace_y2<T, P>), dim3(tiles), dim3(6 * ky2_lines<P>() * TL), 0, s, c);
             return true;
         }
         return false;

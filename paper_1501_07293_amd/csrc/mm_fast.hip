@@ -47,6 +47,13 @@ __global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspa
     body_kspace_y<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
+template <typename T, int P, bool FULL>
+__global__ __launch_bounds__(6 * ky2_lines<P>() * (P / Sched<P>::R0)) void k_kspace_y2(Ky2Args a)
+{
+    __shared__ cpx<T> lds[kspace_y2_lds_elems<P>()];
+    body_kspace_y2<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
 // ------------------------------------------------------------------ dispatch
 template <typename T, bool INV, bool FULL>
 static bool yline_dispatch(const YLineArgs& a, int P, hipStream_t s)
@@ -219,6 +226,64 @@ bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s)
     return kspace_y_dispatch<T, false>(a, P, s);
 }
 
+template <typename T, bool FULL>
+static bool kspace_y2_dispatch(const Ky2Args& a, int P, hipStream_t s)
+{
+    auto go = [&](auto kern, int L, int nt) {
+        const int grid = (a.hx + L - 1) / L;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), 0, s, a);
+        return true;
+    };
+#define MM_KY2CASE(PP)                                                                          \
+    case PP:                                                                                    \
+        if constexpr (kspace_y2_lds_elems<PP>() * (int)sizeof(cpx<T>) <= kLdsBudget)           \
+            return go(k_kspace_y2<T, PP, FULL>, ky2_lines<PP>(), 6 * ky2_lines<PP>() * (PP / Sched<PP>::R0)); \
+        return false;
+    switch (P) {
+        MM_KY2CASE(16)
+        MM_KY2CASE(32)
+        MM_KY2CASE(64)
+        MM_KY2CASE(96)
+        MM_KY2CASE(128)
+        MM_KY2CASE(160)
+        MM_KY2CASE(192)
+        MM_KY2CASE(224)
+        MM_KY2CASE(256)
+        MM_KY2CASE(512)
+        MM_KY2CASE(1024)
+    default: return false;
+    }
+#undef MM_KY2CASE
+}
+
+template <typename T>
+bool launch_kspace_y2(const Ky2Args& a, int P, hipStream_t s)
+{
+    if (a.hx <= 0) return true;
+    if (a.ny > P) return false;
+    // valid samples in the first half: pruned body; whole lines (periodic y): FULL
+    if (2 * a.ny > P) return kspace_y2_dispatch<T, true>(a, P, s);
+    return kspace_y2_dispatch<T, false>(a, P, s);
+}
+
+int fast_ky2_lines(int P)
+{
+    switch (P) {
+    case 16: return ky2_lines<16>();
+    case 32: return ky2_lines<32>();
+    case 64: return ky2_lines<64>();
+    case 96: return ky2_lines<96>();
+    case 128: return ky2_lines<128>();
+    case 160: return ky2_lines<160>();
+    case 192: return ky2_lines<192>();
+    case 224: return ky2_lines<224>();
+    case 256: return ky2_lines<256>();
+    case 512: return ky2_lines<512>();
+    case 1024: return ky2_lines<1024>();
+    default: return 0;
+    }
+}
+
 int fast_first_radix(int P)
 {
     switch (P) {
@@ -259,6 +324,8 @@ int fast_ky_lines(int P)
     }
 }
 
+template bool launch_kspace_y2<float>(const Ky2Args&, int, hipStream_t);
+template bool launch_kspace_y2<double>(const Ky2Args&, int, hipStream_t);
 template bool launch_kspace_y<float>(const KyArgs&, int, hipStream_t);
 template bool launch_kspace_y<double>(const KyArgs&, int, hipStream_t);
 template bool launch_yline<float>(const YLineArgs&, int, int, hipStream_t);

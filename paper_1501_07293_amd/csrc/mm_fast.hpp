@@ -659,6 +659,107 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
     }
 }
 
+// ------------------------------------------------- y k-space (two cells thick)
+// Grids of two cells along z (nz = 2, open z): the z coupling of the two planes
+// is a 2 x 2 block sum with the tensor planes at z offsets -1, 0, 1 (the layout
+// and parities of the 10 coefficient planes are given with Ky2Args), so no z
+// transform, no z padding and no Py-long spectrum in HBM: a work-group holds L
+// x bins, six lines each (three components of both planes), runs the forward
+// y FFT (stage 1 from global memory), the block product in LDS, and the inverse
+// (last stage to global memory).
+template <int P>
+constexpr int ky2_lines() { return (256 / (6 * (P / Sched<P>::R0))) > 0 ? 256 / (6 * (P / Sched<P>::R0)) : 1; }
+
+template <typename T, int P, bool FULL = false>
+__device__ inline void body_kspace_y2(const Ky2Args& a, int tile, cpx<T>* lds)
+{
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = ky2_lines<P>(), NT = 6 * L * TL;
+    constexpr int LP = padded_len<P>();
+    const int line = threadIdx.x / TL, u = threadIdx.x % TL;
+    const int cz = line / L, l = line - cz * L;  // cz = 2 component + plane
+    const int kx = tile * L + l;
+    const bool ok = kx < a.hx;
+    cpx<T>* g = (cpx<T>*)a.buf + (cz >> 1) * a.comp_stride + (cz & 1) * a.plane_stride +
+                (int64_t)(ok ? kx : 0) * a.line_stride;
+    cpx<T>* ln = lds + line * LP;
+    const cpx<T>* tw = (const cpx<T>*)a.tw;
+    LineTw<T, P> W;
+    W.load(u, tw);
+    cpx<T> v[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+        const int e = u + TL * r;
+        cpx<T> x = {(T)0, (T)0};
+        if ((FULL || 2 * r < R0) && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
+        v[r] = x;
+    }
+    Dft<T, R0>::run(v);
+    if constexpr (Sched<P>::NS == 1) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
+    } else {
+        finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+    }
+    __syncthreads();
+    const T* K = (const T*)a.kern;
+    const int64_t cs = a.k_cs;
+    for (int idx = threadIdx.x; idx < L * P; idx += NT) {
+        const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
+        if (kx2 >= a.hx) continue;
+        int ky = e;
+        T sy = (T)1;
+        if (2 * ky > P) {
+            ky = P - ky;
+            sy = (T)-1;
+        }
+        const T* Kp = K + (int64_t)kx2 * a.k_xs + ky;
+        const T xx0 = Kp[0], xx1 = Kp[cs], xy0 = sy * Kp[2 * cs], xy1 = sy * Kp[3 * cs];
+        const T sxz = Kp[4 * cs], yy0 = Kp[5 * cs], yy1 = Kp[6 * cs], syz = sy * Kp[7 * cs];
+        const T zz0 = Kp[8 * cs], zz1 = Kp[9 * cs];
+        // line (component c, plane z) of bin l2 at LDS line (2 c + z) L + l2
+        cpx<T>* p[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) p[q] = lds + (q * L + l2) * LP + pad16(e);
+        const cpx<T> ax = *p[0], bx = *p[1], ay = *p[2], by = *p[3], az = *p[4], bz = *p[5];
+        // plane 0 (observer z = 0): K^(0) a + K^(-1) b, with K^(-1)_xz = -i Sxz, K^(-1)_yz = -i Syz
+        // plane 1 (observer z = 1): K^(1) a + K^(0) b, with K^(1)_xz = i Sxz, K^(1)_yz = i Syz
+        // (-i s (u + i v) = s v - i s u; i s (u + i v) = -s v + i s u)
+        const cpx<T> h0x = {xx0 * ax.re + xy0 * ay.re + xx1 * bx.re + xy1 * by.re + sxz * bz.im,
+                            xx0 * ax.im + xy0 * ay.im + xx1 * bx.im + xy1 * by.im - sxz * bz.re};
+        const cpx<T> h0y = {xy0 * ax.re + yy0 * ay.re + xy1 * bx.re + yy1 * by.re + syz * bz.im,
+                            xy0 * ax.im + yy0 * ay.im + xy1 * bx.im + yy1 * by.im - syz * bz.re};
+        const cpx<T> h0z = {zz0 * az.re + zz1 * bz.re + sxz * bx.im + syz * by.im,
+                            zz0 * az.im + zz1 * bz.im - sxz * bx.re - syz * by.re};
+        const cpx<T> h1x = {xx1 * ax.re + xy1 * ay.re + xx0 * bx.re + xy0 * by.re - sxz * az.im,
+                            xx1 * ax.im + xy1 * ay.im + xx0 * bx.im + xy0 * by.im + sxz * az.re};
+        const cpx<T> h1y = {xy1 * ax.re + yy1 * ay.re + xy0 * bx.re + yy0 * by.re - syz * az.im,
+                            xy1 * ax.im + yy1 * ay.im + xy0 * bx.im + yy0 * by.im + syz * az.re};
+        const cpx<T> h1z = {zz1 * az.re + zz0 * bz.re - sxz * ax.im - syz * ay.im,
+                            zz1 * az.im + zz0 * bz.im + sxz * ax.re + syz * ay.re};
+        // stored conjugated: the inverse transform runs as a forward one
+        *p[0] = conj(h0x);
+        *p[1] = conj(h1x);
+        *p[2] = conj(h0y);
+        *p[3] = conj(h1y);
+        *p[4] = conj(h0z);
+        *p[5] = conj(h1z);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = ln[pad16(u + TL * r)];
+    Dft<T, R0>::run(v);
+    auto put = [&](int e, cpx<T> val) {
+        if (ok && e < a.ny) g[e] = conj(val);
+    };
+    if constexpr (Sched<P>::NS == 1) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) put(r, v[r]);
+    } else {
+        __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
+        finish_line<T, P, !FULL>(ln, u, v, W, put);
+    }
+}
+
 // LDS entries (complex) each body needs.
 template <int P>
 constexpr int yline_lds_elems() { return yline_lines<P>() * padded_len<P>(); }
@@ -673,5 +774,7 @@ template <typename T, int PZ>
 constexpr int kspace_z_lds_elems() { return 3 * PZ * kspace_z_cols<T>(); }
 template <int P>
 constexpr int kspace_y_lds_elems() { return 3 * ky_lines<P>() * padded_len<P>(); }
+template <int P>
+constexpr int kspace_y2_lds_elems() { return 6 * ky2_lines<P>() * padded_len<P>(); }
 
 }  // namespace mm

@@ -152,10 +152,34 @@ struct KyArgs {              // y k-space pass of a one-cell-thick grid, lines (
     const void* kern;        // octant [4][1][hx][Py/2+1]: xx, xy, yy, zz
     int64_t k_cs, k_xs;
 };
+// y k-space pass of a two-cell-thick grid (nz = 2), lines (component, plane, kx).
+// The coupling along z of two planes is taken directly, not by a z transform:
+// with K^(d) the 2-D spectrum of the tensor plane at z offset d (observer minus
+// source), the field of plane 0 is K^(0) M0 + K^(-1) M1 and of plane 1
+// K^(1) M0 + K^(0) M1.  kern holds 10 real planes [10][hx][Py/2+1], scaled by
+// 1 / (Px Py): xx0, xx1, xy0, xy1, Sxz, yy0, yy1, Syz, zz0, zz1, where d = 0
+// planes end in 0, d = 1 planes in 1, and the d = 1 xz and yz spectra are
+// i Sxz and i Syz (odd in x resp. y: imaginary).  Parities fill in the rest:
+// K^(-1) equals K^(1) except xz and yz, which change sign; xy and Syz are odd in
+// ky, the others even.
+struct Ky2Args {
+    void* buf;
+    int64_t comp_stride;     // 2 hx ny
+    int64_t plane_stride;    // hx ny
+    int64_t line_stride;     // ny
+    int hx, ny;
+    const void* tw;
+    const void* kern;
+    int64_t k_cs, k_xs;      // plane stride hx (Py/2+1); kx stride Py/2+1
+};
+constexpr int kTwoPlaneTablePlanes = 10;
 template <typename T>
 bool launch_yline(const YLineArgs& a, int P, int inverse, hipStream_t s);
 template <typename T>
 bool launch_kspace_y(const KyArgs& a, int P, hipStream_t s);
+// false when P has no specialised two-plane pass
+template <typename T>
+bool launch_kspace_y2(const Ky2Args& a, int P, hipStream_t s);
 // Last-axis k-space pass with the length P fixed at compile time (P = 128 .. 1024);
 // false when P has no such pass.
 template <typename T>
@@ -192,6 +216,13 @@ hipError_t launch_twiddles(void* tw, int P, hipStream_t s);
 template <typename T>
 hipError_t launch_octant(void* out, const void* spec, int hx, int Py, int Pz, int64_t sx,
                          double scale, unsigned long long* imag_max_bits, hipStream_t s);
+// The coefficient planes of one component for the two-plane schedule (see
+// Ky2Args) from its [4][Py][sx] FP64 spectrum (Pz = 4): two planes for xx, xy,
+// yy, zz, one for xz, yz, times scale = 1 / (Px Py).  Records, like
+// launch_octant, the largest value that must vanish and the largest kept one.
+template <typename T>
+hipError_t launch_table_z2(void* out, const void* spec, int comp, int hx, int Py, int64_t sx,
+                           double scale, unsigned long long* stats, hipStream_t s);
 
 // ---------------------------------------------------------------- LLG
 template <typename T>
@@ -319,7 +350,7 @@ struct BatchClass {
     const cpx<T>* tw;
 };
 // kind: 0 x forward, 1 y (inverse flag), 2 z k-space, 3 y k-space (one cell
-// thick), 4 x inverse.  Returns false when no specialised kernel has length P.
+// thick), 4 x inverse, 5 two-plane y k-space (two cells thick).  Returns false when no specialised kernel has length P.
 template <typename T>
 bool launch_batch_class(int kind, int P, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s);
 // First radix of the specialised schedule of length P (0 if none), and the
@@ -337,6 +368,8 @@ constexpr int kspace_z_cols() { return kspace_z_cols_for(sizeof(T)); }
 // 255 us, 32 columns 240 us, 64 columns 325 us per launch)
 constexpr int kspace_z_split_cols() { return 32; }
 int fast_ky_lines(int P);
+// kx bins per work-group of the two-plane y k-space pass (0 if P has none)
+int fast_ky2_lines(int P);
 
 // which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse, 4 LLG stage.
 template <typename T>

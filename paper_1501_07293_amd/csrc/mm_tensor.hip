@@ -265,6 +265,50 @@ __global__ void k_octant(T* out, const cpx<double>* spec, int hx, int Py, int Pz
     }
 }
 
+// Coefficient planes of the two-plane schedule (nz = 2) from the FP64 3-D
+// spectrum of one component padded to Pz = 4 along z.  With K^(d) the 2-D
+// spectrum of the tensor plane at z offset d, the z transform gives
+// S(kz) = K^(0) + K^(1) (-i)^kz + K^(-1) i^kz.  Components even in z (xx, xy,
+// yy, zz: K^(-1) = K^(1)): K^(0) = S(1), K^(1) = (S(0) - S(2)) / 4.  Odd in z
+// (xz, yz: K^(0) = 0, K^(-1) = -K^(1) = -i s): S(1) = 2 s, the plane stores s.
+// comp: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz; out: that component's first plane
+// (planes of hx (Py/2+1) values, ky fastest); scale = 1 / (Px Py).
+template <typename T>
+__global__ void k_table_z2(T* out, const cpx<double>* spec, int comp, int hx, int Py, int64_t sx,
+                           double scale, unsigned long long* stats)
+{
+    const int oy = Py / 2 + 1;
+    const int64_t plane = (int64_t)hx * oy;
+    const bool odd = comp == 2 || comp == 4;
+    double im_max = 0.0, re_max = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < plane;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int ky = (int)(q % oy);
+        const int kx = (int)(q / oy);
+        const cpx<double> s0 = spec[((int64_t)0 * Py + ky) * sx + kx];
+        const cpx<double> s1 = spec[((int64_t)1 * Py + ky) * sx + kx];
+        const cpx<double> s2 = spec[((int64_t)2 * Py + ky) * sx + kx];
+        if (odd) {
+            out[q] = (T)(0.5 * s1.re * scale);
+            im_max = fmax(im_max, fmax(fabs(s1.im), fmax(fabs(s0.re), fabs(s2.re))) * scale);
+            re_max = fmax(re_max, fabs(s1.re * scale));
+        } else {
+            out[q] = (T)(s1.re * scale);
+            out[plane + q] = (T)(0.25 * (s0.re - s2.re) * scale);
+            im_max = fmax(im_max, fmax(fabs(s0.im), fmax(fabs(s1.im), fabs(s2.im))) * scale);
+            re_max = fmax(re_max, fmax(fabs(s0.re), fabs(s2.re)) * scale);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        im_max = fmax(im_max, __shfl_xor(im_max, off));
+        re_max = fmax(re_max, __shfl_xor(re_max, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_pos(&stats[0], im_max);
+        atomic_max_pos(&stats[1], re_max);
+    }
+}
+
 static int grid_for(int64_t n, int block)
 {
     int64_t g = (n + block - 1) / block;
@@ -307,6 +351,20 @@ hipError_t launch_octant(void* out, const void* spec, int hx, int Py, int Pz, in
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_table_z2(void* out, const void* spec, int comp, int hx, int Py, int64_t sx,
+                           double scale, unsigned long long* stats, hipStream_t s)
+{
+    const int64_t total = (int64_t)(Py / 2 + 1) * hx;
+    hipLaunchKernelGGL(k_table_z2<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, (T*)out,
+                       (const cpx<double>*)spec, comp, hx, Py, sx, scale, stats);
+    return hipGetLastError();
+}
+
+template hipError_t launch_table_z2<float>(void*, const void*, int, int, int, int64_t, double,
+                                           unsigned long long*, hipStream_t);
+template hipError_t launch_table_z2<double>(void*, const void*, int, int, int, int64_t, double,
+                                            unsigned long long*, hipStream_t);
 template hipError_t launch_twiddles<float>(void*, int, hipStream_t);
 template hipError_t launch_twiddles<double>(void*, int, hipStream_t);
 template hipError_t launch_octant<float>(void*, const void*, int, int, int, int64_t, double,

@@ -120,11 +120,19 @@ def test_batch_step_model_sums_the_single_grid_model():
     real3, half_x, kern = 3 * N * 4, 3 * 8 * 33 * 8, 4 * 33 * 9 * 4
     one = (real3 + half_x) * 2 + (2 * half_x + kern) + 21 * 3 * N * 4 // 4
     assert bench.batch_step_bytes([(32, 8, 1)], "pow2") == 4 * one
-    # a two-cell-thick grid takes the five-pass model with pz = 4
+    # a two-cell-thick grid under the size classes takes the two-plane schedule:
+    # x passes on [3][2][65][47], one y pass reading and writing that spectrum and the
+    # 10 coefficient planes of 65 x 65 values
     p = bench.grid_plan(33, 47, 2, "pow2")
-    assert (p["px"], p["py"], p["pz"], p["passes"]) == (128, 128, 4, 5)
-    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], "pow2") == \
-        4 * one + 4 * sum(bench.algorithmic_bytes(p, 33, 47, 2, 4).values())
+    assert (p["px"], p["py"], p["pz"], p["passes"]) == (128, 128, 4, 3)
+    assert p["spectrum_elems"] == 10 * 65 * 65
+    N2 = 33 * 47 * 2
+    real3b, half_xb, kernb = 3 * N2 * 4, 3 * 2 * 47 * 65 * 8, 10 * 65 * 65 * 4
+    two = (real3b + half_xb) * 2 + (2 * half_xb + kernb) + 21 * 3 * N2 * 4 // 4
+    assert sum(bench.algorithmic_bytes(p, 33, 47, 2, 4).values()) == two
+    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], "pow2") == 4 * one + 4 * two
+    # with 7-smooth padding (runtime-radix passes) it keeps the five passes
+    assert bench.grid_plan(33, 47, 2, False)["passes"] == 5
     # 7-smooth padding: 2n when 7-smooth (2 x 33 = 66 = 2 3 11 is not: 65 = 5 13 no, 66..70: 70)
     assert bench.pad_length(33, False) == 70 and bench.pad_length(32, False) == 64
     assert bench.pad_length(47, True) == 128 and bench.pad_length(2, True) == 4

@@ -76,9 +76,13 @@ def test_one_wg_graph_replay_and_euler():
 
 
 def test_one_wg_is_ignored_where_the_volume_does_not_fit():
+    # the default schedule of this grid (the two-plane one: two cells thick) runs instead
     s = make((64, 48, 2), "f32", one_wg=True)
-    assert s.plan()["passes"] == 5
+    d = make((64, 48, 2), "f32")
+    assert s.plan()["passes"] == d.plan()["passes"] != 1
+    assert s.plan()["two_plane"] == d.plan()["two_plane"]
     s.close()
+    d.close()
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
