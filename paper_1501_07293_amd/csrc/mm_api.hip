@@ -1282,8 +1282,10 @@ mm_status backward_impl(mm_sim* s, int64_t nsteps, double dt, int64_t ck, const 
 }
 
 // ---------------------------------------------------------------- batched
+constexpr int kBatchLlgKind = 6;
 struct BatchClassHost {
-    int kind;  // 0 x passes, 1 y passes, 2 z k-space, 3 y k-space, 5 two-plane y k-space
+    int kind;  // 0 x passes, 1 y passes, 2 z k-space, 3 y k-space, 5 two-plane y k-space,
+               // kBatchLlgKind the LLG stage (P = planes per thread)
     int P;
     std::vector<int> members, prefix;
     size_t off;  // element offset of members, then prefix, in the device int array
@@ -1308,7 +1310,7 @@ struct BatchLayout {
     size_t o_classes = 0;
     int64_t class_ints = 0;
     std::vector<BatchDesc> desc;
-    std::vector<int> prefix[5];   // x forward, y, k-space, x inverse, LLG
+    std::vector<int> prefix[4];   // runtime-radix passes: x forward, y, k-space, x inverse
     int64_t vec_elems = 0, S_elems = 0, kern_elems = 0, tw_elems = 0, cells = 0;
     size_t scratch = 0;
     size_t o_desc, o_prefix, o_mn, o_ma, o_mb, o_acc, o_hd, o_S, o_kern, o_tw, o_flags, o_scratch, total;
@@ -1354,7 +1356,7 @@ mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* 
     L->class_ints = 0;
     L->plans.assign(n, Plan{});
     L->desc.resize(n);
-    for (int q = 0; q < 5; ++q) L->prefix[q].assign(n + 1, 0);
+    for (int q = 0; q < 4; ++q) L->prefix[q].assign(n + 1, 0);
     for (int s = 0; s < n; ++s) {
         Plan& p = L->plans[s];
         mm_status st = build_plan(&grids[s], &o, &p);
@@ -1394,13 +1396,12 @@ mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* 
         L->cells += p.N;
         L->scratch = std::max(L->scratch, p.total);
         const int npairs = (3 * p.nz * p.ny + 1) / 2;
-        const int tiles[5] = {
+        const int tiles[4] = {
             (npairs + p.x_lines - 1) / p.x_lines,
             p.three_d ? (3 * p.nz * p.hx + d.y_lines - 1) / d.y_lines : 0,
             p.three_d ? (int)((p.hx * (int64_t)p.Py + p.k_tw - 1) / p.k_tw) : (p.hx + p.k_tw - 1) / p.k_tw,
-            (npairs + p.x_lines - 1) / p.x_lines,
-            (int)llg_blocks(p.nx, p.ny, p.nz)};
-        for (int q = 0; q < 5; ++q) L->prefix[q][s + 1] = L->prefix[q][s] + tiles[q];
+            (npairs + p.x_lines - 1) / p.x_lines};
+        for (int q = 0; q < 4; ++q) L->prefix[q][s + 1] = L->prefix[q][s] + tiles[q];
     }
     L->prec = o.prec;
     L->esz = o.prec == MM_F32 ? 4 : 8;
@@ -1444,18 +1445,31 @@ mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* 
                 add(3, p.Py, p.ny, (p.hx + Lk - 1) / Lk);
             }
         }
-        if (ok) {
+        if (ok)
             L->fast = true;
-            int64_t at = 0;
-            for (auto& c : L->classes) {
-                c.off = at;
-                at += (int64_t)c.members.size() + (int64_t)c.prefix.size();
-            }
-            L->class_ints = at;
-        } else {
+        else
             L->classes.clear();
-        }
     }
+    // LLG classes (every layout): the grids grouped by planes per thread
+    for (int s = 0; s < n; ++s) {
+        const Plan& p = L->plans[s];
+        const int kz = llg_z_for(p.nz);
+        BatchClassHost* c = nullptr;
+        for (auto& e : L->classes)
+            if (e.kind == kBatchLlgKind && e.P == kz) c = &e;
+        if (!c) {
+            L->classes.push_back(BatchClassHost{kBatchLlgKind, kz, {}, {0}, 0});
+            c = &L->classes.back();
+        }
+        c->members.push_back(s);
+        c->prefix.push_back(c->prefix.back() + (int)llg_blocks(p.nx, p.ny, p.nz));
+    }
+    int64_t at = 0;
+    for (auto& c : L->classes) {
+        c.off = at;
+        at += (int64_t)c.members.size() + (int64_t)c.prefix.size();
+    }
+    L->class_ints = at;
     return MM_OK;
 }
 
@@ -1469,7 +1483,7 @@ mm_status batch_layout_offsets(int32_t n, BatchLayout* L)
     };
     const size_t vec = (size_t)L->vec_elems * L->esz;
     L->o_desc = take(n * sizeof(BatchDesc));
-    L->o_prefix = take(5 * (size_t)(n + 1) * sizeof(int));
+    L->o_prefix = take(4 * (size_t)(n + 1) * sizeof(int));
     L->o_mn = take(vec);
     L->o_ma = take(vec);
     L->o_mb = take(vec);
@@ -1558,15 +1572,15 @@ mm_status batch_demag(mm_batch* b, const T* in, hipStream_t st)
     p.out = b->at<T>(L.o_hd);
     p.in = in;
     p.prefix = pre + 0 * (n + 1);
-    HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, nullptr, st));
+    HIP_TRY(launch_batch_pass<T>(0, p, L.prefix[0][n], 0, st));
     p.prefix = pre + 1 * (n + 1);
-    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 0, nullptr, st));
+    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 0, st));
     p.prefix = pre + 2 * (n + 1);
-    HIP_TRY(launch_batch_pass<T>(2, p, L.prefix[2][n], 0, nullptr, st));
+    HIP_TRY(launch_batch_pass<T>(2, p, L.prefix[2][n], 0, st));
     p.prefix = pre + 1 * (n + 1);
-    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 1, nullptr, st));
+    HIP_TRY(launch_batch_pass<T>(1, p, L.prefix[1][n], 1, st));
     p.prefix = pre + 3 * (n + 1);
-    HIP_TRY(launch_batch_pass<T>(3, p, L.prefix[3][n], 0, nullptr, st));
+    HIP_TRY(launch_batch_pass<T>(3, p, L.prefix[3][n], 0, st));
     return MM_OK;
 }
 
@@ -1581,13 +1595,10 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
     T* hd = b->at<T>(L.o_hd);
     T* src[4] = {mn, ma, mb, ma};
     T* dst[4] = {ma, mb, ma, mn};
-    const int* pre = b->at<int>(L.o_prefix);
-    const int n = b->n;
     const bool with_demag = !(b->flags & MM_NO_DEMAG);
-    BatchPass<T> p{};
-    p.d = b->at<BatchDesc>(L.o_desc);
-    p.n = n;
-    p.prefix = pre + 4 * (n + 1);
+    BatchClass<T> bc{};
+    bc.d = b->at<BatchDesc>(L.o_desc);
+    const int* cints = b->at<int>(L.o_classes);
     BatchLlg<T> g{};
     g.mn = mn;
     g.acc = acc;
@@ -1598,7 +1609,13 @@ mm_status batch_rk4_step(mm_batch* b, double dt, hipStream_t st)
         g.ms = src[stg];
         g.out = dst[stg];
         g.stage = stg + 1;
-        HIP_TRY(launch_batch_pass<T>(4, p, L.prefix[4][n], 0, &g, st));
+        for (const BatchClassHost& c : L.classes) {
+            if (c.kind != kBatchLlgKind) continue;
+            bc.members = cints + c.off;
+            bc.prefix = cints + c.off + c.members.size();
+            bc.nmem = (int)c.members.size();
+            HIP_TRY(launch_batch_llg<T>(c.P, bc, c.prefix.back(), g, st));
+        }
     }
     return MM_OK;
 }
@@ -2529,8 +2546,8 @@ static mm_status batch_build(int32_t n, const mm_grid* grids, const mm_material*
     e = hipMemcpyAsync(b->at<char>(BL.o_desc), BL.desc.data(), n * sizeof(BatchDesc),
                        hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return bail(fail(MM_EHIP, "descriptor upload: %s", hipGetErrorString(e)));
-    std::vector<int> pre(5 * (size_t)(n + 1));
-    for (int q = 0; q < 5; ++q)
+    std::vector<int> pre(4 * (size_t)(n + 1));
+    for (int q = 0; q < 4; ++q)
         for (int s = 0; s <= n; ++s) pre[q * (n + 1) + s] = BL.prefix[q][s];
     e = hipMemcpyAsync(b->at<char>(BL.o_prefix), pre.data(), pre.size() * sizeof(int),
                        hipMemcpyHostToDevice, hs);

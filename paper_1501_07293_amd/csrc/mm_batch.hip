@@ -134,12 +134,13 @@ __global__ __launch_bounds__(kBatchNT) void kb_xinv(BatchPass<T> p)
     body_row_c2r<T, kBatchNT>(a, d.fx, tile - p.prefix[s], lds);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g)
+// One launch per LLG class: the grids whose planes per thread are KZ.
+template <typename T, int KZ>
+__global__ __launch_bounds__(kBatchNT) void kbf_llg(BatchClass<T> c, BatchLlg<T> g)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int s = find_sample(p.prefix, p.n, tile);
-    const BatchDesc& d = p.d[s];
+    const int q = find_sample(c.prefix, c.nmem, tile);
+    const BatchDesc& d = c.d[c.members[q]];
     LlgArgs<T> a{};
     a.ms = g.ms + d.moff;
     a.mn = g.mn + d.moff;
@@ -159,8 +160,26 @@ __global__ __launch_bounds__(kBatchNT) void kb_llg(BatchPass<T> p, BatchLlg<T> g
     a.alpha = (T)d.alpha;
     a.gdt = (T)d.gdt;
     a.stage = g.stage;
-    body_llg_stage<T>(a, tile - p.prefix[s], threadIdx.x);
+    body_llg_stage<T, KZ>(a, tile - c.prefix[q], threadIdx.x);
 }
+
+template <typename T>
+hipError_t launch_batch_llg(int kz, const BatchClass<T>& c, int tiles, const BatchLlg<T>& g, hipStream_t s)
+{
+    if (tiles <= 0) return hipSuccess;
+    switch (kz) {
+    case 1: hipLaunchKernelGGL((kbf_llg<T, 1>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
+    case 2: hipLaunchKernelGGL((kbf_llg<T, 2>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
+    case kLlgZ: hipLaunchKernelGGL((kbf_llg<T, kLlgZ>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_llg<float>(int, const BatchClass<float>&, int, const BatchLlg<float>&,
+                                            hipStream_t);
+template hipError_t launch_batch_llg<double>(int, const BatchClass<double>&, int, const BatchLlg<double>&,
+                                             hipStream_t);
 
 // ---- size classes: the specialised bodies, one launch per padded length
 template <typename T, int P, int L>
@@ -310,8 +329,7 @@ template bool launch_batch_class<float>(int, int, const BatchClass<float>&, int,
 template bool launch_batch_class<double>(int, int, const BatchClass<double>&, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,
-                             const BatchLlg<T>* g, hipStream_t s)
+hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse, hipStream_t s)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid(total_tiles), block(kBatchNT);
@@ -319,15 +337,12 @@ hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, 
     case 0: hipLaunchKernelGGL(kb_xfwd<T>, grid, block, 0, s, p); break;
     case 1: hipLaunchKernelGGL(kb_y<T>, grid, block, 0, s, p, inverse); break;
     case 2: hipLaunchKernelGGL(kb_kspace<T>, grid, block, 0, s, p); break;
-    case 3: hipLaunchKernelGGL(kb_xinv<T>, grid, block, 0, s, p); break;
-    default: hipLaunchKernelGGL(kb_llg<T>, grid, block, 0, s, p, *g); break;
+    default: hipLaunchKernelGGL(kb_xinv<T>, grid, block, 0, s, p); break;
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_batch_pass<float>(int, const BatchPass<float>&, int, int,
-                                             const BatchLlg<float>*, hipStream_t);
-template hipError_t launch_batch_pass<double>(int, const BatchPass<double>&, int, int,
-                                              const BatchLlg<double>*, hipStream_t);
+template hipError_t launch_batch_pass<float>(int, const BatchPass<float>&, int, int, hipStream_t);
+template hipError_t launch_batch_pass<double>(int, const BatchPass<double>&, int, int, hipStream_t);
 
 }  // namespace mm

@@ -243,14 +243,18 @@ struct LlgArgs {
     int stage;       // 1..4 (RK4 stages), 0 (explicit Euler with renormalisation)
     int per;         // periodic axes (bit 0 x, 1 y, 2 z): the exchange stencil wraps
 };
-// the LLG stage gives each thread one (x, y) column and kLlgZ consecutive planes;
-// a work-group of kLlgNT threads covers kLlgNT consecutive columns of one chunk,
-// and the chunks of the same columns are consecutive work-groups
+// the LLG stage gives each thread one (x, y) column and llg_z_for(nz) consecutive
+// planes (one or two for grids one or two cells thick, whose threads would
+// otherwise load clamped copies of the same planes, else kLlgZ); a work-group of
+// kLlgNT threads covers kLlgNT consecutive columns of one chunk, and the chunks
+// of the same columns are consecutive work-groups
 constexpr int kLlgZ = 4;
 constexpr int kLlgNT = 256;
+__host__ __device__ constexpr int llg_z_for(int nz) { return nz == 1 ? 1 : (nz == 2 ? 2 : kLlgZ); }
 __host__ __device__ inline int64_t llg_blocks(int nx, int ny, int nz)
 {
-    return ((int64_t)nx * ny + kLlgNT - 1) / kLlgNT * ((nz + kLlgZ - 1) / kLlgZ);
+    const int kz = llg_z_for(nz);
+    return ((int64_t)nx * ny + kLlgNT - 1) / kLlgNT * ((nz + kz - 1) / kz);
 }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s);
@@ -350,7 +354,8 @@ struct BatchClass {
     const cpx<T>* tw;
 };
 // kind: 0 x forward, 1 y (inverse flag), 2 z k-space, 3 y k-space (one cell
-// thick), 4 x inverse, 5 two-plane y k-space (two cells thick).  Returns false when no specialised kernel has length P.
+// thick), 4 x inverse, 5 two-plane y k-space (two cells thick).  (LLG classes,
+// grouped by planes per thread, launch through launch_batch_llg.)  Returns false when no specialised kernel has length P.
 template <typename T>
 bool launch_batch_class(int kind, int P, const BatchClass<T>& c, int tiles, int inverse, hipStream_t s);
 // First radix of the specialised schedule of length P (0 if none), and the
@@ -371,10 +376,13 @@ int fast_ky_lines(int P);
 // kx bins per work-group of the two-plane y k-space pass (0 if P has none)
 int fast_ky2_lines(int P);
 
-// which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse, 4 LLG stage.
+// which: 0 x forward, 1 y (inverse flag), 2 k-space, 3 x inverse.
 template <typename T>
-hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse,
-                             const BatchLlg<T>* g, hipStream_t s);
+hipError_t launch_batch_pass(int which, const BatchPass<T>& p, int total_tiles, int inverse, hipStream_t s);
+// The LLG stage over the grids of class c, whose members all take kz =
+// llg_z_for(nz) planes per thread; tiles = the class's llg_blocks total.
+template <typename T>
+hipError_t launch_batch_llg(int kz, const BatchClass<T>& c, int tiles, const BatchLlg<T>& g, hipStream_t s);
 
 // m <- m / |m| per cell; counts zero-norm or non-finite cells into *bad.
 template <typename T>

@@ -68,10 +68,10 @@ __device__ inline void heff_at(const LlgArgs<T>& a, int64_t c, const Cell<T>& o,
 
 // XCD-aware: consecutive tiles (neighbouring rows of a plane) run on the same
 // XCD, so the y-neighbour rows one work-group reads are in that XCD's L2.
-template <typename T>
+template <typename T, int KZ>
 __global__ __launch_bounds__(kLlgNT) void k_llg_stage(LlgArgs<T> a)
 {
-    body_llg_stage<T>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
+    body_llg_stage<T, KZ>(a, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 template <typename T>
@@ -248,7 +248,12 @@ static int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_llg_stage<T>, dim3((int)llg_blocks(a.nx, a.ny, a.nz)), dim3(kLlgNT), 0, s, a);
+    const dim3 grid((int)llg_blocks(a.nx, a.ny, a.nz));
+    switch (llg_z_for(a.nz)) {
+    case 1: hipLaunchKernelGGL((k_llg_stage<T, 1>), grid, dim3(kLlgNT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_llg_stage<T, 2>), grid, dim3(kLlgNT), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_llg_stage<T, kLlgZ>), grid, dim3(kLlgNT), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 

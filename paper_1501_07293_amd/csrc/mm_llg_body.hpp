@@ -59,15 +59,14 @@ __device__ inline void llg_cell(const LlgArgs<T>& a, int64_t c, const T (&m)[3],
     for (int d = 0; d < 3; ++d) a.out[d * N + c] = res[d];
 }
 
-// The stage update of the planes k0 .. k0+kLlgZ-1 of column pc from the gathered
-// m (col, planes k0-1 .. k0+kLlgZ), Laplacian, demag field, m_n, RK4 accumulator
+// The stage update of the planes k0 .. k0+KZ-1 of column pc from the gathered
+// m (col, planes k0-1 .. k0+KZ), Laplacian, demag field, m_n, RK4 accumulator
 // and reduced anisotropy constant.
-template <typename T>
-__device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const T (&col)[kLlgZ + 2][3],
-                                  const T (&lap)[kLlgZ][3], const T (&hd)[kLlgZ][3],
-                                  const T (&mn)[kLlgZ][3], const T (&ac)[kLlgZ][3], const T (&kan)[kLlgZ])
+template <typename T, int KZ>
+__device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const T (&col)[KZ + 2][3],
+                                  const T (&lap)[KZ][3], const T (&hd)[KZ][3],
+                                  const T (&mn)[KZ][3], const T (&ac)[KZ][3], const T (&kan)[KZ])
 {
-    constexpr int KZ = kLlgZ;
     const int64_t plane = (int64_t)a.nx * a.ny;
 #pragma unroll
     for (int q = 0; q < KZ; ++q) {
@@ -78,7 +77,7 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
     }
 }
 
-// One thread per (x, y) column and chunk of kLlgZ planes.  Every load of the
+// One thread per (x, y) column and chunk of KZ planes.  Every load of the
 // chunk (m of planes k0-1 .. k0+kLlgZ, in-plane neighbours, H_d, Ku, m_n, acc)
 // is issued before the first store, so a thread keeps many loads in flight;
 // the z neighbours inside the chunk come from registers, the x and y neighbours
@@ -87,15 +86,15 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
 // consecutive work-groups, so the two planes a chunk shares with its z
 // neighbours are read from HBM once and found in L2 the second time.
 
-// Thread `lane` of work-group `blk` (0 <= blk < llg_blocks, 0 <= lane < kLlgNT).
+// Thread `lane` of work-group `blk` (0 <= blk < llg_blocks, 0 <= lane < kLlgNT);
+// KZ = llg_z_for(a.nz), the chunk size llg_blocks counts with.
 // A neighbour missing at the boundary is the cell itself (Eq. 7): its address
 // is clamped to the cell's own, which adds mc - mc = 0, so every load is issued
 // unconditionally and none waits on a per-lane branch.  Along a periodic axis
 // (a.per) the neighbour across the boundary is the cell at the other end.
-template <typename T>
+template <typename T, int KZ>
 __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane)
 {
-    constexpr int KZ = kLlgZ;
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int nzc = (a.nz + KZ - 1) / KZ;
     const int kc = (int)(blk % nzc);
@@ -146,7 +145,7 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane
         }
         kan[q] = a.ku ? a.ku[c] : a.can;
     }
-    llg_update<T>(a, pc, k0, col, lap, hd, mn, ac, kan);
+    llg_update<T, KZ>(a, pc, k0, col, lap, hd, mn, ac, kan);
 }
 
 
