@@ -881,8 +881,77 @@ def summarize_rocprof(run_dir: str, out_dir: str, command: str) -> str:
     return path
 
 
+def summarize_batch_rocprof(run_dir: str, out_dir: str, command: str) -> str:
+    """Summary of one profiled batched leg (bench.py --leg batched): per-kernel
+    time (run_dir/kt), HBM bytes per dispatch from FETCH_SIZE (run_dir/pf) and
+    WRITE_SIZE (run_dir/pw) with the counter scale of the 1 GiB device copy of
+    the main summary (FETCH x2, WRITE x1), their sum over one RK4 step, and the
+    share of the step's span the GPU sits between kernels."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(pattern):
+        found = glob.glob(os.path.join(run_dir, pattern), recursive=True)
+        if not found:
+            raise SystemExit(f"no {pattern} under {run_dir}")
+        return found[0]
+
+    stats = {kernel_key(r["Name"]): r for r in csv.DictReader(open(one("kt/**/*kernel_stats.csv")))}
+    line = [l for l in open(os.path.join(run_dir, "kt.log")) if l.startswith("{")][-1]
+    b = json.loads(line)
+
+    def counter(pattern, name):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(one(pattern))):
+            if r["Counter_Name"] == name:
+                per[kernel_key(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return per
+
+    fetch = counter("pf/**/*counter_collection.csv", "FETCH_SIZE")
+    write = counter("pw/**/*counter_collection.csv", "WRITE_SIZE")
+    rows = []
+    for k in sorted(set(fetch) & set(write) & set(stats)):
+        if not k.startswith("mm::kb"):
+            continue
+        hbm = 1024 * (COPY_SCALE["FETCH_SIZE"] * sum(fetch[k]) / len(fetch[k]) +
+                      COPY_SCALE["WRITE_SIZE"] * sum(write[k]) / len(write[k]))
+        t = float(stats[k]["AverageNs"])
+        rows.append((t, k, int(stats[k]["Calls"]), hbm))
+    rows.sort(reverse=True)
+    trace = [r for r in csv.DictReader(open(one("kt/**/*kernel_trace.csv"))) if r["Kernel_Name"].startswith(
+        ("void mm::kb", "mm::kb"))]
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace)
+    gaps = [int(y["Start_Timestamp"]) - int(x["End_Timestamp"]) for x, y in zip(trace, trace[1:])]
+    idle = sum(g for g in gaps if 0 < g < 200000)   # longer gaps: host syncs between runs
+    step_us = sum(4 * t for t, _, calls, _ in rows if calls) / 1e3
+    step_mb = sum(4 * hbm for _, _, _, hbm in rows) / 1e6
+    lines = [f"# Batched step: {b['grids']} grids, {b['cells']} cells, {b['padding']} padding, {b['passes']}", "",
+             "Commands:", "", "```", command.strip(), "```", "",
+             "## Kernels of one field evaluation and LLG stage (four per RK4 step)", "",
+             "| kernel | calls | avg µs | HBM MB per launch | GB/s |", "|---|---|---|---|---|"]
+    for t, k, calls, hbm in rows:
+        lines.append(f"| `{k}` | {calls} | {t / 1e3:.1f} | {hbm / 1e6:.1f} | {hbm / t:.0f} |")
+    lines += ["", f"Sum over one RK4 step (4 launches of each kernel): {step_us:.0f} µs of kernel time, "
+                  f"{step_mb:.0f} MB of HBM traffic ({step_mb / step_us * 1e3:.0f} GB/s); "
+                  f"the algorithmic model gives {b['step_model_bytes'] / 1e6:.0f} MB per step.",
+              f"Between consecutive batched kernels the GPU is idle {100 * idle / (idle + busy):.2f}% of the "
+              f"time (gaps under 200 µs, graph replay): the step is kernel time, not launch gaps.",
+              "", f"Bench line of the kernel-trace run: {b['value']:.4g} {b['unit']}, {b['ms_per_step']:.3f} ms "
+                  f"per step (profiler attached).", ""]
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"batched_{b['grids']}_grids_{b['padding'].split()[0]}_f32.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines))
+    return path
+
+
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-batch-rocprof":
+        # bench.py --summarize-batch-rocprof RUN_DIR OUT_DIR "COMMANDS"
+        print(summarize_batch_rocprof(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
         # bench.py --summarize-rocprof RUN_DIR OUT_DIR "COMMANDS"
         print(summarize_rocprof(sys.argv[2], sys.argv[3], sys.argv[4]))
     else:

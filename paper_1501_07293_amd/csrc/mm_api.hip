@@ -8,6 +8,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <array>
+#include <iterator>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -1317,10 +1319,12 @@ struct BatchLayout {
     int prec;
     size_t esz;
     bool plan_generic = false;  // the plans were built with the runtime-radix passes forced
+    std::vector<std::array<int, 2>> pad;  // per grid explicit (px, py), 0 = automatic
 };
 
 mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* opt, bool classes,
                              BatchLayout* L);
+bool merge_small_classes(int32_t n, BatchLayout* L);
 mm_status batch_layout_offsets(int32_t n, BatchLayout* L);
 
 mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, BatchLayout* L)
@@ -1340,11 +1344,46 @@ mm_status batch_layout(int32_t n, const mm_grid* grids, const mm_options* opt, B
         mm_options oa = o;
         if (attempt == 1) oa.flags |= MM_GENERIC_FFT;
         L->plan_generic = attempt == 1;
-        mm_status st = batch_layout_plans(n, grids, &oa, want_fast && attempt == 0, L);
-        if (st != MM_OK) return st;
+        L->pad.assign(n, {0, 0});
+        // size classes holding a small share of the cells are padded up into the next
+        // class of their axis (at most a few rounds: each round removes a class)
+        for (int round = 0; round < 8; ++round) {
+            mm_status st = batch_layout_plans(n, grids, &oa, want_fast && attempt == 0, L);
+            if (st != MM_OK) return st;
+            if (!L->fast || !merge_small_classes(n, L)) break;
+        }
         if (L->fast || !want_fast) break;
     }
     return batch_layout_offsets(n, L);
+}
+
+// A size class costs one launch per pass whatever its size (a few microseconds
+// of fill and drain).  The grids of an x or y class holding under 1/32 of the
+// batch's cells move to the next larger padded length of that axis present in
+// the batch: any length >= 2n - 1 gives the same linear convolution, and the
+// few extra bytes of those grids cost less than the launches they save.
+// Returns true when some grid moved (the plans must then be rebuilt).
+bool merge_small_classes(int32_t n, BatchLayout* L)
+{
+    bool moved = false;
+    for (int axis = 0; axis < 2; ++axis) {
+        std::map<int, int64_t> cells;  // padded length -> cells of its grids
+        for (int s = 0; s < n; ++s) cells[axis ? L->plans[s].Py : L->plans[s].Px] += L->plans[s].N;
+        if (cells.size() < 2) continue;
+        for (auto it = cells.begin(); std::next(it) != cells.end(); ++it) {
+            if (it->second * 32 >= L->cells) continue;
+            const int to = std::next(it)->first;
+            for (int s = 0; s < n; ++s) {
+                const Plan& p = L->plans[s];
+                if ((axis ? p.Py : p.Px) == it->first) {
+                    L->pad[s][axis] = to;
+                    moved = true;
+                }
+            }
+            break;  // one class per axis and round; the plans are rebuilt in between
+        }
+    }
+    return moved;
 }
 
 mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* opt, bool classes,
@@ -1359,7 +1398,12 @@ mm_status batch_layout_plans(int32_t n, const mm_grid* grids, const mm_options* 
     for (int q = 0; q < 4; ++q) L->prefix[q].assign(n + 1, 0);
     for (int s = 0; s < n; ++s) {
         Plan& p = L->plans[s];
-        mm_status st = build_plan(&grids[s], &o, &p);
+        mm_options og = o;
+        if (s < (int)L->pad.size()) {
+            og.px = L->pad[s][0];
+            og.py = L->pad[s][1];
+        }
+        mm_status st = build_plan(&grids[s], &og, &p);
         if (st != MM_OK) {
             std::string keep = g_err;
             return fail(st, "grid %d: %s", s, keep.c_str());
@@ -2574,7 +2618,10 @@ static mm_status batch_build(int32_t n, const mm_grid* grids, const mm_material*
         const Plan& p = BL.plans[s];
         const BatchDesc& d = BL.desc[s];
         mm_sim* t = nullptr;
-        mm_status r = mm_create(&grids[s], &b->mats[s], &o, b->at<char>(BL.o_scratch), BL.scratch, stream, &t);
+        mm_options og = o;  // the grid's padded sizes as the layout planned them
+        og.px = BL.pad[s][0];
+        og.py = BL.pad[s][1];
+        mm_status r = mm_create(&grids[s], &b->mats[s], &og, b->at<char>(BL.o_scratch), BL.scratch, stream, &t);
         if (r != MM_OK) return bail(r);
         const size_t esz = BL.esz;
         hipError_t ce = hipMemcpyAsync(b->at<char>(BL.o_kern) + d.koff * esz, t->at<char>(p.o_kern),

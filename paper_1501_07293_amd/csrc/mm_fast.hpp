@@ -615,6 +615,22 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
         if ((FULL || 2 * r < R0) && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
         v[r] = x;
     }
+    // the spectra of the product elements this thread takes do not depend on the
+    // data: loaded here, their latency overlaps the forward transform
+    constexpr int NI = (L * P + NT - 1) / NT;
+    const T* K = (const T*)a.kern;
+    T kv[NI][4];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
+        const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
+        int ky = e;
+        if (2 * ky > P) ky = P - ky;
+        const bool in = idx < L * P && kx2 < a.hx;
+        const T* Kp = K + (in ? (int64_t)kx2 * a.k_xs + ky : 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kv[it][c] = Kp[c * a.k_cs];
+    }
     Dft<T, R0>::run(v);
     if constexpr (Sched<P>::NS == 1) {
 #pragma unroll
@@ -623,18 +639,13 @@ __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
         finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
     }
     __syncthreads();
-    const T* K = (const T*)a.kern;
-    for (int idx = threadIdx.x; idx < L * P; idx += NT) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
         const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
-        if (kx2 >= a.hx) continue;
-        int ky = e;
-        T sy = (T)1;
-        if (2 * ky > P) {
-            ky = P - ky;
-            sy = (T)-1;
-        }
-        const T* Kp = K + (int64_t)kx2 * a.k_xs + ky;
-        const T kxx = Kp[0], kxy = sy * Kp[a.k_cs], kyy = Kp[2 * a.k_cs], kzz = Kp[3 * a.k_cs];
+        if (idx >= L * P || kx2 >= a.hx) continue;
+        const T sy = 2 * e > P ? (T)-1 : (T)1;
+        const T kxx = kv[it][0], kxy = sy * kv[it][1], kyy = kv[it][2], kzz = kv[it][3];
         cpx<T>* px = lds + (0 * L + l2) * LP + pad16(e);
         cpx<T>* py = lds + (1 * L + l2) * LP + pad16(e);
         cpx<T>* pz = lds + (2 * L + l2) * LP + pad16(e);
@@ -693,6 +704,22 @@ __device__ inline void body_kspace_y2(const Ky2Args& a, int tile, cpx<T>* lds)
         if ((FULL || 2 * r < R0) && ok && e < a.ny) x = g[e];  // e >= P/2 is zero padding
         v[r] = x;
     }
+    // the coefficients of this thread's product elements, loaded with the data
+    constexpr int NI = (L * P + NT - 1) / NT;
+    const T* K = (const T*)a.kern;
+    const int64_t cs = a.k_cs;
+    T kv[NI][kTwoPlaneTablePlanes];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
+        const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
+        int ky = e;
+        if (2 * ky > P) ky = P - ky;
+        const bool in = idx < L * P && kx2 < a.hx;
+        const T* Kp = K + (in ? (int64_t)kx2 * a.k_xs + ky : 0);
+#pragma unroll
+        for (int c = 0; c < kTwoPlaneTablePlanes; ++c) kv[it][c] = Kp[c * cs];
+    }
     Dft<T, R0>::run(v);
     if constexpr (Sched<P>::NS == 1) {
 #pragma unroll
@@ -701,21 +728,15 @@ __device__ inline void body_kspace_y2(const Ky2Args& a, int tile, cpx<T>* lds)
         finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
     }
     __syncthreads();
-    const T* K = (const T*)a.kern;
-    const int64_t cs = a.k_cs;
-    for (int idx = threadIdx.x; idx < L * P; idx += NT) {
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = (int)threadIdx.x + it * NT;
         const int l2 = idx / P, e = idx - l2 * P, kx2 = tile * L + l2;
-        if (kx2 >= a.hx) continue;
-        int ky = e;
-        T sy = (T)1;
-        if (2 * ky > P) {
-            ky = P - ky;
-            sy = (T)-1;
-        }
-        const T* Kp = K + (int64_t)kx2 * a.k_xs + ky;
-        const T xx0 = Kp[0], xx1 = Kp[cs], xy0 = sy * Kp[2 * cs], xy1 = sy * Kp[3 * cs];
-        const T sxz = Kp[4 * cs], yy0 = Kp[5 * cs], yy1 = Kp[6 * cs], syz = sy * Kp[7 * cs];
-        const T zz0 = Kp[8 * cs], zz1 = Kp[9 * cs];
+        if (idx >= L * P || kx2 >= a.hx) continue;
+        const T sy = 2 * e > P ? (T)-1 : (T)1;
+        const T xx0 = kv[it][0], xx1 = kv[it][1], xy0 = sy * kv[it][2], xy1 = sy * kv[it][3];
+        const T sxz = kv[it][4], yy0 = kv[it][5], yy1 = kv[it][6], syz = sy * kv[it][7];
+        const T zz0 = kv[it][8], zz1 = kv[it][9];
         // line (component c, plane z) of bin l2 at LDS line (2 c + z) L + l2
         cpx<T>* p[6];
 #pragma unroll
