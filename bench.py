@@ -126,60 +126,6 @@ def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
     return b
 
 
-def smooth7(v: int) -> bool:
-    for f in (2, 3, 5, 7):
-        while v % f == 0:
-            v //= f
-    return v == 1
-
-
-def pad_length(n: int, pad) -> int:
-    """The library's automatic padded length of an open axis of n > 1 cells.  pad:
-    "pow2" (or True) the smallest power of two >= 2n - 1; "fast" the smallest
-    length >= 2n - 1 among the powers of two and 96, 160, 192, 224 (along z, line
-    False: powers of two only); "7-smooth" (or False) 2n if 7-smooth, else the
-    smallest 7-smooth length >= 2n - 1."""
-    return _pad(n, pad, True)
-
-
-def _pad(n: int, pad, line: bool) -> int:
-    if pad is True or pad == "pow2" or pad == "fast":
-        p = 1
-        while p < 2 * n - 1:
-            p *= 2
-        if pad == "fast" and line:
-            p = min([q for q in (96, 160, 192, 224) if q >= 2 * n - 1] + [p])
-        return p
-    if smooth7(2 * n):
-        return 2 * n
-    p = 2 * n - 1
-    while not smooth7(p):
-        p += 1
-    return p
-
-
-def grid_plan(nx: int, ny: int, nz: int, pad) -> dict:
-    """Padded sizes, stored x bins, schedule and kernel-spectrum size of one
-    open-boundary grid.  Two cells thick with the specialised passes (power-of-two
-    or fast padding): the two-plane schedule (3 passes, 10 coefficient planes)."""
-    px, py = _pad(nx, pad, True), _pad(ny, pad, True)
-    pz = 1 if nz == 1 else _pad(nz, pad, False)
-    hx = px // 2 + 1
-    if nz == 2 and pz == 4 and pad in (True, "pow2", "fast") and py <= 1024:
-        return {"px": px, "py": py, "pz": pz, "hx": hx, "passes": 3,
-                "spectrum_elems": 10 * hx * (py // 2 + 1)}
-    ncomp = 6 if pz > 1 else 4
-    return {"px": px, "py": py, "pz": pz, "hx": hx, "passes": 5 if pz > 1 else 3,
-            "spectrum_elems": ncomp * (pz // 2 + 1) * hx * (py // 2 + 1)}
-
-
-def batch_step_bytes(grids, pad, esz: int = 4) -> int:
-    """Algorithmic bytes of one RK4 step of a batch: every grid's passes and LLG
-    stage by the single-grid model, four field evaluations each."""
-    return sum(4 * sum(algorithmic_bytes(grid_plan(nx, ny, nz, pad), nx, ny, nz, esz).values())
-               for nx, ny, nz in grids)
-
-
 def run_gpu(args, cfg, precision: str, steps: int, warmup: int, profile: bool, repeats: int = 1,
             autotune: bool = False):
     """Times `repeats` runs of exactly `steps` RK4 steps (each bracketed by device
@@ -291,7 +237,10 @@ def batched_leg(steps: int, autotune: bool, warmup: int = 2, check: bool = False
         times.append(time.perf_counter() - t0)
     dt = float(np.median(times))
     pad = "pow2" if info["pow2_pad"] else ("fast" if info["fast_pad"] else "7-smooth")
-    step_bytes = batch_step_bytes(grids, pad)
+    # the padded sizes and schedule each grid runs with (size classes may pad a grid
+    # beyond its own automatic length)
+    step_bytes = sum(4 * sum(algorithmic_bytes(b.grid_plan(i), nx, ny, nz, 4).values())
+                     for i, (nx, ny, nz) in enumerate(grids))
     out = {"grids": len(grids), "cells": b.cells, "steps": steps, "ms_per_step": 1e3 * dt / steps,
            "value": b.cells * steps / dt, "unit": "cell-updates/s", "dtype": "f32",
            "step_model_bytes": step_bytes, "effective_gbs": step_bytes / (dt / steps) / 1e9,

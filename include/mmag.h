@@ -340,6 +340,11 @@ typedef struct {
     size_t workspace_bytes;  /* device bytes the layout uses */
 } mm_batch_info;
 mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out);
+/* The plan of grid i (0 <= i < n) as the batch runs it: padded sizes (which the
+ * size-class layouts may raise above the grid's own automatic ones), stored x
+ * bins, kernel-spectrum size, passes and the two-plane schedule.  The tuner
+ * fields are 0.  MM_EINVAL for a NULL argument or i out of range. */
+mm_status mm_batch_get_grid_plan(mm_batch* b, int32_t i, mm_plan_info* out);
 
 /* ---- differentiation (adjoint) ------------------------------------------
  * Gradients of a loss of the final state of an RK4 rollout with respect to the

@@ -38,7 +38,7 @@ EXPORTS = ["mm_workspace_query", "mm_create", "mm_destroy", "mm_set_stream", "mm
            "mm_get_energy", "mm_get_mean_m", "mm_get_max_torque", "mm_get_plan", "mm_get_kernel_spectrum",
            "mm_demag_tensor", "mm_demag_tensor_newell", "mm_batch_workspace_query", "mm_batch_create", "mm_batch_destroy",
            "mm_batch_set_stream", "mm_batch_set_m", "mm_batch_get_m", "mm_batch_step", "mm_batch_get_field",
-           "mm_batch_cells", "mm_batch_get_info", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward", "mm_backward_noalloc", "mm_normalize_backward",
+           "mm_batch_cells", "mm_batch_get_info", "mm_batch_get_grid_plan", "mm_rollout", "mm_adjoint_workspace_query", "mm_backward", "mm_backward_noalloc", "mm_normalize_backward",
            "mm_profile_begin", "mm_profile_sample", "mm_profile_end", "mm_kernel_name", "mm_status_string",
            "mm_last_error"]
 
@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_batch_get_field": [vp, i32, vp, ctypes.c_int],
         "mm_batch_cells": [vp, ctypes.POINTER(i64)],
         "mm_batch_get_info": [vp, ctypes.POINTER(BatchInfo)],
+        "mm_batch_get_grid_plan": [vp, ctypes.c_int32, ctypes.POINTER(PlanInfo)],
         "mm_rollout": [vp, i64, dbl, i64, vp],
         "mm_adjoint_workspace_query": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "mm_backward": [vp, i64, dbl, i64, vp, vp, vp, vp, vp, ctypes.c_size_t],
@@ -473,6 +474,12 @@ class BatchSim:
         p = BatchInfo()
         _check(self._lib.mm_batch_get_info(self._h, ctypes.byref(p)), "mm_batch_get_info")
         return {k: getattr(p, k) for k, _ in BatchInfo._fields_}
+
+    def grid_plan(self, i: int) -> dict:
+        """Padded sizes and schedule of grid i as the batch runs it."""
+        p = PlanInfo()
+        _check(self._lib.mm_batch_get_grid_plan(self._h, int(i), ctypes.byref(p)), "mm_batch_get_grid_plan")
+        return {k: getattr(p, k) for k, _ in PlanInfo._fields_}
 
     def set_m(self, ms):
         """ms: list of per-grid (3, nz, ny, nx) arrays (or one flat array)."""

@@ -2709,6 +2709,27 @@ mm_status mm_batch_get_info(mm_batch* b, mm_batch_info* out)
     return MM_OK;
 }
 
+mm_status mm_batch_get_grid_plan(mm_batch* b, int32_t i, mm_plan_info* out)
+{
+    if (!b || !out) return fail(MM_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->n) return fail(MM_EINVAL, "grid index %d outside 0..%d", i, b->n - 1);
+    const Plan& p = b->L.plans[i];
+    memset(out, 0, sizeof *out);
+    out->px = p.Px;
+    out->py = p.Py;
+    out->pz = p.Pz;
+    out->hx = p.hx;
+    out->ncomp = p.ncomp;
+    out->threads = p.nt;
+    out->spectrum_elems = (int64_t)p.kplanes * p.oct_elems;
+    out->passes = (p.three_d && !p.zd) ? 5 : 3;
+    out->generic_fft = b->L.fast ? 0 : 1;
+    out->x_lines = p.xl;
+    out->x_lines_inv = p.xl_inv;
+    out->two_plane = p.zd ? 1 : 0;
+    return MM_OK;
+}
+
 mm_status mm_batch_destroy(mm_batch* b)
 {
     if (!b) return MM_OK;

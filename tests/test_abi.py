@@ -86,6 +86,7 @@ def test_batch_autotune_workspace_covers_every_layout(lib):
     assert sizes["pow2"] > sizes["plain"]
     info = mm.BatchInfo()
     assert lib.mm_batch_get_info(None, ctypes.byref(info)) == -1
+    assert lib.mm_batch_get_grid_plan(None, 0, ctypes.byref(mm.PlanInfo())) == -1
 
 
 @pytest.mark.parametrize("args", [(0, 4, 4), (4, -1, 4), (4, 4, 0)])

@@ -114,31 +114,28 @@ def test_bench_refuses_several_gpus():
     assert "one GPU" in r.stdout + r.stderr
 
 
-def test_batch_step_model_sums_the_single_grid_model():
-    # 32x8x1 with power-of-two padding: 64 x 16 points, 33 x bins, 4 kernel spectra
+def test_algorithmic_bytes_of_the_batched_schedules():
+    # the byte model the batched leg sums over its grids, on plans as the library
+    # reports them (mm_batch_get_grid_plan).  32x8x1 at 64 x 16 points: 33 x bins,
+    # 4 kernel spectra, three passes (one cell thick)
     N = 256
     real3, half_x, kern = 3 * N * 4, 3 * 8 * 33 * 8, 4 * 33 * 9 * 4
     one = (real3 + half_x) * 2 + (2 * half_x + kern) + 21 * 3 * N * 4 // 4
-    assert bench.batch_step_bytes([(32, 8, 1)], "pow2") == 4 * one
-    # a two-cell-thick grid under the size classes takes the two-plane schedule:
-    # x passes on [3][2][65][47], one y pass reading and writing that spectrum and the
-    # 10 coefficient planes of 65 x 65 values
-    p = bench.grid_plan(33, 47, 2, "pow2")
-    assert (p["px"], p["py"], p["pz"], p["passes"]) == (128, 128, 4, 3)
-    assert p["spectrum_elems"] == 10 * 65 * 65
+    p1 = {"hx": 33, "py": 16, "passes": 3, "spectrum_elems": 4 * 33 * 9}
+    assert sum(bench.algorithmic_bytes(p1, 32, 8, 1, 4).values()) == one
+    # 33x47x2 under the two-plane schedule at 128 x 128 points: x passes on
+    # [3][2][65][47], one y pass reading and writing that spectrum and the 10
+    # coefficient planes of 65 x 65 values
     N2 = 33 * 47 * 2
     real3b, half_xb, kernb = 3 * N2 * 4, 3 * 2 * 47 * 65 * 8, 10 * 65 * 65 * 4
     two = (real3b + half_xb) * 2 + (2 * half_xb + kernb) + 21 * 3 * N2 * 4 // 4
-    assert sum(bench.algorithmic_bytes(p, 33, 47, 2, 4).values()) == two
-    assert bench.batch_step_bytes([(32, 8, 1), (33, 47, 2)], "pow2") == 4 * one + 4 * two
-    # with 7-smooth padding (runtime-radix passes) it keeps the five passes
-    assert bench.grid_plan(33, 47, 2, False)["passes"] == 5
-    # 7-smooth padding: 2n when 7-smooth (2 x 33 = 66 = 2 3 11 is not: 65 = 5 13 no, 66..70: 70)
-    assert bench.pad_length(33, False) == 70 and bench.pad_length(32, False) == 64
-    assert bench.pad_length(47, True) == 128 and bench.pad_length(2, True) == 4
-    # the specialised set: powers of two and 96, 160, 192, 224 along x and y, powers of
-    # two along z
-    assert [bench.pad_length(n, "fast") for n in (32, 33, 48, 49, 64, 65, 80, 81, 96, 97, 112, 113)] == \
-        [64, 96, 96, 128, 128, 160, 160, 192, 192, 224, 224, 256]
-    q = bench.grid_plan(33, 47, 2, "fast")
-    assert (q["px"], q["py"], q["pz"], q["hx"]) == (96, 96, 4, 49)
+    p2 = {"hx": 65, "py": 128, "passes": 3, "spectrum_elems": 10 * 65 * 65}
+    assert sum(bench.algorithmic_bytes(p2, 33, 47, 2, 4).values()) == two
+    # the same grid through five passes (z transformed, Pz = 4): the y passes expand
+    # to the padded 128 rows and the octant has 6 x 3 planes
+    full_y = 3 * 2 * 128 * 65 * 8
+    five = (real3b + half_xb) * 2 + 2 * (half_xb + full_y) + (2 * full_y + 6 * 3 * 65 * 65 * 4) \
+        + 21 * 3 * N2 * 4 // 4
+    p5 = {"hx": 65, "py": 128, "passes": 5, "spectrum_elems": 6 * 3 * 65 * 65}
+    assert sum(bench.algorithmic_bytes(p5, 33, 47, 2, 4).values()) == five
+    assert two < five / 2

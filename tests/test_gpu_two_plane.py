@@ -197,3 +197,22 @@ def test_batch_of_two_plane_grids_matches_single_runs_and_oracle():
         assert np.abs(to_np(s.get_m()) - got[i]).max() <= 1e-6
         s.close()
     b.close()
+
+
+def test_small_size_class_is_padded_into_the_next_and_stays_exact():
+    # one 32x40 grid beside forty 100x100 grids: its x class (64 points) holds under
+    # 1/32 of the cells, so it runs in the 256-point class; the field is unchanged
+    grids = [(32, 40, 2)] + [(100, 100, 1)] * 40
+    b = mmag.BatchSim(grids, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0, alpha=0.5, precision="f64", pow2_pad=True)
+    assert b.info()["size_classes"] == 1
+    p0, p1 = b.grid_plan(0), b.grid_plan(1)
+    assert (p1["px"], p1["py"]) == (256, 256)
+    assert (p0["px"], p0["py"]) == (256, 256) and p0["two_plane"] == 1 and p0["passes"] == 3
+    with pytest.raises(mmag.MMError):
+        b.grid_plan(len(grids))
+    b.set_m([random_unit_m((3, nz, ny, nx), seed=i) for i, (nx, ny, nz) in enumerate(grids)])
+    m0 = to_np(b.get_m()[0])
+    h0 = to_np(b.field("demag")[0])
+    pb = oracle.Problem(32, 40, 2, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0, alpha=0.5)
+    assert rel_max(h0, oracle.demag(pb, m0)) <= FIELD_TOL["f64"]
+    b.close()
