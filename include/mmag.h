@@ -107,6 +107,14 @@ typedef enum {
  * is set; takes precedence over MM_FUSED_YZ; MM_AUTOTUNE times it where it
  * applies. */
 #define MM_ONE_WG 0x800u
+/* One-cell-thick grids of up to 2^20 cells with open boundaries and
+ * size-specialised passes run each RK4 stage as two launches: the y k-space pass
+ * and one fused pass doing the x inverse, the stage update and the x forward of
+ * the stage output on a block of rows (the demag field never leaves LDS).  Small
+ * grids are bound by the latency of dependent launches, not by bandwidth (the
+ * 128x128x1 film: four launches of 4-7 us per stage).  Results equal the
+ * separate passes to rounding.  This flag keeps the separate passes. */
+#define MM_SPLIT_STAGE 0x2000u
 #define MM_PERIODIC_X 0x80u
 #define MM_PERIODIC_Y 0x100u
 #define MM_PERIODIC_Z 0x200u
@@ -148,7 +156,7 @@ typedef struct {
                             A periodic axis takes n (0 or n accepted). */
     uint32_t flags;      /* MM_NO_DEMAG | MM_USE_GRAPH | MM_GENERIC_FFT | MM_AUTOTUNE | MM_POW2_PAD | MM_FAST_PAD |
                             MM_NEWELL | MM_PER_GRID_MATERIAL (batches) | MM_PERIODIC_X/Y/Z |
-                            MM_FUSED_YZ | MM_ONE_WG (single-grid handles) */
+                            MM_FUSED_YZ | MM_ONE_WG | MM_SPLIT_STAGE (single-grid handles) */
     int32_t threads;     /* threads per FFT work-group: 0 = automatic, 256 or 512 */
     int32_t x_lines;     /* row pairs per work-group of the size-specialised x passes:
                             0 = automatic (FP32 8 forward, 4 inverse; FP64 4 and 4 at
@@ -183,6 +191,7 @@ typedef struct {
                             xy0, xy1, sxz, yy0, yy1, syz, zz0, zz1 (suffix 0: z offset 0; 1: z
                             offset +1, the observer above the source; at offset +1 the xz and
                             yz spectra are i sxz and i syz) */
+    int32_t fused_stage; /* 1: RK4 stages run the fused stage pass (see MM_SPLIT_STAGE) */
 } mm_plan_info;
 
 typedef struct mm_sim mm_sim;

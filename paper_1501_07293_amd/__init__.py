@@ -26,6 +26,7 @@ MM_NEWELL, MM_PER_GRID_MATERIAL = 0x20, 0x40
 MM_PERIODIC_X, MM_PERIODIC_Y, MM_PERIODIC_Z = 0x80, 0x100, 0x200
 MM_FUSED_YZ = 0x400
 MM_ONE_WG = 0x800
+MM_SPLIT_STAGE = 0x2000
 MM_FAST_PAD = 0x1000
 MM_RK4, MM_EULER = 0, 1
 MM_NOALLOC_SCRATCH_BYTES = 96 << 20  # static adjoint scratch of mm_backward_noalloc
@@ -77,7 +78,8 @@ class PlanInfo(ctypes.Structure):
                 ("kernel_imag_ratio", ctypes.c_double), ("generic_fft", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("tuned_demag_ms", ctypes.c_double), ("x_lines", ctypes.c_int32),
-                ("x_lines_inv", ctypes.c_int32), ("two_plane", ctypes.c_int32)]
+                ("x_lines_inv", ctypes.c_int32), ("two_plane", ctypes.c_int32),
+                ("fused_stage", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -186,7 +188,7 @@ class Sim:
                  graph: bool = False, threads: int = 0, generic_fft: bool = False,
                  autotune: bool = False, x_lines: int = 0, pow2_pad: bool = False, fast_pad: bool = False,
                  tensor: str = "point", periodic: Sequence[bool] = (False, False, False),
-                 images: int = 0, fused_yz: bool = False, one_wg: bool = False,
+                 images: int = 0, fused_yz: bool = False, one_wg: bool = False, split_stage: bool = False,
                  device: str = "cuda:0"):
         """periodic: per axis x, y, z, no zero padding and a wrapped exchange
         stencil; images: images on each side beyond the nearest one in the
@@ -207,7 +209,7 @@ class Sim:
                  | (MM_POW2_PAD if pow2_pad else 0) | (MM_FAST_PAD if fast_pad else 0)
                  | _tensor_flag(tensor) | (MM_PERIODIC_X if periodic[0] else 0) | (MM_PERIODIC_Y if periodic[1] else 0)
                  | (MM_PERIODIC_Z if periodic[2] else 0) | (MM_FUSED_YZ if fused_yz else 0)
-                 | (MM_ONE_WG if one_wg else 0))
+                 | (MM_ONE_WG if one_wg else 0) | (MM_SPLIT_STAGE if split_stage else 0))
         self._opt = Options(MM_F32 if precision == "f32" else MM_F64, pad[0], pad[1], pad[2], flags,
                             threads, x_lines, images)
         nbytes = ctypes.c_size_t()

@@ -128,12 +128,21 @@ struct Plan {
     int images;                // images on each side beyond the nearest (periodic axes)
     bool zd;                   // two cells along z: the two-plane y k-space pass replaces y forward,
                                // z k-space and y inverse (the z coupling taken directly)
+    bool fs;                   // one cell thick and small: the fused stage pass (x inverse, stage
+                               // update, x forward) with a second spectrum buffer, two launches
+                               // per RK4 stage
+    int fs_lines;              // its row pairs per work-group
     int64_t oct_elems;         // per component (two-plane schedule: per coefficient plane)
     int kplanes;               // blocks of oct_elems in the kernel region (ncomp, or 10)
     // workspace offsets
-    size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_kern, o_twx, o_twy, o_twz;
+    size_t o_mn, o_ma, o_mb, o_acc, o_hd, o_ku, o_S, o_S2, o_kern, o_twx, o_twy, o_twz;
     size_t o_twxd, o_twyd, o_twzd, o_red, o_redout, o_flags, o_setR, o_setS, total;
 };
+
+// The fused stage pass applies up to this many cells: beyond, the separate
+// passes (whose x transposes move 128-byte segments) are bandwidth-bound, not
+// latency-bound.
+constexpr int64_t kFusedStageMaxCells = (int64_t)1 << 20;
 
 mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
 {
@@ -252,6 +261,14 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->zd = p->nz == 2 && p->Pz == 4 && !(p->per & 4) && !p->yz && !p->wg1 &&
             !(o->flags & MM_GENERIC_FFT) && fast_ky2_lines(p->Py) > 0 && p->ny <= p->Py &&
             !(p->esz == 8 && p->Py > 1024);
+    // one cell thick, open, small (latency-bound), with the specialised passes: the
+    // fused stage pass
+    p->fs_lines = 0;
+    if (!p->three_d && p->per == 0 && !p->yz && !p->wg1 && p->N <= kFusedStageMaxCells &&
+        !(o->flags & (MM_GENERIC_FFT | MM_SPLIT_STAGE | MM_NO_DEMAG)) && fast_ky_lines(p->Py) > 0 &&
+        2 * p->ny <= p->Py)
+        p->fs_lines = fused_stage_lines(p->Px, p->nx, p->ny, p->esz);
+    p->fs = p->fs_lines > 0;
     // spectrum [3][nz][hx][S_rows]: the y pass expands ny rows to Py in place on 3-D grids
     p->S_planes = p->nz;
     p->S_rows = (p->three_d && !p->zd) ? p->Py : p->ny;
@@ -277,6 +294,7 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->o_hd = take(vec);
     p->o_ku = take((size_t)p->N * p->esz);
     p->o_S = take(3 * (size_t)p->S_planes * p->hx * p->S_rows * 2 * p->esz);
+    p->o_S2 = p->fs ? take(3 * (size_t)p->S_planes * p->hx * p->S_rows * 2 * p->esz) : 0;
     p->o_kern = take((size_t)p->kplanes * p->oct_elems * p->esz);
     p->o_twx = take((size_t)p->Px * 2 * p->esz);
     p->o_twy = take((size_t)p->Py * 2 * p->esz);
@@ -689,9 +707,13 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // One RK4 step of dt on stream st.  Stage inputs cycle m_n -> m_a -> m_b -> m_a;
 // stage 4 writes the renormalised result back into m_n.
 template <typename T>
+mm_status rk4_fused_steps(mm_sim* s, int64_t nsteps, double dt, bool prologue, hipStream_t st);
+
+template <typename T>
 mm_status rk4_step(mm_sim* s, double dt, hipStream_t st)
 {
     const Plan& p = s->p;
+    if (p.fs) return rk4_fused_steps<T>(s, 1, dt, true, st);
     T* mn = s->at<T>(p.o_mn);
     T* ma = s->at<T>(p.o_ma);
     T* mb = s->at<T>(p.o_mb);
@@ -711,6 +733,45 @@ mm_status rk4_step(mm_sim* s, double dt, hipStream_t st)
         a.out = dst[stg];
         a.stage = stg + 1;
         LAUNCH(KLLG, launch_llg_stage<T>(a, st));
+    }
+    return MM_OK;
+}
+
+// RK4 steps of a fused-stage plan (one cell thick, small).  The spectrum of the
+// stage input sits in S: the prologue forms it for m_n (x forward); each stage
+// then runs the y k-space pass on it in place and the fused pass, which writes
+// the stage output and its x half spectrum into the other buffer.  Four stages
+// per step return the spectrum to S, holding that of the new m_n.
+template <typename T>
+mm_status rk4_fused_steps(mm_sim* s, int64_t nsteps, double dt, bool prologue, hipStream_t st)
+{
+    const Plan& p = s->p;
+    T* mn = s->at<T>(p.o_mn);
+    T* ma = s->at<T>(p.o_ma);
+    T* mb = s->at<T>(p.o_mb);
+    T* src[4] = {mn, ma, mb, ma};
+    T* dst[4] = {ma, mb, ma, mn};
+    PassCtx c = pass_ctx(s);
+    void* bufs[2] = {s->at<char>(p.o_S), s->at<char>(p.o_S2)};
+    if (prologue) LAUNCH(KX_FWD, pass_x_forward<T>(c, mn, st));
+    FusedStageArgs<T> f{};
+    f.g = llg_args<T>(s, dt);
+    f.g.mn = mn;
+    f.g.acc = s->at<T>(p.o_acc);
+    f.g.hd = nullptr;
+    f.tw = c.twx;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        for (int stg = 0; stg < 4; ++stg) {
+            c.S = bufs[stg & 1];
+            LAUNCH(KSPACE, pass_kspace<T>(c, st));
+            f.g.ms = src[stg];
+            f.g.out = dst[stg];
+            f.g.stage = stg + 1;
+            f.S_in = bufs[stg & 1];
+            f.S_out = bufs[(stg + 1) & 1];
+            LAUNCH(KLLG, launch_fused_stage_2d<T>(f, p.Px, p.fs_lines, st) ? hipGetLastError()
+                                                                            : hipErrorInvalidValue);
+        }
     }
     return MM_OK;
 }
@@ -876,11 +937,45 @@ void drop_bwd_graphs(mm_sim* s)
     }
 }
 
+// Steps of a fused-stage plan: one prologue per call (the spectrum of m_n), then
+// the steps, replaying captured 8-step graphs that leave S as they found it.
+template <typename T>
+mm_status fused_step_impl(mm_sim* s, int64_t nsteps, double dt, bool use_graph)
+{
+    hipStream_t st = s->stream;
+    if (nsteps <= 0) return MM_OK;
+    if (!use_graph) return rk4_fused_steps<T>(s, nsteps, dt, true, st);
+    const int chunk = 8;
+    if (!s->graph_valid || s->graph_dt != dt || s->graph_method != MM_RK4) {
+        drop_graph(s);
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = rk4_fused_steps<T>(s, chunk, dt, false, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (r != MM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        s->graph = g;
+        HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+        s->graph_valid = true;
+        s->graph_dt = dt;
+        s->graph_chunk = chunk;
+        s->graph_method = MM_RK4;
+    }
+    if (mm_status r = rk4_fused_steps<T>(s, 0, dt, true, st); r != MM_OK) return r;  // prologue
+    int64_t n = 0;
+    for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, st));
+    return rk4_fused_steps<T>(s, nsteps - n, dt, false, st);
+}
+
 template <typename T>
 mm_status step_impl(mm_sim* s, int64_t nsteps, double dt, bool force_graph = false)
 {
     hipStream_t st = s->stream;
     const bool use_graph = ((s->flags & MM_USE_GRAPH) || force_graph) && s->prof_kernel < 0;
+    if (s->p.fs) return fused_step_impl<T>(s, nsteps, dt, use_graph);
     if (!use_graph) {
         for (int64_t n = 0; n < nsteps; ++n) {
             mm_status r = rk4_step<T>(s, dt, st);
@@ -2401,6 +2496,7 @@ mm_status mm_get_plan(mm_sim* s, mm_plan_info* out)
     out->x_lines = s->p.xl;
     out->x_lines_inv = s->p.xl_inv;
     out->two_plane = s->p.zd ? 1 : 0;
+    out->fused_stage = s->p.fs ? 1 : 0;
     return MM_OK;
 }
 

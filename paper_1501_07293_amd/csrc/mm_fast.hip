@@ -1,6 +1,7 @@
 // mm_fast.hip -- single-grid kernels of the size-specialised FFT passes (bodies
 // in mm_fast.hpp) and their dispatch by padded size.
 #include "mm_fast.hpp"
+#include "mm_fused.hpp"
 
 namespace mm {
 
@@ -52,6 +53,14 @@ __global__ __launch_bounds__(6 * ky2_lines<P>() * (P / Sched<P>::R0)) void k_ksp
 {
     __shared__ cpx<T> lds[kspace_y2_lds_elems<P>()];
     body_kspace_y2<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
+template <typename T, int P, int L>
+__global__ __launch_bounds__(3 * L * (P / Sched<P>::R0)) void k_fused_stage_2d(FusedStageArgs<T> a)
+{
+    __shared__ cpx<T> lds[3 * fused_region<P, L>()];
+    __shared__ T cell[3 * 2 * L * (P / 2)];
+    body_fused_stage_2d<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds, cell);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -284,6 +293,85 @@ int fast_ky2_lines(int P)
     }
 }
 
+template <typename T, int P>
+static bool fused_dispatch(const FusedStageArgs<T>& a, int L, hipStream_t s)
+{
+    constexpr int TL = P / Sched<P>::R0;
+    auto go = [&](auto kern, int lines) {
+        const int grid = (a.g.ny + 2 * lines - 1) / (2 * lines);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(3 * lines * TL), 0, s, a);
+        return true;
+    };
+    if constexpr (fused_lds_bytes<T, P, 4>() <= kLdsBudget && 3 * 4 * TL <= 1024)
+        if (L == 4) return go(k_fused_stage_2d<T, P, 4>, 4);
+    if constexpr (fused_lds_bytes<T, P, 2>() <= kLdsBudget && 3 * 2 * TL <= 1024)
+        if (L == 2) return go(k_fused_stage_2d<T, P, 2>, 2);
+    if constexpr (fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 1024)
+        if (L == 1) return go(k_fused_stage_2d<T, P, 1>, 1);
+    return false;
+}
+
+template <typename T>
+bool launch_fused_stage_2d(const FusedStageArgs<T>& a, int Px, int L, hipStream_t s)
+{
+    if (a.g.ny <= 0) return true;
+    if (2 * a.g.nx > Px || a.g.nz != 1) return false;
+    switch (Px) {
+    case 16: return fused_dispatch<T, 16>(a, L, s);
+    case 32: return fused_dispatch<T, 32>(a, L, s);
+    case 64: return fused_dispatch<T, 64>(a, L, s);
+    case 96: return fused_dispatch<T, 96>(a, L, s);
+    case 128: return fused_dispatch<T, 128>(a, L, s);
+    case 160: return fused_dispatch<T, 160>(a, L, s);
+    case 192: return fused_dispatch<T, 192>(a, L, s);
+    case 224: return fused_dispatch<T, 224>(a, L, s);
+    case 256: return fused_dispatch<T, 256>(a, L, s);
+    case 512: return fused_dispatch<T, 512>(a, L, s);
+    case 1024: return fused_dispatch<T, 1024>(a, L, s);
+    default: return false;
+    }
+}
+
+// Lines per work-group: about 256 work-groups or more where the grid has the rows
+// (latency-bound sizes gain from spreading over CUs), within the LDS budget.
+template <typename T, int P>
+static int fused_lines_for(int ny)
+{
+    constexpr int TL = P / Sched<P>::R0;
+    const int want = ny >= 2048 ? 4 : (ny >= 1024 ? 2 : 1);
+    for (int L = want; L >= 1; L /= 2) {
+        if (L == 4 && fused_lds_bytes<T, P, 4>() <= kLdsBudget && 12 * TL <= 1024) return 4;
+        if (L == 2 && fused_lds_bytes<T, P, 2>() <= kLdsBudget && 6 * TL <= 1024) return 2;
+        if (L == 1 && fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 1024) return 1;
+    }
+    return 0;
+}
+
+template <typename T>
+static int fused_lines_t(int Px, int ny)
+{
+    switch (Px) {
+    case 16: return fused_lines_for<T, 16>(ny);
+    case 32: return fused_lines_for<T, 32>(ny);
+    case 64: return fused_lines_for<T, 64>(ny);
+    case 96: return fused_lines_for<T, 96>(ny);
+    case 128: return fused_lines_for<T, 128>(ny);
+    case 160: return fused_lines_for<T, 160>(ny);
+    case 192: return fused_lines_for<T, 192>(ny);
+    case 224: return fused_lines_for<T, 224>(ny);
+    case 256: return fused_lines_for<T, 256>(ny);
+    case 512: return fused_lines_for<T, 512>(ny);
+    case 1024: return fused_lines_for<T, 1024>(ny);
+    default: return 0;
+    }
+}
+
+int fused_stage_lines(int Px, int nx, int ny, size_t esz)
+{
+    if (2 * nx > Px) return 0;
+    return esz == 8 ? fused_lines_t<double>(Px, ny) : fused_lines_t<float>(Px, ny);
+}
+
 int fast_first_radix(int P)
 {
     switch (P) {
@@ -324,6 +412,8 @@ int fast_ky_lines(int P)
     }
 }
 
+template bool launch_fused_stage_2d<float>(const FusedStageArgs<float>&, int, int, hipStream_t);
+template bool launch_fused_stage_2d<double>(const FusedStageArgs<double>&, int, int, hipStream_t);
 template bool launch_kspace_y2<float>(const Ky2Args&, int, hipStream_t);
 template bool launch_kspace_y2<double>(const Ky2Args&, int, hipStream_t);
 template bool launch_kspace_y<float>(const KyArgs&, int, hipStream_t);

@@ -1,0 +1,191 @@
+// mm_fused.hpp -- the fused stage pass of small one-cell-thick grids: x inverse
+// of the demag spectrum, the LLG + RK4 stage update, and x forward of the stage
+// output, for a block of rows and all three components in one work-group.
+//
+// A grid one cell thick evaluates its field in three passes (x forward, y
+// k-space, x inverse) and then runs the stage update: four dependent launches
+// per RK4 stage, each a few microseconds of latency on a small grid.  Here the
+// x inverse leaves the demag field of the block in LDS, the stage update reads
+// it there (and m, its in-plane neighbours, m_n and the accumulator from
+// global memory, as the plain stage kernel does), and the x forward of the
+// block's new state writes the half spectrum the next stage's y k-space pass
+// takes: two launches per stage.  The input and output spectra are different
+// buffers (other work-groups still read the input).  Every per-cell operation
+// is the one the separate passes perform, in the same order.
+#pragma once
+#include "mm_fast.hpp"
+#include "mm_llg_body.hpp"
+
+namespace mm {
+
+// LDS of one work-group: per component the x-inverse staging (2L half-spectrum
+// rows) or the FFT lines (L lines), whichever is larger, then the cells of the
+// block [3][2L][P/2] as real values.
+template <int P, int L>
+constexpr int fused_region() { return (L * padded_len<P>() > 2 * L * (P / 2 + 1)) ? L * padded_len<P>() : 2 * L * (P / 2 + 1); }
+template <typename T, int P, int L>
+constexpr int fused_lds_bytes() { return (int)(3 * fused_region<P, L>() * sizeof(cpx<T>) + 3 * 2 * L * (P / 2) * sizeof(T)); }
+
+// Work-group `tile` takes rows 2L tile .. 2L tile + 2L - 1; 3 L (P / R0) threads,
+// thread (component, line l, lane u).  Needs 2 nx <= P (the pruned x lines).
+template <typename T, int P, int L>
+__device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile, cpx<T>* lds, T* cell)
+{
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = 3 * L * TL, LP = padded_len<P>();
+    constexpr int HX = P / 2 + 1, ROWS = 2 * L, REG = fused_region<P, L>(), XH = P / 2;
+    const LlgArgs<T>& a = f.g;
+    const int nx = a.nx, ny = a.ny;
+    const int yb = tile * ROWS;
+    const int tid = (int)threadIdx.x;
+    const int comp = tid / (L * TL), l = (tid / TL) % L, u = tid % TL;
+    cpx<T>* reg = lds + comp * REG;
+    LineTw<T, P> W;
+    W.load(u, (const cpx<T>*)f.tw);
+
+    // ---- x inverse: gather the block's half-spectrum rows of the three components
+    // (for one bin, the rows of the block are adjacent in [3][hx][ny]); every load
+    // is issued before the first LDS store
+    {
+        const cpx<T>* src = (const cpx<T>*)f.S_in;
+        constexpr int NEL = HX * ROWS, ITER = (3 * NEL + NT - 1) / NT;
+        cpx<T> gv[ITER];
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int idx = tid + it * NT;
+            const int c = idx / NEL, rem = idx - c * NEL, kx = rem / ROWS, rr = rem - kx * ROWS;
+            const int y = yb + rr;
+            gv[it] = cpx<T>{(T)0, (T)0};
+            if (idx < 3 * NEL && y < ny) gv[it] = src[((int64_t)c * HX + kx) * ny + y];
+        }
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int idx = tid + it * NT;
+            if (idx < 3 * NEL) {
+                const int c = idx / NEL, rem = idx - c * NEL, kx = rem / ROWS, rr = rem - kx * ROWS;
+                lds[c * REG + rr * HX + kx] = gv[it];
+            }
+        }
+    }
+    __syncthreads();
+    {
+        const cpx<T>* ra = reg + (2 * l) * HX;
+        const cpx<T>* rb = reg + (2 * l + 1) * HX;
+        cpx<T> v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = u + TL * r;
+            cpx<T> A, B;
+            if (k < HX) {
+                A = ra[k];
+                B = rb[k];
+                if (k == 0 || 2 * k == P) {  // DC and Nyquist bins of a real row are real
+                    A.im = (T)0;
+                    B.im = (T)0;
+                }
+            } else {
+                A = conj(ra[P - k]);
+                B = conj(rb[P - k]);
+            }
+            v[r] = conj(cpx<T>{A.re - B.im, A.im + B.re});  // conj(A + i B): inverse by conjugation
+        }
+        Dft<T, R0>::run(v);
+        __syncthreads();  // every staged row is read before the lines reuse the LDS
+        T* cl = cell + comp * (ROWS * XH);
+        auto put = [&](int e, cpx<T> val) {  // rows 2l, 2l+1 of the block: re, -im
+            if (e < nx) {
+                cl[(2 * l) * XH + e] = val.re;
+                cl[(2 * l + 1) * XH + e] = -val.im;
+            }
+        };
+        if constexpr (Sched<P>::NS == 1) {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) put(r, v[r]);
+        } else {
+            finish_line<T, P, true>(reg + l * LP, u, v, W, put);
+        }
+    }
+    __syncthreads();
+
+    // ---- stage update of the block's cells: the demag field from LDS, the rest as
+    // the plain stage kernel reads it (a missing neighbour is the cell itself, Eq. 7);
+    // the result overwrites the cell's field in LDS
+    {
+        const int64_t N = a.N;
+        for (int idx = tid; idx < ROWS * nx; idx += NT) {
+            const int r = idx / nx, i = idx - r * nx, j = yb + r;
+            if (j >= ny) break;
+            const int64_t c = (int64_t)j * nx + i;
+            const int64_t dxm = i > 0 ? -1 : 0, dxp = i < nx - 1 ? 1 : 0;
+            const int64_t dym = j > 0 ? -(int64_t)nx : 0, dyp = j < ny - 1 ? (int64_t)nx : 0;
+            T m[3], lap[3], hd[3], mn[3], ac[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T* uu = a.ms + d * N + c;
+                const T mc = uu[0];
+                T s = (T)0;
+                s += uu[dxm] - mc;
+                s += uu[dxp] - mc;
+                s += uu[dym] - mc;
+                s += uu[dyp] - mc;
+                m[d] = mc;
+                lap[d] = s;
+                hd[d] = cell[d * ROWS * XH + r * XH + i];
+                mn[d] = (T)0;
+                ac[d] = (T)0;
+                if (a.stage > 1) {
+                    mn[d] = a.mn[d * N + c];
+                    ac[d] = a.acc[d * N + c];
+                }
+            }
+            const T kan = a.ku ? a.ku[c] : a.can;
+            T res[3];
+            llg_cell<T>(a, c, m, lap, hd, mn, ac, kan, res);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cell[d * ROWS * XH + r * XH + i] = res[d];
+        }
+    }
+    __syncthreads();
+
+    // ---- x forward of the stage output rows, half spectrum stored transposed
+    {
+        const T* cl = cell + comp * (ROWS * XH);
+        const int y0 = yb + 2 * l;
+        const bool ok0 = y0 < ny, ok1 = y0 + 1 < ny;
+        cpx<T> v[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int e = u + TL * r;
+            cpx<T> x = {(T)0, (T)0};
+            if (2 * r < R0 && e < nx) {  // e >= P/2 is zero padding
+                if (ok0) x.re = cl[(2 * l) * XH + e];
+                if (ok1) x.im = cl[(2 * l + 1) * XH + e];
+            }
+            v[r] = x;
+        }
+        Dft<T, R0>::run(v);
+        cpx<T>* ln = reg + l * LP;
+        if constexpr (Sched<P>::NS == 1) {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
+        } else {
+            finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+        }
+        __syncthreads();
+        cpx<T>* out = (cpx<T>*)f.S_out;
+        for (int idx = tid; idx < 3 * HX * L; idx += NT) {
+            const int c = idx / (HX * L), rem = idx - c * (HX * L), q = rem % L, kx = rem / L;
+            const cpx<T>* lq = lds + c * REG + q * LP;
+            const cpx<T> zk = lq[pad16(kx)];
+            const cpx<T> zm = lq[pad16(kx == 0 ? 0 : P - kx)];
+            // Z = FFT(a + i b): A = (Z_k + conj Z_-k)/2, B = (Z_k - conj Z_-k)/(2i)
+            const cpx<T> A = scale(zk + conj(zm), (T)0.5);
+            const cpx<T> B = scale(mul_mi(zk - conj(zm)), (T)0.5);
+            const int y = yb + 2 * q;
+            cpx<T>* o = out + ((int64_t)c * HX + kx) * ny + y;
+            if (y < ny) o[0] = A;
+            if (y + 1 < ny) o[1] = B;
+        }
+    }
+}
+
+}  // namespace mm
