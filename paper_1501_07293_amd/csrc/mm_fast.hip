@@ -338,11 +338,13 @@ template <typename T, int P>
 static int fused_lines_for(int ny)
 {
     constexpr int TL = P / Sched<P>::R0;
-    const int want = ny >= 2048 ? 4 : (ny >= 1024 ? 2 : 1);
+    // at most 512 threads (two waves per SIMD leave 256 registers a thread), and one
+    // line at 512 points or more in FP64: the larger shapes spill
+    const int want = (sizeof(T) == 8 && P >= 512) ? 1 : (ny >= 2048 ? 4 : (ny >= 1024 ? 2 : 1));
     for (int L = want; L >= 1; L /= 2) {
-        if (L == 4 && fused_lds_bytes<T, P, 4>() <= kLdsBudget && 12 * TL <= 1024) return 4;
-        if (L == 2 && fused_lds_bytes<T, P, 2>() <= kLdsBudget && 6 * TL <= 1024) return 2;
-        if (L == 1 && fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 1024) return 1;
+        if (L == 4 && fused_lds_bytes<T, P, 4>() <= kLdsBudget && 12 * TL <= 512) return 4;
+        if (L == 2 && fused_lds_bytes<T, P, 2>() <= kLdsBudget && 6 * TL <= 512) return 2;
+        if (L == 1 && fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 512) return 1;
     }
     return 0;
 }

@@ -108,40 +108,64 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
 
     // ---- stage update of the block's cells: the demag field from LDS, the rest as
     // the plain stage kernel reads it (a missing neighbour is the cell itself, Eq. 7);
-    // the result overwrites the cell's field in LDS
+    // the result overwrites the cell's field in LDS.  A thread takes up to NC cells
+    // and issues the loads of CH of them before their updates (the updates store to
+    // global memory, so the compiler would not hoist later loads above them): one
+    // memory latency per CH cells instead of one per cell.
     {
+        constexpr int NC = (ROWS * XH + NT - 1) / NT, CH = NC < 3 ? NC : 3;
         const int64_t N = a.N;
-        for (int idx = tid; idx < ROWS * nx; idx += NT) {
-            const int r = idx / nx, i = idx - r * nx, j = yb + r;
-            if (j >= ny) break;
-            const int64_t c = (int64_t)j * nx + i;
-            const int64_t dxm = i > 0 ? -1 : 0, dxp = i < nx - 1 ? 1 : 0;
-            const int64_t dym = j > 0 ? -(int64_t)nx : 0, dyp = j < ny - 1 ? (int64_t)nx : 0;
-            T m[3], lap[3], hd[3], mn[3], ac[3];
+        for (int q0 = 0; q0 < NC; q0 += CH) {
+            T mv[CH][3][5], mnv[CH][3], acv[CH][3], kan[CH];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const T* uu = a.ms + d * N + c;
-                const T mc = uu[0];
-                T s = (T)0;
-                s += uu[dxm] - mc;
-                s += uu[dxp] - mc;
-                s += uu[dym] - mc;
-                s += uu[dyp] - mc;
-                m[d] = mc;
-                lap[d] = s;
-                hd[d] = cell[d * ROWS * XH + r * XH + i];
-                mn[d] = (T)0;
-                ac[d] = (T)0;
-                if (a.stage > 1) {
-                    mn[d] = a.mn[d * N + c];
-                    ac[d] = a.acc[d * N + c];
+            for (int q = 0; q < CH; ++q) {
+                const int idx = tid + (q0 + q) * NT;
+                const int r = idx / nx, i = idx - r * nx, j = yb + r;
+                const bool in = q0 + q < NC && idx < ROWS * nx && j < ny;
+                const int64_t c = in ? (int64_t)j * nx + i : 0;
+                const int64_t dxm = in && i > 0 ? -1 : 0, dxp = in && i < nx - 1 ? 1 : 0;
+                const int64_t dym = in && j > 0 ? -(int64_t)nx : 0, dyp = in && j < ny - 1 ? (int64_t)nx : 0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const T* uu = a.ms + d * N + c;
+                    mv[q][d][0] = uu[0];
+                    mv[q][d][1] = uu[dxm];
+                    mv[q][d][2] = uu[dxp];
+                    mv[q][d][3] = uu[dym];
+                    mv[q][d][4] = uu[dyp];
+                    mnv[q][d] = (T)0;
+                    acv[q][d] = (T)0;
+                    if (a.stage > 1) {
+                        mnv[q][d] = a.mn[d * N + c];
+                        acv[q][d] = a.acc[d * N + c];
+                    }
                 }
+                kan[q] = a.ku ? a.ku[c] : a.can;
             }
-            const T kan = a.ku ? a.ku[c] : a.can;
-            T res[3];
-            llg_cell<T>(a, c, m, lap, hd, mn, ac, kan, res);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) cell[d * ROWS * XH + r * XH + i] = res[d];
+            for (int q = 0; q < CH; ++q) {
+                const int idx = tid + (q0 + q) * NT;
+                const int r = idx / nx, i = idx - r * nx, j = yb + r;
+                if (q0 + q >= NC || idx >= ROWS * nx || j >= ny) break;
+                const int64_t c = (int64_t)j * nx + i;
+                T m[3], lap[3], hd[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const T mc = mv[q][d][0];
+                    T s = (T)0;
+                    s += mv[q][d][1] - mc;
+                    s += mv[q][d][2] - mc;
+                    s += mv[q][d][3] - mc;
+                    s += mv[q][d][4] - mc;
+                    m[d] = mc;
+                    lap[d] = s;
+                    hd[d] = cell[d * ROWS * XH + r * XH + i];
+                }
+                T res[3];
+                llg_cell<T>(a, c, m, lap, hd, mnv[q], acv[q], kan[q], res);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) cell[d * ROWS * XH + r * XH + i] = res[d];
+            }
         }
     }
     __syncthreads();
