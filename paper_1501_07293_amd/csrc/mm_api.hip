@@ -2133,7 +2133,8 @@ mm_status autotune(const mm_grid* g, const mm_material* mat, const mm_options* o
             const Plan& pi = plans[i];
             const Plan& pj = plans[j];
             if (done[j] || pj.Px != pi.Px || pj.Py != pi.Py || pj.Pz != pi.Pz || pj.total != pi.total ||
-                pj.o_kern != pi.o_kern || pj.o_S != pi.o_S || pj.o_twz != pi.o_twz)
+                pj.o_kern != pi.o_kern || pj.o_S != pi.o_S || pj.o_twz != pi.o_twz || pj.zd != pi.zd ||
+                pj.fs != pi.fs)
                 continue;
             done[j] = true;
             if (r != MM_OK) continue;
