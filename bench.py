@@ -696,7 +696,12 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
     x_ok = fast and pow2(px) and 16 <= px <= (2048 if t == "float" else 1024)
     y_ok = fast and pow2(py) and 16 <= py <= 2048
     if k == "llg":
-        return f"mm::k_llg_stage<{t}>"
+        if plan.get("fused_stage"):
+            # the fused stage pass's row pairs per work-group, as the library picks them
+            lines = 1 if (t == "double" and px >= 512) else (4 if ny >= 2048 else (2 if ny >= 1024 else 1))
+            return f"mm::k_fused_stage_2d<{t}, {px}, {lines}>"
+        kz = 1 if nz == 1 else (2 if nz == 2 else 4)   # planes per thread
+        return f"mm::k_llg_stage<{t}, {kz}>"
     if plan["passes"] == 1:
         return f"mm::k_demag_1wg<{t}, {plan['threads']}>"
     if k in ("x_fwd", "x_inv"):
@@ -717,6 +722,8 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
         if fast and pz in (128, 256, 512, 1024):
             return f"mm::k_kspace_fixed<{t}, 256, {pz}>"
         return f"mm::k_kspace<{t}, {plan['threads']}>"
+    if plan.get("two_plane"):  # two cells thick: the two-plane y k-space pass
+        return f"mm::k_kspace_y2<{t}, {py}, {b(2 * ny > py)}>"
     if pz > 1:  # three passes on a 3-D grid: the fused y-z pass
         return f"mm::k_kspace_yz<{t}, {plan['threads']}>"
     ky_ok = fast and pow2(py) and 16 <= py <= 1024

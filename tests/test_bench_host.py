@@ -48,7 +48,15 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("y_fwd") == "mm::k_yline<float, 1024, false, false>"
     assert sym("y_inv") == "mm::k_yline<float, 1024, true, false>"
     assert sym("kspace") == "mm::k_kspace_z<float, 32>"
-    assert sym("llg") == "mm::k_llg_stage<float>"
+    assert sym("llg") == "mm::k_llg_stage<float, 4>"
+    # planes per thread of the stage update: 1 or 2 for grids one or two cells thick
+    assert sym("llg", n=(512, 512, 1)) == "mm::k_llg_stage<float, 1>"
+    assert sym("llg", n=(512, 512, 2)) == "mm::k_llg_stage<float, 2>"
+    # small one-cell-thick grids: the fused stage pass; two cells thick: the two-plane pass
+    small = dict(FILM, px=256, py=256, pz=1, hx=129, passes=3, fused_stage=1)
+    assert sym("llg", plan=small, n=(128, 128, 1)) == "mm::k_fused_stage_2d<float, 256, 1>"
+    two = dict(FILM, px=128, py=128, pz=4, hx=65, passes=3, two_plane=1)
+    assert sym("kspace", plan=two, n=(33, 47, 2)) == "mm::k_kspace_y2<float, 128, false>"
     # FP64 lines with a zero upper half take the two-lane z pass
     assert sym("kspace", "f64") == "mm::k_kspace_z_split<double, 32>"
     # periodic x and y: whole lines
