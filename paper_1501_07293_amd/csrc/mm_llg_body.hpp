@@ -37,14 +37,14 @@ __device__ inline void llg_cell(const LlgArgs<T>& a, int64_t c, const T (&m)[3],
     } else if (a.stage == 1) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            a.acc[d * N + c] = F[d];
+            st_later(F[d], a.acc + d * N + c);
             res[d] = m[d] + (T)0.5 * F[d];
         }
     } else if (a.stage == 2 || a.stage == 3) {
         const T w = a.stage == 2 ? (T)0.5 : (T)1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            a.acc[d * N + c] = ac[d] + (T)2 * F[d];
+            st_later(ac[d] + (T)2 * F[d], a.acc + d * N + c);
             res[d] = mn[d] + w * F[d];
         }
     } else {
@@ -137,10 +137,10 @@ __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane
             hd[q][d] = (T)0;
             mn[q][d] = (T)0;
             ac[q][d] = (T)0;
-            if (a.hd) hd[q][d] = a.hd[d * N + c];
+            if (a.hd) hd[q][d] = ld_last(a.hd + d * N + c);
             if (a.stage > 1) {
-                mn[q][d] = a.mn[d * N + c];
-                ac[q][d] = a.acc[d * N + c];
+                mn[q][d] = ld_last(a.mn + d * N + c);
+                ac[q][d] = ld_last(a.acc + d * N + c);
             }
         }
         kan[q] = a.ku ? a.ku[c] : a.can;
