@@ -221,7 +221,9 @@ __device__ inline void body_yline(const YLineArgs& a, int tile, cpx<T>* lds)
     const int l = threadIdx.x / TL, u = threadIdx.x % TL;
     const int line = tile * L + l;
     const bool ok = line < a.nlines;  // launched with L * TL threads
-    cpx<T>* g = (cpx<T>*)a.buf + (int64_t)(ok ? line : 0) * a.line_stride;
+    int mline = ok ? line : 0;        // its place in memory: plane * hx + bin
+    if (a.kx_major) mline = (mline % a.kx_major) * (a.nlines / a.kx_major) + mline / a.kx_major;
+    cpx<T>* g = (cpx<T>*)a.buf + (int64_t)mline * a.line_stride;
     const cpx<T>* tw = (const cpx<T>*)a.tw;
     LineTw<T, P> W;
     W.load(u, tw);

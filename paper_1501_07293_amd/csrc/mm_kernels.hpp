@@ -123,6 +123,8 @@ struct YLineArgs {           // contiguous lines, transformed in place
     int64_t line_stride;
     int nin, nout;           // inputs beyond nin are zero; first nout outputs stored
     const void* tw;
+    int kx_major;            // 0: lines in memory order; > 0: this many planes, and the
+                             // lines taken bin by bin (every plane of bin 0 first)
 };
 struct XLineArgs {           // x pass over [nplanes][ny][nx] real rows <-> [nplanes][hx][srows] bins
     const void* in;
