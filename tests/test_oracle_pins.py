@@ -42,6 +42,22 @@ def test_tensor_traceless_off_origin():
         assert abs(k[XX] + k[YY] + k[ZZ]) < 1e-14
 
 
+@pytest.mark.parametrize("dims,P", [((5, 4, 3), (10, 8, 6)), ((7, 3, 2), (14, 6, 4)), ((4, 4, 4), (7, 7, 7))])
+def test_tensor_spectrum_trace_is_minus_one(dims, P):
+    # Trace -1 at the origin and 0 elsewhere: the padded spectra (numpy FFT of the
+    # wrapped table) satisfy Kxx + Kyy + Kzz = -1 at every frequency.
+    nx, ny, nz = dims
+    Px, Py, Pz = P
+    tab = oracle.tensor_table(nx, ny, nz)
+    I, J, K = (np.arange(-(n - 1), n) % q for n, q in zip(dims, P))
+    tr = 0
+    for c in (0, 3, 5):
+        w = np.zeros((Pz, Py, Px))
+        w[np.ix_(K, J, I)] = tab[c]
+        tr = tr + np.fft.fftn(w)
+    assert np.abs(tr + 1).max() < 1e-14
+
+
 def test_tensor_parities_and_permutations():
     g = np.random.default_rng(2)
     for _ in range(200):
