@@ -41,11 +41,11 @@ __global__ __launch_bounds__(6 * kspace_z_split_cols()) void k_kspace_z_split(Kz
     body_kspace_z_split<T, PZ>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
-template <typename T, int P, bool FULL>
-__global__ __launch_bounds__(3 * ky_lines<P>() * (P / Sched<P>::R0)) void k_kspace_y(KyArgs a)
+template <typename T, int P, bool FULL, int L>
+__global__ __launch_bounds__(3 * L * (P / Sched<P>::R0)) void k_kspace_y(KyArgs a)
 {
-    __shared__ cpx<T> lds[kspace_y_lds_elems<P>()];
-    body_kspace_y<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+    __shared__ cpx<T> lds[kspace_y_lds_elems<P, L>()];
+    body_kspace_y<T, P, FULL, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int P, bool FULL>
@@ -197,6 +197,11 @@ bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
     }
 }
 
+// Grids of 64 to 256 x bins (small, latency-bound ones) take one bin per
+// work-group: more work-groups, each a single wave or two (128x128x1, 129 bins,
+// FP32 RK4: 65.9 -> 62.7 us per step; 32x8x1, 33 bins: 40.6 -> 42.0, so not there).
+constexpr int kKySingleBinMinBins = 64, kKySingleBinMaxBins = 256;
+
 template <typename T, bool FULL>
 static bool kspace_y_dispatch(const KyArgs& a, int P, hipStream_t s)
 {
@@ -207,7 +212,10 @@ static bool kspace_y_dispatch(const KyArgs& a, int P, hipStream_t s)
     };
 #define MM_KYCASE(PP)                                                                          \
     case PP:                                                                                   \
-        return go(k_kspace_y<T, PP, FULL>, ky_lines<PP>(), 3 * ky_lines<PP>() * (PP / Sched<PP>::R0));
+        if (a.hx >= kKySingleBinMinBins && a.hx <= kKySingleBinMaxBins)                        \
+            return go(k_kspace_y<T, PP, FULL, 1>, 1, 3 * (PP / Sched<PP>::R0));                \
+        return go(k_kspace_y<T, PP, FULL, ky_lines<PP>()>, ky_lines<PP>(),                      \
+                  3 * ky_lines<PP>() * (PP / Sched<PP>::R0));
     switch (P) {
         MM_KYCASE(16)
         MM_KYCASE(32)

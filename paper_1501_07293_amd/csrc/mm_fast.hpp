@@ -595,10 +595,10 @@ __device__ inline void body_kspace_z_split(const KzArgs& a, int tile, cpx<T>* sh
 template <int P>
 constexpr int ky_lines() { return (256 / (3 * (P / Sched<P>::R0))) > 0 ? 256 / (3 * (P / Sched<P>::R0)) : 1; }
 
-template <typename T, int P, bool FULL = false>
+template <typename T, int P, bool FULL = false, int L = ky_lines<P>()>
 __device__ inline void body_kspace_y(const KyArgs& a, int tile, cpx<T>* lds)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, L = ky_lines<P>(), NT = 3 * L * TL;
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = 3 * L * TL;
     constexpr int LP = padded_len<P>();
     const int line = threadIdx.x / TL, u = threadIdx.x % TL;
     const int comp = line / L, l = line - comp * L;
@@ -795,8 +795,8 @@ constexpr int xinv_lds_elems()
 }
 template <typename T, int PZ>
 constexpr int kspace_z_lds_elems() { return 3 * PZ * kspace_z_cols<T>(); }
-template <int P>
-constexpr int kspace_y_lds_elems() { return 3 * ky_lines<P>() * padded_len<P>(); }
+template <int P, int L = ky_lines<P>()>
+constexpr int kspace_y_lds_elems() { return 3 * L * padded_len<P>(); }
 template <int P>
 constexpr int kspace_y2_lds_elems() { return 6 * ky2_lines<P>() * padded_len<P>(); }
 
