@@ -56,7 +56,7 @@ __global__ __launch_bounds__(6 * ky2_lines<P>() * (P / Sched<P>::R0)) void k_ksp
 }
 
 template <typename T, int P, int L>
-__global__ __launch_bounds__(3 * L * (P / Sched<P>::R0)) void k_fused_stage_2d(FusedStageArgs<T> a)
+__global__ __launch_bounds__((fused_threads<P, L>())) void k_fused_stage_2d(FusedStageArgs<T> a)
 {
     __shared__ cpx<T> lds[3 * fused_region<P, L>()];
     __shared__ T cell[3 * 2 * L * (P / 2)];
@@ -305,17 +305,17 @@ template <typename T, int P>
 static bool fused_dispatch(const FusedStageArgs<T>& a, int L, hipStream_t s)
 {
     constexpr int TL = P / Sched<P>::R0;
-    auto go = [&](auto kern, int lines) {
+    auto go = [&](auto kern, int lines, int threads) {
         const int grid = (a.g.ny + 2 * lines - 1) / (2 * lines);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(3 * lines * TL), 0, s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, a);
         return true;
     };
     if constexpr (fused_lds_bytes<T, P, 4>() <= kLdsBudget && 3 * 4 * TL <= 1024)
-        if (L == 4) return go(k_fused_stage_2d<T, P, 4>, 4);
+        if (L == 4) return go(k_fused_stage_2d<T, P, 4>, 4, fused_threads<P, 4>());
     if constexpr (fused_lds_bytes<T, P, 2>() <= kLdsBudget && 3 * 2 * TL <= 1024)
-        if (L == 2) return go(k_fused_stage_2d<T, P, 2>, 2);
+        if (L == 2) return go(k_fused_stage_2d<T, P, 2>, 2, fused_threads<P, 2>());
     if constexpr (fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 1024)
-        if (L == 1) return go(k_fused_stage_2d<T, P, 1>, 1);
+        if (L == 1) return go(k_fused_stage_2d<T, P, 1>, 1, fused_threads<P, 1>());
     return false;
 }
 

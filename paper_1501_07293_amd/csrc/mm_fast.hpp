@@ -69,9 +69,10 @@ struct StageTw {
 };
 
 // Stage S >= 1 on one LDS line: each thread does up to NB butterflies.  Reads
-// all, barrier, writes all, barrier.
+// all, barrier, writes all, barrier.  act = false: a thread that only takes part
+// in the barriers (a work-group with more threads than its lines need).
 template <typename T, int P, int S>
-__device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
+__device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W, bool act = true)
 {
     constexpr int R = radix_of<P, S>(), R0 = Sched<P>::R0, TL = P / R0;
     constexpr int p = span_of<P, S>(), m = P / R, NB = stage_nb<P, S>();
@@ -80,7 +81,7 @@ __device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int i = u + TL * q, k = (int)((unsigned)i % (unsigned)p);
-        if (EXACT || i < m) {
+        if (act && (EXACT || i < m)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = ln[pad16(i + r * m)];
             if (k != 0) {
@@ -94,7 +95,7 @@ __device__ inline void mid_stage(cpx<T>* ln, int u, const StageTw<T, P, S>& W)
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int i = u + TL * q, k = (int)((unsigned)i % (unsigned)p), j = (i - k) * R + k;
-        if (EXACT || i < m) {
+        if (act && (EXACT || i < m)) {
 #pragma unroll
             for (int r = 0; r < R; ++r) ln[pad16(j + r * p)] = v[q][r];
         }
@@ -157,14 +158,17 @@ struct LineTw<T, P, 3> {
 // run the remaining stages, deliver outputs through put (HALF: those below
 // P / 2 only).  NS >= 2.
 template <typename T, int P, bool HALF = false, typename Put>
-__device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const LineTw<T, P>& W, Put put)
+__device__ inline void finish_line(cpx<T>* ln, int u, cpx<T>* v, const LineTw<T, P>& W, Put put,
+                                   bool act = true)
 {
     constexpr int NS = Sched<P>::NS, R0 = Sched<P>::R0;
+    if (act) {
 #pragma unroll
-    for (int r = 0; r < R0; ++r) ln[pad16(u * R0 + r)] = v[r];
+        for (int r = 0; r < R0; ++r) ln[pad16(u * R0 + r)] = v[r];
+    }
     __syncthreads();
-    if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, W.wm);
-    last_stage<T, P, NS - 1, HALF>(ln, u, W.wl, put);
+    if constexpr (NS == 3) mid_stage<T, P, 1>(ln, u, W.wm, act);
+    if (act) last_stage<T, P, NS - 1, HALF>(ln, u, W.wl, put);
 }
 
 // In-register FFT of N points (N <= 64), all indices compile-time; Stockham

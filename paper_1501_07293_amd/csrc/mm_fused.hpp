@@ -25,19 +25,29 @@ template <int P, int L>
 constexpr int fused_region() { return (L * padded_len<P>() > 2 * L * (P / 2 + 1)) ? L * padded_len<P>() : 2 * L * (P / 2 + 1); }
 template <typename T, int P, int L>
 constexpr int fused_lds_bytes() { return (int)(3 * fused_region<P, L>() * sizeof(cpx<T>) + 3 * 2 * L * (P / 2) * sizeof(T)); }
+// Threads per work-group: the 3 L lines take 3 L (P / R0) of them; small lines leave
+// that below 256, and the gather, the stage update and the transposed store then
+// run with 256 (one cell update per thread at 128x128x1 instead of six in one wave),
+// the extra threads joining only the barriers of the line transforms.
+template <int P, int L>
+constexpr int fused_threads() { return 3 * L * (P / Sched<P>::R0) > 256 ? 3 * L * (P / Sched<P>::R0) : 256; }
 
-// Work-group `tile` takes rows 2L tile .. 2L tile + 2L - 1; 3 L (P / R0) threads,
-// thread (component, line l, lane u).  Needs 2 nx <= P (the pruned x lines).
+// Work-group `tile` takes rows 2L tile .. 2L tile + 2L - 1; fused_threads<P, L>()
+// threads, the first 3 L (P / R0) of them (component, line l, lane u) for the line
+// transforms.  Needs 2 nx <= P (the pruned x lines).
 template <typename T, int P, int L>
 __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile, cpx<T>* lds, T* cell)
 {
-    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = 3 * L * TL, LP = padded_len<P>();
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NL = 3 * L * TL, LP = padded_len<P>();
+    constexpr int NT = fused_threads<P, L>();
     constexpr int HX = P / 2 + 1, ROWS = 2 * L, REG = fused_region<P, L>(), XH = P / 2;
     const LlgArgs<T>& a = f.g;
     const int nx = a.nx, ny = a.ny;
     const int yb = tile * ROWS;
     const int tid = (int)threadIdx.x;
-    const int comp = tid / (L * TL), l = (tid / TL) % L, u = tid % TL;
+    const bool act = tid < NL;          // takes part in the line transforms
+    const int lt = act ? tid : 0;
+    const int comp = lt / (L * TL), l = (lt / TL) % L, u = lt % TL;
     cpx<T>* reg = lds + comp * REG;
     LineTw<T, P> W;
     W.load(u, (const cpx<T>*)f.tw);
@@ -74,8 +84,9 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k = u + TL * r;
-            cpx<T> A, B;
-            if (k < HX) {
+            cpx<T> A = {(T)0, (T)0}, B = {(T)0, (T)0};
+            if (!act) {
+            } else if (k < HX) {
                 A = ra[k];
                 B = rb[k];
                 if (k == 0 || 2 * k == P) {  // DC and Nyquist bins of a real row are real
@@ -98,10 +109,12 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
             }
         };
         if constexpr (Sched<P>::NS == 1) {
+            if (act) {
 #pragma unroll
-            for (int r = 0; r < R0; ++r) put(r, v[r]);
+                for (int r = 0; r < R0; ++r) put(r, v[r]);
+            }
         } else {
-            finish_line<T, P, true>(reg + l * LP, u, v, W, put);
+            finish_line<T, P, true>(reg + l * LP, u, v, W, put, act);
         }
     }
     __syncthreads();
@@ -180,7 +193,7 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
         for (int r = 0; r < R0; ++r) {
             const int e = u + TL * r;
             cpx<T> x = {(T)0, (T)0};
-            if (2 * r < R0 && e < nx) {  // e >= P/2 is zero padding
+            if (act && 2 * r < R0 && e < nx) {  // e >= P/2 is zero padding
                 if (ok0) x.re = cl[(2 * l) * XH + e];
                 if (ok1) x.im = cl[(2 * l + 1) * XH + e];
             }
@@ -189,10 +202,12 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
         Dft<T, R0>::run(v);
         cpx<T>* ln = reg + l * LP;
         if constexpr (Sched<P>::NS == 1) {
+            if (act) {
 #pragma unroll
-            for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
+                for (int r = 0; r < R0; ++r) ln[pad16(r)] = v[r];
+            }
         } else {
-            finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+            finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; }, act);
         }
         __syncthreads();
         cpx<T>* out = (cpx<T>*)f.S_out;
