@@ -373,6 +373,8 @@ struct mm_sim {
     double graph_dt;
     int graph_chunk;
     int graph_method;
+    hipGraphExec_t rem_exec = nullptr;  // fused-stage steps: the remainder of a step count
+    int64_t rem_len = 0;                // past whole chunks (e.g. 2 of a 50-step segment)
     // reverse-sweep graphs: one per segment length (a full segment and the
     // shorter last one), valid while the baked-in arguments are unchanged
     struct BwdGraph {
@@ -929,8 +931,11 @@ void drop_graph(mm_sim* s)
 {
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->rem_exec) (void)hipGraphExecDestroy(s->rem_exec);
     s->gexec = nullptr;
     s->graph = nullptr;
+    s->rem_exec = nullptr;
+    s->rem_len = 0;
     s->graph_valid = false;
 }
 
@@ -969,10 +974,28 @@ mm_status fused_step_impl(mm_sim* s, int64_t nsteps, double dt, bool use_graph)
         s->graph_chunk = chunk;
         s->graph_method = MM_RK4;
     }
+    // the steps past whole chunks replay a graph of their own (kept while the chunk
+    // graph is valid, for one remainder length): a rollout's segments of 50 steps
+    // take six chunks and two steps each
+    const int64_t rem = nsteps % s->graph_chunk;
+    if (rem > 0 && (!s->rem_exec || s->rem_len != rem)) {
+        if (s->rem_exec) (void)hipGraphExecDestroy(s->rem_exec);
+        s->rem_exec = nullptr;
+        s->rem_len = 0;
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mm_status r = rk4_fused_steps<T>(s, rem, dt, false, s->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (r == MM_OK && e == hipSuccess) e = hipGraphInstantiate(&s->rem_exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (r != MM_OK) return r;
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        s->rem_len = rem;
+    }
     if (mm_status r = rk4_fused_steps<T>(s, 0, dt, true, st); r != MM_OK) return r;  // prologue
-    int64_t n = 0;
-    for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, st));
-    return rk4_fused_steps<T>(s, nsteps - n, dt, false, st);
+    for (int64_t n = 0; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, st));
+    if (rem > 0) HIP_TRY(hipGraphLaunch(s->rem_exec, st));
+    return MM_OK;
 }
 
 template <typename T>
@@ -1224,7 +1247,36 @@ mm_status backward_segment(mm_sim* s, const AdjBufs<T>& b, int64_t len, double d
     T* hd = s->at<T>(p.o_hd);
     LlgArgs<T> la = llg_args<T>(s, dt);
     la.acc = b.scr;
-    for (int64_t n = 0; n < len; ++n) {
+    if (p.fs && with_demag) {
+        // fused stages (small one-cell-thick grids): the y k-space pass and one fused
+        // pass per stage, which also stores the stage's effective field; the segment's
+        // final stage output is not needed (the next segment starts from its
+        // checkpoint) and goes to the reverse sweep's still unused mu buffer
+        PassCtx c = pass_ctx(s);
+        void* bufs[2] = {s->at<char>(p.o_S), s->at<char>(p.o_S2)};
+        HIP_TRY(pass_x_forward<T>(c, b.at(0, 0), st));
+        FusedStageArgs<T> f{};
+        f.g = la;
+        f.g.hd = nullptr;
+        f.tw = c.twx;
+        for (int64_t n = 0; n < len; ++n) {
+            f.g.mn = b.at(n, 0);
+            for (int stg = 0; stg < 4; ++stg) {
+                c.S = bufs[stg & 1];
+                HIP_TRY(pass_kspace<T>(c, st));
+                f.g.ms = b.at(n, stg);
+                f.g.out = (stg == 3 && n == len - 1) ? b.mu : (stg < 3 ? b.at(n, stg + 1) : b.at(n + 1, 0));
+                f.g.stage = stg + 1;
+                f.hout = b.at(n, 4 + stg);
+                f.S_in = bufs[stg & 1];
+                f.S_out = bufs[(stg + 1) & 1];
+                if (!launch_fused_stage_2d<T>(f, p.Px, p.fs_lines, st))
+                    return fail(MM_ENOTSUP, "no fused stage pass of length %d", p.Px);
+                HIP_TRY(hipGetLastError());
+            }
+        }
+    }
+    for (int64_t n = 0; n < len && !(p.fs && with_demag); ++n) {
         la.mn = b.at(n, 0);
         for (int stg = 0; stg < 4; ++stg) {
             la.ms = b.at(n, stg);

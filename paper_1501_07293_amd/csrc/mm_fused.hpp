@@ -175,7 +175,7 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
                     hd[d] = cell[d * ROWS * XH + r * XH + i];
                 }
                 T res[3];
-                llg_cell<T>(a, c, m, lap, hd, mnv[q], acv[q], kan[q], res);
+                llg_cell<T>(a, c, m, lap, hd, mnv[q], acv[q], kan[q], res, f.hout);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) cell[d * ROWS * XH + r * XH + i] = res[d];
             }

@@ -269,6 +269,7 @@ struct FusedStageArgs {
     const void* S_in;    // [3][hx][ny] spectrum after the y k-space pass
     void* S_out;         // [3][hx][ny] half spectrum of the stage output
     const void* tw;      // x twiddles (Px)
+    T* hout;             // the stage's reduced effective field [3][ny][nx], or nullptr
 };
 // Rows per work-group / 2 (L in 1, 2, 4) the pass takes for this grid, 0 when
 // no fused pass of length Px exists (or 2 nx > Px).

@@ -11,14 +11,20 @@ namespace mm {
 // The stage update of cell c (Eq. 2 for the field of Eqs. 3-8, then the RK4 stage
 // combine, or the explicit Euler step) from its m, Laplacian, demag field, m_n,
 // RK4 accumulator and reduced anisotropy constant; writes the stage output (and
-// the accumulator) and returns the stage output in res.
+// the accumulator) and returns the stage output in res.  heff: where to write the
+// reduced effective field of the cell as well (nullptr: nowhere).
 template <typename T>
 __device__ inline void llg_cell(const LlgArgs<T>& a, int64_t c, const T (&m)[3], const T (&lap)[3],
-                                const T (&hd)[3], const T (&mn)[3], const T (&ac)[3], T kan, T (&res)[3])
+                                const T (&hd)[3], const T (&mn)[3], const T (&ac)[3], T kan, T (&res)[3],
+                                T* heff = nullptr)
 {
     const int64_t N = a.N;
     const T h[3] = {a.cex * lap[0] + kan * m[0] + a.hx + hd[0], a.cex * lap[1] + a.hy + hd[1],
                     a.cex * lap[2] + a.hz + hd[2]};
+    if (heff) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) heff[d * N + c] = h[d];
+    }
     const T tx = m[1] * h[2] - m[2] * h[1];
     const T ty = m[2] * h[0] - m[0] * h[2];
     const T tz = m[0] * h[1] - m[1] * h[0];
