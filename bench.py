@@ -700,7 +700,7 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
             # the fused stage pass's row pairs per work-group, as the library picks them
             lines = 1 if (t == "double" and px >= 512) else (4 if ny >= 2048 else (2 if ny >= 1024 else 1))
             return f"mm::k_fused_stage_2d<{t}, {px}, {lines}>"
-        kz = 1 if nz == 1 else (2 if nz == 2 else 4)   # planes per thread
+        kz = 1 if nz == 1 else 2   # planes per thread
         return f"mm::k_llg_stage<{t}, {kz}>"
     if plan["passes"] == 1:
         return f"mm::k_demag_1wg<{t}, {plan['threads']}>"

@@ -169,7 +169,6 @@ hipError_t launch_batch_llg(int kz, const BatchClass<T>& c, int tiles, const Bat
     if (tiles <= 0) return hipSuccess;
     switch (kz) {
     case 1: hipLaunchKernelGGL((kbf_llg<T, 1>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
-    case 2: hipLaunchKernelGGL((kbf_llg<T, 2>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
     case kLlgZ: hipLaunchKernelGGL((kbf_llg<T, kLlgZ>), dim3(tiles), dim3(kBatchNT), 0, s, c, g); break;
     default: return hipErrorInvalidValue;
     }

@@ -251,7 +251,6 @@ hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s)
     const dim3 grid((int)llg_blocks(a.nx, a.ny, a.nz));
     switch (llg_z_for(a.nz)) {
     case 1: hipLaunchKernelGGL((k_llg_stage<T, 1>), grid, dim3(kLlgNT), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_llg_stage<T, 2>), grid, dim3(kLlgNT), 0, s, a); break;
     default: hipLaunchKernelGGL((k_llg_stage<T, kLlgZ>), grid, dim3(kLlgNT), 0, s, a); break;
     }
     return hipGetLastError();

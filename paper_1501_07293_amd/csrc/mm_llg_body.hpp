@@ -84,7 +84,7 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
 }
 
 // One thread per (x, y) column and chunk of KZ planes.  Every load of the
-// chunk (m of planes k0-1 .. k0+kLlgZ, in-plane neighbours, H_d, Ku, m_n, acc)
+// chunk (m of planes k0-1 .. k0+KZ, in-plane neighbours, H_d, Ku, m_n, acc)
 // is issued before the first store, so a thread keeps many loads in flight;
 // the z neighbours inside the chunk come from registers, the x and y neighbours
 // from rows that neighbouring threads load anyway.  Work-group b takes chunk

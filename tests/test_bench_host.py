@@ -48,7 +48,7 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("y_fwd") == "mm::k_yline<float, 1024, false, false>"
     assert sym("y_inv") == "mm::k_yline<float, 1024, true, false>"
     assert sym("kspace") == "mm::k_kspace_z<float, 32>"
-    assert sym("llg") == "mm::k_llg_stage<float, 4>"
+    assert sym("llg") == "mm::k_llg_stage<float, 2>"
     # planes per thread of the stage update: 1 or 2 for grids one or two cells thick
     assert sym("llg", n=(512, 512, 1)) == "mm::k_llg_stage<float, 1>"
     assert sym("llg", n=(512, 512, 2)) == "mm::k_llg_stage<float, 2>"

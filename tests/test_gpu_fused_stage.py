@@ -82,8 +82,8 @@ def test_fused_stage_trajectory_matches_oracle(precision):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fused_stage_rollout_adjoint_matches_oracle_adjoint(precision):
-    # the rollout (checkpointed forward) runs the fused stages; the reverse sweep
-    # recomputes its segments through the separate passes
+    # the rollout (checkpointed forward) runs the fused stages, and so does the
+    # reverse sweep's recompute of each segment (storing every stage's field)
     import torch
     g = np.random.default_rng(31)
     nx, ny, nz = 32, 16, 1
