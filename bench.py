@@ -379,8 +379,9 @@ def cube_sweep_leg(steps: int = 200) -> dict:
     Ms = 1.0e6
     Ku = 4e-7 * np.pi * Ms * 1.0e5 / 2
     rows = []
-    for n in (8, 16, 32, 64, 128):
-        row = {"N": n}
+    for n in (8, 16, 32, 64, 128, 256):
+        k = steps if n < 256 else max(steps // 4, 8)   # 256^3: milliseconds per step
+        row = {"N": n, "steps": k}
         for prec in ("f32", "f64"):
             sim = mm.Sim(n, n, n, 34e-9 / n, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0, precision=prec,
                          graph=True)
@@ -388,9 +389,9 @@ def cube_sweep_leg(steps: int = 200) -> dict:
             sim.step_euler(16, 1e-14)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sim.step_euler(steps, 1e-14)
+            sim.step_euler(k, 1e-14)
             torch.cuda.synchronize()
-            row[f"ms_per_step_{prec}"] = 1e3 * (time.perf_counter() - t0) / steps
+            row[f"ms_per_step_{prec}"] = 1e3 * (time.perf_counter() - t0) / k
             sim.close()
         if n in PAPER_TABLE1_MS:
             cpu, g64, g32 = PAPER_TABLE1_MS[n]
@@ -720,7 +721,7 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
                 return f"mm::k_kspace_z_split<{t}, {pz}>"
             return f"mm::k_kspace_z<{t}, {pz}>"
         if fast and pz in (128, 256, 512, 1024):
-            return f"mm::k_kspace_fixed<{t}, 256, {pz}>"
+            return f"mm::k_kspace_fixed<{t}, {512 if pz == 512 else 256}, {pz}>"
         return f"mm::k_kspace<{t}, {plan['threads']}>"
     if plan.get("two_plane"):  # two cells thick: the two-plane y k-space pass
         return f"mm::k_kspace_y2<{t}, {py}, {b(2 * ny > py)}>"

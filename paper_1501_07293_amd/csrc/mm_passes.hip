@@ -81,12 +81,15 @@ template <typename T>
 bool launch_kspace_fixed(const KspArgs& a, int P, hipStream_t s)
 {
     // 256 threads: 5 columns at PZ = 256 and 4 work-groups per CU (FP32) measured
-    // faster than 384 (8 columns) or 768 (16 columns, one work-group per CU)
+    // faster than 384 (8 columns) or 768 (16 columns, one work-group per CU).  At
+    // PZ = 512, 256 threads hold 2 columns; 512 threads (5 columns) measured faster
+    // on the 256^3 cube (Euler step FP32 3.04 -> 2.97 ms, FP64 5.30 -> 5.08 ms),
+    // 1024 threads (10 columns, FP32) no better (3.09 ms)
     constexpr int NT = 256;
     switch (P) {
     case 128: return kspace_fixed_go<T, NT, 128>(a, s);
     case 256: return kspace_fixed_go<T, NT, 256>(a, s);
-    case 512: return kspace_fixed_go<T, NT, 512>(a, s);
+    case 512: return kspace_fixed_go<T, 512, 512>(a, s);
     case 1024: return kspace_fixed_go<T, NT, 1024>(a, s);
     default: return false;
     }

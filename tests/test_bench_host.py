@@ -69,6 +69,8 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("kspace", plan=gen) == "mm::k_kspace<float, 256>"
     cube = dict(FILM, px=256, py=256, pz=256)
     assert sym("kspace", plan=cube, n=(128, 128, 128)) == "mm::k_kspace_fixed<float, 256, 256>"
+    cube512 = dict(cube, px=512, py=512, pz=512)
+    assert sym("kspace", plan=cube512, n=(256, 256, 256)) == "mm::k_kspace_fixed<float, 512, 512>"
     thin = dict(FILM, pz=1, passes=3)
     assert sym("kspace", plan=thin, n=(512, 512, 1)) == "mm::k_kspace_y<float, 1024, false>"
     fused = dict(FILM, px=512, py=128, pz=8, passes=3)

@@ -342,6 +342,36 @@ def test_largest_lengths_sampled_against_direct_sum(dims, precision):
     assert err <= FIELD_TOL[precision]
 
 
+def test_cube_256_sampled_against_direct_sum():
+    # The largest cube of the Euler sweep: 256^3 cells (standard-problem-#3 material),
+    # padded 512^3, so the z k-space pass runs with its length fixed at 512.  Demag and
+    # effective field at 160 observation cells (all 8 corners, cells on every edge and
+    # face, the rest uniform) against the oracle's direct sum, FP64 then FP32; a few
+    # Euler steps keep every cell unit length.
+    import synthetic
+    n = 256
+    Ms = 1.0e6
+    pb = problem(n, n, n, cell=34e-9 / n, Ms=Ms, A=1e-11, Ku=4e-7 * np.pi * Ms * 1.0e5 / 2, alpha=1.0)
+    obs = synthetic.observation_cells(n, n, n, 160, seed=257)
+    m0 = random_unit_m(pb.shape, seed=256)
+    for precision in ("f64", "f32"):
+        sim = make_sim(pb, precision)
+        assert sim.plan()["pz"] == 512
+        sim.set_m(m0)
+        m_gpu = to_np(sim.get_m())
+        hd_ref = oracle.demag(pb, m_gpu, obs)
+        err = rel_max(to_np(sim.field("demag")).reshape(3, -1)[:, obs], hd_ref)
+        ref = hd_ref + oracle.exchange(pb, m_gpu).reshape(3, -1)[:, obs] + \
+            oracle.anisotropy(pb, m_gpu).reshape(3, -1)[:, obs]
+        err_eff = rel_max(to_np(sim.field("eff")).reshape(3, -1)[:, obs], ref)
+        print(f"256^3 {precision}: demag {err:.2e}, effective {err_eff:.2e}", flush=True)
+        assert err <= FIELD_TOL[precision] and err_eff <= FIELD_TOL[precision]
+        sim.step_euler(4, 1e-14)
+        m = to_np(sim.get_m())
+        assert np.abs(np.sqrt((m * m).sum(axis=0)) - 1).max() < (1e-12 if precision == "f64" else 1e-6)
+        sim.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("dims", [(8, 8, 64), (5, 4, 256), (3, 2, 512)])
 def test_long_z_lines_match_oracle(dims, precision):
