@@ -698,9 +698,15 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
     y_ok = fast and pow2(py) and 16 <= py <= 2048
     if k == "llg":
         if plan.get("fused_stage"):
-            # the fused stage pass's row pairs per work-group, as the library picks them
-            lines = 1 if (t == "double" and px >= 512) else (4 if ny >= 2048 else (2 if ny >= 1024 else 1))
-            return f"mm::k_fused_stage_2d<{t}, {px}, {lines}>"
+            # the fused stage pass's row pairs per work-group, as the library picks them:
+            # by the ny nz rows, one line from 512 points, at most 512 threads (3 lines of
+            # P / R0 threads each)
+            rows = ny * nz
+            lines = 1 if px >= 512 else (4 if rows >= 2048 else (2 if rows >= 1024 else 1))
+            tl = px // {16: 16, 32: 8, 64: 8, 128: 16, 256: 16, 512: 8, 1024: 16}.get(px, 16)
+            while lines > 1 and 3 * lines * tl > 512:
+                lines //= 2
+            return f"mm::k_fused_stage<{t}, {px}, {lines}>"
         kz = 1 if nz == 1 else 2   # planes per thread
         return f"mm::k_llg_stage<{t}, {kz}>"
     if plan["passes"] == 1:

@@ -107,13 +107,15 @@ typedef enum {
  * is set; takes precedence over MM_FUSED_YZ; MM_AUTOTUNE times it where it
  * applies. */
 #define MM_ONE_WG 0x800u
-/* One-cell-thick grids of up to 2^20 cells with open boundaries and
- * size-specialised passes run each RK4 stage as two launches: the y k-space pass
- * and one fused pass doing the x inverse, the stage update and the x forward of
- * the stage output on a block of rows (the demag field never leaves LDS).  Small
- * grids are bound by the latency of dependent launches, not by bandwidth (the
- * 128x128x1 film: four launches of 4-7 us per stage).  Results equal the
- * separate passes to rounding.  This flag keeps the separate passes. */
+/* Grids of up to 2^20 cells with open boundaries and a size-specialised x pass
+ * run each RK4 stage as the y / z passes (the y k-space pass of one-cell-thick
+ * grids, the two-plane pass of grids two cells thick, else y forward, z k-space,
+ * y inverse) and one fused pass doing the x inverse, the stage update and the x
+ * forward of the stage output on a block of rows of one plane (the demag field
+ * never leaves LDS): two launches per stage fewer.  Small grids are bound by the
+ * latency of dependent launches, not by bandwidth (the 128x128x1 film: four
+ * launches of 4-7 us per stage).  Results equal the separate passes to rounding.
+ * This flag keeps the separate passes. */
 #define MM_SPLIT_STAGE 0x2000u
 #define MM_PERIODIC_X 0x80u
 #define MM_PERIODIC_Y 0x100u

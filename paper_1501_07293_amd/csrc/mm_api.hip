@@ -128,9 +128,9 @@ struct Plan {
     int images;                // images on each side beyond the nearest (periodic axes)
     bool zd;                   // two cells along z: the two-plane y k-space pass replaces y forward,
                                // z k-space and y inverse (the z coupling taken directly)
-    bool fs;                   // one cell thick and small: the fused stage pass (x inverse, stage
-                               // update, x forward) with a second spectrum buffer, two launches
-                               // per RK4 stage
+    bool fs;                   // small and open: the fused stage pass (x inverse, stage update,
+                               // x forward) with a second spectrum buffer, two launches per RK4
+                               // stage fewer
     int fs_lines;              // its row pairs per work-group
     int64_t oct_elems;         // per component (two-plane schedule: per coefficient plane)
     int kplanes;               // blocks of oct_elems in the kernel region (ncomp, or 10)
@@ -261,13 +261,13 @@ mm_status build_plan(const mm_grid* g, const mm_options* o, Plan* p)
     p->zd = p->nz == 2 && p->Pz == 4 && !(p->per & 4) && !p->yz && !p->wg1 &&
             !(o->flags & MM_GENERIC_FFT) && fast_ky2_lines(p->Py) > 0 && p->ny <= p->Py &&
             !(p->esz == 8 && p->Py > 1024);
-    // one cell thick, open, small (latency-bound), with the specialised passes: the
-    // fused stage pass
+    // open, small (latency-bound), with the specialised passes: the fused stage pass
+    // (the y / z passes of one-cell-thick and thicker grids run between its launches)
     p->fs_lines = 0;
-    if (!p->three_d && p->per == 0 && !p->yz && !p->wg1 && p->N <= kFusedStageMaxCells &&
-        !(o->flags & (MM_GENERIC_FFT | MM_SPLIT_STAGE | MM_NO_DEMAG)) && fast_ky_lines(p->Py) > 0 &&
-        2 * p->ny <= p->Py)
-        p->fs_lines = fused_stage_lines(p->Px, p->nx, p->ny, p->esz);
+    if (p->per == 0 && !p->yz && !p->wg1 && p->N <= kFusedStageMaxCells &&
+        !(o->flags & (MM_GENERIC_FFT | MM_SPLIT_STAGE | MM_NO_DEMAG)) && 2 * p->ny <= p->Py &&
+        (p->three_d || fast_ky_lines(p->Py) > 0))
+        p->fs_lines = fused_stage_lines(p->Px, p->nx, p->ny * p->nz, p->esz);
     p->fs = p->fs_lines > 0;
     // spectrum [3][nz][hx][S_rows]: the y pass expands ny rows to Py in place on 3-D grids
     p->S_planes = p->nz;
@@ -744,11 +744,27 @@ mm_status rk4_step(mm_sim* s, double dt, hipStream_t st)
     return MM_OK;
 }
 
-// RK4 steps of a fused-stage plan (one cell thick, small).  The spectrum of the
-// stage input sits in S: the prologue forms it for m_n (x forward); each stage
-// then runs the y k-space pass on it in place and the fused pass, which writes
-// the stage output and its x half spectrum into the other buffer.  Four stages
-// per step return the spectrum to S, holding that of the new m_n.
+// The passes between the x forward and the x inverse of one demag evaluation, in
+// place on c.S: the two-plane y pass, or y forward, the k-space pass (along z, or
+// along y on one-cell-thick grids) and y inverse.
+template <typename T>
+mm_status demag_mid(mm_sim* s, const PassCtx& c, hipStream_t st)
+{
+    if (c.p.zd) {
+        LAUNCH(KSPACE, pass_kspace_y2<T>(c, st));
+        return MM_OK;
+    }
+    if (c.p.three_d) LAUNCH(KY_FWD, pass_y<T>(c, 0, st));
+    LAUNCH(KSPACE, pass_kspace<T>(c, st));
+    if (c.p.three_d) LAUNCH(KY_INV, pass_y<T>(c, 1, st));
+    return MM_OK;
+}
+
+// RK4 steps of a fused-stage plan (small, open).  The spectrum of the stage input
+// sits in S: the prologue forms it for m_n (x forward); each stage then runs the
+// y / z passes on it in place and the fused pass, which writes the stage output
+// and its x half spectrum into the other buffer.  Four stages per step return the
+// spectrum to S, holding that of the new m_n.
 template <typename T>
 mm_status rk4_fused_steps(mm_sim* s, int64_t nsteps, double dt, bool prologue, hipStream_t st)
 {
@@ -766,17 +782,19 @@ mm_status rk4_fused_steps(mm_sim* s, int64_t nsteps, double dt, bool prologue, h
     f.g.mn = mn;
     f.g.acc = s->at<T>(p.o_acc);
     f.g.hd = nullptr;
+    f.sy = c.Sy;
     f.tw = c.twx;
     for (int64_t n = 0; n < nsteps; ++n) {
         for (int stg = 0; stg < 4; ++stg) {
             c.S = bufs[stg & 1];
-            LAUNCH(KSPACE, pass_kspace<T>(c, st));
+            mm_status r = demag_mid<T>(s, c, st);
+            if (r != MM_OK) return r;
             f.g.ms = src[stg];
             f.g.out = dst[stg];
             f.g.stage = stg + 1;
             f.S_in = bufs[stg & 1];
             f.S_out = bufs[(stg + 1) & 1];
-            LAUNCH(KLLG, launch_fused_stage_2d<T>(f, p.Px, p.fs_lines, st) ? hipGetLastError()
+            LAUNCH(KLLG, launch_fused_stage<T>(f, p.Px, p.fs_lines, st) ? hipGetLastError()
                                                                             : hipErrorInvalidValue);
         }
     }
@@ -1248,8 +1266,8 @@ mm_status backward_segment(mm_sim* s, const AdjBufs<T>& b, int64_t len, double d
     LlgArgs<T> la = llg_args<T>(s, dt);
     la.acc = b.scr;
     if (p.fs && with_demag) {
-        // fused stages (small one-cell-thick grids): the y k-space pass and one fused
-        // pass per stage, which also stores the stage's effective field; the segment's
+        // fused stages (small grids): the y / z passes and one fused pass per stage,
+        // which also stores the stage's effective field; the segment's
         // final stage output is not needed (the next segment starts from its
         // checkpoint) and goes to the reverse sweep's still unused mu buffer
         PassCtx c = pass_ctx(s);
@@ -1258,19 +1276,21 @@ mm_status backward_segment(mm_sim* s, const AdjBufs<T>& b, int64_t len, double d
         FusedStageArgs<T> f{};
         f.g = la;
         f.g.hd = nullptr;
+        f.sy = c.Sy;
         f.tw = c.twx;
         for (int64_t n = 0; n < len; ++n) {
             f.g.mn = b.at(n, 0);
             for (int stg = 0; stg < 4; ++stg) {
                 c.S = bufs[stg & 1];
-                HIP_TRY(pass_kspace<T>(c, st));
+                mm_status r = demag_mid<T>(s, c, st);
+                if (r != MM_OK) return r;
                 f.g.ms = b.at(n, stg);
                 f.g.out = (stg == 3 && n == len - 1) ? b.mu : (stg < 3 ? b.at(n, stg + 1) : b.at(n + 1, 0));
                 f.g.stage = stg + 1;
                 f.hout = b.at(n, 4 + stg);
                 f.S_in = bufs[stg & 1];
                 f.S_out = bufs[(stg + 1) & 1];
-                if (!launch_fused_stage_2d<T>(f, p.Px, p.fs_lines, st))
+                if (!launch_fused_stage<T>(f, p.Px, p.fs_lines, st))
                     return fail(MM_ENOTSUP, "no fused stage pass of length %d", p.Px);
                 HIP_TRY(hipGetLastError());
             }

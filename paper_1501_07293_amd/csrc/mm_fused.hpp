@@ -1,17 +1,17 @@
-// mm_fused.hpp -- the fused stage pass of small one-cell-thick grids: x inverse
-// of the demag spectrum, the LLG + RK4 stage update, and x forward of the stage
-// output, for a block of rows and all three components in one work-group.
+// mm_fused.hpp -- the fused stage pass of small grids: x inverse of the demag
+// spectrum, the LLG + RK4 stage update, and x forward of the stage output, for a
+// block of rows of one plane and all three components in one work-group.
 //
-// A grid one cell thick evaluates its field in three passes (x forward, y
-// k-space, x inverse) and then runs the stage update: four dependent launches
-// per RK4 stage, each a few microseconds of latency on a small grid.  Here the
-// x inverse leaves the demag field of the block in LDS, the stage update reads
-// it there (and m, its in-plane neighbours, m_n and the accumulator from
-// global memory, as the plain stage kernel does), and the x forward of the
-// block's new state writes the half spectrum the next stage's y k-space pass
-// takes: two launches per stage.  The input and output spectra are different
-// buffers (other work-groups still read the input).  Every per-cell operation
-// is the one the separate passes perform, in the same order.
+// A small grid evaluates its field in three to five passes (x forward, the y / z
+// passes, x inverse) and then runs the stage update: four to six dependent
+// launches per RK4 stage, each a few microseconds of latency.  Here the x
+// inverse leaves the demag field of the block in LDS, the stage update reads it
+// there (and m, its neighbours, m_n and the accumulator from global memory, as
+// the plain stage kernel does), and the x forward of the block's new state
+// writes the half spectrum the next stage's y / z passes take: two launches per
+// stage fewer.  The input and output spectra are different buffers (other
+// work-groups still read the input).  Every per-cell operation is the one the
+// separate passes perform, in the same order.
 #pragma once
 #include "mm_fast.hpp"
 #include "mm_llg_body.hpp"
@@ -32,18 +32,22 @@ constexpr int fused_lds_bytes() { return (int)(3 * fused_region<P, L>() * sizeof
 template <int P, int L>
 constexpr int fused_threads() { return 3 * L * (P / Sched<P>::R0) > 256 ? 3 * L * (P / Sched<P>::R0) : 256; }
 
-// Work-group `tile` takes rows 2L tile .. 2L tile + 2L - 1; fused_threads<P, L>()
-// threads, the first 3 L (P / R0) of them (component, line l, lane u) for the line
-// transforms.  Needs 2 nx <= P (the pruned x lines).
+// Work-group `tile` takes rows 2L t .. 2L t + 2L - 1 of plane z (tile = z tpp + t,
+// tpp = ceil(ny / 2L)); fused_threads<P, L>() threads, the first 3 L (P / R0) of
+// them (component, line l, lane u) for the line transforms.  Spectrum element
+// (c, z, kx, y) at ((c nz + z) hx + kx) sy + y.  Needs 2 nx <= P (the pruned x
+// lines) and open boundaries.
 template <typename T, int P, int L>
-__device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile, cpx<T>* lds, T* cell)
+__device__ inline void body_fused_stage(const FusedStageArgs<T>& f, int tile, cpx<T>* lds, T* cell)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, NL = 3 * L * TL, LP = padded_len<P>();
     constexpr int NT = fused_threads<P, L>();
     constexpr int HX = P / 2 + 1, ROWS = 2 * L, REG = fused_region<P, L>(), XH = P / 2;
     const LlgArgs<T>& a = f.g;
-    const int nx = a.nx, ny = a.ny;
-    const int yb = tile * ROWS;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int tpp = (ny + ROWS - 1) / ROWS;
+    const int z = tile / tpp, yb = (tile - z * tpp) * ROWS;
+    const int64_t sy = f.sy;
     const int tid = (int)threadIdx.x;
     const bool act = tid < NL;          // takes part in the line transforms
     const int lt = act ? tid : 0;
@@ -53,8 +57,8 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
     W.load(u, (const cpx<T>*)f.tw);
 
     // ---- x inverse: gather the block's half-spectrum rows of the three components
-    // (for one bin, the rows of the block are adjacent in [3][hx][ny]); every load
-    // is issued before the first LDS store
+    // (for one bin, the rows of the block are adjacent); every load is issued
+    // before the first LDS store
     {
         const cpx<T>* src = (const cpx<T>*)f.S_in;
         constexpr int NEL = HX * ROWS, ITER = (3 * NEL + NT - 1) / NT;
@@ -65,7 +69,7 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
             const int c = idx / NEL, rem = idx - c * NEL, kx = rem / ROWS, rr = rem - kx * ROWS;
             const int y = yb + rr;
             gv[it] = cpx<T>{(T)0, (T)0};
-            if (idx < 3 * NEL && y < ny) gv[it] = src[((int64_t)c * HX + kx) * ny + y];
+            if (idx < 3 * NEL && y < ny) gv[it] = src[(((int64_t)c * nz + z) * HX + kx) * sy + y];
         }
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
@@ -120,24 +124,26 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
     __syncthreads();
 
     // ---- stage update of the block's cells: the demag field from LDS, the rest as
-    // the plain stage kernel reads it (a missing neighbour is the cell itself, Eq. 7);
+    // the plain stage kernel reads it (a missing neighbour is the cell itself, Eq. 7,
+    // which adds m - m = 0: the x, y, z neighbours in the plain kernel's order);
     // the result overwrites the cell's field in LDS.  A thread takes up to NC cells
     // and issues the loads of CH of them before their updates (the updates store to
     // global memory, so the compiler would not hoist later loads above them): one
     // memory latency per CH cells instead of one per cell.
     {
         constexpr int NC = (ROWS * XH + NT - 1) / NT, CH = NC < 3 ? NC : 3;
-        const int64_t N = a.N;
+        const int64_t N = a.N, plane = (int64_t)nx * ny;
         for (int q0 = 0; q0 < NC; q0 += CH) {
-            T mv[CH][3][5], mnv[CH][3], acv[CH][3], kan[CH];
+            T mv[CH][3][7], mnv[CH][3], acv[CH][3], kan[CH];
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
                 const int idx = tid + (q0 + q) * NT;
                 const int r = idx / nx, i = idx - r * nx, j = yb + r;
                 const bool in = q0 + q < NC && idx < ROWS * nx && j < ny;
-                const int64_t c = in ? (int64_t)j * nx + i : 0;
+                const int64_t c = in ? z * plane + (int64_t)j * nx + i : 0;
                 const int64_t dxm = in && i > 0 ? -1 : 0, dxp = in && i < nx - 1 ? 1 : 0;
                 const int64_t dym = in && j > 0 ? -(int64_t)nx : 0, dyp = in && j < ny - 1 ? (int64_t)nx : 0;
+                const int64_t dzm = in && z > 0 ? -plane : 0, dzp = in && z < nz - 1 ? plane : 0;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const T* uu = a.ms + d * N + c;
@@ -146,6 +152,8 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
                     mv[q][d][2] = uu[dxp];
                     mv[q][d][3] = uu[dym];
                     mv[q][d][4] = uu[dyp];
+                    mv[q][d][5] = uu[dzm];
+                    mv[q][d][6] = uu[dzp];
                     mnv[q][d] = (T)0;
                     acv[q][d] = (T)0;
                     if (a.stage > 1) {
@@ -160,7 +168,7 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
                 const int idx = tid + (q0 + q) * NT;
                 const int r = idx / nx, i = idx - r * nx, j = yb + r;
                 if (q0 + q >= NC || idx >= ROWS * nx || j >= ny) break;
-                const int64_t c = (int64_t)j * nx + i;
+                const int64_t c = z * plane + (int64_t)j * nx + i;
                 T m[3], lap[3], hd[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -170,6 +178,8 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
                     s += mv[q][d][2] - mc;
                     s += mv[q][d][3] - mc;
                     s += mv[q][d][4] - mc;
+                    s += mv[q][d][5] - mc;
+                    s += mv[q][d][6] - mc;
                     m[d] = mc;
                     lap[d] = s;
                     hd[d] = cell[d * ROWS * XH + r * XH + i];
@@ -220,7 +230,7 @@ __device__ inline void body_fused_stage_2d(const FusedStageArgs<T>& f, int tile,
             const cpx<T> A = scale(zk + conj(zm), (T)0.5);
             const cpx<T> B = scale(mul_mi(zk - conj(zm)), (T)0.5);
             const int y = yb + 2 * q;
-            cpx<T>* o = out + ((int64_t)c * HX + kx) * ny + y;
+            cpx<T>* o = out + (((int64_t)c * nz + z) * HX + kx) * sy + y;
             if (y < ny) o[0] = A;
             if (y + 1 < ny) o[1] = B;
         }

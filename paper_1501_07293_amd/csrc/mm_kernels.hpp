@@ -263,21 +263,22 @@ __host__ __device__ inline int64_t llg_blocks(int nx, int ny, int nz)
 template <typename T>
 hipError_t launch_llg_stage(const LlgArgs<T>& a, hipStream_t s);
 
-// The fused stage pass of a one-cell-thick grid (x inverse, stage update, x
-// forward of the stage output; mm_fused.hpp).
+// The fused stage pass of a small grid with open boundaries (x inverse, stage
+// update, x forward of the stage output; mm_fused.hpp).
 template <typename T>
 struct FusedStageArgs {
-    LlgArgs<T> g;        // the stage (nz == 1, open boundaries)
-    const void* S_in;    // [3][hx][ny] spectrum after the y k-space pass
-    void* S_out;         // [3][hx][ny] half spectrum of the stage output
+    LlgArgs<T> g;        // the stage (open boundaries)
+    const void* S_in;    // [3][nz][hx][sy] spectrum after the y / z passes (rows < ny read)
+    void* S_out;         // [3][nz][hx][sy] half spectrum of the stage output (rows < ny written)
+    int64_t sy;          // row stride of both spectra
     const void* tw;      // x twiddles (Px)
-    T* hout;             // the stage's reduced effective field [3][ny][nx], or nullptr
+    T* hout;             // the stage's reduced effective field [3][nz][ny][nx], or nullptr
 };
-// Rows per work-group / 2 (L in 1, 2, 4) the pass takes for this grid, 0 when
-// no fused pass of length Px exists (or 2 nx > Px).
-int fused_stage_lines(int Px, int nx, int ny, size_t esz);
+// Rows per work-group / 2 (L in 1, 2, 4) the pass takes for a grid of `rows` x rows
+// (ny nz), 0 when no fused pass of length Px exists (or 2 nx > Px).
+int fused_stage_lines(int Px, int nx, int rows, size_t esz);
 template <typename T>
-bool launch_fused_stage_2d(const FusedStageArgs<T>& a, int Px, int L, hipStream_t s);
+bool launch_fused_stage(const FusedStageArgs<T>& a, int Px, int L, hipStream_t s);
 
 // Per-term field in A/m: term 0 exch, 1 anis, 2 demag, 3 ext, 4 effective.
 template <typename T>

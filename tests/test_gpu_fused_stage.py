@@ -1,6 +1,7 @@
-"""GPU: the fused stage pass of small one-cell-thick grids (x inverse, stage
-update and x forward of the stage output in one launch, two launches per RK4
-stage) against the separate passes (MM_SPLIT_STAGE) and against the oracle."""
+"""GPU: the fused stage pass of small grids (x inverse, stage update and x forward of the
+stage output in one launch; the y / z passes run between its launches) against the
+separate passes (MM_SPLIT_STAGE) and against the oracle, on one-cell-thick grids, grids
+two cells thick (two-plane schedule) and thicker 3-D grids."""
 import numpy as np
 import pytest
 
@@ -21,9 +22,14 @@ def make(dims, precision, Ku=500.0, alpha=0.5, hext=(4.0, -7.0, 2.0), **kw):
 
 
 # (dims, options): the strip of the small workload, the 128x128 film, power-of-two
-# and mixed-radix padding, rows not a multiple of the block, one column
+# and mixed-radix padding, rows not a multiple of the block, one column; two cells
+# thick (the two-plane y pass between the fused launches); the mid-size film, a
+# cube and ragged 3-D grids (y forward, z k-space, y inverse between them), with
+# one, two and four row pairs per work-group
 GRIDS = [((32, 8, 1), {}), ((128, 128, 1), {}), ((100, 37, 1), {"pow2_pad": True}),
-         ((45, 61, 1), {"fast_pad": True}), ((17, 24, 1), {"pow2_pad": True}), ((64, 9, 1), {"pow2_pad": True})]
+         ((45, 61, 1), {"fast_pad": True}), ((17, 24, 1), {"pow2_pad": True}), ((64, 9, 1), {"pow2_pad": True}),
+         ((64, 48, 2), {}), ((33, 47, 2), {"pow2_pad": True}), ((256, 64, 4), {}), ((32, 32, 32), {}),
+         ((40, 21, 3), {"pow2_pad": True}), ((45, 30, 5), {"fast_pad": True}), ((60, 64, 20), {"pow2_pad": True})]
 
 
 @pytest.mark.parametrize("dims,kw", GRIDS)
@@ -64,11 +70,12 @@ def test_fused_stage_graph_replay_and_readouts_in_between(precision):
         s.close()
 
 
+@pytest.mark.parametrize("dims", [(40, 24, 1), (20, 12, 3)])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_fused_stage_trajectory_matches_oracle(precision):
+def test_fused_stage_trajectory_matches_oracle(precision, dims):
     hext = mT_to_Apm([3.0, 8.0, -5.0])
-    pb = oracle.Problem(40, 24, 1, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0, alpha=0.5, hext=tuple(hext))
-    sim = make((40, 24, 1), precision, pow2_pad=True, hext=(3.0, 8.0, -5.0))
+    pb = oracle.Problem(*dims, 5e-9, Ms=8e5, A=1.3e-11, Ku=500.0, alpha=0.5, hext=tuple(hext))
+    sim = make(dims, precision, pow2_pad=True, hext=(3.0, 8.0, -5.0))
     assert sim.plan()["fused_stage"] == 1
     sim.set_m(random_unit_m(pb.shape, seed=9))
     m0 = to_np(sim.get_m())
@@ -80,13 +87,14 @@ def test_fused_stage_trajectory_matches_oracle(precision):
     sim.close()
 
 
+@pytest.mark.parametrize("dims", [(32, 16, 1), (16, 8, 3)])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_fused_stage_rollout_adjoint_matches_oracle_adjoint(precision):
+def test_fused_stage_rollout_adjoint_matches_oracle_adjoint(precision, dims):
     # the rollout (checkpointed forward) runs the fused stages, and so does the
     # reverse sweep's recompute of each segment (storing every stage's field)
     import torch
     g = np.random.default_rng(31)
-    nx, ny, nz = 32, 16, 1
+    nx, ny, nz = dims
     ku = 500.0 + 50.0 * g.standard_normal((nz, ny, nx))
     hext = mT_to_Apm([6.0, -2.0, 4.0])
     pb = oracle.Problem(nx, ny, nz, 5e-9, Ku=0.0, alpha=0.1, ku_map=ku, hext=tuple(hext))
@@ -112,8 +120,9 @@ def test_fused_stage_rollout_adjoint_matches_oracle_adjoint(precision):
 
 
 def test_fused_stage_is_not_taken_where_it_does_not_apply():
-    # periodic axes, two cells thick, runtime-radix passes: the separate passes
+    # periodic axes, runtime-radix passes, beyond 2^20 cells: the separate passes
     assert make((32, 32, 1), "f32", periodic=(True, False, False)).plan()["fused_stage"] == 0
-    assert make((32, 32, 2), "f32").plan()["fused_stage"] == 0
+    assert make((32, 32, 8), "f32", periodic=(False, False, True)).plan()["fused_stage"] == 0
+    assert make((128, 128, 128), "f32").plan()["fused_stage"] == 0
     assert make((32, 32, 1), "f32", generic_fft=True).plan()["fused_stage"] == 0
     assert make((30, 30, 1), "f32").plan()["fused_stage"] == 0   # 60 points: no specialised pass
