@@ -913,7 +913,7 @@ bool piece_ramps(const mm_segment& g)
 // the piece's step n0 + n.
 template <typename T>
 mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt, const mm_segment* g = nullptr,
-                     int64_t n0 = 0, hipStream_t st = nullptr)
+                     int64_t n0 = 0, hipStream_t st = nullptr, bool prologue = true)
 {
     const Plan& p = s->p;
     if (!st) st = s->stream;
@@ -921,6 +921,41 @@ mm_status euler_impl(mm_sim* s, int64_t nsteps, double dt, const mm_segment* g =
     T* hd = s->at<T>(p.o_hd);
     LlgArgs<T> a = llg_args<T>(s, dt);
     a.stage = 0;
+    if (p.fs && !(s->flags & MM_NO_DEMAG)) {
+        // fused stage plans: the spectrum of m_n from the prologue (or left by the
+        // previous even group of steps), then per step the y / z passes and one fused
+        // pass (x inverse, Euler update, x forward of the new m); m and the spectrum
+        // both alternate between two buffers
+        PassCtx c = pass_ctx(s);
+        void* sb[2] = {s->at<char>(p.o_S), s->at<char>(p.o_S2)};
+        if (prologue) LAUNCH(KX_FWD, pass_x_forward<T>(c, bufs[0], st));
+        FusedStageArgs<T> f{};
+        f.g = a;
+        f.g.acc = s->at<T>(p.o_acc);
+        f.g.hd = nullptr;
+        f.sy = c.Sy;
+        f.tw = c.twx;
+        for (int64_t n = 0; n < nsteps; ++n) {
+            if (g) {
+                piece_field(*g, n0 + n, s->hext);
+                f.g.hx = (T)(s->hext[0] / s->mat.Ms);
+                f.g.hy = (T)(s->hext[1] / s->mat.Ms);
+                f.g.hz = (T)(s->hext[2] / s->mat.Ms);
+            }
+            c.S = sb[n & 1];
+            mm_status r = demag_mid<T>(s, c, st);
+            if (r != MM_OK) return r;
+            f.g.ms = f.g.mn = bufs[n & 1];
+            f.g.out = bufs[(n + 1) & 1];
+            f.S_in = sb[n & 1];
+            f.S_out = sb[(n + 1) & 1];
+            LAUNCH(KLLG, launch_fused_stage<T>(f, p.Px, p.fs_lines, st) ? hipGetLastError()
+                                                                        : hipErrorInvalidValue);
+        }
+        if (nsteps & 1)
+            HIP_TRY(hipMemcpyAsync(bufs[0], bufs[1], 3 * (size_t)p.N * sizeof(T), hipMemcpyDeviceToDevice, st));
+        return MM_OK;
+    }
     for (int64_t n = 0; n < nsteps; ++n) {
         T* src = bufs[n & 1];
         T* dst = bufs[(n + 1) & 1];
@@ -1064,12 +1099,14 @@ template <typename T>
 mm_status euler_steps(mm_sim* s, int64_t nsteps, double dt)
 {
     const bool use_graph = (s->flags & MM_USE_GRAPH) && s->prof_kernel < 0;
-    const int chunk = 8;  // even: the captured steps end in m_n without a copy
+    const int chunk = 8;  // even: the captured steps end in m_n (and a fused plan's
+                          // spectrum in S) without a copy
     if (!use_graph || nsteps < chunk) return euler_impl<T>(s, nsteps, dt);
     if (!s->graph_valid || s->graph_dt != dt || s->graph_method != MM_EULER) {
         drop_graph(s);
         HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-        mm_status r = euler_impl<T>(s, chunk, dt, nullptr, 0, s->cap_stream);
+        // a fused plan's graph takes the spectrum of m_n as it finds it in S
+        mm_status r = euler_impl<T>(s, chunk, dt, nullptr, 0, s->cap_stream, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
         if (r != MM_OK) {
@@ -1084,9 +1121,17 @@ mm_status euler_steps(mm_sim* s, int64_t nsteps, double dt)
         s->graph_chunk = chunk;
         s->graph_method = MM_EULER;
     }
+    if (s->p.fs && !(s->flags & MM_NO_DEMAG)) {
+        const PassCtx c = pass_ctx(s);
+        hipStream_t st = s->stream;
+        LAUNCH(KX_FWD, pass_x_forward<T>(c, s->at<T>(s->p.o_mn), st));
+    }
     int64_t n = 0;
     for (; n + s->graph_chunk <= nsteps; n += s->graph_chunk) HIP_TRY(hipGraphLaunch(s->gexec, s->stream));
-    return n < nsteps ? euler_impl<T>(s, nsteps - n, dt) : MM_OK;
+    // the remainder continues from the spectrum the groups left in S, as one plain
+    // call would (the fused pass's x forward and the x forward pass round alike only
+    // up to the compiler's contractions)
+    return n < nsteps ? euler_impl<T>(s, nsteps - n, dt, nullptr, 0, nullptr, false) : MM_OK;
 }
 
 // One row of the mean-magnetisation trace, enqueued on the handle's stream.

@@ -126,3 +126,42 @@ def test_fused_stage_is_not_taken_where_it_does_not_apply():
     assert make((128, 128, 128), "f32").plan()["fused_stage"] == 0
     assert make((32, 32, 1), "f32", generic_fft=True).plan()["fused_stage"] == 0
     assert make((30, 30, 1), "f32").plan()["fused_stage"] == 0   # 60 points: no specialised pass
+
+
+@pytest.mark.parametrize("dims,kw", [((32, 8, 1), {}), ((16, 16, 16), {}), ((40, 21, 3), {"pow2_pad": True}),
+                                     ((64, 48, 2), {})])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_fused_euler_matches_separate_passes(dims, kw, precision):
+    # the explicit Euler step (stage 0) through the fused pass: odd counts (the result
+    # copied back), an RK4 call in between, graph replay of 8-step groups plus a
+    # remainder bitwise equal to eager launches, and the separate passes to rounding
+    m0 = random_unit_m((3, dims[2], dims[1], dims[0]), seed=sum(dims) + 1)
+    runs = {}
+    for name, opts in (("eager", {}), ("graph", {"graph": True}), ("split", {"split_stage": True})):
+        s = make(dims, precision, alpha=1.0, **kw, **opts)
+        assert s.plan()["fused_stage"] == (0 if name == "split" else 1)
+        s.set_m(m0)
+        s.step_euler(21, 1e-13)
+        s.step(3, 1e-13)
+        s.step_euler(19, 1e-13)
+        runs[name] = to_np(s.get_m())
+        s.close()
+    assert np.array_equal(runs["eager"], runs["graph"])
+    assert np.abs(runs["eager"] - runs["split"]).max() <= (1e-13 if precision == "f64" else 2e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_fused_euler_matches_oracle(precision):
+    # standard-problem-#3-like material on a fused 3-D plan against the oracle's Euler
+    Ms = 1.0e6
+    Ku = 4e-7 * np.pi * Ms * 1.0e5 / 2
+    dims = (10, 7, 3)
+    pb = oracle.Problem(*dims, 4e-9, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0)
+    sim = mmag.Sim(*dims, 4e-9, Ms=Ms, A=1e-11, Ku=Ku, alpha=1.0, precision=precision, pow2_pad=True)
+    assert sim.plan()["fused_stage"] == 1
+    sim.set_m(random_unit_m(pb.shape, seed=31))
+    m_used = to_np(sim.get_m())
+    sim.step_euler(25, 2e-14)
+    err = np.abs(to_np(sim.get_m()) - oracle.euler(pb, m_used, 2e-14, 25)).max()
+    assert err <= (1e-11 if precision == "f64" else 2e-5), err
+    sim.close()
