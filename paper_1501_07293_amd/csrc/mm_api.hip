@@ -1008,7 +1008,9 @@ mm_status fused_step_impl(mm_sim* s, int64_t nsteps, double dt, bool use_graph)
     hipStream_t st = s->stream;
     if (nsteps <= 0) return MM_OK;
     if (!use_graph) return rk4_fused_steps<T>(s, nsteps, dt, true, st);
-    const int chunk = 8;
+    // 32 steps a graph: on the 128x128x1 film 49.9 -> 49.4 us per step against 8
+    // (fewer graph launches; a rollout segment of 50 steps is one chunk and 18 steps)
+    const int chunk = 32;
     if (!s->graph_valid || s->graph_dt != dt || s->graph_method != MM_RK4) {
         drop_graph(s);
         HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1028,8 +1030,7 @@ mm_status fused_step_impl(mm_sim* s, int64_t nsteps, double dt, bool use_graph)
         s->graph_method = MM_RK4;
     }
     // the steps past whole chunks replay a graph of their own (kept while the chunk
-    // graph is valid, for one remainder length): a rollout's segments of 50 steps
-    // take six chunks and two steps each
+    // graph is valid, for one remainder length)
     const int64_t rem = nsteps % s->graph_chunk;
     if (rem > 0 && (!s->rem_exec || s->rem_len != rem)) {
         if (s->rem_exec) (void)hipGraphExecDestroy(s->rem_exec);
@@ -2444,8 +2445,11 @@ mm_status mm_set_hext(mm_sim* s, const double h[3])
     if (!s || !h) return fail(MM_EINVAL, "sim or h is NULL");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(h[a])) return fail(MM_EINVAL, "applied field must be finite");
-    for (int a = 0; a < 3; ++a) s->hext[a] = h[a];
-    s->graph_valid = false;
+    // captured steps hold the field as a kernel argument: a new value retires them
+    for (int a = 0; a < 3; ++a) {
+        if (s->hext[a] != h[a]) s->graph_valid = false;
+        s->hext[a] = h[a];
+    }
     return MM_OK;
 }
 
@@ -2453,16 +2457,18 @@ mm_status mm_set_alpha(mm_sim* s, double alpha)
 {
     if (!s) return fail(MM_EINVAL, "sim is NULL");
     if (!(alpha >= 0) || !std::isfinite(alpha)) return fail(MM_EINVAL, "alpha must be finite and >= 0");
+    if (s->alpha != alpha) s->graph_valid = false;
     s->alpha = alpha;
-    s->graph_valid = false;
     return MM_OK;
 }
 
 mm_status mm_set_ku_map(mm_sim* s, const void* ku, int on_device)
 {
     if (!s) return fail(MM_EINVAL, "sim is NULL");
-    s->graph_valid = false;
+    // captured steps read the map from the handle's own buffer: only switching it on
+    // or off retires them
     if (!ku) {
+        if (s->has_ku_map) s->graph_valid = false;
         s->has_ku_map = false;
         return MM_OK;
     }
@@ -2496,6 +2502,7 @@ mm_status mm_set_ku_map(mm_sim* s, const void* ku, int on_device)
         HIP_TRY(hipMemcpyAsync(s->at<char>(p.o_ku), h.data(), n * 8, hipMemcpyHostToDevice, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
+    if (!s->has_ku_map) s->graph_valid = false;
     s->has_ku_map = true;
     return MM_OK;
 }
