@@ -706,7 +706,9 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
             tl = px // {16: 16, 32: 8, 64: 8, 128: 16, 256: 16, 512: 8, 1024: 16}.get(px, 16)
             while lines > 1 and 3 * lines * tl > 512:
                 lines //= 2
-            return f"mm::k_fused_stage<{t}, {px}, {lines}>"
+            # launches of at most 256 work-groups take the prefetching instantiation
+            pre = nz * ((ny + 2 * lines - 1) // (2 * lines)) <= 256
+            return f"mm::k_fused_stage<{t}, {px}, {lines}, {b(pre)}>"
         kz = 1 if nz == 1 else 2   # planes per thread
         return f"mm::k_llg_stage<{t}, {kz}>"
     if plan["passes"] == 1:

@@ -5,6 +5,8 @@
 
 namespace mm {
 
+constexpr int kFusedPrefetchGroups = 256;
+
 // FULL: whole lines (a periodic axis, n = P); otherwise the padding half is pruned
 template <typename T, int P, bool INV, bool FULL>
 __global__ __launch_bounds__(256) void k_yline(YLineArgs a)
@@ -55,12 +57,12 @@ __global__ __launch_bounds__(6 * ky2_lines<P>() * (P / Sched<P>::R0)) void k_ksp
     body_kspace_y2<T, P, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool PREFETCH>
 __global__ __launch_bounds__((fused_threads<P, L>())) void k_fused_stage(FusedStageArgs<T> a)
 {
     __shared__ cpx<T> lds[3 * fused_region<P, L>()];
     __shared__ T cell[3 * 2 * L * (P / 2)];
-    body_fused_stage<T, P, L>(a, xcd_tile(blockIdx.x, gridDim.x), lds, cell);
+    body_fused_stage<T, P, L, PREFETCH>(a, xcd_tile(blockIdx.x, gridDim.x), lds, cell);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -305,17 +307,24 @@ template <typename T, int P>
 static bool fused_dispatch(const FusedStageArgs<T>& a, int L, hipStream_t s)
 {
     constexpr int TL = P / Sched<P>::R0;
-    auto go = [&](auto kern, int lines, int threads) {
+    // launches of at most kFusedPrefetchGroups work-groups (no more than one per CU)
+    // are latency-bound: their stage-update loads go out with the gather's.  On the
+    // 128x128x1 film 49.9 -> 47.8 us per RK4 step; with more work-groups the lower
+    // occupancy costs more (256x256x16 FP32 388 -> 404 us, 64^3 FP64 297 -> 318 us)
+    auto go = [&](auto kern, auto kern_pre, int lines, int threads) {
         const int grid = a.g.nz * ((a.g.ny + 2 * lines - 1) / (2 * lines));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, a);
+        if (grid <= kFusedPrefetchGroups)
+            hipLaunchKernelGGL(kern_pre, dim3(grid), dim3(threads), 0, s, a);
+        else
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, s, a);
         return true;
     };
     if constexpr (fused_lds_bytes<T, P, 4>() <= kLdsBudget && 3 * 4 * TL <= 1024)
-        if (L == 4) return go(k_fused_stage<T, P, 4>, 4, fused_threads<P, 4>());
+        if (L == 4) return go(k_fused_stage<T, P, 4, false>, k_fused_stage<T, P, 4, true>, 4, fused_threads<P, 4>());
     if constexpr (fused_lds_bytes<T, P, 2>() <= kLdsBudget && 3 * 2 * TL <= 1024)
-        if (L == 2) return go(k_fused_stage<T, P, 2>, 2, fused_threads<P, 2>());
+        if (L == 2) return go(k_fused_stage<T, P, 2, false>, k_fused_stage<T, P, 2, true>, 2, fused_threads<P, 2>());
     if constexpr (fused_lds_bytes<T, P, 1>() <= kLdsBudget && 3 * TL <= 1024)
-        if (L == 1) return go(k_fused_stage<T, P, 1>, 1, fused_threads<P, 1>());
+        if (L == 1) return go(k_fused_stage<T, P, 1, false>, k_fused_stage<T, P, 1, true>, 1, fused_threads<P, 1>());
     return false;
 }
 

@@ -37,7 +37,7 @@ constexpr int fused_threads() { return 3 * L * (P / Sched<P>::R0) > 256 ? 3 * L 
 // them (component, line l, lane u) for the line transforms.  Spectrum element
 // (c, z, kx, y) at ((c nz + z) hx + kx) sy + y.  Needs 2 nx <= P (the pruned x
 // lines) and open boundaries.
-template <typename T, int P, int L>
+template <typename T, int P, int L, bool PREFETCH>
 __device__ inline void body_fused_stage(const FusedStageArgs<T>& f, int tile, cpx<T>* lds, T* cell)
 {
     constexpr int R0 = Sched<P>::R0, TL = P / R0, NL = 3 * L * TL, LP = padded_len<P>();
@@ -56,6 +56,49 @@ __device__ inline void body_fused_stage(const FusedStageArgs<T>& f, int tile, cp
     LineTw<T, P> W;
     W.load(u, (const cpx<T>*)f.tw);
 
+    // The stage update's inputs of a chunk of CH of the thread's NC cells: m and its
+    // six neighbours (a missing neighbour is the cell itself, Eq. 7, which adds
+    // m - m = 0), m_n, the accumulator, Ku.  With PREFETCH, where all of a thread's
+    // cells form one chunk, these loads are issued right after the gather's, before
+    // the x inverse: the barriers of the transforms wait for LDS only, so their
+    // latency passes while the lines are transformed (the gather's loads, issued
+    // first, are the ones its LDS stores wait for).  The registers they hold lower
+    // the waves per SIMD, which only launches of few work-groups can spare.
+    constexpr int NC = (ROWS * XH + NT - 1) / NT, CH = NC < 3 ? NC : 3;
+    constexpr bool PRE = PREFETCH && NC <= CH;
+    const int64_t N = a.N, plane = (int64_t)nx * ny;
+    T mv[CH][3][7], mnv[CH][3], acv[CH][3], kan[CH];
+    auto load_chunk = [&](int q0) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int idx = tid + (q0 + q) * NT;
+            const int r = idx / nx, i = idx - r * nx, j = yb + r;
+            const bool in = q0 + q < NC && idx < ROWS * nx && j < ny;
+            const int64_t c = in ? z * plane + (int64_t)j * nx + i : 0;
+            const int64_t dxm = in && i > 0 ? -1 : 0, dxp = in && i < nx - 1 ? 1 : 0;
+            const int64_t dym = in && j > 0 ? -(int64_t)nx : 0, dyp = in && j < ny - 1 ? (int64_t)nx : 0;
+            const int64_t dzm = in && z > 0 ? -plane : 0, dzp = in && z < nz - 1 ? plane : 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T* uu = a.ms + d * N + c;
+                mv[q][d][0] = uu[0];
+                mv[q][d][1] = uu[dxm];
+                mv[q][d][2] = uu[dxp];
+                mv[q][d][3] = uu[dym];
+                mv[q][d][4] = uu[dyp];
+                mv[q][d][5] = uu[dzm];
+                mv[q][d][6] = uu[dzp];
+                mnv[q][d] = (T)0;
+                acv[q][d] = (T)0;
+                if (a.stage > 1) {
+                    mnv[q][d] = a.mn[d * N + c];
+                    acv[q][d] = a.acc[d * N + c];
+                }
+            }
+            kan[q] = a.ku ? a.ku[c] : a.can;
+        }
+    };
+
     // ---- x inverse: gather the block's half-spectrum rows of the three components
     // (for one bin, the rows of the block are adjacent); every load is issued
     // before the first LDS store
@@ -71,6 +114,7 @@ __device__ inline void body_fused_stage(const FusedStageArgs<T>& f, int tile, cp
             gv[it] = cpx<T>{(T)0, (T)0};
             if (idx < 3 * NEL && y < ny) gv[it] = src[(((int64_t)c * nz + z) * HX + kx) * sy + y];
         }
+        if constexpr (PRE) load_chunk(0);
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
             const int idx = tid + it * NT;
@@ -124,45 +168,14 @@ __device__ inline void body_fused_stage(const FusedStageArgs<T>& f, int tile, cp
     __syncthreads();
 
     // ---- stage update of the block's cells: the demag field from LDS, the rest as
-    // the plain stage kernel reads it (a missing neighbour is the cell itself, Eq. 7,
-    // which adds m - m = 0: the x, y, z neighbours in the plain kernel's order);
-    // the result overwrites the cell's field in LDS.  A thread takes up to NC cells
-    // and issues the loads of CH of them before their updates (the updates store to
+    // the plain stage kernel reads it (the x, y, z neighbours in its order); the
+    // result overwrites the cell's field in LDS.  A thread takes up to NC cells and
+    // issues the loads of CH of them before their updates (the updates store to
     // global memory, so the compiler would not hoist later loads above them): one
     // memory latency per CH cells instead of one per cell.
     {
-        constexpr int NC = (ROWS * XH + NT - 1) / NT, CH = NC < 3 ? NC : 3;
-        const int64_t N = a.N, plane = (int64_t)nx * ny;
         for (int q0 = 0; q0 < NC; q0 += CH) {
-            T mv[CH][3][7], mnv[CH][3], acv[CH][3], kan[CH];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int idx = tid + (q0 + q) * NT;
-                const int r = idx / nx, i = idx - r * nx, j = yb + r;
-                const bool in = q0 + q < NC && idx < ROWS * nx && j < ny;
-                const int64_t c = in ? z * plane + (int64_t)j * nx + i : 0;
-                const int64_t dxm = in && i > 0 ? -1 : 0, dxp = in && i < nx - 1 ? 1 : 0;
-                const int64_t dym = in && j > 0 ? -(int64_t)nx : 0, dyp = in && j < ny - 1 ? (int64_t)nx : 0;
-                const int64_t dzm = in && z > 0 ? -plane : 0, dzp = in && z < nz - 1 ? plane : 0;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const T* uu = a.ms + d * N + c;
-                    mv[q][d][0] = uu[0];
-                    mv[q][d][1] = uu[dxm];
-                    mv[q][d][2] = uu[dxp];
-                    mv[q][d][3] = uu[dym];
-                    mv[q][d][4] = uu[dyp];
-                    mv[q][d][5] = uu[dzm];
-                    mv[q][d][6] = uu[dzp];
-                    mnv[q][d] = (T)0;
-                    acv[q][d] = (T)0;
-                    if (a.stage > 1) {
-                        mnv[q][d] = a.mn[d * N + c];
-                        acv[q][d] = a.acc[d * N + c];
-                    }
-                }
-                kan[q] = a.ku ? a.ku[c] : a.can;
-            }
+            if (!PRE) load_chunk(q0);
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
                 const int idx = tid + (q0 + q) * NT;

@@ -54,11 +54,13 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("llg", n=(512, 512, 2)) == "mm::k_llg_stage<float, 2>"
     # small one-cell-thick grids: the fused stage pass; two cells thick: the two-plane pass
     small = dict(FILM, px=256, py=256, pz=1, hx=129, passes=3, fused_stage=1)
-    assert sym("llg", plan=small, n=(128, 128, 1)) == "mm::k_fused_stage<float, 256, 1>"
+    assert sym("llg", plan=small, n=(128, 128, 1)) == "mm::k_fused_stage<float, 256, 1, true>"
     # 3-D: lines by the ny nz rows, within 512 threads
-    assert sym("llg", plan=dict(small, pz=128), n=(64, 64, 64)) == "mm::k_fused_stage<float, 256, 4>"
-    assert sym("llg", plan=dict(small, px=1024, pz=32), n=(512, 128, 16)) == "mm::k_fused_stage<float, 1024, 1>"
-    assert sym("llg", plan=dict(small, px=160, pz=32), n=(80, 512, 16)) == "mm::k_fused_stage<float, 160, 4>"
+    assert sym("llg", plan=dict(small, pz=128), n=(64, 64, 64)) == "mm::k_fused_stage<float, 256, 4, false>"
+    assert sym("llg", plan=dict(small, px=1024, pz=32), n=(512, 128, 16)) == "mm::k_fused_stage<float, 1024, 1, false>"
+    assert sym("llg", plan=dict(small, px=160, pz=32), n=(80, 512, 16)) == "mm::k_fused_stage<float, 160, 4, false>"
+    # at most 256 work-groups: the prefetching instantiation
+    assert sym("llg", plan=dict(small, px=512, pz=8), n=(256, 64, 4)) == "mm::k_fused_stage<float, 512, 1, true>"
     two = dict(FILM, px=128, py=128, pz=4, hx=65, passes=3, two_plane=1)
     assert sym("kspace", plan=two, n=(33, 47, 2)) == "mm::k_kspace_y2<float, 128, false>"
     # FP64 lines with a zero upper half take the two-lane z pass
