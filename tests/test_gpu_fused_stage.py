@@ -165,3 +165,26 @@ def test_fused_euler_matches_oracle(precision):
     err = np.abs(to_np(sim.get_m()) - oracle.euler(pb, m_used, 2e-14, 25)).max()
     assert err <= (1e-11 if precision == "f64" else 2e-5), err
     sim.close()
+
+
+@pytest.mark.parametrize("dims", [(24, 16, 1), (24, 16, 2), (20, 12, 3)])
+@pytest.mark.parametrize("method", ["euler", "rk4"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_fused_schedule_with_ramps_matches_separate_passes(dims, method, precision):
+    # a time-dependent protocol (field ramps, a damping switch, a constant piece) on
+    # fused plans: the applied field changes every step inside the fused launches
+    pieces = [(7, (1e4, 0.0, 0.0), (2e4, 5e3, 0.0), 0.5), (9, (2e4, 5e3, 0.0), (2e4, 5e3, 0.0), 0.02),
+              (6, (0.0, 1e4, 0.0), (-1e4, 0.0, 3e3), 0.3)]
+    dt = 2e-14 if method == "euler" else 1e-13
+    m0 = random_unit_m((3, dims[2], dims[1], dims[0]), seed=77)
+    out = {}
+    for split in (False, True):
+        s = make(dims, precision, pow2_pad=True, split_stage=split)
+        assert s.plan()["fused_stage"] == (0 if split else 1)
+        s.set_m(m0)
+        rows = to_np(s.run_schedule(pieces, dt, 4, method=method))
+        out[split] = (rows, to_np(s.get_m()))
+        s.close()
+    tol = 1e-13 if precision == "f64" else 2e-6
+    assert np.abs(out[False][0] - out[True][0]).max() <= tol
+    assert np.abs(out[False][1] - out[True][1]).max() <= tol
