@@ -728,6 +728,10 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
             if t == "double" and pz in (16, 32) and 2 * nz <= pz:
                 return f"mm::k_kspace_z_split<{t}, {pz}>"
             return f"mm::k_kspace_z<{t}, {pz}>"
+        if fast and pz in (128, 256, 512, 1024) and 2 * nz <= pz and not (t == "double" and pz == 1024):
+            # long z lines: C columns a work-group, as many as the threads and LDS allow
+            cols = {"float": {128: 32, 256: 16, 512: 4, 1024: 2}, "double": {128: 16, 256: 8, 512: 4}}[t][pz]
+            return f"mm::k_kspace_zl<{t}, {pz}, {cols}>"
         if fast and pz in (128, 256, 512, 1024):
             return f"mm::k_kspace_fixed<{t}, {512 if pz == 512 else 256}, {pz}>"
         return f"mm::k_kspace<{t}, {plan['threads']}>"

@@ -22,6 +22,13 @@ __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xfwd(XLineArgs a)
     body_xfwd<T, P, L, FULL>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
+template <typename T, int P, int C>
+__global__ __launch_bounds__(3 * C * (P / Sched<P>::R0)) void k_kspace_zl(KzArgs a)
+{
+    __shared__ cpx<T> lds[3 * C * padded_len<P>()];
+    body_kspace_zl<T, P, C>(a, xcd_tile(blockIdx.x, gridDim.x), lds);
+}
+
 template <typename T, int P, int L, bool FULL>
 __global__ __launch_bounds__(L * (P / Sched<P>::R0)) void k_xinv(XLineArgs a)
 {
@@ -181,6 +188,25 @@ bool launch_kspace_z(const KzArgs& a, int PZ, hipStream_t s)
             else
                 hipLaunchKernelGGL((k_kspace_z_split<T, 32>), dim3(sgrid), dim3(6 * SC), 0, s, a);
             return true;
+        }
+    }
+    // lines of 128 points or more: C columns a work-group, register radix stages (FP64
+    // lines of 1024 points take the LDS-staged pass, launch_kspace_fixed)
+    auto zl = [&](auto kern, int C, int tl) {
+        const int zgrid = (a.ncols + C - 1) / C;
+        hipLaunchKernelGGL(kern, dim3(zgrid), dim3(3 * C * tl), 0, s, a);
+        return true;
+    };
+    if (PZ >= 128 && 2 * a.nz <= PZ) {
+        switch (PZ) {
+        case 128: return zl(k_kspace_zl<T, 128, kzl_cols<T, 128>()>, kzl_cols<T, 128>(), 128 / Sched<128>::R0);
+        case 256: return zl(k_kspace_zl<T, 256, kzl_cols<T, 256>()>, kzl_cols<T, 256>(), 256 / Sched<256>::R0);
+        case 512: return zl(k_kspace_zl<T, 512, kzl_cols<T, 512>()>, kzl_cols<T, 512>(), 512 / Sched<512>::R0);
+        case 1024:
+            if constexpr (sizeof(T) == 4)
+                return zl(k_kspace_zl<T, 1024, kzl_cols<T, 1024>()>, kzl_cols<T, 1024>(), 1024 / Sched<1024>::R0);
+            return false;
+        default: return false;
         }
     }
     switch (PZ) {

@@ -493,6 +493,109 @@ __device__ inline void body_kspace_z(const KzArgs& a, int tile, cpx<T>* sh)
     }
 }
 
+// ------------------------------------------------------- z k-space, long lines
+// Lines of 128 points or more (thick 3-D grids such as the cubes), whose whole
+// lines do not fit a thread's registers: a work-group holds C adjacent columns
+// (kx, ky), three component lines each, and transforms them with the line
+// passes' register radix stages exchanged through LDS (the input's upper half is
+// zero, the kept outputs are the first nz).  Lanes run column fastest, so each
+// load and store of one z point covers the C columns as one contiguous segment,
+// and the octant loads of the product run along ky.
+// Columns per work-group: as many as 1024 threads (3 C (P / R0)) and the LDS (3 C
+// padded lines) allow, up to 32: the segments are what the pass waits on (128^3
+// cube, Pz = 256, FP32: 8 columns 244 us per Euler step, 16 columns 209 us).  At
+// 1024 points at most 512 threads, whose 256 registers a thread hold the lines
+// without spilling (FP64 spills even so and keeps the LDS-staged pass).
+template <typename T, int P>
+constexpr int kzl_cols()
+{
+    constexpr int TL = P / Sched<P>::R0, MAXT = P >= 1024 ? 512 : 1024;
+    int c = 32;
+    while (c > 1 && (3 * c * TL > MAXT || 3 * c * padded_len<P>() * (int)sizeof(cpx<T>) > kLdsBudget)) c /= 2;
+    return c;
+}
+
+template <typename T, int P, int C>
+__device__ inline void body_kspace_zl(const KzArgs& a, int tile, cpx<T>* lds)
+{
+    constexpr int R0 = Sched<P>::R0, TL = P / R0, NT = 3 * C * TL, LP = padded_len<P>();
+    static_assert(Sched<P>::NS >= 2, "lines of 128 points or more");
+    const int t = (int)threadIdx.x;
+    const int l = t % C, u = (t / C) % TL, comp = t / (C * TL);
+    const int col = tile * C + l;
+    const bool ok = col < a.ncols;
+    const int64_t zs = a.ncols;
+    cpx<T>* g = (cpx<T>*)a.buf + comp * a.comp_stride + (ok ? col : 0);
+    cpx<T>* ln = lds + (comp * C + l) * LP;
+    LineTw<T, P> W;
+    W.load(u, (const cpx<T>*)a.tw);
+    cpx<T> v[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+        const int e = u + TL * r;
+        cpx<T> x = {(T)0, (T)0};
+        if (2 * r < R0 && ok && e < a.nz) x = g[e * zs];  // e >= P/2 is zero padding
+        v[r] = x;
+    }
+    // Eq. 14 spectra of the product elements this thread takes (element idx: column
+    // idx % C, kz = idx / C), loaded with the data so their latency overlaps the
+    // forward transform; negative frequencies mirror with the component parities
+    // (xy odd in y, xz odd in z, yz odd in y and z)
+    constexpr int NI = (C * P + NT - 1) / NT;
+    const T* K = (const T*)a.kern;
+    T kv[NI][6];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = t + it * NT;
+        const int l2 = idx % C, e = idx / C, col2 = tile * C + l2;
+        const bool in = idx < C * P && col2 < a.ncols;
+        const int cc = in ? col2 : 0;
+        const int kx = cc / a.Py;
+        int ky = cc - kx * a.Py, kz = e;
+        T sy = (T)1, sz = (T)1;
+        if (2 * ky > a.Py) {
+            ky = a.Py - ky;
+            sy = (T)-1;
+        }
+        if (2 * kz > P) {
+            kz = P - kz;
+            sz = (T)-1;
+        }
+        const T* Kp = K + (in ? kz * a.k_zs + kx * a.k_xs + ky : 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kv[it][c] = Kp[c * a.k_cs];
+        kv[it][1] *= sy;
+        kv[it][2] *= sz;
+        kv[it][4] *= sy * sz;
+    }
+    Dft<T, R0>::run(v);
+    finish_line<T, P>(ln, u, v, W, [&](int e, cpx<T> val) { ln[pad16(e)] = val; });
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = t + it * NT;
+        const int l2 = idx % C, e = idx / C;
+        if (idx >= C * P || tile * C + l2 >= a.ncols) continue;
+        const T kxx = kv[it][0], kxy = kv[it][1], kxz = kv[it][2], kyy = kv[it][3], kyz = kv[it][4],
+                kzz = kv[it][5];
+        cpx<T>* px = lds + (0 * C + l2) * LP + pad16(e);
+        cpx<T>* py = lds + (1 * C + l2) * LP + pad16(e);
+        cpx<T>* pz = lds + (2 * C + l2) * LP + pad16(e);
+        const cpx<T> mx = *px, my = *py, mz = *pz;
+        *px = conj(cpx<T>{kxx * mx.re + kxy * my.re + kxz * mz.re, kxx * mx.im + kxy * my.im + kxz * mz.im});
+        *py = conj(cpx<T>{kxy * mx.re + kyy * my.re + kyz * mz.re, kxy * mx.im + kyy * my.im + kyz * mz.im});
+        *pz = conj(cpx<T>{kxz * mx.re + kyz * my.re + kzz * mz.re, kxz * mx.im + kyz * my.im + kzz * mz.im});
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[r] = ln[pad16(u + TL * r)];
+    Dft<T, R0>::run(v);
+    __syncthreads();  // stage-1 reads of every line are done before LDS is rewritten
+    finish_line<T, P, true>(ln, u, v, W, [&](int e, cpx<T> val) {
+        if (ok && e < a.nz) g[e * zs] = conj(val);  // inverse by conjugation
+    });
+}
+
 // Split z lines (FP64, nz <= PZ / 2): two adjacent lanes share a (column,
 // component) line, so each holds PZ / 2 values instead of PZ.  With the upper
 // half of the input zero, the even outputs are FFT_{PZ/2}(x) and the odd ones

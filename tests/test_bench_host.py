@@ -74,9 +74,13 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("x_fwd", plan=gen) == "mm::k_row_r2c<float, 256>"
     assert sym("kspace", plan=gen) == "mm::k_kspace<float, 256>"
     cube = dict(FILM, px=256, py=256, pz=256)
-    assert sym("kspace", plan=cube, n=(128, 128, 128)) == "mm::k_kspace_fixed<float, 256, 256>"
+    assert sym("kspace", plan=cube, n=(128, 128, 128)) == "mm::k_kspace_zl<float, 256, 16>"
     cube512 = dict(cube, px=512, py=512, pz=512)
-    assert sym("kspace", plan=cube512, n=(256, 256, 256)) == "mm::k_kspace_fixed<float, 512, 512>"
+    assert sym("kspace", plan=cube512, n=(256, 256, 256)) == "mm::k_kspace_zl<float, 512, 4>"
+    assert sym("kspace", "f64", plan=cube512, n=(256, 256, 256)) == "mm::k_kspace_zl<double, 512, 4>"
+    # FP64 lines of 1024 points keep the LDS-staged pass
+    cube1k = dict(cube, px=1024, py=1024, pz=1024)
+    assert sym("kspace", "f64", plan=cube1k, n=(512, 512, 512)) == "mm::k_kspace_fixed<double, 256, 1024>"
     thin = dict(FILM, pz=1, passes=3)
     assert sym("kspace", plan=thin, n=(512, 512, 1)) == "mm::k_kspace_y<float, 1024, false>"
     fused = dict(FILM, px=512, py=128, pz=8, passes=3)
