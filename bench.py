@@ -39,7 +39,7 @@ CSRC = os.path.join(ROOT, "paper_1501_07293_amd", "csrc")
 KERNEL_TU = [("mm::kbf_", "mm_batch.hip"), ("mm::kb_", "mm_batch.hip"),
              ("mm::k_xfwd", "mm_fast.hip"), ("mm::k_xinv", "mm_fast.hip"),
              ("mm::k_yline", "mm_fast.hip"), ("mm::k_kspace_z", "mm_fast.hip"),
-             ("mm::k_kspace_y", "mm_fast.hip"), ("mm::k_fused_stage", "mm_fast.hip"),
+             ("mm::k_kspace_y", "mm_fast.hip"), ("mm::k_fused_", "mm_fused.hip"),
              ("mm::k_llg_stage", "mm_llg.hip"),
              ("mm::k_row_", "mm_passes.hip"), ("mm::k_col_fft", "mm_passes.hip"),
              ("mm::k_kspace<", "mm_passes.hip"), ("mm::k_kspace_fixed", "mm_passes.hip")]

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmag.so")
-SOURCES = ["mm_api.hip", "mm_passes.hip", "mm_fast.hip", "mm_tensor.hip", "mm_llg.hip",
+# the two largest first, so that the pool compiles them side by side
+SOURCES = ["mm_fast.hip", "mm_fused.hip", "mm_api.hip", "mm_passes.hip", "mm_tensor.hip", "mm_llg.hip",
            "mm_adjoint.hip", "mm_batch.hip"]
 ARCH = os.environ.get("MMAG_ARCH", "gfx950")
 
@@ -28,7 +29,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # The size-specialised FFT bodies feed literal zeros (the padding half of a line)
 # into their first stage; with signed zeros ignored the compiler drops the
 # additions of those zeros.  Only the sign of a zero result can differ.
-EXTRA = {"mm_fast.hip": ["-fno-signed-zeros"], "mm_batch.hip": ["-fno-signed-zeros"]}
+EXTRA = {"mm_fast.hip": ["-fno-signed-zeros"], "mm_fused.hip": ["-fno-signed-zeros"],
+         "mm_batch.hip": ["-fno-signed-zeros"]}
 
 
 def _compile(src: str) -> str:

@@ -12,43 +12,9 @@
 // so dLoss/dKu(c) gathers nu_x(c) m_x(c) 2/(mu0 Ms^2) from every stage.
 #include "mm_common.hpp"
 #include "mm_kernels.hpp"
+#include "mm_adjoint_body.hpp"
 
 namespace mm {
-
-template <typename T>
-__device__ inline void xprod(const T a[3], const T b[3], T o[3])
-{
-    o[0] = a[1] * b[2] - a[2] * b[1];
-    o[1] = a[2] * b[0] - a[0] * b[2];
-    o[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-template <typename T>
-__device__ inline void ld3(const T* p, int64_t N, int64_t c, T v[3])
-{
-    v[0] = p[c];
-    v[1] = p[N + c];
-    v[2] = p[2 * N + c];
-}
-
-template <typename T>
-__device__ inline void st3(T* p, int64_t N, int64_t c, const T v[3])
-{
-    p[c] = v[0];
-    p[N + c] = v[1];
-    p[2 * N + c] = v[2];
-}
-
-// F(m, h) for one cell
-template <typename T>
-__device__ inline void stage_F(const T m[3], const T h[3], T G, T alpha, T F[3])
-{
-    T t[3], d[3];
-    xprod(m, h, t);
-    xprod(m, t, d);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) F[q] = -G * (t[q] + alpha * d[q]);
-}
 
 // Renormalisation step: m' = m* / |m*| with m* = m_n + (F1 + 2F2 + 2F3 + F4)/6.
 // mu = (lam - (lam . m') m') / |m*|;  dF = mu / 6;  accl = mu.
@@ -58,7 +24,7 @@ __global__ __launch_bounds__(256) void k_adj_renorm(AdjArgs<T> a)
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= a.N) return;
     const int64_t N = a.N;
-    T ms[4][3], hs[4][3], F[4][3];
+    T ms[4][3], hs[4][3];
     ld3(a.mn, N, c, ms[0]);
     ld3(a.m2, N, c, ms[1]);
     ld3(a.m3, N, c, ms[2]);
@@ -67,20 +33,9 @@ __global__ __launch_bounds__(256) void k_adj_renorm(AdjArgs<T> a)
     ld3(a.h2, N, c, hs[1]);
     ld3(a.h3, N, c, hs[2]);
     ld3(a.h4, N, c, hs[3]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) stage_F(ms[s], hs[s], a.G, a.alpha, F[s]);
-    T mstar[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-        mstar[q] = ms[0][q] + (F[0][q] + (T)2 * F[1][q] + (T)2 * F[2][q] + F[3][q]) / (T)6;
-    const T nrm = sqrt(mstar[0] * mstar[0] + mstar[1] * mstar[1] + mstar[2] * mstar[2]);
-    const T mp[3] = {mstar[0] / nrm, mstar[1] / nrm, mstar[2] / nrm};
-    T lam[3];
+    T lam[3], mu[3];
     ld3(a.lam, N, c, lam);
-    const T dot = lam[0] * mp[0] + lam[1] * mp[1] + lam[2] * mp[2];
-    T mu[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) mu[q] = (lam[q] - dot * mp[q]) / nrm;
+    adj_renorm_cell(ms, hs, lam, a.G, a.alpha, mu);
     st3(a.mu, N, c, mu);
     st3(a.accl, N, c, mu);
     const T df[3] = {mu[0] / (T)6, mu[1] / (T)6, mu[2] / (T)6};
@@ -98,19 +53,8 @@ __global__ __launch_bounds__(256) void k_adj_nu(AdjArgs<T> a, const T* ms, const
     ld3(ms, N, c, m);
     ld3(hs, N, c, h);
     ld3(a.dF, N, c, l);
-    T lxm[3], t4[3], t1[3], mxh[3], t2[3], t3[3];
-    xprod(l, m, lxm);    // dF x m
-    xprod(lxm, m, t4);   // (dF x m) x m
-    xprod(h, l, t1);     // h x dF
-    xprod(m, h, mxh);    // m x h
-    xprod(mxh, l, t2);   // (m x h) x dF
-    xprod(h, lxm, t3);   // h x (dF x m)
     T nu[3], loc[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        nu[q] = -a.G * (lxm[q] + a.alpha * t4[q]);
-        loc[q] = -a.G * (t1[q] + a.alpha * (t2[q] + t3[q]));
-    }
+    adj_nu_cell(m, h, l, a.G, a.alpha, nu, loc);
     st3(a.nu, N, c, nu);
     st3(a.loc, N, c, loc);
     if (a.dku) a.dku[c] += (double)nu[0] * (double)m[0] * a.kfac;

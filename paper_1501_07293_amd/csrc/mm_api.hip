@@ -1379,7 +1379,68 @@ mm_status backward_segment(mm_sim* s, const AdjBufs<T>& b, int64_t len, double d
     T* accl = b.accl;
     const T cmu[4] = {(T)0, (T)(1.0 / 6.0), (T)(2.0 / 6.0), (T)(2.0 / 6.0)};
     const T ca[4] = {(T)0, (T)0.5, (T)0.5, (T)1};
-    for (int64_t n = len - 1; n >= 0; --n) {
+    if (p.fs && with_demag) {
+        // fused reverse sweep: the renormalisation and last-stage nu of the last step
+        // and the x forward of that nu; then per stage the y / z passes and one fused
+        // pass (x inverse of nu's field, the apply, and the stage before's nu, or at
+        // a step boundary the renormalisation of the step before and its last
+        // stage's nu, with the x forward of the new nu).  The spectrum and nu
+        // alternate between two buffers (scr is free once the recompute is done).
+        PassCtx c = pass_ctx(s);
+        void* sb[2] = {s->at<char>(p.o_S), s->at<char>(p.o_S2)};
+        T* nub[2] = {b.nu, b.scr};
+        const int64_t nl = len - 1;
+        aa.mn = b.at(nl, 0);
+        aa.m2 = b.at(nl, 1);
+        aa.m3 = b.at(nl, 2);
+        aa.m4 = b.at(nl, 3);
+        aa.h1 = b.at(nl, 4);
+        aa.h2 = b.at(nl, 5);
+        aa.h3 = b.at(nl, 6);
+        aa.h4 = b.at(nl, 7);
+        aa.lam = lam;
+        aa.accl = accl;
+        aa.nu = nub[0];
+        HIP_TRY(launch_adj_renorm<T>(aa, st));
+        HIP_TRY(launch_adj_nu<T>(aa, b.at(nl, 3), b.at(nl, 7), st));
+        c.S = sb[0];
+        HIP_TRY(pass_x_forward<T>(c, nub[0], st));
+        FusedAdjArgs<T> fa{};
+        fa.a = aa;
+        fa.sy = c.Sy;
+        fa.tw = c.twx;
+        int k = 0;  // fused passes so far: spectrum sb[k & 1], nu nub[k & 1]
+        for (int64_t n = len - 1; n >= 0; --n) {
+            for (int stg = 3; stg >= 0; --stg, ++k) {
+                c.S = sb[k & 1];
+                mm_status r = demag_mid<T>(s, c, st);
+                if (r != MM_OK) return r;
+                fa.a.accl = accl;
+                fa.nu_in = nub[k & 1];
+                fa.nu_out = nub[(k + 1) & 1];
+                fa.cmu = cmu[stg];
+                fa.ca = ca[stg];
+                fa.S_in = sb[k & 1];
+                fa.S_out = sb[(k + 1) & 1];
+                if (stg > 0) {
+                    fa.mode = 1;
+                    fa.ms = b.at(n, stg - 1);
+                    fa.hs = b.at(n, 4 + stg - 1);
+                } else if (n > 0) {
+                    fa.mode = 2;
+                    for (int q = 0; q < 8; ++q) fa.st[q] = b.at(n - 1, q);
+                    fa.accl_prev = lam;  // the step before's accumulator once swapped
+                } else {
+                    fa.mode = 0;
+                }
+                if (!launch_fused_adjoint<T>(fa, p.Px, p.fs_lines, st))
+                    return fail(MM_ENOTSUP, "no fused adjoint pass of length %d", p.Px);
+                HIP_TRY(hipGetLastError());
+            }
+            std::swap(lam, accl);
+        }
+    }
+    for (int64_t n = len - 1; n >= 0 && !(p.fs && with_demag); --n) {
         aa.mn = b.at(n, 0);
         aa.m2 = b.at(n, 1);
         aa.m3 = b.at(n, 2);

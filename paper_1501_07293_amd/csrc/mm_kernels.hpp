@@ -312,6 +312,33 @@ struct AdjArgs {
     double kfac;                 // 2 / (mu0 Ms^2)
     int per;                     // periodic axes (bit 0 x, 1 y, 2 z): the stencil wraps
 };
+// One fused stage of the reverse sweep on fused-stage plans (mm_fused.hpp): the
+// x inverse of the spectrum of nu's demag field, the apply of that stage (a =
+// loc + Lop nu, accl += a, dF = cmu mu + ca a; accl stored in modes 0 and 1),
+// then by `mode`
+//   0: nothing more (the sweep's last stage);
+//   1: nu and loc of the stage before at (ms, hs) from that dF;
+//   2: the renormalisation of the step before (lam = the new accl, its stage
+//      states and fields st[0..7]; mu and accl_prev = mu stored, dF = mu / 6),
+//      then nu and loc of its last stage (st[3], st[7]);
+// and for modes 1 and 2 the x forward of the new nu into S_out.
+template <typename T>
+struct FusedAdjArgs {
+    AdjArgs<T> a;         // constants and buffers (mu, accl, loc, dku, ku); a.nu, a.hd unused
+    const T* nu_in;       // nu of the stage applied (read with its neighbours)
+    T* nu_out;            // nu of the stage before (another buffer)
+    T cmu, ca;
+    int mode;
+    const T *ms, *hs;     // mode 1
+    const T* st[8];       // mode 2: m_n, m2, m3, m4, h1 .. h4 of the step before
+    T* accl_prev;         // mode 2: its accumulator (the other buffer)
+    const void* S_in;
+    void* S_out;
+    int64_t sy;
+    const void* tw;
+};
+template <typename T>
+bool launch_fused_adjoint(const FusedAdjArgs<T>& a, int Px, int L, hipStream_t s);
 template <typename T>
 hipError_t launch_adj_renorm(const AdjArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -266,15 +266,16 @@ def test_fp32_vs_fp64_gpu_agree_mid_film():
 
 
 def test_autotuner_picks_a_schedule_that_matches_the_oracle():
-    # 65x33x3: candidates are 7-smooth (135, 70, 6) or power-of-two (256, 128, 8) padding,
-    # specialised or runtime-radix passes, 256 or 512 threads.
+    # 65x33x3: candidates are 7-smooth (135, 70, 6), power-of-two (256, 128, 8) or fast
+    # (160, 96 or 128, 8) padding, specialised or runtime-radix passes, 256 or 512 threads;
+    # which one wins is a matter of timing, the field must match the oracle whichever.
     pb = problem(65, 33, 3, 4e-9, Ku=500.0)
     m0 = random_unit_m(pb.shape, seed=17)
     sim = make_sim(pb, "f32", autotune=True)
     p = sim.plan()
     print("autotuner choice:", p)
     assert p["tuned"] == 1 and p["candidates"] >= 8 and p["tuned_demag_ms"] > 0
-    assert p["px"] in (135, 256) and p["py"] in (70, 128) and p["pz"] in (6, 8)
+    assert p["px"] in (135, 160, 256) and p["py"] in (70, 96, 128) and p["pz"] in (6, 8)
     sim.set_m(m0)
     m_gpu = to_np(sim.get_m())
     ref = oracle.heff_terms(pb, m_gpu)["demag"]
