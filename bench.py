@@ -710,7 +710,8 @@ def mm_kernel_symbol(k: str, precision: str, plan: dict, n: tuple | None = None)
             pre = nz * ((ny + 2 * lines - 1) // (2 * lines)) <= 256
             return f"mm::k_fused_stage<{t}, {px}, {lines}, {b(pre)}>"
         kz = 1 if nz == 1 else 2   # planes per thread
-        return f"mm::k_llg_stage<{t}, {kz}>"
+        ty = 2 if nx % 128 == 0 and ny % 2 == 0 else 1   # rows per work-group tile
+        return f"mm::k_llg_stage<{t}, {kz}, {ty}>"
     if plan["passes"] == 1:
         return f"mm::k_demag_1wg<{t}, {plan['threads']}>"
     if k in ("x_fwd", "x_inv"):

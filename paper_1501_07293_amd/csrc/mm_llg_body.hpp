@@ -98,13 +98,26 @@ __device__ inline void llg_update(const LlgArgs<T>& a, int64_t pc, int k0, const
 // is clamped to the cell's own, which adds mc - mc = 0, so every load is issued
 // unconditionally and none waits on a per-lane branch.  Along a periodic axis
 // (a.per) the neighbour across the boundary is the cell at the other end.
-template <typename T, int KZ>
+//
+// TY > 1: the work-group's columns form a tile of kLlgNT / TY columns by TY rows
+// (needs nx a multiple of kLlgNT / TY and ny of TY, so the tiles cover the plane
+// exactly and llg_blocks counts them), so most y neighbours a thread reads are
+// cells its own work-group loads.
+template <typename T, int KZ, int TY = 1>
 __device__ inline void body_llg_stage(const LlgArgs<T>& a, int64_t blk, int lane)
 {
     const int64_t plane = (int64_t)a.nx * a.ny;
     const int nzc = (a.nz + KZ - 1) / KZ;
     const int kc = (int)(blk % nzc);
-    const int64_t pc = (blk / nzc) * kLlgNT + lane;
+    int64_t pc;
+    if constexpr (TY == 1) {
+        pc = (blk / nzc) * kLlgNT + lane;
+    } else {
+        constexpr int TX = kLlgNT / TY;
+        const int64_t cb = blk / nzc, tiles_x = a.nx / TX;
+        const int64_t ty = cb / tiles_x, tx = cb - ty * tiles_x;
+        pc = (ty * TY + lane / TX) * a.nx + tx * TX + lane % TX;
+    }
     if (pc >= plane) return;
     const int i = (int)(pc % a.nx), j = (int)(pc / a.nx);
     const int k0 = kc * KZ;

@@ -48,10 +48,14 @@ def test_kernel_symbols_follow_the_dispatch():
     assert sym("y_fwd") == "mm::k_yline<float, 1024, false, false>"
     assert sym("y_inv") == "mm::k_yline<float, 1024, true, false>"
     assert sym("kspace") == "mm::k_kspace_z<float, 32>"
-    assert sym("llg") == "mm::k_llg_stage<float, 2>"
+    assert sym("llg") == "mm::k_llg_stage<float, 2, 2>"
     # planes per thread of the stage update: 1 or 2 for grids one or two cells thick
-    assert sym("llg", n=(512, 512, 1)) == "mm::k_llg_stage<float, 1>"
-    assert sym("llg", n=(512, 512, 2)) == "mm::k_llg_stage<float, 2>"
+    assert sym("llg", n=(512, 512, 1)) == "mm::k_llg_stage<float, 1, 2>"
+    assert sym("llg", n=(512, 512, 2)) == "mm::k_llg_stage<float, 2, 2>"
+    # rows per work-group tile: 2 where the plane splits into 128 x 2 tiles, else 1
+    assert sym("llg", n=(384, 500, 16)) == "mm::k_llg_stage<float, 2, 2>"
+    assert sym("llg", n=(500, 512, 16)) == "mm::k_llg_stage<float, 2, 1>"
+    assert sym("llg", n=(512, 511, 16)) == "mm::k_llg_stage<float, 2, 1>"
     # small one-cell-thick grids: the fused stage pass; two cells thick: the two-plane pass
     small = dict(FILM, px=256, py=256, pz=1, hx=129, passes=3, fused_stage=1)
     assert sym("llg", plan=small, n=(128, 128, 1)) == "mm::k_fused_stage<float, 256, 1, true>"
