@@ -128,20 +128,21 @@ def algorithmic_bytes(plan: dict, nx: int, ny: int, nz: int, esz: int) -> dict:
 
 
 def run_gpu(args, cfg, precision: str, steps: int, warmup: int, profile: bool, repeats: int = 1,
-            autotune: bool = False):
+            autotune: bool = False, graph: bool | None = None):
     """Times `repeats` runs of exactly `steps` RK4 steps (each bracketed by device
     synchronisation) after `warmup` untimed steps; returns the handle, its plan,
     the list of run times, the per-kernel averages of a short untimed profiling
     pass, and the dominant kernel's average launch time over all timed runs
-    (HIP events around one launch in PROFILE_EVERY)."""
+    (HIP events around one launch in PROFILE_EVERY).  graph: replay step graphs
+    (default: the --graph flag)."""
     import torch
 
     import paper_1501_07293_amd as mm
     from synthetic import random_unit_m
 
     sim = mm.Sim(cfg.nx, cfg.ny, cfg.nz, cfg.cell, Ms=cfg.Ms, A=cfg.A, Ku=cfg.Ku, alpha=cfg.alpha,
-                 gamma=cfg.gamma, precision=precision, graph=args.graph, autotune=autotune,
-                 device="cuda:0")
+                 gamma=cfg.gamma, precision=precision, graph=args.graph if graph is None else graph,
+                 autotune=autotune, device="cuda:0")
     sim.set_hext(cfg.hext)
     m0 = random_unit_m(cfg.shape, seed=0)
     sim.set_m(m0)
@@ -481,12 +482,15 @@ def cpu_baseline(cfg, pb, m, target_s: float):
 
 def mid_leg(args, steps: int) -> dict:
     """The 256x64x4 film (padded 512x128x8) in FP32 with the autotuned schedule (which
-    also times the fused y-z pass there): median rate of 5 runs of `steps` steps and
-    the demag field against the oracle's direct sum at every cell."""
+    also times the fused y-z pass there) and step-graph replay (its kernels run a few
+    microseconds each, so launches cost measurably: 0.0900 against 0.0870 ms per step):
+    median rate of 5 runs of `steps` steps and the demag field against the oracle's
+    direct sum at every cell."""
     import oracle
     import synthetic
     c = synthetic.MID
-    sim, plan, times, _, _, _, _, _ = run_gpu(args, c, "f32", steps, 5, False, repeats=5, autotune=True)
+    sim, plan, times, _, _, _, _, _ = run_gpu(args, c, "f32", steps, 5, False, repeats=5, autotune=True,
+                                              graph=True)
     med = float(np.median(times))
     pb = oracle.Problem(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
                         gamma=c.gamma, hext=tuple(c.hext))
@@ -495,7 +499,7 @@ def mid_leg(args, steps: int) -> dict:
     return {"workload": f"{c.name} cells={c.N} cell={c.cell:g} m, RK4 dt={c.dt:g} s, "
                         f"padded FFT {plan['px']}x{plan['py']}x{plan['pz']}",
             "steps": steps, "repeats": len(times), "ms_per_step": 1e3 * med / steps,
-            "value": c.N * steps / med, "unit": "cell-updates/s", "dtype": "f32",
+            "value": c.N * steps / med, "unit": "cell-updates/s", "dtype": "f32", "graph": True,
             "schedule": {k: plan[k] for k in ("passes", "generic_fft", "threads", "tuned", "candidates")},
             "err": {"demag_field_rel_max": err, "cells": nobs, "tolerance": 1e-5}}
 
