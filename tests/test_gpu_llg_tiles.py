@@ -40,3 +40,39 @@ def test_stage_update_mappings_match_oracle(dims, periodic, precision):
     err = np.abs(m - ref).max()
     assert err <= (1e-11 if precision == "f64" else 2e-5), err
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_full_film_euler_step_sampled_against_oracle(precision):
+    # The 512x512x16 film at full size in the default launch configuration (two-row
+    # tiles): one explicit Euler step (the stage update's stage 0) at the 1024 seeded
+    # observation cells against the oracle: its direct-sum demag field there, its
+    # exchange and anisotropy fields, its LLG right-hand side, then the step and the
+    # renormalisation the oracle's Euler integrator applies.
+    import synthetic
+    c = synthetic.LARGE
+    pb = oracle.Problem(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha,
+                        gamma=c.gamma, hext=tuple(c.hext))
+    sim = mmag.Sim(c.nx, c.ny, c.nz, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
+                   precision=precision)
+    assert sim.plan()["fused_stage"] == 0
+    sim.set_hext(c.hext)
+    sim.set_m(random_unit_m(pb.shape, seed=103))
+    m0 = to_np(sim.get_m()).reshape(3, -1)
+    sim.step_euler(1, c.dt)
+    m1 = to_np(sim.get_m()).reshape(3, -1)
+    obs = synthetic.observation_cells(c.nx, c.ny, c.nz, 1024, seed=104)
+    h = oracle.demag(pb, m0.reshape(pb.shape), obs) + \
+        oracle.exchange(pb, m0.reshape(pb.shape)).reshape(3, -1)[:, obs] + \
+        oracle.anisotropy(pb, m0.reshape(pb.shape)).reshape(3, -1)[:, obs] + \
+        np.asarray(c.hext, dtype=np.float64).reshape(3, 1)
+    n = len(obs)
+    ps = oracle.Problem(n, 1, 1, c.cell, Ms=c.Ms, A=c.A, Ku=c.Ku, alpha=c.alpha, gamma=c.gamma,
+                        hext=tuple(c.hext))
+    k = oracle.llg_rhs(ps, m0[:, obs].reshape(3, 1, 1, n), h.reshape(3, 1, 1, n)).reshape(3, n)
+    v = m0[:, obs] + c.dt * k
+    ref = v / np.sqrt((v * v).sum(axis=0))
+    err = np.abs(m1[:, obs] - ref).max()
+    print(f"full film Euler step {precision}: {err:.2e} over {n} cells")
+    assert err <= (1e-12 if precision == "f64" else 2e-6), err
+    sim.close()
