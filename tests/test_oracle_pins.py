@@ -655,3 +655,25 @@ def test_max_torque_sets_the_largest_llg_rate():
     rate = np.sqrt((f * f).sum(axis=0)).max()
     assert np.isclose(oracle.max_torque(pb, m) * pb.gamma / np.sqrt(1 + pb.alpha ** 2), rate,
                       rtol=1e-12)
+
+
+def test_sampled_euler_recipe_equals_oracle_euler():
+    # The per-cell recipe the full-film GPU test applies at sampled cells (direct-sum
+    # demag there, exchange, anisotropy, applied field, right-hand side on a 1-D problem
+    # of the sampled cells, step, renormalisation) equals the oracle's Euler step.
+    pb = oracle.Problem(12, 8, 3, 3e-9, Ms=8e5, A=1.3e-11, Ku=500.0, alpha=0.1, gamma=2.211e5,
+                        hext=(1e3, -2e3, 5e2))
+    m0 = random_unit_m(pb.shape, seed=1)
+    obs = np.array([0, 5, 17, 100, 287])
+    h = oracle.demag(pb, m0, obs) + oracle.exchange(pb, m0).reshape(3, -1)[:, obs] + \
+        oracle.anisotropy(pb, m0).reshape(3, -1)[:, obs] + np.asarray(pb.hext).reshape(3, 1)
+    n = len(obs)
+    ps = oracle.Problem(n, 1, 1, pb.cell, Ms=pb.Ms, A=pb.A, Ku=pb.Ku, alpha=pb.alpha, gamma=pb.gamma,
+                        hext=pb.hext)
+    m0s = m0.reshape(3, -1)[:, obs]
+    k = oracle.llg_rhs(ps, m0s.reshape(3, 1, 1, n), h.reshape(3, 1, 1, n)).reshape(3, n)
+    v = m0s + 5e-14 * k
+    ref = v / np.sqrt((v * v).sum(axis=0))
+    full = oracle.euler(pb, m0, 5e-14, 1).reshape(3, -1)[:, obs]
+    assert np.abs(ref - full).max() <= 1e-15
+    assert np.abs(full - m0s).max() > 1e-3   # the step moves m
